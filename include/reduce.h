@@ -1,0 +1,146 @@
+/*
+ * libreduce -- CCD frame reduction on MI355X (gfx950): dark subtraction, flat
+ * division, translation registration, bilinear shift and sigma-clipped co-adding
+ * of a stack of 16-bit frames, as in the reduction pipeline of Niwano et al.
+ * (PASJ 2020), Sections 2.1-2.2.
+ *
+ * Conventions shared by every entry point:
+ *
+ *  - Ownership: the caller allocates every buffer.  "device" pointers are HIP
+ *    device memory, "host" pointers are ordinary host memory.  The library never
+ *    allocates or frees memory inside a call; scratch space is a caller-provided
+ *    device workspace whose size the matching *_ws() query returns.
+ *  - Streams: `stream` is a hipStream_t (NULL = the legacy default stream).  Every
+ *    call only enqueues work on that stream and returns; results are ready when
+ *    the stream is synchronised.  No call synchronises the device.
+ *  - Errors: every call validates its arguments on the host before launching
+ *    anything and returns one of the REDUCE_* status codes below; on failure
+ *    nothing was enqueued (except REDUCE_ERR_HIP, which reports a failed launch).
+ *    reduce_last_error() gives a thread-local description of the last failure.
+ *    Faults inside kernels surface at the caller's next synchronisation.
+ *  - Layout: images are row-major, x contiguous, row y = 0 first (the paper puts
+ *    the origin at the lower-left corner, X horizontal, Y vertical; Section
+ *    3.1.1).  Pitches are counted in elements.  W, H, N are int32.
+ *  - Offsets: s = (sx, sy) is the offset with frame(x + s) ~ ref(x).
+ *  - Preconditions not checked on the device: flat > 0 and finite, dark finite.
+ */
+#ifndef REDUCE_H
+#define REDUCE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------------- */
+#define REDUCE_OK               0
+#define REDUCE_ERR_NULL         1  /* a required pointer is NULL */
+#define REDUCE_ERR_SHAPE        2  /* sizes or pitches are inconsistent */
+#define REDUCE_ERR_RANGE        3  /* a parameter is outside its valid range */
+#define REDUCE_ERR_WORKSPACE    4  /* workspace missing or smaller than *_ws() */
+#define REDUCE_ERR_HIP          5  /* the HIP runtime reported an error */
+#define REDUCE_ERR_UNSUPPORTED  6  /* valid request this build cannot serve */
+
+/* ---- registration result ------------------------------------------------- */
+#define REDUCE_EDGE_X    1   /* x argmax on the window border: no sub-pixel step */
+#define REDUCE_EDGE_Y    2
+#define REDUCE_NEAR_TIE  4   /* margin below REDUCE_NEAR_TIE_MARGIN */
+#define REDUCE_FALLBACK  8   /* proposal path fell back to the full search */
+#define REDUCE_CLIPPED   16  /* window [c-R, c+R] was clipped at +-radius_max */
+#define REDUCE_NEAR_TIE_MARGIN 1e-9
+
+typedef struct {
+    int32_t dx, dy;        /* integer argmax of the score S(d) */
+    float sx, sy;          /* d + parabola vertex, rounded to float */
+    double peak;           /* S(d*) */
+    double second;         /* best score among the other candidates (-inf if none) */
+    double margin;         /* (peak - second) / |peak| (+inf if no other candidate) */
+    int32_t flags;         /* REDUCE_EDGE_X | ... */
+    int32_t pad;
+} reduce_offset_t;         /* 48 bytes */
+
+const char *reduce_status_str(int status);
+const char *reduce_last_error(void);
+int reduce_version(void);
+
+/* ---- calibrate ------------------------------------------------------------
+ * Dark subtraction and flat fielding after the 16-bit to float cast (Section 2.1,
+ * "bias subtraction, dark subtraction, flat fielding"; Section 2.2).  For every
+ * frame k:  out[k][y][x] = (float(raw[k][y][x]) - dark[y][x]) / flat[y][x]  in
+ * IEEE single precision with a correctly rounded division.  The master dark is
+ * taken to include the bias.
+ *   raw    device uint16, frame k row y at raw + k*raw_frame_pitch + y*raw_row_pitch
+ *          (a pitch larger than W expresses the overscan cut of Section 2.1 as a
+ *          zero-copy region of interest)
+ *   dark, flat  device float [H] rows of pitch cal_row_pitch
+ *   out    device float, dense [N][H][W]
+ * Errors: NULL -> REDUCE_ERR_NULL; W, H, N < 1 or pitches too small -> SHAPE. */
+int reduce_calibrate(const uint16_t *raw, int64_t raw_row_pitch, int64_t raw_frame_pitch,
+                     const float *dark, const float *flat, int64_t cal_row_pitch,
+                     float *out, int32_t W, int32_t H, int32_t N, void *stream);
+
+/* ---- register -------------------------------------------------------------
+ * Translation registration by brute-force cross-correlation (the paper takes the
+ * relative positions from WCS headers, Section 2.2; this call replaces that step).
+ * With the template T = tmpl (or the interior [Rmax, W-Rmax) x [Rmax, H-Rmax)),
+ * r' = ref - mean_T(ref) and, for each frame k and every integer d in the window
+ * [c_k - R, c_k + R]^2 clipped to [-Rmax, Rmax]^2 (c_k = centers[k] or 0):
+ *     S_k(d) = sum_{p in T} r'(p) * frame_k(p + d)        (FP64 accumulation)
+ * d* = argmax S_k (equal scores: smaller dy, then smaller dx); per axis the vertex
+ * of the parabola through S at d*-1, d*, d*+1 refines d* unless d* is on the window
+ * border (then the fraction is 0 and EDGE is set).
+ *   ref     device float [H][W];  frames device float [N][H][W]
+ *   centers device int32 [N][2] (cx, cy) or NULL
+ *   tmpl    host int32 {x0, y0, w, h} or NULL; T dilated by Rmax must lie in the frame
+ *   out     device reduce_offset_t [N]
+ *   scores  device double [N][2R+1][2R+1] or NULL: S_k at (dy-cy+R, dx-cx+R), -inf
+ *           outside the clipped window
+ *   ws      device workspace of at least reduce_register_ws(W, H, N, R, Rmax) bytes
+ * Errors: R < 0, Rmax < 0 or an invalid template -> RANGE; small ws -> WORKSPACE. */
+size_t reduce_register_ws(int32_t W, int32_t H, int32_t N, int32_t radius, int32_t radius_max);
+int reduce_register(const float *ref, const float *frames, int32_t W, int32_t H, int32_t N,
+                    int32_t radius, int32_t radius_max, const int32_t *centers,
+                    const int32_t *tmpl, reduce_offset_t *out, double *scores,
+                    void *ws, size_t ws_bytes, void *stream);
+
+/* ---- common overlap -------------------------------------------------------
+ * The alignment crops every frame to the area all frames cover (Section 3.1.2,
+ * note to the table of co-adding data sets).  Output x must satisfy
+ * 0 <= x + s_kx <= W - 1 for every k:  x in [max_k ceil(-s_kx), min_k floor(W-1-s_kx)],
+ * likewise y.  Host-only computation.
+ *   offs  host float [N][2];  rect  host int32 out {x0, y0, w, h}
+ * Errors: non-finite offsets or an empty overlap -> RANGE. */
+int reduce_valid_rect(const float *offs, int32_t N, int32_t W, int32_t H, int32_t *rect);
+
+/* ---- shift ----------------------------------------------------------------
+ * Sub-pixel alignment by bilinear interpolation (the paper shifts by bicubic
+ * splines and names bilinear interpolation as the cheaper alternative, Section
+ * 3.2.1).  out[k][v][u] = f_k(x0 + u + sx_k, y0 + v + sy_k) with the integer part
+ * floor(s) applied in integer arithmetic and the fraction a = s - floor(s) as
+ * bilinear weights (computed in double, rounded once to float).
+ *   in    device float [N][H][W];  out  device float dense [N][h][w]
+ *   offs  device float [N][2];     rect host int32 {x0, y0, w, h}
+ *   integer_mode != 0: exact copy f_k(x + floor(sx), y + floor(sy)).
+ * Errors: an empty rect -> SHAPE.  The caller guarantees that rect lies inside the
+ * overlap of the offsets (reduce_valid_rect); taps are clamped to the frame. */
+int reduce_shift(const float *in, float *out, int32_t W, int32_t H, int32_t N,
+                 const float *offs, const int32_t *rect, int32_t integer_mode, void *stream);
+
+/* ---- combine --------------------------------------------------------------
+ * Co-adding by sigma-clipped mean (Sections 2.1 and 3.1.2).  Per pixel, over the
+ * N aligned values: up to max_iters times, take the mean m and population sigma of
+ * the kept values (in double) and drop every kept value with |x - m| > ksigma*sigma;
+ * stop when an iteration drops nothing; out = mean of the kept values.
+ *   aligned  device float [N][h][w];  out device float [h][w]
+ *   keep     device uint8 [N][h][w] (1 = kept) or NULL
+ *   n_rej    device int64 [1], set to the number of dropped values, or NULL
+ * Errors: ksigma <= 0, max_iters < 0 -> RANGE; N > 48 -> UNSUPPORTED. */
+int reduce_combine(const float *aligned, int32_t w, int32_t h, int32_t N, float ksigma,
+                   int32_t max_iters, float *out, uint8_t *keep, int64_t *n_rej, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* REDUCE_H */

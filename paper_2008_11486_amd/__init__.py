@@ -1,0 +1,213 @@
+"""CCD frame reduction on MI355X: Python binding of libreduce (see include/reduce.h).
+
+Argument marshalling only: every function passes device pointers of caller-owned
+torch tensors and the current HIP stream to the C ABI.  All arithmetic runs in the
+library's HIP kernels; there is no CPU fallback, and importing the binding fails
+loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libreduce.so")
+
+OK, ERR_NULL, ERR_SHAPE, ERR_RANGE, ERR_WORKSPACE, ERR_HIP, ERR_UNSUPPORTED = range(7)
+EDGE_X, EDGE_Y, NEAR_TIE, FALLBACK, CLIPPED = 1, 2, 4, 8, 16
+
+# reduce_offset_t
+OFFSET_DTYPE = np.dtype([("dx", "<i4"), ("dy", "<i4"), ("sx", "<f4"), ("sy", "<f4"),
+                         ("peak", "<f8"), ("second", "<f8"), ("margin", "<f8"),
+                         ("flags", "<i4"), ("pad", "<i4")])
+OFFSET_BYTES = 48
+
+
+class ReduceError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"libreduce status {status}: {detail}")
+        self.status = status
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def build(verbose: bool = False) -> str:
+    from . import builder
+    return builder.build(verbose=verbose)
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2008_11486_amd.build()")
+        _lib = ctypes.CDLL(LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+def _declare(L):
+    P, I32, I64, F, D, SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float,
+                             ctypes.c_double, ctypes.c_size_t)
+    L.reduce_status_str.restype = ctypes.c_char_p
+    L.reduce_status_str.argtypes = [ctypes.c_int]
+    L.reduce_last_error.restype = ctypes.c_char_p
+    L.reduce_version.restype = ctypes.c_int
+    L.reduce_calibrate.argtypes = [P, I64, I64, P, P, I64, P, I32, I32, I32, P]
+    L.reduce_register_ws.argtypes = [I32, I32, I32, I32, I32]
+    L.reduce_register_ws.restype = SZ
+    L.reduce_register.argtypes = [P, P, I32, I32, I32, I32, I32, P, P, P, P, P, SZ, P]
+    L.reduce_valid_rect.argtypes = [P, I32, I32, I32, P]
+    L.reduce_shift.argtypes = [P, P, I32, I32, I32, P, P, I32, P]
+    L.reduce_combine.argtypes = [P, I32, I32, I32, F, I32, P, P, P, P]
+    for n in ("reduce_calibrate", "reduce_register", "reduce_valid_rect", "reduce_shift", "reduce_combine"):
+        getattr(L, n).restype = ctypes.c_int
+    for n, args in _EXTRA_DECLS.items():
+        if hasattr(L, n):
+            fn = getattr(L, n)
+            fn.argtypes, fn.restype = args
+
+
+_EXTRA_DECLS: dict = {}
+
+
+def exported_symbols() -> Sequence[str]:
+    """Names declared in include/reduce.h that the binding knows about."""
+    return ("reduce_status_str", "reduce_last_error", "reduce_version", "reduce_calibrate",
+            "reduce_register_ws", "reduce_register", "reduce_valid_rect", "reduce_shift",
+            "reduce_combine")
+
+
+def _check(rc: int) -> None:
+    if rc != OK:
+        raise ReduceError(rc, lib().reduce_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    return t
+
+
+def _raw_view(raw: torch.Tensor) -> torch.Tensor:
+    if raw.dtype not in (torch.uint16, torch.int16):
+        raise TypeError("raw must be uint16 (or int16 carrying the same bits)")
+    return raw
+
+
+# ---------------------------------------------------------------------------- calibrate
+def calibrate(raw: torch.Tensor, dark: torch.Tensor, flat: torch.Tensor,
+              out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """raw [N][H][W] uint16 (row/frame strides honoured), dark/flat [H][W] float32."""
+    raw = _raw_view(_dev(raw, "raw"))
+    if raw.dim() == 2:
+        raw = raw.unsqueeze(0)
+    N, H, W = raw.shape
+    if raw.stride(2) != 1 or dark.stride(1) != 1 or flat.stride() != dark.stride():
+        raise ValueError("x must be contiguous and dark/flat must share strides")
+    if dark.dtype != torch.float32 or flat.dtype != torch.float32:
+        raise TypeError("dark and flat must be float32")
+    if out is None:
+        out = torch.empty((N, H, W), dtype=torch.float32, device=raw.device)
+    _check(lib().reduce_calibrate(_ptr(raw), raw.stride(1), raw.stride(0), _ptr(dark), _ptr(flat),
+                                  dark.stride(0), _ptr(out), W, H, N, _stream(stream)))
+    return out
+
+
+# ---------------------------------------------------------------------------- register
+def register_ws_bytes(W: int, H: int, N: int, radius: int, radius_max: Optional[int] = None) -> int:
+    return int(lib().reduce_register_ws(W, H, N, radius, radius if radius_max is None else radius_max))
+
+
+def register(ref: torch.Tensor, frames: torch.Tensor, radius: int, radius_max: Optional[int] = None,
+             centers: Optional[torch.Tensor] = None, tmpl: Optional[Sequence[int]] = None,
+             want_scores: bool = False, ws: Optional[torch.Tensor] = None, stream=None):
+    """Returns a device uint8 tensor [N][48] of reduce_offset_t (decode with offsets_to_numpy)
+    and, if asked, the score cube float64 [N][2R+1][2R+1]."""
+    _dev(ref, "ref")
+    _dev(frames, "frames")
+    if frames.dim() == 2:
+        frames = frames.unsqueeze(0)
+    N, H, W = frames.shape
+    rmax = radius if radius_max is None else radius_max
+    if not (ref.is_contiguous() and frames.is_contiguous()):
+        raise ValueError("ref and frames must be contiguous")
+    need = register_ws_bytes(W, H, N, radius, rmax)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=frames.device)
+    out = torch.empty((N, OFFSET_BYTES), dtype=torch.uint8, device=frames.device)
+    scores = (torch.empty((N, 2 * radius + 1, 2 * radius + 1), dtype=torch.float64, device=frames.device)
+              if want_scores else None)
+    if centers is not None:
+        centers = _dev(centers, "centers")
+        if centers.dtype != torch.int32 or not centers.is_contiguous():
+            raise TypeError("centers must be a contiguous int32 device tensor [N][2]")
+    t = None
+    if tmpl is not None:
+        t = (ctypes.c_int32 * 4)(*[int(v) for v in tmpl])
+    _check(lib().reduce_register(_ptr(ref), _ptr(frames), W, H, N, radius, rmax, _ptr(centers),
+                                 t, _ptr(out), _ptr(scores), _ptr(ws), ws.numel(), _stream(stream)))
+    return (out, scores) if want_scores else out
+
+
+def offsets_to_numpy(raw_offsets: torch.Tensor) -> np.ndarray:
+    """Device reduce_offset_t bytes -> host structured array (a copy; synchronises)."""
+    b = raw_offsets.detach().cpu().numpy().reshape(-1)
+    return b.view(OFFSET_DTYPE).copy()
+
+
+# ---------------------------------------------------------------------------- overlap / shift
+def valid_rect(offs: np.ndarray, W: int, H: int) -> np.ndarray:
+    o = np.ascontiguousarray(offs, dtype=np.float32).reshape(-1, 2)
+    rect = np.zeros(4, dtype=np.int32)
+    _check(lib().reduce_valid_rect(o.ctypes.data_as(ctypes.c_void_p), o.shape[0], W, H,
+                                   rect.ctypes.data_as(ctypes.c_void_p)))
+    return rect
+
+
+def shift(frames: torch.Tensor, offs: torch.Tensor, rect: Sequence[int], integer_mode: bool = False,
+          out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """frames float32 [N][H][W], offs float32 device [N][2], rect host (x0, y0, w, h)."""
+    _dev(frames, "frames")
+    _dev(offs, "offs")
+    if frames.dim() == 2:
+        frames = frames.unsqueeze(0)
+    N, H, W = frames.shape
+    if offs.dtype != torch.float32 or not offs.is_contiguous() or offs.numel() != 2 * N:
+        raise TypeError("offs must be a contiguous float32 device tensor [N][2]")
+    r = (ctypes.c_int32 * 4)(*[int(v) for v in rect])
+    if out is None:
+        out = torch.empty((N, int(rect[3]), int(rect[2])), dtype=torch.float32, device=frames.device)
+    _check(lib().reduce_shift(_ptr(frames.contiguous()), _ptr(out), W, H, N, _ptr(offs), r,
+                              1 if integer_mode else 0, _stream(stream)))
+    return out
+
+
+# ---------------------------------------------------------------------------- combine
+def combine(aligned: torch.Tensor, ksigma: float = 3.0, max_iters: int = 3, want_keep: bool = False,
+            want_nrej: bool = False, stream=None):
+    """Returns (out [h][w] float32, keep uint8 [N][h][w] or None, n_rej int64 [1] or None)."""
+    _dev(aligned, "aligned")
+    N, h, w = aligned.shape
+    if not aligned.is_contiguous():
+        raise ValueError("aligned must be contiguous")
+    out = torch.empty((h, w), dtype=torch.float32, device=aligned.device)
+    keep = torch.empty((N, h, w), dtype=torch.uint8, device=aligned.device) if want_keep else None
+    nrej = torch.empty(1, dtype=torch.int64, device=aligned.device) if want_nrej else None
+    _check(lib().reduce_combine(_ptr(aligned), w, h, N, float(ksigma), int(max_iters), _ptr(out),
+                                _ptr(keep), _ptr(nrej), _stream(stream)))
+    return out, keep, nrej

@@ -1,0 +1,110 @@
+// Sigma-clipped mean co-add along the frame axis (Sections 2.1, 3.1.2).
+//
+// A workgroup stages a 256-pixel tile of every frame in LDS (one coalesced 1 KB row
+// per frame), then groups of L lanes clip one pixel column at a time: each lane
+// holds the frames l, l+L, l+2L, ... of the column in registers and the group's
+// sums, squared deviations and drop counts are combined with wavefront butterfly
+// reductions.  L = 1 keeps the whole column in one lane (no cross-lane traffic).
+// Mean and sigma are evaluated in double.  Bytes per input pixel: 4 read, plus
+// 4/N for the output and 1 per value when the keep mask is requested.
+#include "common.h"
+#include "combine_core.h"
+
+namespace rd {
+
+template <int L, int MAXV>
+__global__ __launch_bounds__(COMB_TILE) void combine_kernel(
+    const float *__restrict__ aligned, int64_t plane, int32_t N, double ksigma, int32_t max_iters,
+    float *__restrict__ out, uint8_t *__restrict__ keep, unsigned long long *__restrict__ n_rej)
+{
+    extern __shared__ float tile[];  // [N][COMB_TILE]
+    const int64_t p0 = (int64_t)blockIdx.x * COMB_TILE;
+    const int t = threadIdx.x;
+    for (int32_t k = 0; k < N; ++k) {
+        const int64_t p = p0 + t;
+        tile[k * COMB_TILE + t] = p < plane ? aligned[k * plane + p] : 0.0f;
+    }
+    __syncthreads();
+
+    const int lane = t % L;
+    const int group = t / L;
+    constexpr int GROUPS = COMB_TILE / L;
+    unsigned dropped_here = 0;
+    for (int r = 0; r < L; ++r) {
+        const int px = group + GROUPS * r;
+        const int64_t p = p0 + px;
+        float x[MAXV];
+#pragma unroll
+        for (int i = 0; i < MAXV; ++i) {
+            const int k = lane + L * i;
+            x[i] = k < N ? tile[k * COMB_TILE + px] : 0.0f;
+        }
+        ClipResult<MAXV> res = clip_column<L, MAXV>(x, N, lane, ksigma, max_iters);
+        if (p < plane) {
+            if (lane == 0) out[p] = res.mean;
+            if (keep) {
+#pragma unroll
+                for (int i = 0; i < MAXV; ++i) {
+                    const int k = lane + L * i;
+                    if (k < N) keep[k * plane + p] = (uint8_t)((res.kept >> i) & 1u);
+                }
+            }
+            if (lane == 0) dropped_here += (unsigned)res.dropped;
+        }
+    }
+    if (n_rej) {
+        const unsigned total = block_sum_u32(dropped_here);
+        if (t == 0 && total) atomicAdd(n_rej, (unsigned long long)total);
+    }
+}
+
+__global__ void zero_u64(unsigned long long *p) { *p = 0ull; }
+
+template <int L, int MAXV>
+static void launch_combine(const float *aligned, int64_t plane, int32_t N, double ksigma, int32_t max_iters,
+                           float *out, uint8_t *keep, unsigned long long *n_rej, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)ceil_div(plane, COMB_TILE);
+    const size_t lds = sizeof(float) * (size_t)N * COMB_TILE;
+    hipLaunchKernelGGL((combine_kernel<L, MAXV>), dim3(blocks), dim3(COMB_TILE), lds, s, aligned, plane, N, ksigma,
+                       max_iters, out, keep, n_rej);
+}
+
+int combine_lanes_for(int32_t N);
+
+void combine_dispatch(int lanes, const float *aligned, int64_t plane, int32_t N, double ksigma, int32_t max_iters,
+                      float *out, uint8_t *keep, unsigned long long *n_rej, hipStream_t s)
+{
+    switch (lanes) {
+    case 1:
+        if (N <= 16) launch_combine<1, 16>(aligned, plane, N, ksigma, max_iters, out, keep, n_rej, s);
+        else if (N <= 32) launch_combine<1, 32>(aligned, plane, N, ksigma, max_iters, out, keep, n_rej, s);
+        else launch_combine<1, 64>(aligned, plane, N, ksigma, max_iters, out, keep, n_rej, s);
+        break;
+    case 2: launch_combine<2, 32>(aligned, plane, N, ksigma, max_iters, out, keep, n_rej, s); break;
+    case 4: launch_combine<4, 16>(aligned, plane, N, ksigma, max_iters, out, keep, n_rej, s); break;
+    case 8: launch_combine<8, 8>(aligned, plane, N, ksigma, max_iters, out, keep, n_rej, s); break;
+    case 16: launch_combine<16, 4>(aligned, plane, N, ksigma, max_iters, out, keep, n_rej, s); break;
+    case 32: launch_combine<32, 2>(aligned, plane, N, ksigma, max_iters, out, keep, n_rej, s); break;
+    default: launch_combine<64, 1>(aligned, plane, N, ksigma, max_iters, out, keep, n_rej, s); break;
+    }
+}
+
+}  // namespace rd
+
+using namespace rd;
+
+extern "C" int reduce_combine(const float *aligned, int32_t w, int32_t h, int32_t N, float ksigma,
+                              int32_t max_iters, float *out, uint8_t *keep, int64_t *n_rej, void *stream)
+{
+    if (!aligned || !out) return fail(REDUCE_ERR_NULL, "reduce_combine: NULL buffer");
+    if (w < 1 || h < 1 || N < 1) return fail(REDUCE_ERR_SHAPE, "reduce_combine: w, h, N must be >= 1");
+    if (!(ksigma > 0.0f) || !std::isfinite(ksigma) || max_iters < 0)
+        return fail(REDUCE_ERR_RANGE, "reduce_combine: ksigma must be > 0 and max_iters >= 0");
+    if (N > COMB_MAX_N) return fail(REDUCE_ERR_UNSUPPORTED, "reduce_combine: N above 48");
+    hipStream_t s = as_stream(stream);
+    unsigned long long *nr = reinterpret_cast<unsigned long long *>(n_rej);
+    if (nr) hipLaunchKernelGGL(zero_u64, dim3(1), dim3(1), 0, s, nr);
+    combine_dispatch(combine_lanes_for(N), aligned, (int64_t)w * h, N, (double)ksigma, max_iters, out, keep, nr, s);
+    return check_launch("reduce_combine");
+}

@@ -1,0 +1,76 @@
+"""The C-ABI library loads on the CPU and exports every entry point of include/reduce.h;
+host-only entry points (argument validation, overlap, workspace sizes) are checked
+without touching a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "reduce.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(reduce_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def rd():
+    import paper_2008_11486_amd as rd
+    return rd
+
+
+def test_every_declared_symbol_is_exported(rd):
+    names = header_functions()
+    assert len(names) >= 9
+    L = rd.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(rd.exported_symbols()) <= set(names)
+
+
+def test_status_strings(rd):
+    L = rd.lib()
+    assert L.reduce_status_str(0) == b"ok"
+    assert L.reduce_status_str(4) == b"workspace too small"
+    assert L.reduce_version() >= 1
+
+
+def test_null_and_shape_errors_before_launch(rd):
+    L = rd.lib()
+    assert L.reduce_calibrate(None, 8, 64, None, None, 8, None, 8, 8, 1, None) == rd.ERR_NULL
+    b = ctypes.c_void_p(16)  # never dereferenced: validation fails first
+    assert L.reduce_calibrate(b, 4, 64, b, b, 8, b, 8, 8, 1, None) == rd.ERR_SHAPE
+    assert b"pitch" in L.reduce_last_error()
+    assert L.reduce_combine(b, 4, 4, 3, ctypes.c_float(0.0), 3, b, None, None, None) == rd.ERR_RANGE
+    assert L.reduce_combine(b, 4, 4, 49, ctypes.c_float(3.0), 3, b, None, None, None) == rd.ERR_UNSUPPORTED
+    assert L.reduce_register(b, b, 32, 32, 1, -1, 2, None, None, b, None, b, 1 << 20, None) == rd.ERR_RANGE
+    assert L.reduce_register(b, b, 32, 32, 1, 2, 2, None, None, b, None, b, 8, None) == rd.ERR_WORKSPACE
+    r = (ctypes.c_int32 * 4)(0, 0, 0, 5)
+    assert L.reduce_shift(b, b, 8, 8, 1, b, r, 0, None) == rd.ERR_SHAPE
+
+
+def test_register_ws_is_monotone(rd):
+    a = rd.register_ws_bytes(512, 512, 5, 8)
+    b = rd.register_ws_bytes(1024, 1024, 10, 21)
+    c = rd.register_ws_bytes(6144, 6160, 16, 65)
+    assert 0 < a < b < c
+    assert c < 2 << 30
+    assert rd.register_ws_bytes(16, 16, 1, 8) == 0  # no template left
+
+
+def test_valid_rect_matches_oracle(rd, orc):
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        W, H = int(rng.integers(8, 200)), int(rng.integers(8, 200))
+        N = int(rng.integers(1, 8))
+        offs = rng.uniform(-5, 5, size=(N, 2)).astype(np.float32)
+        if rng.random() < 0.3:
+            offs = np.rint(offs)
+        offs[0] = 0
+        assert np.array_equal(rd.valid_rect(offs, W, H), orc.valid_rect(offs, W, H))
+    with pytest.raises(rd.ReduceError):
+        rd.valid_rect(np.array([[0, 0], [50, 0]], np.float32), 40, 40)

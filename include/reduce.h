@@ -65,6 +65,14 @@ const char *reduce_status_str(int status);
 const char *reduce_last_error(void);
 int reduce_version(void);
 
+/* Kernel timing: reduce_prof_enable(1) clears earlier records and makes every
+ * following launch of a named kernel ("calibrate", "score_tiles", "shift",
+ * "combine", ...) record a HIP event pair on its own stream; reduce_prof_query
+ * waits for the recorded events and returns the summed elapsed milliseconds and the
+ * number of launches of one kernel.  Host-side bookkeeping only; 0 disables. */
+int reduce_prof_enable(int on);
+int reduce_prof_query(const char *kernel, double *total_ms, int64_t *launches);
+
 /* ---- calibrate ------------------------------------------------------------
  * Dark subtraction and flat fielding after the 16-bit to float cast (Section 2.1,
  * "bias subtraction, dark subtraction, flat fielding"; Section 2.2).  For every
@@ -100,6 +108,12 @@ int reduce_calibrate(const uint16_t *raw, int64_t raw_row_pitch, int64_t raw_fra
  *   ws      device workspace of at least reduce_register_ws(W, H, N, R, Rmax) bytes
  * Errors: R < 0, Rmax < 0 or an invalid template -> RANGE; small ws -> WORKSPACE. */
 size_t reduce_register_ws(int32_t W, int32_t H, int32_t N, int32_t radius, int32_t radius_max);
+
+/* Launch plan the search would use for these sizes (host-only, for diagnostics and
+ * tuning): fields = {D, K, NBX, C, G, CW, S, threads, TX, TY, BR, JS, FR, FC,
+ * lds_bytes, n_tiles}.  Errors: no template for the sizes -> RANGE. */
+int reduce_register_plan(int32_t W, int32_t H, int32_t N, int32_t radius, int32_t radius_max,
+                         int32_t *fields);
 int reduce_register(const float *ref, const float *frames, int32_t W, int32_t H, int32_t N,
                     int32_t radius, int32_t radius_max, const int32_t *centers,
                     const int32_t *tmpl, reduce_offset_t *out, double *scores,
@@ -139,6 +153,31 @@ int reduce_shift(const float *in, float *out, int32_t W, int32_t H, int32_t N,
  * Errors: ksigma <= 0, max_iters < 0 -> RANGE; N > 48 -> UNSUPPORTED. */
 int reduce_combine(const float *aligned, int32_t w, int32_t h, int32_t N, float ksigma,
                    int32_t max_iters, float *out, uint8_t *keep, int64_t *n_rej, void *stream);
+
+/* ---- autotuner --------------------------------------------------------------
+ * Launch shapes (tiles, workgroup sizes, lanes per pixel) are chosen per problem
+ * size by timing candidates on the caller's data with HIP events; the winner is
+ * cached in the process and used by every later call of that size (including the
+ * batched path).  Tuning calls synchronise `stream`.
+ *   reduce_tune_register: candidates of the correlation search for (W, H, radius,
+ *     radius_max), each run reps times on ref/frames; only shapes whose workspace
+ *     fits ws_bytes are tried; out receives the offsets (device reduce_offset_t [N]);
+ *     fields (host int32[16] or NULL) receives the chosen plan as in
+ *     reduce_register_plan.
+ *   reduce_tune_combine: lanes per pixel column L in {1, 2, 4, 8, 16} for N frames;
+ *     out (device float [h][w]) is overwritten; lanes (host, or NULL) gets L.
+ *   reduce_tune_save / reduce_tune_load: the cache as JSON lines tagged with the
+ *     device architecture; entries of other architectures are ignored on load.
+ * Errors: as the calls they time; no fitting candidate -> WORKSPACE; unreadable or
+ * unwritable file -> RANGE. */
+int reduce_tune_register(const float *ref, const float *frames, int32_t W, int32_t H, int32_t N,
+                         int32_t radius, int32_t radius_max, reduce_offset_t *out, void *ws,
+                         size_t ws_bytes, int32_t reps, void *stream, int32_t *fields);
+int reduce_tune_combine(const float *aligned, int32_t w, int32_t h, int32_t N, float ksigma,
+                        int32_t max_iters, float *out, int32_t reps, void *stream, int32_t *lanes);
+int reduce_tune_save(const char *path);
+int reduce_tune_load(const char *path);
+int reduce_tune_clear(void);
 
 #ifdef __cplusplus
 }

@@ -65,7 +65,19 @@ def _declare(L):
     L.reduce_valid_rect.argtypes = [P, I32, I32, I32, P]
     L.reduce_shift.argtypes = [P, P, I32, I32, I32, P, P, I32, P]
     L.reduce_combine.argtypes = [P, I32, I32, I32, F, I32, P, P, P, P]
-    for n in ("reduce_calibrate", "reduce_register", "reduce_valid_rect", "reduce_shift", "reduce_combine"):
+    L.reduce_register_plan.argtypes = [I32, I32, I32, I32, I32, P]
+    L.reduce_register_plan.restype = ctypes.c_int
+    L.reduce_tune_register.argtypes = [P, P, I32, I32, I32, I32, I32, P, P, SZ, I32, P, P]
+    L.reduce_tune_combine.argtypes = [P, I32, I32, I32, F, I32, P, I32, P, P]
+    L.reduce_tune_save.argtypes = [ctypes.c_char_p]
+    L.reduce_tune_load.argtypes = [ctypes.c_char_p]
+    for n in ("reduce_tune_register", "reduce_tune_combine", "reduce_tune_save", "reduce_tune_load",
+              "reduce_tune_clear"):
+        getattr(L, n).restype = ctypes.c_int
+    L.reduce_prof_enable.argtypes = [ctypes.c_int]
+    L.reduce_prof_query.argtypes = [ctypes.c_char_p, P, P]
+    for n in ("reduce_calibrate", "reduce_register", "reduce_valid_rect", "reduce_shift", "reduce_combine",
+              "reduce_prof_enable", "reduce_prof_query"):
         getattr(L, n).restype = ctypes.c_int
     for n, args in _EXTRA_DECLS.items():
         if hasattr(L, n):
@@ -80,12 +92,26 @@ def exported_symbols() -> Sequence[str]:
     """Names declared in include/reduce.h that the binding knows about."""
     return ("reduce_status_str", "reduce_last_error", "reduce_version", "reduce_calibrate",
             "reduce_register_ws", "reduce_register", "reduce_valid_rect", "reduce_shift",
-            "reduce_combine")
+            "reduce_combine", "reduce_prof_enable", "reduce_prof_query", "reduce_register_plan",
+            "reduce_tune_register", "reduce_tune_combine", "reduce_tune_save", "reduce_tune_load",
+            "reduce_tune_clear")
 
 
 def _check(rc: int) -> None:
     if rc != OK:
         raise ReduceError(rc, lib().reduce_last_error().decode())
+
+
+def prof_enable(on: bool = True) -> None:
+    _check(lib().reduce_prof_enable(1 if on else 0))
+
+
+def prof_query(kernel: str):
+    """(total milliseconds, launches) of one kernel since prof_enable(True)."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(lib().reduce_prof_query(kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -162,6 +188,53 @@ def register(ref: torch.Tensor, frames: torch.Tensor, radius: int, radius_max: O
     _check(lib().reduce_register(_ptr(ref), _ptr(frames), W, H, N, radius, rmax, _ptr(centers),
                                  t, _ptr(out), _ptr(scores), _ptr(ws), ws.numel(), _stream(stream)))
     return (out, scores) if want_scores else out
+
+
+PLAN_FIELDS = ("D", "K", "NBX", "C", "G", "CW", "S", "threads", "TX", "TY", "BR", "JS", "FR", "FC",
+               "lds", "n_tiles")
+
+
+def register_plan(W: int, H: int, N: int, radius: int, radius_max: Optional[int] = None) -> dict:
+    f = (ctypes.c_int32 * 16)()
+    _check(lib().reduce_register_plan(W, H, N, radius, radius if radius_max is None else radius_max, f))
+    return dict(zip(PLAN_FIELDS, list(f)))
+
+
+def tune_register(ref: torch.Tensor, frames: torch.Tensor, radius: int, radius_max: Optional[int] = None,
+                  reps: int = 3, stream=None) -> dict:
+    """Time candidate launch shapes of the search on these frames; caches and returns the winner."""
+    if frames.dim() == 2:
+        frames = frames.unsqueeze(0)
+    N, H, W = frames.shape
+    rmax = radius if radius_max is None else radius_max
+    ws = torch.empty(max(register_ws_bytes(W, H, N, radius, rmax), 1), dtype=torch.uint8, device=frames.device)
+    out = torch.empty((N, OFFSET_BYTES), dtype=torch.uint8, device=frames.device)
+    f = (ctypes.c_int32 * 16)()
+    _check(lib().reduce_tune_register(_ptr(ref), _ptr(frames), W, H, N, radius, rmax, _ptr(out), _ptr(ws),
+                                      ws.numel(), reps, _stream(stream), f))
+    return dict(zip(PLAN_FIELDS, list(f)))
+
+
+def tune_combine(aligned: torch.Tensor, ksigma: float = 3.0, max_iters: int = 3, reps: int = 3,
+                 stream=None) -> int:
+    N, h, w = aligned.shape
+    out = torch.empty((h, w), dtype=torch.float32, device=aligned.device)
+    lanes = ctypes.c_int32(0)
+    _check(lib().reduce_tune_combine(_ptr(aligned), w, h, N, float(ksigma), int(max_iters), _ptr(out), reps,
+                                     _stream(stream), ctypes.byref(lanes)))
+    return lanes.value
+
+
+def tune_save(path: str) -> None:
+    _check(lib().reduce_tune_save(path.encode()))
+
+
+def tune_load(path: str) -> None:
+    _check(lib().reduce_tune_load(path.encode()))
+
+
+def tune_clear() -> None:
+    _check(lib().reduce_tune_clear())
 
 
 def offsets_to_numpy(raw_offsets: torch.Tensor) -> np.ndarray:

@@ -3,7 +3,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "common.h"
 
@@ -26,9 +29,88 @@ int check_launch(const char *what)
     return REDUCE_OK;
 }
 
+// ---- kernel timing ------------------------------------------------------------
+struct ProfRec {
+    std::string name;
+    hipEvent_t start, stop;
+};
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<ProfRec> g_prof;
+static std::vector<hipEvent_t> g_event_pool;
+
+bool prof_on() { return g_prof_on; }
+
+static hipEvent_t take_event()
+{
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void prof_record(const char *name, hipStream_t s, bool start)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (start) {
+        ProfRec r{name, take_event(), nullptr};
+        if (r.start) hipEventRecord(r.start, s);
+        g_prof.push_back(r);
+    } else {
+        for (auto it = g_prof.rbegin(); it != g_prof.rend(); ++it)
+            if (it->stop == nullptr && it->name == name) {
+                it->stop = take_event();
+                if (it->stop) hipEventRecord(it->stop, s);
+                break;
+            }
+    }
+}
+
+static void prof_clear()
+{
+    for (auto &r : g_prof) {
+        if (r.start) g_event_pool.push_back(r.start);
+        if (r.stop) g_event_pool.push_back(r.stop);
+    }
+    g_prof.clear();
+}
+
 }  // namespace rd
 
 extern "C" {
+
+int reduce_prof_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(rd::g_prof_mu);
+    rd::prof_clear();
+    rd::g_prof_on = on != 0;
+    return REDUCE_OK;
+}
+
+int reduce_prof_query(const char *kernel, double *total_ms, int64_t *launches)
+{
+    using namespace rd;
+    if (!kernel || !total_ms || !launches) return fail(REDUCE_ERR_NULL, "reduce_prof_query: NULL argument");
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    double t = 0.0;
+    int64_t n = 0;
+    for (auto &r : g_prof) {
+        if (r.name != kernel || !r.start || !r.stop) continue;
+        if (hipEventSynchronize(r.stop) != hipSuccess) return fail(REDUCE_ERR_HIP, "reduce_prof_query: event");
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess)
+            return fail(REDUCE_ERR_HIP, "reduce_prof_query: elapsed time");
+        t += ms;
+        ++n;
+    }
+    *total_ms = t;
+    *launches = n;
+    return REDUCE_OK;
+}
 
 int reduce_version(void) { return 1; }
 

@@ -80,6 +80,7 @@ extern "C" int reduce_calibrate(const uint16_t *raw, int64_t raw_row_pitch, int6
     const bool vec = (W % CAL_VEC == 0) && (raw_row_pitch % CAL_VEC == 0) && (raw_frame_pitch % CAL_VEC == 0) &&
                      (cal_row_pitch % 4 == 0) && aligned16(raw) && aligned16(dark) && aligned16(flat) &&
                      aligned16(out);
+    ProfScope prof("calibrate", s);
     if (vec) {
         const int64_t groups = (int64_t)(W / CAL_VEC) * H;
         hipLaunchKernelGGL(calibrate_vec8, dim3((unsigned)ceil_div(groups, CAL_BLOCK)), dim3(CAL_BLOCK), 0, s,

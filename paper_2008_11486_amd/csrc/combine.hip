@@ -66,6 +66,7 @@ static void launch_combine(const float *aligned, int64_t plane, int32_t N, doubl
 {
     const unsigned blocks = (unsigned)ceil_div(plane, COMB_TILE);
     const size_t lds = sizeof(float) * (size_t)N * COMB_TILE;
+    ProfScope prof("combine", s);
     hipLaunchKernelGGL((combine_kernel<L, MAXV>), dim3(blocks), dim3(COMB_TILE), lds, s, aligned, plane, N, ksigma,
                        max_iters, out, keep, n_rej);
 }

@@ -20,6 +20,26 @@ int check_launch(const char *what);
 
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// ---- kernel timing (enabled by reduce_prof_enable) ----------------------------
+// When enabled, ProfScope records a HIP event pair around a launch on its stream;
+// reduce_prof_query() sums the elapsed times per kernel name.
+bool prof_on();
+void prof_record(const char *name, hipStream_t s, bool start);
+
+struct ProfScope {
+    const char *name;
+    hipStream_t stream;
+    bool on;
+    ProfScope(const char *n, hipStream_t s) : name(n), stream(s), on(prof_on())
+    {
+        if (on) prof_record(name, stream, true);
+    }
+    ~ProfScope()
+    {
+        if (on) prof_record(name, stream, false);
+    }
+};
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // ---- per-element arithmetic ----------------------------------------------------

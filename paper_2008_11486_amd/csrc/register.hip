@@ -77,8 +77,20 @@ struct ScoreArgs {
     double *partial;        // [N][n_tiles][D*D]
     int32_t W, H, R, Rmax, D;
     int32_t tx0, ty0, tw, th;
-    int32_t TY, TX, NXB, BR, NBX, C, CW, S, JS, FR, FC, n_xchunks, n_tiles;
+    int32_t TY, TX, NXB, BR, NBX, C, CW, S, JS, FR, FC, n_xchunks, n_tiles, N, G;
 };
+
+// Workgroups are dispatched round-robin over the 8 XCDs.  Give each XCD a
+// contiguous run of logical work items (tile fastest, then candidate group, then
+// frame) so that neighbouring tiles, which share frame rows and columns, hit the
+// same L2.
+__device__ __forceinline__ int32_t xcd_logical_id(int32_t lin, int32_t total)
+{
+    constexpr int32_t NXCD = 8;
+    const int32_t per = total / NXCD, rem = total % NXCD;
+    const int32_t x = lin % NXCD, slot = lin / NXCD;
+    return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + slot;
+}
 
 template <int K>
 __global__ __launch_bounds__(512) void score_tiles(ScoreArgs a)
@@ -87,11 +99,16 @@ __global__ __launch_bounds__(512) void score_tiles(ScoreArgs a)
     double *rt = reinterpret_cast<double *>(smem);                         // [TY][TX]
     float *ft = reinterpret_cast<float *>(smem + sizeof(double) * a.TY * a.TX);  // [FR][FC]
 
-    const int32_t k = blockIdx.z;
-    const int32_t tile = blockIdx.x;
+    const int32_t G = a.G;
+    const int32_t total = a.n_tiles * G * a.N;
+    const int32_t lid = xcd_logical_id((int32_t)blockIdx.x, total);
+    const int32_t tile = lid % a.n_tiles;
+    const int32_t gk = lid / a.n_tiles;
+    const int32_t g = gk % G;
+    const int32_t k = gk / G;
     const int32_t band = tile / a.n_xchunks;
     const int32_t xc = tile - band * a.n_xchunks;
-    const int32_t c0 = blockIdx.y * a.CW;
+    const int32_t c0 = g * a.CW;
     const int32_t x_t = xc * a.TX;                 // first template column of the tile
     const int32_t yb0 = band * a.BR;               // first template row of the band
     const int32_t yb1 = min(yb0 + a.BR, a.th);
@@ -100,6 +117,9 @@ __global__ __launch_bounds__(512) void score_tiles(ScoreArgs a)
     const int32_t j_lo = c0 / a.NBX;
 
     const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wave = t >> 6;
+    const int nwaves = blockDim.x >> 6;
     const int cl = t % a.CW;
     const int s = t / a.CW;
     const int c = c0 + cl;
@@ -120,22 +140,28 @@ __global__ __launch_bounds__(512) void score_tiles(ScoreArgs a)
     const int pairs = a.TY * a.NXB;
     for (int32_t yc = yb0; yc < yb1; yc += a.TY) {
         __syncthreads();
-        // template tile, zero outside T (contributes exactly nothing)
-        for (int idx = t; idx < a.TY * a.TX; idx += blockDim.x) {
-            const int yy = idx / a.TX, xx = idx - yy * a.TX;
-            double v = 0.0;
-            if (yc + yy < yb1 && x_t + xx < a.tw)
-                v = (double)a.ref[(int64_t)(a.ty0 + yc + yy) * a.W + a.tx0 + x_t + xx] - mean;
-            rt[idx] = v;
+        // template tile, zero outside T (contributes exactly nothing); one wave per row
+        for (int yy = wave; yy < a.TY; yy += nwaves) {
+            const bool row_ok = yc + yy < yb1;
+            const float *src = a.ref + (int64_t)(a.ty0 + yc + yy) * a.W + a.tx0 + x_t;
+            for (int xx = lane; xx < a.TX; xx += 64) {
+                double v = 0.0;
+                if (row_ok && x_t + xx < a.tw) v = (double)src[xx] - mean;
+                rt[yy * a.TX + xx] = v;
+            }
         }
-        // frame tile, zero outside the frame
+        // frame tile, zero outside the frame; one wave per row
         const int32_t fy0 = a.ty0 + yc + cy - a.R + j_lo;
-        for (int idx = t; idx < a.FR * a.FC; idx += blockDim.x) {
-            const int rr = idx / a.FC, cc = idx - rr * a.FC;
-            const int32_t gy = fy0 + rr, gx = fx0 + cc;
-            float v = 0.0f;
-            if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) v = f[(int64_t)gy * a.W + gx];
-            ft[idx] = v;
+        for (int rr = wave; rr < a.FR; rr += nwaves) {
+            const int32_t gy = fy0 + rr;
+            const bool row_ok = gy >= 0 && gy < a.H;
+            const float *src = f + (int64_t)gy * a.W;
+            for (int cc = lane; cc < a.FC; cc += 64) {
+                const int32_t gx = fx0 + cc;
+                float v = 0.0f;
+                if (row_ok && gx >= 0 && gx < a.W) v = src[gx];
+                ft[rr * a.FC + cc] = v;
+            }
         }
         __syncthreads();
         if (active) {
@@ -334,7 +360,9 @@ static RegWs reg_ws_layout(const RegPlan &p, int32_t N, int32_t th_max)
 template <int K>
 static void launch_score(const ScoreArgs &a, const RegPlan &p, int32_t N, hipStream_t s)
 {
-    hipLaunchKernelGGL(score_tiles<K>, dim3(p.n_tiles, p.G, N), dim3(p.threads), p.lds, s, a);
+    ProfScope prof("score_tiles", s);
+    hipLaunchKernelGGL(score_tiles<K>, dim3((unsigned)((int64_t)p.n_tiles * p.G * N)), dim3(p.threads), p.lds, s,
+                       a);
 }
 
 int register_launch(const float *ref, const float *frames, int32_t W, int32_t H, int32_t N, int32_t R,
@@ -366,7 +394,7 @@ int register_launch(const float *ref, const float *frames, int32_t W, int32_t H,
     a.W = W; a.H = H; a.R = R; a.Rmax = Rmax; a.D = p.D;
     a.tx0 = tx0; a.ty0 = ty0; a.tw = tw; a.th = th;
     a.TY = p.TY; a.TX = p.TX; a.NXB = p.NXB; a.BR = p.BR; a.NBX = p.NBX; a.C = p.C; a.CW = p.CW; a.S = p.S;
-    a.JS = p.JS; a.FR = p.FR; a.FC = p.FC; a.n_xchunks = q.n_xchunks; a.n_tiles = q.n_tiles;
+    a.JS = p.JS; a.FR = p.FR; a.FC = p.FC; a.n_xchunks = q.n_xchunks; a.n_tiles = q.n_tiles; a.N = N; a.G = p.G;
     switch (p.K) {
     case 5: launch_score<5>(a, q, N, s); break;
     case 9: launch_score<9>(a, q, N, s); break;
@@ -392,6 +420,7 @@ extern "C" size_t reduce_register_ws(int32_t W, int32_t H, int32_t N, int32_t ra
     if (W < 1 || H < 1 || N < 1 || radius < 0 || radius_max < 0) return 0;
     if (W - 2 * radius_max < 1 || H - 2 * radius_max < 1) return 0;
     const RegPlan p = reg_plan(W, H, N, radius, radius_max);
+    if (p.D == 0) return 0;
     return register_ws_bytes(p, N);
 }
 
@@ -415,6 +444,7 @@ extern "C" int reduce_register(const float *ref, const float *frames, int32_t W,
     }
     if (N > 65535) return fail(REDUCE_ERR_UNSUPPORTED, "reduce_register: N above 65535");
     const RegPlan p = reg_plan(W, H, N, radius, radius_max);
+    if (p.D == 0) return fail(REDUCE_ERR_UNSUPPORTED, "reduce_register: window too large for any launch shape");
     const size_t need = register_ws_bytes(p, N);
     if (!ws || ws_bytes < need)
         return fail(REDUCE_ERR_WORKSPACE, "reduce_register: workspace needs " + std::to_string(need) + " bytes");

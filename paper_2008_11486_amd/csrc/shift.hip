@@ -75,6 +75,7 @@ extern "C" int reduce_shift(const float *in, float *out, int32_t W, int32_t H, i
     if (N > 65535 || h > 65535) return fail(REDUCE_ERR_UNSUPPORTED, "reduce_shift: N or h above 65535");
     const bool vec_store = (w % SH_VEC == 0) && ((reinterpret_cast<uintptr_t>(out) & 15u) == 0);
     dim3 grid((unsigned)ceil_div(w, (int64_t)SH_BLOCK * SH_VEC), (unsigned)h, (unsigned)N);
+    ProfScope prof("shift", as_stream(stream));
     if (integer_mode)
         hipLaunchKernelGGL(shift_kernel<true>, grid, dim3(SH_BLOCK), 0, as_stream(stream), in, out, W, H, offs, x0,
                            y0, w, h, vec_store);

@@ -1,0 +1,162 @@
+// Autotuner: times candidate launch shapes on the caller's data with HIP events and
+// caches the fastest per problem size; the cache persists as JSON lines keyed by the
+// device architecture.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "register_plan.h"
+
+namespace rd {
+
+int register_launch(const float *ref, const float *frames, int32_t W, int32_t H, int32_t N, int32_t R,
+                    int32_t Rmax, const int32_t *centers, int32_t tx0, int32_t ty0, int32_t tw, int32_t th,
+                    reduce_offset_t *out, double *scores, void *ws, const RegPlan &p, hipStream_t s);
+size_t register_ws_bytes(const RegPlan &p, int32_t N);
+void combine_dispatch(int lanes, const float *aligned, int64_t plane, int32_t N, double ksigma, int32_t max_iters,
+                      float *out, uint8_t *keep, unsigned long long *n_rej, hipStream_t s);
+int tune_save(const char *path, const char *arch);
+int tune_load(const char *path, const char *arch);
+void tune_clear();
+
+static std::string device_arch()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+// Average milliseconds of `reps` calls of fn after one warm-up call.
+template <typename F>
+static int time_ms(hipStream_t s, int reps, F fn, double *ms)
+{
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return fail(REDUCE_ERR_HIP, "autotune: event");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return fail(REDUCE_ERR_HIP, "autotune: event");
+    }
+    int rc = fn();
+    if (rc == REDUCE_OK) {
+        hipEventRecord(e0, s);
+        for (int i = 0; i < reps && rc == REDUCE_OK; ++i) rc = fn();
+        hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) rc = fail(REDUCE_ERR_HIP, "autotune: synchronize");
+    }
+    float t = 0.0f;
+    if (rc == REDUCE_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = fail(REDUCE_ERR_HIP, "autotune: time");
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    *ms = (double)t / reps;
+    return rc;
+}
+
+}  // namespace rd
+
+using namespace rd;
+
+extern "C" int reduce_tune_register(const float *ref, const float *frames, int32_t W, int32_t H, int32_t N,
+                                    int32_t radius, int32_t radius_max, reduce_offset_t *out, void *ws,
+                                    size_t ws_bytes, int32_t reps, void *stream, int32_t *fields)
+{
+    if (!ref || !frames || !ws || !out) return fail(REDUCE_ERR_NULL, "reduce_tune_register: NULL buffer");
+    if (W < 1 || H < 1 || N < 1 || radius < 0 || radius_max < 0 || W - 2 * radius_max < 1 ||
+        H - 2 * radius_max < 1)
+        return fail(REDUCE_ERR_RANGE, "reduce_tune_register: no template for these sizes");
+    if (reps < 1) reps = 1;
+    hipStream_t s = as_stream(stream);
+    constexpr int MAXC = 32;
+    RegShape cand[MAXC];
+    int n = 0;
+    reg_shape_candidates(W, H, N, radius, radius_max, cand, &n, MAXC);
+    double best_ms = 1e30;
+    RegShape best{};
+    const int32_t tx0 = radius_max, ty0 = radius_max, tw = W - 2 * radius_max, th = H - 2 * radius_max;
+    int rc = REDUCE_OK;
+    for (int i = 0; i < n; ++i) {
+        RegPlan p;
+        if (!reg_plan_from_shape(W, H, N, radius, radius_max, cand[i], &p)) continue;
+        if (register_ws_bytes(p, N) > ws_bytes) continue;
+        double ms = 0.0;
+        rc = time_ms(s, reps,
+                     [&]() {
+                         return register_launch(ref, frames, W, H, N, radius, radius_max, nullptr, tx0, ty0, tw, th,
+                                                out, nullptr, ws, p, s);
+                     },
+                     &ms);
+        if (rc != REDUCE_OK) break;
+        if (std::getenv("REDUCE_TUNE_VERBOSE"))
+            std::fprintf(stderr, "tune register K=%d G=%d S=%d TY=%d threads=%d tiles=%d: %.4f ms\n", p.K, p.G, p.S,
+                         p.TY, p.threads, p.n_tiles, ms);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = cand[i];
+        }
+    }
+    if (rc != REDUCE_OK) return rc;
+    if (best_ms >= 1e30) return fail(REDUCE_ERR_WORKSPACE, "reduce_tune_register: no candidate fits the workspace");
+    set_tuned_reg_shape(W, H, radius, radius_max, best, best_ms);
+    if (fields) {
+        RegPlan p;
+        reg_plan_from_shape(W, H, N, radius, radius_max, best, &p);
+        const int32_t v[16] = {p.D, p.K, p.NBX, p.C, p.G, p.CW, p.S, p.threads, p.TX, p.TY, p.BR, p.JS, p.FR, p.FC,
+                               (int32_t)p.lds, p.n_tiles};
+        for (int i = 0; i < 16; ++i) fields[i] = v[i];
+    }
+    return REDUCE_OK;
+}
+
+extern "C" int reduce_tune_combine(const float *aligned, int32_t w, int32_t h, int32_t N, float ksigma,
+                                   int32_t max_iters, float *out, int32_t reps, void *stream, int32_t *lanes)
+{
+    if (!aligned || !out) return fail(REDUCE_ERR_NULL, "reduce_tune_combine: NULL buffer");
+    if (w < 1 || h < 1 || N < 1 || N > 48) return fail(REDUCE_ERR_SHAPE, "reduce_tune_combine: bad sizes");
+    if (!(ksigma > 0.0f) || max_iters < 0) return fail(REDUCE_ERR_RANGE, "reduce_tune_combine: bad clip parameters");
+    if (reps < 1) reps = 1;
+    hipStream_t s = as_stream(stream);
+    double best_ms = 1e30;
+    int best = 1;
+    for (int L : {1, 2, 4, 8, 16}) {
+        double ms = 0.0;
+        const int rc = time_ms(s, reps,
+                               [&]() {
+                                   combine_dispatch(L, aligned, (int64_t)w * h, N, (double)ksigma, max_iters, out,
+                                                    nullptr, nullptr, s);
+                                   return check_launch("reduce_tune_combine");
+                               },
+                               &ms);
+        if (rc != REDUCE_OK) return rc;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = L;
+        }
+    }
+    set_tuned_combine_lanes(N, best, best_ms);
+    if (lanes) *lanes = best;
+    return REDUCE_OK;
+}
+
+extern "C" int reduce_tune_save(const char *path)
+{
+    if (!path) return fail(REDUCE_ERR_NULL, "reduce_tune_save: NULL path");
+    return tune_save(path, device_arch().c_str());
+}
+
+extern "C" int reduce_tune_load(const char *path)
+{
+    if (!path) return fail(REDUCE_ERR_NULL, "reduce_tune_load: NULL path");
+    return tune_load(path, device_arch().c_str());
+}
+
+extern "C" int reduce_tune_clear(void)
+{
+    tune_clear();
+    return REDUCE_OK;
+}

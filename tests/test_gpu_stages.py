@@ -226,3 +226,27 @@ def test_combine_closed_forms(rd, orc):
     for iters in (0, 1, 2, 5):
         v = np.array([0.0] * 30 + [1e6, 1e4, 1e2, 12.0], np.float32).reshape(-1, 1, 1)
         _combine_check(rd, orc, v, iters=iters)
+
+
+# ----------------------------------------------------------------------------- autotuner
+def test_tuned_shapes_keep_results(rd, orc, tmp_path):
+    spec = synth.small_spec(3, 200, 180, n_stars=40, shift_bound=7.0, radius=8, seed=(5,))
+    st = synth.make_stack(spec)
+    cal = rd.calibrate(*_stack_dev(st))
+    ref = cal[0].contiguous()
+    rd.tune_clear()
+    base = rd.offsets_to_numpy(rd.register(ref, cal, 8))
+    plan = rd.tune_register(ref, cal, 8, reps=1)
+    assert rd.register_plan(200, 180, 3, 8) == plan
+    tuned = rd.offsets_to_numpy(rd.register(ref, cal, 8))
+    assert np.array_equal(base[["dx", "dy"]], tuned[["dx", "dy"]])
+    cal64 = cal.cpu().numpy().astype(np.float64)
+    _check_offsets(tuned, orc.register(cal64[0], cal64, 8), "tuned")
+    path = str(tmp_path / "tuned.json")
+    rd.tune_save(path)
+    rd.tune_clear()
+    rd.tune_load(path)
+    assert rd.register_plan(200, 180, 3, 8) == plan
+    lanes = rd.tune_combine(cal[:, :64, :64].contiguous(), reps=1)
+    assert lanes in (1, 2, 4, 8, 16)
+    rd.tune_clear()

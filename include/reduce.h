@@ -154,6 +154,47 @@ int reduce_shift(const float *in, float *out, int32_t W, int32_t H, int32_t N,
 int reduce_combine(const float *aligned, int32_t w, int32_t h, int32_t N, float ksigma,
                    int32_t max_iters, float *out, uint8_t *keep, int64_t *n_rej, void *stream);
 
+/* ---- batched stacks -----------------------------------------------------------
+ * The whole chain for many independent stacks (for instance the three bands of the
+ * paper's cameras, Section 2.1, or many fields) of uneven frame counts and sizes in
+ * one persistent kernel launch, replayed from a cached HIP graph.  For every stack:
+ * calibrate all frames as reduce_calibrate; register every frame k != ref_index
+ * against frame ref_index as reduce_register with radius_max = radius and the
+ * interior template; the reference frame gets the offset 0 (peak 0, second -inf,
+ * margin +inf, flags 0); the common overlap as reduce_valid_rect of the sub-pixel
+ * offsets (of the integer offsets in integer_mode); shift as reduce_shift; combine
+ * as reduce_combine.  With the same launch shapes (the autotuner's, if any) every
+ * output is bit-identical to that stage-wise chain.
+ *   out       device float, room for W*H values; the combined image, dense [h][w]
+ *   out_rect  device int32[4] {x0, y0, w, h} of the overlap in reference pixels
+ *   offsets   device reduce_offset_t [N]
+ *   n_rej     device int64[1] (values dropped by the clip) or NULL
+ * ws: device workspace of reduce_stack_batch_ws(stacks, n) bytes (calibrated frames,
+ * partial scores, work queue); query again after tuning.  The stack descriptors are
+ * copied at the call; a repeated call with identical descriptors and workspace
+ * replays the cached graph without copying.  Calls sharing one workspace must not
+ * overlap.  Errors: as the stage-wise calls, per stack; N > 48 -> UNSUPPORTED.
+ * reduce_stack_batch_check synchronises `stream` and reports REDUCE_ERR_HIP if a
+ * dependency wait inside the kernel exceeded its spin limit. */
+typedef struct {
+    const uint16_t *raw;
+    int64_t raw_row_pitch, raw_frame_pitch;
+    const float *dark, *flat;
+    int64_t cal_row_pitch;
+    int32_t W, H, N, ref_index, radius, max_iters;
+    float ksigma;
+    int32_t integer_mode;
+    float *out;
+    int32_t *out_rect;
+    reduce_offset_t *offsets;
+    int64_t *n_rej;
+} reduce_stack_t;
+
+size_t reduce_stack_batch_ws(const reduce_stack_t *stacks, int32_t n);
+int reduce_stack_batch(const reduce_stack_t *stacks, int32_t n, void *ws, size_t ws_bytes, void *stream);
+int reduce_stack_batch_check(const void *ws, size_t ws_bytes, const reduce_stack_t *stacks, int32_t n,
+                             void *stream);
+
 /* ---- autotuner --------------------------------------------------------------
  * Launch shapes (tiles, workgroup sizes, lanes per pixel) are chosen per problem
  * size by timing candidates on the caller's data with HIP events; the winner is

@@ -74,6 +74,12 @@ def _declare(L):
     for n in ("reduce_tune_register", "reduce_tune_combine", "reduce_tune_save", "reduce_tune_load",
               "reduce_tune_clear"):
         getattr(L, n).restype = ctypes.c_int
+    L.reduce_stack_batch_ws.argtypes = [P, I32]
+    L.reduce_stack_batch_ws.restype = SZ
+    L.reduce_stack_batch.argtypes = [P, I32, P, SZ, P]
+    L.reduce_stack_batch.restype = ctypes.c_int
+    L.reduce_stack_batch_check.argtypes = [P, SZ, P, I32, P]
+    L.reduce_stack_batch_check.restype = ctypes.c_int
     L.reduce_prof_enable.argtypes = [ctypes.c_int]
     L.reduce_prof_query.argtypes = [ctypes.c_char_p, P, P]
     for n in ("reduce_calibrate", "reduce_register", "reduce_valid_rect", "reduce_shift", "reduce_combine",
@@ -94,7 +100,7 @@ def exported_symbols() -> Sequence[str]:
             "reduce_register_ws", "reduce_register", "reduce_valid_rect", "reduce_shift",
             "reduce_combine", "reduce_prof_enable", "reduce_prof_query", "reduce_register_plan",
             "reduce_tune_register", "reduce_tune_combine", "reduce_tune_save", "reduce_tune_load",
-            "reduce_tune_clear")
+            "reduce_tune_clear", "reduce_stack_batch_ws", "reduce_stack_batch", "reduce_stack_batch_check")
 
 
 def _check(rc: int) -> None:
@@ -284,3 +290,68 @@ def combine(aligned: torch.Tensor, ksigma: float = 3.0, max_iters: int = 3, want
     _check(lib().reduce_combine(_ptr(aligned), w, h, N, float(ksigma), int(max_iters), _ptr(out),
                                 _ptr(keep), _ptr(nrej), _stream(stream)))
     return out, keep, nrej
+
+
+# ---------------------------------------------------------------------------- batched stacks
+class StackDesc(ctypes.Structure):
+    """reduce_stack_t"""
+    _fields_ = [("raw", ctypes.c_void_p), ("raw_row_pitch", ctypes.c_int64), ("raw_frame_pitch", ctypes.c_int64),
+                ("dark", ctypes.c_void_p), ("flat", ctypes.c_void_p), ("cal_row_pitch", ctypes.c_int64),
+                ("W", ctypes.c_int32), ("H", ctypes.c_int32), ("N", ctypes.c_int32), ("ref_index", ctypes.c_int32),
+                ("radius", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("ksigma", ctypes.c_float),
+                ("integer_mode", ctypes.c_int32), ("out", ctypes.c_void_p), ("out_rect", ctypes.c_void_p),
+                ("offsets", ctypes.c_void_p), ("n_rej", ctypes.c_void_p)]
+
+
+class StackBatch:
+    """Device buffers and descriptors of a batch of stacks (caller-owned torch tensors).
+
+    Each stack is (raw uint16 [N][H][W], dark [H][W], flat [H][W], radius); outputs
+    are allocated here once: out [H*W] float32 (the image is out[:h*w] as [h][w]),
+    rect int32 [4], offsets [N][48] bytes, n_rej int64 [1].
+    """
+
+    def __init__(self, stacks, ksigma: float = 3.0, max_iters: int = 3, ref_index=0, integer_mode=False):
+        self.items = []
+        descs = []
+        for i, (raw, dark, flat, radius) in enumerate(stacks):
+            raw = _raw_view(_dev(raw, "raw"))
+            N, H, W = raw.shape
+            dev = raw.device
+            ref = ref_index[i] if isinstance(ref_index, (list, tuple)) else ref_index
+            imode = integer_mode[i] if isinstance(integer_mode, (list, tuple)) else integer_mode
+            out = torch.empty(H * W, dtype=torch.float32, device=dev)
+            rect = torch.zeros(4, dtype=torch.int32, device=dev)
+            offs = torch.zeros((N, OFFSET_BYTES), dtype=torch.uint8, device=dev)
+            nrej = torch.zeros(1, dtype=torch.int64, device=dev)
+            d = StackDesc(raw.data_ptr(), raw.stride(1), raw.stride(0), dark.data_ptr(), flat.data_ptr(),
+                          dark.stride(0), W, H, N, int(ref), int(radius), int(max_iters), float(ksigma),
+                          1 if imode else 0, out.data_ptr(), rect.data_ptr(), offs.data_ptr(), nrej.data_ptr())
+            descs.append(d)
+            self.items.append(dict(raw=raw, dark=dark, flat=flat, out=out, rect=rect, offsets=offs, n_rej=nrej,
+                                   W=W, H=H, N=N))
+        self.descs = (StackDesc * len(descs))(*descs)
+        self.n = len(descs)
+        self.ws = None
+
+    def ws_bytes(self) -> int:
+        return int(lib().reduce_stack_batch_ws(self.descs, self.n))
+
+    def run(self, stream=None) -> None:
+        need = self.ws_bytes()
+        if need == 0:
+            raise ReduceError(ERR_SHAPE, "invalid batch: " + lib().reduce_last_error().decode())
+        if self.ws is None or self.ws.numel() < need:
+            self.ws = torch.empty(need, dtype=torch.uint8, device=self.items[0]["raw"].device)
+        _check(lib().reduce_stack_batch(self.descs, self.n, _ptr(self.ws), self.ws.numel(), _stream(stream)))
+
+    def check(self, stream=None) -> None:
+        _check(lib().reduce_stack_batch_check(_ptr(self.ws), self.ws.numel(), self.descs, self.n,
+                                              _stream(stream)))
+
+    def result(self, i: int):
+        """(image [h][w] float32 tensor, rect numpy, offsets structured numpy, n_rej int)."""
+        it = self.items[i]
+        rect = it["rect"].cpu().numpy()
+        h, w = int(rect[3]), int(rect[2])
+        return it["out"][: h * w].view(h, w), rect, offsets_to_numpy(it["offsets"]), int(it["n_rej"].cpu()[0])

@@ -25,33 +25,7 @@ __global__ __launch_bounds__(COMB_TILE) void combine_kernel(
         tile[k * COMB_TILE + t] = p < plane ? aligned[k * plane + p] : 0.0f;
     }
     __syncthreads();
-
-    const int lane = t % L;
-    const int group = t / L;
-    constexpr int GROUPS = COMB_TILE / L;
-    unsigned dropped_here = 0;
-    for (int r = 0; r < L; ++r) {
-        const int px = group + GROUPS * r;
-        const int64_t p = p0 + px;
-        float x[MAXV];
-#pragma unroll
-        for (int i = 0; i < MAXV; ++i) {
-            const int k = lane + L * i;
-            x[i] = k < N ? tile[k * COMB_TILE + px] : 0.0f;
-        }
-        ClipResult<MAXV> res = clip_column<L, MAXV>(x, N, lane, ksigma, max_iters);
-        if (p < plane) {
-            if (lane == 0) out[p] = res.mean;
-            if (keep) {
-#pragma unroll
-                for (int i = 0; i < MAXV; ++i) {
-                    const int k = lane + L * i;
-                    if (k < N) keep[k * plane + p] = (uint8_t)((res.kept >> i) & 1u);
-                }
-            }
-            if (lane == 0) dropped_here += (unsigned)res.dropped;
-        }
-    }
+    const unsigned dropped_here = clip_tile<L, MAXV>(tile, p0, plane, N, ksigma, max_iters, out, keep);
     if (n_rej) {
         const unsigned total = block_sum_u32(dropped_here);
         if (t == 0 && total) atomicAdd(n_rej, (unsigned long long)total);
@@ -60,36 +34,33 @@ __global__ __launch_bounds__(COMB_TILE) void combine_kernel(
 
 __global__ void zero_u64(unsigned long long *p) { *p = 0ull; }
 
-template <int L, int MAXV>
-static void launch_combine(const float *aligned, int64_t plane, int32_t N, double ksigma, int32_t max_iters,
-                           float *out, uint8_t *keep, unsigned long long *n_rej, hipStream_t s)
+void combine_dispatch(int lanes, const float *aligned, int64_t plane, int32_t N, double ksigma, int32_t max_iters,
+                      float *out, uint8_t *keep, unsigned long long *n_rej, hipStream_t s)
 {
     const unsigned blocks = (unsigned)ceil_div(plane, COMB_TILE);
     const size_t lds = sizeof(float) * (size_t)N * COMB_TILE;
     ProfScope prof("combine", s);
-    hipLaunchKernelGGL((combine_kernel<L, MAXV>), dim3(blocks), dim3(COMB_TILE), lds, s, aligned, plane, N, ksigma,
-                       max_iters, out, keep, n_rej);
+    auto launch = [&](auto Lc, auto Vc) {
+        constexpr int L = decltype(Lc)::value, V = decltype(Vc)::value;
+        hipLaunchKernelGGL((combine_kernel<L, V>), dim3(blocks), dim3(COMB_TILE), lds, s, aligned, plane, N, ksigma,
+                           max_iters, out, keep, n_rej);
+    };
+    switch (lanes) {
+    case 1:
+        if (N <= 16) launch(std::integral_constant<int, 1>{}, std::integral_constant<int, 16>{});
+        else if (N <= 32) launch(std::integral_constant<int, 1>{}, std::integral_constant<int, 32>{});
+        else launch(std::integral_constant<int, 1>{}, std::integral_constant<int, 48>{});
+        break;
+    case 2: launch(std::integral_constant<int, 2>{}, std::integral_constant<int, 24>{}); break;
+    case 4: launch(std::integral_constant<int, 4>{}, std::integral_constant<int, 12>{}); break;
+    case 8: launch(std::integral_constant<int, 8>{}, std::integral_constant<int, 6>{}); break;
+    case 16: launch(std::integral_constant<int, 16>{}, std::integral_constant<int, 3>{}); break;
+    case 32: launch(std::integral_constant<int, 32>{}, std::integral_constant<int, 2>{}); break;
+    default: launch(std::integral_constant<int, 64>{}, std::integral_constant<int, 1>{}); break;
+    }
 }
 
 int combine_lanes_for(int32_t N);
-
-void combine_dispatch(int lanes, const float *aligned, int64_t plane, int32_t N, double ksigma, int32_t max_iters,
-                      float *out, uint8_t *keep, unsigned long long *n_rej, hipStream_t s)
-{
-    switch (lanes) {
-    case 1:
-        if (N <= 16) launch_combine<1, 16>(aligned, plane, N, ksigma, max_iters, out, keep, n_rej, s);
-        else if (N <= 32) launch_combine<1, 32>(aligned, plane, N, ksigma, max_iters, out, keep, n_rej, s);
-        else launch_combine<1, 64>(aligned, plane, N, ksigma, max_iters, out, keep, n_rej, s);
-        break;
-    case 2: launch_combine<2, 32>(aligned, plane, N, ksigma, max_iters, out, keep, n_rej, s); break;
-    case 4: launch_combine<4, 16>(aligned, plane, N, ksigma, max_iters, out, keep, n_rej, s); break;
-    case 8: launch_combine<8, 8>(aligned, plane, N, ksigma, max_iters, out, keep, n_rej, s); break;
-    case 16: launch_combine<16, 4>(aligned, plane, N, ksigma, max_iters, out, keep, n_rej, s); break;
-    case 32: launch_combine<32, 2>(aligned, plane, N, ksigma, max_iters, out, keep, n_rej, s); break;
-    default: launch_combine<64, 1>(aligned, plane, N, ksigma, max_iters, out, keep, n_rej, s); break;
-    }
-}
 
 }  // namespace rd
 

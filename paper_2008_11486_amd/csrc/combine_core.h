@@ -3,6 +3,8 @@
 // both evaluate identical operations in identical order.
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace rd {
@@ -35,10 +37,12 @@ __device__ __forceinline__ int group_sum(int v)
 
 // Iterative clip: mean m and population sigma of the kept values, drop |x - m| >
 // ksigma * sigma (all decided against the same m, sigma), stop when nothing drops
-// or after max_iters passes, return the mean of what is kept.  With L = 1 the sums
-// run over the frames in index order.
+// or after max_iters passes, return the mean of what is kept.  Lane `lane` of the
+// group owns the values col[(lane + L*i) * COMB_TILE], read from LDS on every pass
+// (the compiler barrier keeps them from being hoisted into registers).  With L = 1
+// the sums run over the frames in index order.
 template <int L, int MAXV>
-__device__ __forceinline__ ClipResult<MAXV> clip_column(const float (&x)[MAXV], int32_t N, int lane, double ksigma,
+__device__ __forceinline__ ClipResult<MAXV> clip_column(const float *col, int32_t N, int lane, double ksigma,
                                                         int32_t max_iters)
 {
     uint64_t kept = 0;
@@ -48,17 +52,18 @@ __device__ __forceinline__ ClipResult<MAXV> clip_column(const float (&x)[MAXV], 
     int n = N;
     int dropped = 0;
     for (int32_t it = 0; it < max_iters; ++it) {
+        asm volatile("" ::: "memory");
         double s = 0.0;
 #pragma unroll
         for (int i = 0; i < MAXV; ++i)
-            if ((kept >> i) & 1ull) s = __dadd_rn(s, (double)x[i]);
+            if ((kept >> i) & 1ull) s = __dadd_rn(s, (double)col[(lane + L * i) * COMB_TILE]);
         s = group_sum<L>(s);
         const double m = s / (double)n;
         double q = 0.0;
 #pragma unroll
         for (int i = 0; i < MAXV; ++i)
             if ((kept >> i) & 1ull) {
-                const double d = __dsub_rn((double)x[i], m);
+                const double d = __dsub_rn((double)col[(lane + L * i) * COMB_TILE], m);
                 q = __dadd_rn(q, __dmul_rn(d, d));
             }
         q = group_sum<L>(q);
@@ -66,7 +71,7 @@ __device__ __forceinline__ ClipResult<MAXV> clip_column(const float (&x)[MAXV], 
         int drop = 0;
 #pragma unroll
         for (int i = 0; i < MAXV; ++i)
-            if (((kept >> i) & 1ull) && fabs(__dsub_rn((double)x[i], m)) > thr) {
+            if (((kept >> i) & 1ull) && fabs(__dsub_rn((double)col[(lane + L * i) * COMB_TILE], m)) > thr) {
                 kept &= ~(1ull << i);
                 ++drop;
             }
@@ -75,16 +80,69 @@ __device__ __forceinline__ ClipResult<MAXV> clip_column(const float (&x)[MAXV], 
         dropped += drop;
         if (drop == 0) break;
     }
+    asm volatile("" ::: "memory");
     double s = 0.0;
 #pragma unroll
     for (int i = 0; i < MAXV; ++i)
-        if ((kept >> i) & 1ull) s = __dadd_rn(s, (double)x[i]);
+        if ((kept >> i) & 1ull) s = __dadd_rn(s, (double)col[(lane + L * i) * COMB_TILE]);
     s = group_sum<L>(s);
     ClipResult<MAXV> r;
     r.mean = (float)(s / (double)n);
     r.kept = kept;
     r.dropped = dropped;
     return r;
+}
+
+// Clip the COMB_TILE pixel columns staged in LDS (tile[k * COMB_TILE + px] = value of
+// frame k at pixel p0 + px) with groups of L lanes; the first COMB_TILE threads take
+// part.  Writes out[p0 + px] and the keep mask; returns the values this thread
+// dropped (counted in each group's lane 0).
+template <int L, int MAXV>
+__device__ __forceinline__ unsigned clip_tile(const float *tile, int64_t p0, int64_t plane, int32_t N,
+                                              double ksigma, int32_t max_iters, float *out, uint8_t *keep)
+{
+    const int t = threadIdx.x;
+    if (t >= COMB_TILE) return 0u;
+    const int lane = t % L;
+    const int group = t / L;
+    constexpr int GROUPS = COMB_TILE / L;
+    unsigned dropped_here = 0;
+    for (int r = 0; r < L; ++r) {
+        const int px = group + GROUPS * r;
+        const int64_t p = p0 + px;
+        ClipResult<MAXV> res = clip_column<L, MAXV>(tile + px, N, lane, ksigma, max_iters);
+        if (p < plane) {
+            if (lane == 0) out[p] = res.mean;
+            if (keep) {
+#pragma unroll
+                for (int i = 0; i < MAXV; ++i) {
+                    const int k = lane + L * i;
+                    if (k < N) keep[k * plane + p] = (uint8_t)((res.kept >> i) & 1u);
+                }
+            }
+            if (lane == 0) dropped_here += (unsigned)res.dropped;
+        }
+    }
+    return dropped_here;
+}
+
+// Dispatch on the lanes per column; MAXV covers N <= COMB_MAX_N.
+template <typename F>
+__device__ __forceinline__ void lanes_dispatch(int L, int32_t N, F &&f)
+{
+    switch (L) {
+    case 1:
+        if (N <= 16) f(std::integral_constant<int, 1>{}, std::integral_constant<int, 16>{});
+        else if (N <= 32) f(std::integral_constant<int, 1>{}, std::integral_constant<int, 32>{});
+        else f(std::integral_constant<int, 1>{}, std::integral_constant<int, 48>{});
+        break;
+    case 2: f(std::integral_constant<int, 2>{}, std::integral_constant<int, 24>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}, std::integral_constant<int, 12>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}, std::integral_constant<int, 6>{}); break;
+    case 16: f(std::integral_constant<int, 16>{}, std::integral_constant<int, 3>{}); break;
+    case 32: f(std::integral_constant<int, 32>{}, std::integral_constant<int, 2>{}); break;
+    default: f(std::integral_constant<int, 64>{}, std::integral_constant<int, 1>{}); break;
+    }
 }
 
 // Sum of one unsigned per thread over a 256-thread workgroup.

@@ -15,7 +15,7 @@
 namespace rd {
 
 static const int32_t kRegK[] = {5, 9, 12, 17, 18, 22};
-constexpr size_t kLdsLimit = 64 * 1024;
+constexpr size_t kLdsLimit = 63 * 1024;  // leaves room for the batch kernel's static LDS
 constexpr int32_t kMaxThreads = 512;
 
 static int32_t env_int(const char *name)
@@ -69,8 +69,7 @@ static int32_t group_span(int32_t C, int32_t CW, int32_t G, int32_t NBX)
     return JS;
 }
 
-bool reg_plan_from_shape(int32_t W, int32_t H, int32_t N, int32_t R, int32_t Rmax, const RegShape &sh,
-                         RegPlan *out)
+bool reg_plan_from_shape(int32_t W, int32_t H, int32_t R, int32_t Rmax, const RegShape &sh, RegPlan *out)
 {
     RegPlan p{};
     p.D = 2 * R + 1;
@@ -98,16 +97,14 @@ bool reg_plan_from_shape(int32_t W, int32_t H, int32_t N, int32_t R, int32_t Rma
     p.lds = std::max(stage, red);
     if (p.lds > kLdsLimit) return false;
 
-    // template rows per tile: enough workgroups to fill the chip a few times over
+    // tile rows: CPT chunks, at most the template height; independent of the frame
+    // count so that every path with the same shape sums partials in the same order
     const int32_t tw = W - 2 * Rmax, th = H - 2 * Rmax;
     if (tw < 1 || th < 1) return false;
+    if (sh.CPT < 1) return false;
     p.th_max = th;
     p.n_xchunks = (int32_t)ceil_div(tw, p.TX);
-    const int64_t per_band = (int64_t)p.n_xchunks * p.G * N;
-    const int64_t target = 4096;
-    int64_t bands = std::max<int64_t>(1, ceil_div(target, per_band));
-    bands = std::min<int64_t>(bands, ceil_div(th, p.TY));
-    p.BR = (int32_t)(ceil_div(ceil_div(th, bands), p.TY) * p.TY);
+    p.BR = (int32_t)std::min<int64_t>((int64_t)sh.CPT * p.TY, ceil_div(th, p.TY) * p.TY);
     p.n_bands = (int32_t)ceil_div(th, p.BR);
     p.n_tiles = p.n_bands * p.n_xchunks;
     *out = p;
@@ -129,7 +126,16 @@ static double shape_score(const RegPlan &p)
     return useful / (per_wave * waves);
 }
 
-static void all_shapes(int32_t W, int32_t H, int32_t N, int32_t R, int32_t Rmax, int32_t K_only, int32_t TY_only,
+// Chunks per tile aiming at about 2048 tiles x groups per frame.
+static int32_t model_cpt(int32_t W, int32_t H, int32_t Rmax, int32_t TX, int32_t G, int32_t TY)
+{
+    const int64_t tw = W - 2 * Rmax, th = H - 2 * Rmax;
+    const int64_t per_band = ceil_div(tw, TX) * G;
+    const int64_t bands = std::max<int64_t>(1, std::min<int64_t>(ceil_div(2048, per_band), ceil_div(th, TY)));
+    return (int32_t)std::max<int64_t>(1, ceil_div(ceil_div(th, bands), TY));
+}
+
+static void all_shapes(int32_t W, int32_t H, int32_t R, int32_t Rmax, int32_t K_only, int32_t TY_only,
                        std::vector<std::pair<double, RegShape>> *out)
 {
     const int32_t D = 2 * R + 1;
@@ -144,45 +150,46 @@ static void all_shapes(int32_t W, int32_t H, int32_t N, int32_t R, int32_t Rmax,
                 for (int32_t TY = 4; TY <= 64; ++TY) {
                     if (TY_only && TY != TY_only) continue;
                     RegPlan p;
-                    if (!reg_plan_from_shape(W, H, N, R, Rmax, RegShape{K, G, S, TY}, &p)) {
+                    const int32_t TX = K * (int32_t)ceil_div(64, K);
+                    const RegShape sh{K, G, S, TY, model_cpt(W, H, Rmax, TX, G, TY)};
+                    if (!reg_plan_from_shape(W, H, R, Rmax, sh, &p)) {
                         if (TY_only) continue;
                         break;  // larger TY only needs more LDS
                     }
-                    out->push_back({shape_score(p), RegShape{K, G, S, TY}});
+                    out->push_back({shape_score(p), sh});
                 }
         }
     }
 }
 
-RegPlan reg_plan(int32_t W, int32_t H, int32_t N, int32_t R, int32_t Rmax, int32_t K_force, int32_t TY_force)
+RegPlan reg_plan(int32_t W, int32_t H, int32_t R, int32_t Rmax, int32_t K_force, int32_t TY_force)
 {
     if (!K_force) K_force = env_int("REDUCE_REG_K");
     if (!TY_force) TY_force = env_int("REDUCE_REG_TY");
     RegPlan p{};
     RegShape sh{};
-    if (!K_force && !TY_force && tuned_reg_shape(W, H, R, Rmax, &sh) && reg_plan_from_shape(W, H, N, R, Rmax, sh, &p))
+    if (!K_force && !TY_force && tuned_reg_shape(W, H, R, Rmax, &sh) && reg_plan_from_shape(W, H, R, Rmax, sh, &p))
         return p;
     std::vector<std::pair<double, RegShape>> shapes;
-    all_shapes(W, H, N, R, Rmax, K_force, TY_force, &shapes);
-    if (shapes.empty()) all_shapes(W, H, N, R, Rmax, 0, 0, &shapes);
+    all_shapes(W, H, R, Rmax, K_force, TY_force, &shapes);
+    if (shapes.empty()) all_shapes(W, H, R, Rmax, 0, 0, &shapes);
     double best = -1.0;
     for (const auto &c : shapes)
         if (c.first > best * 1.005) {
             best = c.first;
             sh = c.second;
         }
-    if (best < 0.0 || !reg_plan_from_shape(W, H, N, R, Rmax, sh, &p)) {
+    if (best < 0.0 || !reg_plan_from_shape(W, H, R, Rmax, sh, &p)) {
         // a window too large for any shape: leave D = 0 so the caller reports it
         p = RegPlan{};
     }
     return p;
 }
 
-void reg_shape_candidates(int32_t W, int32_t H, int32_t N, int32_t R, int32_t Rmax, RegShape *out, int *count,
-                          int max_count)
+void reg_shape_candidates(int32_t W, int32_t H, int32_t R, int32_t Rmax, RegShape *out, int *count, int max_count)
 {
     std::vector<std::pair<double, RegShape>> shapes;
-    all_shapes(W, H, N, R, Rmax, 0, 0, &shapes);
+    all_shapes(W, H, R, Rmax, 0, 0, &shapes);
     std::stable_sort(shapes.begin(), shapes.end(),
                      [](const std::pair<double, RegShape> &a, const std::pair<double, RegShape> &b) {
                          return a.first > b.first;
@@ -199,6 +206,22 @@ void reg_shape_candidates(int32_t W, int32_t H, int32_t N, int32_t R, int32_t Rm
             seen.push_back(gs);
             out[n++] = c.second;
             if (++taken == 4) break;
+        }
+    }
+    // tile-height variants of the model's overall best shape
+    if (!shapes.empty()) {
+        const RegShape b = shapes.front().second;
+        for (int32_t m : {2, 4}) {
+            if (n >= max_count) break;
+            RegShape v = b;
+            v.CPT = b.CPT * m;
+            RegPlan p;
+            if (reg_plan_from_shape(W, H, R, Rmax, v, &p) && p.BR > b.CPT * b.TY) out[n++] = v;
+        }
+        if (b.CPT > 1 && n < max_count) {
+            RegShape v = b;
+            v.CPT = std::max(1, b.CPT / 2);
+            out[n++] = v;
         }
     }
     *count = n;
@@ -224,8 +247,8 @@ int tune_save(const char *path, const char *arch)
         const RegShape &s = e.second.first;
         std::fprintf(f,
                      "{\"arch\": \"%s\", \"op\": \"register\", \"W\": %d, \"H\": %d, \"R\": %d, \"Rmax\": %d, "
-                     "\"K\": %d, \"G\": %d, \"S\": %d, \"TY\": %d, \"ms\": %.6f}\n",
-                     arch, std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k), s.K, s.G, s.S, s.TY,
+                     "\"K\": %d, \"G\": %d, \"S\": %d, \"TY\": %d, \"CPT\": %d, \"ms\": %.6f}\n",
+                     arch, std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k), s.K, s.G, s.S, s.TY, s.CPT,
                      e.second.second);
     }
     for (const auto &e : g_comb_tuned)
@@ -269,9 +292,9 @@ int tune_load(const char *path, const char *arch)
             RegShape s;
             if (json_int(line, "W", &W) && json_int(line, "H", &H) && json_int(line, "R", &R) &&
                 json_int(line, "Rmax", &Rmax) && json_int(line, "K", &s.K) && json_int(line, "G", &s.G) &&
-                json_int(line, "S", &s.S) && json_int(line, "TY", &s.TY)) {
+                json_int(line, "S", &s.S) && json_int(line, "TY", &s.TY) && json_int(line, "CPT", &s.CPT)) {
                 RegPlan p;
-                if (reg_plan_from_shape(W, H, 1, R, Rmax, s, &p)) set_tuned_reg_shape(W, H, R, Rmax, s, ms);
+                if (reg_plan_from_shape(W, H, R, Rmax, s, &p)) set_tuned_reg_shape(W, H, R, Rmax, s, ms);
             }
         } else if (std::strstr(line, "\"op\": \"combine\"")) {
             int32_t N, lanes;
@@ -301,7 +324,8 @@ extern "C" int reduce_register_plan(int32_t W, int32_t H, int32_t N, int32_t rad
     if (W < 1 || H < 1 || N < 1 || radius < 0 || radius_max < 0 || W - 2 * radius_max < 1 ||
         H - 2 * radius_max < 1)
         return fail(REDUCE_ERR_RANGE, "reduce_register_plan: no template for these sizes");
-    const RegPlan p = reg_plan(W, H, N, radius, radius_max);
+    const RegPlan p = reg_plan(W, H, radius, radius_max);
+    (void)N;
     if (p.D == 0) return fail(REDUCE_ERR_UNSUPPORTED, "reduce_register_plan: window too large");
     const int32_t v[16] = {p.D, p.K, p.NBX, p.C, p.G, p.CW, p.S, p.threads, p.TX, p.TY, p.BR, p.JS, p.FR, p.FC,
                            (int32_t)p.lds, p.n_tiles};

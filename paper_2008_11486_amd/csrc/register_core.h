@@ -1,0 +1,340 @@
+// Device bodies of the correlation search, shared by the stage-wise kernels and the
+// persistent batch kernel so that both produce bit-identical scores and offsets:
+//
+//   S_k(d) = sum_{p in T} r'(p) f_k(p + d),   r' = ref - mean_T(ref),   d in window
+//
+// Work split.  A thread owns one window row dy and K consecutive dx candidates and
+// keeps K double accumulators.  For one template row segment of K pixels it reads
+// the K template values (LDS broadcast) and 2K-1 frame values (LDS), and performs
+// K*K FMAs: the frame value at column m serves every (pixel i, candidate j) pair
+// with i + j = m.  A work item ("tile") is a band of template rows x a column chunk
+// of the template for one group of candidate rows of one frame; the template and
+// frame tiles are staged in LDS chunk by chunk (TY template rows at a time, plus the
+// frame rows and columns the window needs).  When there are fewer candidates than
+// threads, threads also split the chunk's (row, column-block) pairs ("sub-ranges")
+// and their accumulators are summed in a fixed order.  Each tile writes one FP64
+// partial score per candidate; partials are summed over tiles in tile order, and the
+// (score, index) maximum, the runner-up, the parabola vertex and the flags follow.
+// The decomposition depends only on (W, H, R, Rmax) and the launch shape, never on
+// the number of frames, so every path that uses the same shape sums in the same
+// order.
+#pragma once
+
+#include <type_traits>
+
+#include "common.h"
+
+namespace rd {
+
+constexpr int MEAN_THREADS = 256;  // logical threads of the template-mean reduction
+constexpr int MEAN_ROWS = 16;      // template rows per mean part
+
+struct ScoreArgs {
+    const float *ref;
+    const float *frames;     // frame k at frames + (k + (k >= skip)) * W * H
+    const int32_t *centers;  // [N][2] or NULL
+    const double *mean;
+    double *partial;         // [N][n_tiles][D*D]
+    int32_t W, H, R, Rmax, D;
+    int32_t tx0, ty0, tw, th;
+    int32_t TY, TX, NXB, BR, NBX, C, CW, S, JS, FR, FC, n_xchunks, n_tiles, N, G;
+    int32_t threads;         // threads taking part (the first `threads` of the block)
+    int32_t skip;            // index of a frame to step over (the reference), or a large value
+};
+
+// ---- template mean ---------------------------------------------------------------
+// Sum over a wave then over the first `waves` waves in order; threads that have no
+// data contribute exactly zero.
+__device__ __forceinline__ double block_sum_f64(double v, double *scratch, int waves)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0 && w < waves) scratch[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < waves; ++i) t += scratch[i];
+    __syncthreads();
+    return t;
+}
+
+// Sum of template rows [MEAN_ROWS*part, +MEAN_ROWS) with MEAN_THREADS logical threads
+// striding over columns; valid in thread 0.
+__device__ __forceinline__ double tmpl_part_sum(const float *ref, int32_t W, int32_t tx0, int32_t ty0, int32_t tw,
+                                                int32_t th, int32_t part, double *scratch)
+{
+    const int32_t y0 = part * MEAN_ROWS;
+    const int32_t y1 = min(y0 + MEAN_ROWS, th);
+    double s = 0.0;
+    if (threadIdx.x < MEAN_THREADS)
+        for (int32_t y = y0; y < y1; ++y)
+            for (int32_t x = threadIdx.x; x < tw; x += MEAN_THREADS) s += (double)ref[(int64_t)(ty0 + y) * W + tx0 + x];
+    return block_sum_f64(s, scratch, MEAN_THREADS / 64);
+}
+
+__device__ __forceinline__ double tmpl_mean_of_parts(const double *part, int32_t nparts, double count,
+                                                     double *scratch)
+{
+    double s = 0.0;
+    if (threadIdx.x < MEAN_THREADS)
+        for (int32_t i = threadIdx.x; i < nparts; i += MEAN_THREADS) s += part[i];
+    s = block_sum_f64(s, scratch, MEAN_THREADS / 64);
+    return s / count;  // valid in thread 0
+}
+
+// ---- one tile of partial scores ----------------------------------------------------------
+// lid in [0, n_tiles * G * N): tile fastest, then candidate group, then frame.
+template <int K>
+__device__ __forceinline__ void score_tile(const ScoreArgs &a, int32_t lid, unsigned char *smem)
+{
+    double *rt = reinterpret_cast<double *>(smem);                               // [TY][TX]
+    float *ft = reinterpret_cast<float *>(smem + sizeof(double) * a.TY * a.TX);  // [FR][FC]
+
+    const int32_t tile = lid % a.n_tiles;
+    const int32_t gk = lid / a.n_tiles;
+    const int32_t g = gk % a.G;
+    const int32_t k = gk / a.G;
+    const int32_t band = tile / a.n_xchunks;
+    const int32_t xc = tile - band * a.n_xchunks;
+    const int32_t c0 = g * a.CW;
+    const int32_t x_t = xc * a.TX;                 // first template column of the tile
+    const int32_t yb0 = band * a.BR;               // first template row of the band
+    const int32_t yb1 = min(yb0 + a.BR, a.th);
+    const int32_t cx = a.centers ? a.centers[2 * k] : 0;
+    const int32_t cy = a.centers ? a.centers[2 * k + 1] : 0;
+    const int32_t j_lo = c0 / a.NBX;
+
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wave = t >> 6;
+    const int nwaves = a.threads >> 6;
+    const bool in_block = t < a.threads;
+    const int cl = t % a.CW;
+    const int s = t / a.CW;
+    const int c = c0 + cl;
+    const bool active = in_block && (s < a.S) && (c < a.C);
+    const int j = active ? c / a.NBX : j_lo;
+    const int bx = active ? c - j * a.NBX : 0;
+    const int jr = j - j_lo;                       // frame-tile row offset of this thread
+
+    const double mean = *a.mean;
+    const int32_t kf = k + (k >= a.skip ? 1 : 0);
+    const float *f = a.frames + (int64_t)kf * a.W * a.H;
+    // frame tile origin: template row yc + (cy - R + j_lo), column x_t + (cx - R)
+    const int32_t fx0 = a.tx0 + x_t + cx - a.R;
+
+    double acc[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] = 0.0;
+
+    const int pairs = a.TY * a.NXB;
+    for (int32_t yc = yb0; yc < yb1; yc += a.TY) {
+        __syncthreads();
+        if (in_block) {
+            // template tile, zero outside T (contributes exactly nothing); one wave per row
+            for (int yy = wave; yy < a.TY; yy += nwaves) {
+                const bool row_ok = yc + yy < yb1;
+                const float *src = a.ref + (int64_t)(a.ty0 + yc + yy) * a.W + a.tx0 + x_t;
+                for (int xx = lane; xx < a.TX; xx += 64) {
+                    double v = 0.0;
+                    if (row_ok && x_t + xx < a.tw) v = (double)src[xx] - mean;
+                    rt[yy * a.TX + xx] = v;
+                }
+            }
+            // frame tile, zero outside the frame; one wave per row
+            const int32_t fy0 = a.ty0 + yc + cy - a.R + j_lo;
+            for (int rr = wave; rr < a.FR; rr += nwaves) {
+                const int32_t gy = fy0 + rr;
+                const bool row_ok = gy >= 0 && gy < a.H;
+                const float *src = f + (int64_t)gy * a.W;
+                for (int cc = lane; cc < a.FC; cc += 64) {
+                    const int32_t gx = fx0 + cc;
+                    float v = 0.0f;
+                    if (row_ok && gx >= 0 && gx < a.W) v = src[gx];
+                    ft[rr * a.FC + cc] = v;
+                }
+            }
+        }
+        __syncthreads();
+        if (active) {
+            for (int pr = s; pr < pairs; pr += a.S) {
+                const int yy = pr / a.NXB;
+                const int xb = pr - yy * a.NXB;
+                const double *rrow = rt + yy * a.TX + xb * K;
+                const float *frow = ft + (yy + jr) * a.FC + (xb + bx) * K;
+                double r[K];
+#pragma unroll
+                for (int i = 0; i < K; ++i) r[i] = rrow[i];
+#pragma unroll
+                for (int m = 0; m < 2 * K - 1; ++m) {
+                    const double fv = (double)frow[m];
+#pragma unroll
+                    for (int i = 0; i < K; ++i) {
+                        const int q = m - i;
+                        if (q >= 0 && q < K) acc[q] = fma(r[i], fv, acc[q]);
+                    }
+                }
+            }
+        }
+    }
+
+    // sum the sub-ranges in order s = 0, 1, ... (only needed when S > 1)
+    __syncthreads();
+    double *red = reinterpret_cast<double *>(smem);  // [CW][K]
+    if (a.S > 1) {
+        for (int ss = 0; ss < a.S; ++ss) {
+            if (active && s == ss) {
+#pragma unroll
+                for (int q = 0; q < K; ++q) {
+                    double *slot = red + cl * K + q;
+                    *slot = (ss == 0) ? acc[q] : *slot + acc[q];
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (active && s == 0) {
+        double *out = a.partial + ((int64_t)k * a.n_tiles + tile) * (int64_t)a.D * a.D + (int64_t)j * a.D;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            const int i = bx * K + q;
+            if (i < a.D) out[i] = (a.S > 1) ? red[cl * K + q] : acc[q];
+        }
+    }
+    __syncthreads();  // LDS is reused by the caller's next item
+}
+
+template <typename F>
+__device__ __forceinline__ void score_dispatch(int K, F &&f)
+{
+    switch (K) {
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    case 9: f(std::integral_constant<int, 9>{}); break;
+    case 12: f(std::integral_constant<int, 12>{}); break;
+    case 17: f(std::integral_constant<int, 17>{}); break;
+    case 18: f(std::integral_constant<int, 18>{}); break;
+    default: f(std::integral_constant<int, 22>{}); break;
+    }
+}
+
+// ---- scores of one frame from its partials ------------------------------------------------
+// Sum over tiles in tile order; -inf outside the clipped window.
+__device__ __forceinline__ double candidate_score(const double *partial_k, int32_t n_tiles, int32_t D, int32_t R,
+                                                  int32_t Rmax, int32_t cx, int32_t cy, int32_t cand)
+{
+    const int32_t jj = cand / D, ii = cand - jj * D;
+    const int32_t dx = cx - R + ii, dy = cy - R + jj;
+    if (dx < -Rmax || dx > Rmax || dy < -Rmax || dy > Rmax) return -INFINITY;
+    double s = 0.0;
+    for (int32_t tI = 0; tI < n_tiles; ++tI) s += partial_k[(int64_t)tI * D * D + cand];
+    return s;
+}
+
+// ---- argmax, runner-up, parabola -------------------------------------------------
+struct Best {
+    double s;
+    int32_t i;
+};
+
+// Larger score wins; equal scores go to the smaller linear index (smaller dy, then
+// smaller dx).  A total order, so any reduction tree gives the same answer.
+__device__ __forceinline__ Best better_of(Best a, Best b)
+{
+    if (a.s > b.s) return a;
+    if (b.s > a.s) return b;
+    return a.i <= b.i ? a : b;
+}
+
+__device__ __forceinline__ Best block_best(Best v, Best *scratch)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        Best o;
+        o.s = __shfl_xor(v.s, off, 64);
+        o.i = __shfl_xor(v.i, off, 64);
+        v = better_of(v, o);
+    }
+    if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
+    __syncthreads();
+    Best r = scratch[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = better_of(r, scratch[w]);
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double parabola_vertex(double sm, double s0, double sp)
+{
+    const double den = 2.0 * (sm - 2.0 * s0 + sp);
+    if (!(den < 0.0)) return 0.0;
+    double d = (sm - sp) / den;
+    if (d > 0.5) d = 0.5;
+    if (d < -0.5) d = -0.5;
+    return d;
+}
+
+// Offsets of one frame from its score cube S [D*D]; every thread of the block takes
+// part, thread 0 writes *out.  scratch holds one Best per wave.
+__device__ __forceinline__ void pick_frame(const double *S, int32_t D, int32_t R, int32_t Rmax, int32_t cx,
+                                           int32_t cy, reduce_offset_t *out, Best *scratch)
+{
+    const int32_t lox = max(cx - R, -Rmax), hix = min(cx + R, Rmax);
+    const int32_t loy = max(cy - R, -Rmax), hiy = min(cy + R, Rmax);
+    const bool empty = lox > hix || loy > hiy;
+
+    Best b{-INFINITY, 0x7fffffff};
+    for (int32_t c = threadIdx.x; c < D * D; c += blockDim.x) {
+        const int32_t jj = c / D, ii = c - jj * D;
+        const int32_t dx = cx - R + ii, dy = cy - R + jj;
+        if (dx < lox || dx > hix || dy < loy || dy > hiy) continue;
+        b = better_of(b, Best{S[c], c});
+    }
+    const Best best = block_best(b, scratch);
+    Best sb{-INFINITY, 0x7fffffff};
+    for (int32_t c = threadIdx.x; c < D * D; c += blockDim.x) {
+        const int32_t jj = c / D, ii = c - jj * D;
+        const int32_t dx = cx - R + ii, dy = cy - R + jj;
+        if (dx < lox || dx > hix || dy < loy || dy > hiy || c == best.i) continue;
+        sb = better_of(sb, Best{S[c], c});
+    }
+    const Best second = block_best(sb, scratch);
+    if (threadIdx.x != 0) return;
+
+    reduce_offset_t o;
+    if (empty) {
+        o.dx = o.dy = 0;
+        o.sx = o.sy = 0.0f;
+        o.peak = o.second = -INFINITY;
+        o.margin = 0.0;
+        o.flags = REDUCE_CLIPPED | REDUCE_EDGE_X | REDUCE_EDGE_Y | REDUCE_NEAR_TIE;
+        o.pad = 0;
+        *out = o;
+        return;
+    }
+    const int32_t bj = best.i / D, bi = best.i - bj * D;
+    const int32_t bdx = cx - R + bi, bdy = cy - R + bj;
+    int32_t flags = 0;
+    double delx = 0.0, dely = 0.0;
+    if (bdx == lox || bdx == hix) flags |= REDUCE_EDGE_X;
+    else delx = parabola_vertex(S[best.i - 1], best.s, S[best.i + 1]);
+    if (bdy == loy || bdy == hiy) flags |= REDUCE_EDGE_Y;
+    else dely = parabola_vertex(S[best.i - D], best.s, S[best.i + D]);
+    if (lox != cx - R || hix != cx + R || loy != cy - R || hiy != cy + R) flags |= REDUCE_CLIPPED;
+    double margin;
+    if (second.s == -INFINITY) margin = INFINITY;
+    else if (best.s == 0.0) margin = (best.s > second.s) ? INFINITY : 0.0;
+    else margin = (best.s - second.s) / fabs(best.s);
+    if (margin < REDUCE_NEAR_TIE_MARGIN) flags |= REDUCE_NEAR_TIE;
+    o.dx = bdx;
+    o.dy = bdy;
+    o.sx = (float)((double)bdx + delx);
+    o.sy = (float)((double)bdy + dely);
+    o.peak = best.s;
+    o.second = second.s;
+    o.margin = margin;
+    o.flags = flags;
+    o.pad = 0;
+    *out = o;
+}
+
+}  // namespace rd

@@ -31,21 +31,19 @@ struct RegPlan {
 // Per-workgroup shape of a plan; everything else follows from it and the sizes.
 struct RegShape {
     int32_t K, G, S, TY;
+    int32_t CPT;        // LDS chunks per tile: tile rows BR = CPT * TY
 };
 
 // The plan for these sizes: the tuned shape if the autotuner cached one for
 // (W, H, R, Rmax), else the cost model's choice.  K_force / TY_force (or
 // REDUCE_REG_K / REDUCE_REG_TY in the environment) restrict the model's search.
-RegPlan reg_plan(int32_t W, int32_t H, int32_t N, int32_t R, int32_t Rmax, int32_t K_force = 0,
-                 int32_t TY_force = 0);
+RegPlan reg_plan(int32_t W, int32_t H, int32_t R, int32_t Rmax, int32_t K_force = 0, int32_t TY_force = 0);
 
 // Complete a plan from a workgroup shape; returns false if it does not fit.
-bool reg_plan_from_shape(int32_t W, int32_t H, int32_t N, int32_t R, int32_t Rmax, const RegShape &sh,
-                         RegPlan *out);
+bool reg_plan_from_shape(int32_t W, int32_t H, int32_t R, int32_t Rmax, const RegShape &sh, RegPlan *out);
 
 // Candidate shapes for the autotuner: the model's best few for every K.
-void reg_shape_candidates(int32_t W, int32_t H, int32_t N, int32_t R, int32_t Rmax, RegShape *out, int *count,
-                          int max_count);
+void reg_shape_candidates(int32_t W, int32_t H, int32_t R, int32_t Rmax, RegShape *out, int *count, int max_count);
 
 // Tuned-shape cache (keyed by W, H, R, Rmax on the current device).
 bool tuned_reg_shape(int32_t W, int32_t H, int32_t R, int32_t Rmax, RegShape *sh);

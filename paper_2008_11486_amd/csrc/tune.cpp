@@ -75,14 +75,14 @@ extern "C" int reduce_tune_register(const float *ref, const float *frames, int32
     constexpr int MAXC = 32;
     RegShape cand[MAXC];
     int n = 0;
-    reg_shape_candidates(W, H, N, radius, radius_max, cand, &n, MAXC);
+    reg_shape_candidates(W, H, radius, radius_max, cand, &n, MAXC);
     double best_ms = 1e30;
     RegShape best{};
     const int32_t tx0 = radius_max, ty0 = radius_max, tw = W - 2 * radius_max, th = H - 2 * radius_max;
     int rc = REDUCE_OK;
     for (int i = 0; i < n; ++i) {
         RegPlan p;
-        if (!reg_plan_from_shape(W, H, N, radius, radius_max, cand[i], &p)) continue;
+        if (!reg_plan_from_shape(W, H, radius, radius_max, cand[i], &p)) continue;
         if (register_ws_bytes(p, N) > ws_bytes) continue;
         double ms = 0.0;
         rc = time_ms(s, reps,
@@ -93,8 +93,8 @@ extern "C" int reduce_tune_register(const float *ref, const float *frames, int32
                      &ms);
         if (rc != REDUCE_OK) break;
         if (std::getenv("REDUCE_TUNE_VERBOSE"))
-            std::fprintf(stderr, "tune register K=%d G=%d S=%d TY=%d threads=%d tiles=%d: %.4f ms\n", p.K, p.G, p.S,
-                         p.TY, p.threads, p.n_tiles, ms);
+            std::fprintf(stderr, "tune register K=%d G=%d S=%d TY=%d BR=%d threads=%d tiles=%d: %.4f ms\n", p.K,
+                         p.G, p.S, p.TY, p.BR, p.threads, p.n_tiles, ms);
         if (ms < best_ms) {
             best_ms = ms;
             best = cand[i];
@@ -105,7 +105,7 @@ extern "C" int reduce_tune_register(const float *ref, const float *frames, int32
     set_tuned_reg_shape(W, H, radius, radius_max, best, best_ms);
     if (fields) {
         RegPlan p;
-        reg_plan_from_shape(W, H, N, radius, radius_max, best, &p);
+        reg_plan_from_shape(W, H, radius, radius_max, best, &p);
         const int32_t v[16] = {p.D, p.K, p.NBX, p.C, p.G, p.CW, p.S, p.threads, p.TX, p.TY, p.BR, p.JS, p.FR, p.FC,
                                (int32_t)p.lds, p.n_tiles};
         for (int i = 0; i < 16; ++i) fields[i] = v[i];

@@ -74,3 +74,17 @@ def test_valid_rect_matches_oracle(rd, orc):
         assert np.array_equal(rd.valid_rect(offs, W, H), orc.valid_rect(offs, W, H))
     with pytest.raises(rd.ReduceError):
         rd.valid_rect(np.array([[0, 0], [50, 0]], np.float32), 40, 40)
+
+
+def test_stack_batch_workspace_query_is_host_only(rd):
+    import ctypes as C
+    b = 4096  # fake, never dereferenced: the query only validates and sizes
+    ok = rd.StackDesc(b, 512, 512 * 512, b, b, 512, 512, 512, 5, 0, 8, 3, 3.0, 0, b, b, b, 0)
+    arr = (rd.StackDesc * 2)(ok, ok)
+    n1 = rd.lib().reduce_stack_batch_ws(arr, 1)
+    n2 = rd.lib().reduce_stack_batch_ws(arr, 2)
+    assert 5 * 512 * 512 * 4 < n1 < n2
+    bad = rd.StackDesc(b, 512, 512 * 512, b, b, 512, 512, 512, 5, 7, 8, 3, 3.0, 0, b, b, b, 0)  # ref_index >= N
+    assert rd.lib().reduce_stack_batch_ws((rd.StackDesc * 1)(bad), 1) == 0
+    assert rd.lib().reduce_stack_batch(None, 1, None, 0, None) == rd.ERR_NULL
+    assert rd.lib().reduce_stack_batch((rd.StackDesc * 1)(bad), 1, C.c_void_p(b), 1 << 40, None) == rd.ERR_RANGE

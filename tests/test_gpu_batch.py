@@ -1,0 +1,157 @@
+"""The batched persistent path against the stage-wise chain (bit-identical) and the oracle."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from helpers import TOL, err_summary, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rd():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2008_11486_amd as rd
+    rd.lib()
+    return rd
+
+
+def stagewise(rd, raw, dark, flat, R, ref=0, integer_mode=False):
+    """The same chain through the stage-wise entry points."""
+    N, H, W = raw.shape
+    cal = rd.calibrate(raw, dark, flat)
+    offs = np.zeros(N, dtype=rd.OFFSET_DTYPE)
+    offs["second"] = -np.inf
+    offs["margin"] = np.inf
+    s = np.zeros((N, 2), np.float32)
+    if N > 1:
+        others = [k for k in range(N) if k != ref]
+        frames = torch.stack([cal[k] for k in others]).contiguous()
+        o = rd.offsets_to_numpy(rd.register(cal[ref].contiguous(), frames, R))
+        for i, k in enumerate(others):
+            offs[k] = o[i]
+            s[k] = (o["dx"][i], o["dy"][i]) if integer_mode else (o["sx"][i], o["sy"][i])
+    rect = rd.valid_rect(s, W, H)
+    al = rd.shift(cal, to_dev(s), rect, integer_mode=integer_mode)
+    out, _, nrej = rd.combine(al, want_nrej=True)
+    return out.cpu().numpy(), rect, offs, int(nrej.cpu()[0])
+
+
+SPECS = [  # (N, W, H, radius, ref, integer_mode, cosmic)
+    (5, 128, 96, 4, 0, False, False),
+    (11, 160, 160, 6, 3, False, True),
+    (3, 96, 128, 3, 0, True, False),
+    (16, 200, 152, 5, 7, False, True),
+    (1, 64, 64, 2, 0, False, False),
+    (2, 72, 40, 0, 1, False, False),
+]
+
+
+def _make(i, N, W, H, R, cosmic, seed=0):
+    spec = synth.small_spec(N, W, H, n_stars=max(8, W * H // 1000), shift_bound=max(R - 1, 0.3), radius=R,
+                            cosmic=cosmic, seed=(i, seed))
+    if R == 0:
+        spec = synth.small_spec(N, W, H, n_stars=8, shift_kind="zero", radius=0, seed=(i, seed))
+    return synth.make_stack(spec)
+
+
+def test_batch_bit_identical_to_stagewise(rd, orc):
+    stacks = [_make(i, N, W, H, R, cos) for i, (N, W, H, R, _, _, cos) in enumerate(SPECS)]
+    dev = [(to_dev(st.raw), to_dev(st.dark), to_dev(st.flat), sp[3]) for st, sp in zip(stacks, SPECS)]
+    batch = rd.StackBatch(dev, ref_index=[sp[4] for sp in SPECS], integer_mode=[sp[5] for sp in SPECS])
+    batch.run()
+    batch.check()
+    for i, ((raw, dark, flat, R), sp) in enumerate(zip(dev, SPECS)):
+        img, rect, offs, nrej = batch.result(i)
+        ref_img, ref_rect, ref_offs, ref_nrej = stagewise(rd, raw, dark, flat, R, sp[4], sp[5])
+        assert np.array_equal(rect, ref_rect), (i, rect, ref_rect)
+        assert np.array_equal(img.cpu().numpy(), ref_img), f"stack {i}: image differs"
+        assert offs.tobytes() == ref_offs.tobytes(), f"stack {i}: offsets differ\n{offs}\n{ref_offs}"
+        assert nrej == ref_nrej
+    # the stacks with cosmic rays really exercised the clip
+    assert batch.result(1)[3] > 0 and batch.result(3)[3] > 0
+
+
+def test_batch_graph_replays_follow_new_data(rd):
+    specs = SPECS[:4]
+    A = [_make(i, N, W, H, R, cos, seed=1) for i, (N, W, H, R, _, _, cos) in enumerate(specs)]
+    B = [_make(i, N, W, H, R, cos, seed=2) for i, (N, W, H, R, _, _, cos) in enumerate(specs)]
+    dev = [(to_dev(st.raw), to_dev(st.dark), to_dev(st.flat), sp[3]) for st, sp in zip(A, specs)]
+    batch = rd.StackBatch(dev, ref_index=[sp[4] for sp in specs], integer_mode=[sp[5] for sp in specs])
+    for rep, src in enumerate([A, B, A, B]):
+        for (raw, dark, flat, _), st in zip(dev, src):  # eager work between replays: new inputs in place
+            raw.copy_(to_dev(st.raw))
+            dark.copy_(to_dev(st.dark))
+            flat.copy_(to_dev(st.flat))
+        torch.cuda.synchronize()
+        batch.run()
+        batch.check()
+        for i, ((raw, dark, flat, R), sp) in enumerate(zip(dev, specs)):
+            img, rect, offs, nrej = batch.result(i)
+            ref_img, ref_rect, ref_offs, ref_nrej = stagewise(rd, raw, dark, flat, R, sp[4], sp[5])
+            assert np.array_equal(rect, ref_rect) and np.array_equal(img.cpu().numpy(), ref_img), (rep, i)
+            assert offs.tobytes() == ref_offs.tobytes() and nrej == ref_nrej, (rep, i)
+
+
+def test_batch_matches_oracle_end_to_end(rd, orc):
+    st = _make(9, 16, 180, 140, 6, True, seed=3)
+    batch = rd.StackBatch([(to_dev(st.raw), to_dev(st.dark), to_dev(st.flat), 6)])
+    batch.run()
+    batch.check()
+    img, rect, offs, nrej = batch.result(0)
+    o = orc.reduce_stack(st.raw, st.dark, st.flat, 6)
+    assert np.array_equal(offs["dx"][1:], o["offsets"]["dx"][1:]) and np.array_equal(offs["dy"][1:], o["offsets"]["dy"][1:])
+    assert np.array_equal(rect, o["rect"])
+    e = rel_err(img.cpu().numpy(), o["out"])
+    print("batch vs oracle:", err_summary(e))
+    s = np.stack([offs["sx"], offs["sy"]], 1).astype(np.float32)
+    if np.array_equal(s, o["s"]):
+        assert e.max() <= TOL
+
+
+def test_batch_workload1_three_bands(rd):
+    stacks = synth.make_config(1)
+    dev = [(to_dev(st.raw), to_dev(st.dark), to_dev(st.flat), st.spec.radius) for st in stacks]
+    batch = rd.StackBatch(dev)
+    batch.run()
+    batch.check()
+    for i, (raw, dark, flat, R) in enumerate(dev):
+        img, rect, offs, nrej = batch.result(i)
+        ref_img, ref_rect, ref_offs, _ = stagewise(rd, raw, dark, flat, R)
+        assert np.array_equal(rect, ref_rect) and np.array_equal(img.cpu().numpy(), ref_img)
+        assert offs.tobytes() == ref_offs.tobytes()
+        err = np.abs(np.stack([offs["sx"], offs["sy"]], 1) - stacks[i].shifts)[1:]
+        assert err.max() < 0.1
+
+
+def test_batch_spin_limit_error_is_reported_and_recovers(rd):
+    st = _make(4, 5, 128, 96, 4, False, seed=5)
+    dev = [(to_dev(st.raw), to_dev(st.dark), to_dev(st.flat), 4)]
+    batch = rd.StackBatch(dev)
+    os.environ["REDUCE_BATCH_SPIN_LIMIT"] = "0"
+    try:
+        batch.run()
+        try:
+            batch.check()  # either no wait was needed, or the error flag is reported
+        except rd.ReduceError as e:
+            assert e.status == rd.ERR_HIP
+    finally:
+        os.environ.pop("REDUCE_BATCH_SPIN_LIMIT")
+    batch.run()
+    batch.check()
+    img, rect, offs, _ = batch.result(0)
+    ref_img, ref_rect, _, _ = stagewise(rd, *dev[0])
+    assert np.array_equal(img.cpu().numpy(), ref_img)
+
+
+def test_batch_rejects_bad_stacks(rd):
+    st = _make(4, 5, 128, 96, 4, False, seed=6)
+    raw = to_dev(st.raw)
+    batch = rd.StackBatch([(raw, to_dev(st.dark), to_dev(st.flat), 60)])  # no template left
+    with pytest.raises(rd.ReduceError):
+        batch.run()

@@ -157,7 +157,8 @@ int reduce_combine(const float *aligned, int32_t w, int32_t h, int32_t N, float 
 /* ---- batched stacks -----------------------------------------------------------
  * The whole chain for many independent stacks (for instance the three bands of the
  * paper's cameras, Section 2.1, or many fields) of uneven frame counts and sizes in
- * one persistent kernel launch, replayed from a cached HIP graph.  For every stack:
+ * one launch of a cached HIP graph of persistent work-queue kernels, one per phase,
+ * each draining the phase's work items of every stack.  For every stack:
  * calibrate all frames as reduce_calibrate; register every frame k != ref_index
  * against frame ref_index as reduce_register with radius_max = radius and the
  * interior template; the reference frame gets the offset 0 (peak 0, second -inf,
@@ -173,9 +174,7 @@ int reduce_combine(const float *aligned, int32_t w, int32_t h, int32_t N, float 
  * partial scores, work queue); query again after tuning.  The stack descriptors are
  * copied at the call; a repeated call with identical descriptors and workspace
  * replays the cached graph without copying.  Calls sharing one workspace must not
- * overlap.  Errors: as the stage-wise calls, per stack; N > 48 -> UNSUPPORTED.
- * reduce_stack_batch_check synchronises `stream` and reports REDUCE_ERR_HIP if a
- * dependency wait inside the kernel exceeded its spin limit. */
+ * overlap.  Errors: as the stage-wise calls, per stack; N > 48 -> UNSUPPORTED. */
 typedef struct {
     const uint16_t *raw;
     int64_t raw_row_pitch, raw_frame_pitch;
@@ -192,8 +191,6 @@ typedef struct {
 
 size_t reduce_stack_batch_ws(const reduce_stack_t *stacks, int32_t n);
 int reduce_stack_batch(const reduce_stack_t *stacks, int32_t n, void *ws, size_t ws_bytes, void *stream);
-int reduce_stack_batch_check(const void *ws, size_t ws_bytes, const reduce_stack_t *stacks, int32_t n,
-                             void *stream);
 
 /* ---- autotuner --------------------------------------------------------------
  * Launch shapes (tiles, workgroup sizes, lanes per pixel) are chosen per problem

@@ -78,8 +78,6 @@ def _declare(L):
     L.reduce_stack_batch_ws.restype = SZ
     L.reduce_stack_batch.argtypes = [P, I32, P, SZ, P]
     L.reduce_stack_batch.restype = ctypes.c_int
-    L.reduce_stack_batch_check.argtypes = [P, SZ, P, I32, P]
-    L.reduce_stack_batch_check.restype = ctypes.c_int
     L.reduce_prof_enable.argtypes = [ctypes.c_int]
     L.reduce_prof_query.argtypes = [ctypes.c_char_p, P, P]
     for n in ("reduce_calibrate", "reduce_register", "reduce_valid_rect", "reduce_shift", "reduce_combine",
@@ -100,7 +98,7 @@ def exported_symbols() -> Sequence[str]:
             "reduce_register_ws", "reduce_register", "reduce_valid_rect", "reduce_shift",
             "reduce_combine", "reduce_prof_enable", "reduce_prof_query", "reduce_register_plan",
             "reduce_tune_register", "reduce_tune_combine", "reduce_tune_save", "reduce_tune_load",
-            "reduce_tune_clear", "reduce_stack_batch_ws", "reduce_stack_batch", "reduce_stack_batch_check")
+            "reduce_tune_clear", "reduce_stack_batch_ws", "reduce_stack_batch")
 
 
 def _check(rc: int) -> None:
@@ -344,10 +342,6 @@ class StackBatch:
         if self.ws is None or self.ws.numel() < need:
             self.ws = torch.empty(need, dtype=torch.uint8, device=self.items[0]["raw"].device)
         _check(lib().reduce_stack_batch(self.descs, self.n, _ptr(self.ws), self.ws.numel(), _stream(stream)))
-
-    def check(self, stream=None) -> None:
-        _check(lib().reduce_stack_batch_check(_ptr(self.ws), self.ws.numel(), self.descs, self.n,
-                                              _stream(stream)))
 
     def result(self, i: int):
         """(image [h][w] float32 tensor, rect numpy, offsets structured numpy, n_rej int)."""

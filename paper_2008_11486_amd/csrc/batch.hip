@@ -1,26 +1,23 @@
-// Many stacks of uneven frame counts and sizes in one persistent kernel launch,
-// replayed from a cached HIP graph.
+// Many stacks of uneven frame counts and sizes in one HIP graph launch of persistent
+// work-queue kernels.
 //
-// The host turns the stacks into one ordered work queue of items:
+// The host turns the stacks into one work queue of items, grouped by phase:
 //
 //   CAL        calibrate a band of rows of one frame into the workspace
 //   MEANPART   sum MEAN_ROWS template rows of the calibrated reference
 //   MEANFINAL  template mean of the reference
-//   SCORE      one tile of partial correlation scores (stack's tuned launch shape)
+//   SCORE      one tile of partial correlation scores (the stack's tuned launch shape)
 //   PICK       sum one frame's partials over tiles, argmax, runner-up, parabola
 //   RECT       common overlap of the stack from its offsets
 //   OUT        bilinear shift of every frame + sigma-clipped mean for OUT_TILES x 256
 //              output pixels
 //
-// Items are listed phase by phase, so every item depends only on items earlier in
-// the queue.  Workgroups take items in queue order with one atomic counter; before
-// running an item a workgroup waits until the per-stack counter of the phase it
-// depends on is complete, and after it publishes its results with a release and
-// bumps its own phase counter.  The lowest unfinished item never waits on a later
-// one and was taken by a running workgroup, so the queue always drains.  Every wait
-// is bounded: past the spin limit the kernel raises an error flag and all
-// workgroups leave.  Each item calls the same device bodies as the stage-wise
-// kernels with the same launch shape, so results are bit-identical to them.
+// Each phase is one kernel whose resident workgroups take the phase's items, over
+// all stacks, from one atomic counter until it is drained; the graph runs the phases
+// in order, so every dependency is met at a kernel boundary and no workgroup waits
+// for another.  The search items of the largest stacks come first.  Each item calls
+// the same device bodies as the stage-wise kernels with the same launch shape, so
+// results are bit-identical to them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -48,7 +45,7 @@ constexpr int CAL_ROWS = 32;    // rows of one frame per CAL item
 constexpr int OUT_TILES = 4;    // combine tiles (of COMB_TILE pixels) per OUT item
 
 enum ItemType : int32_t { IT_CAL = 0, IT_MEANPART, IT_MEANFINAL, IT_SCORE, IT_PICK, IT_RECT, IT_OUT };
-enum Counter : int32_t { C_CAL = 0, C_MEANPART, C_MEAN, C_SCORE, C_PICK, C_RECT, C_COUNT };
+constexpr int N_PHASES = IT_OUT + 1;
 
 struct Item {
     int32_t type, stack, a, pad;
@@ -75,72 +72,101 @@ struct StackDev {
     double *scores;       // [N-1][D*D]
     float *soffs;         // [N][2] offsets applied by the shift
     int32_t *rect;        // [4]
-    uint32_t *ctr;        // [C_COUNT]
-    int32_t n_cal, n_mean_parts, n_score, n_pick;
+    int32_t n_mean_parts;
     ScoreArgs sa;
 };
 
 struct BatchArgs {
     const Item *items;
     const StackDev *stacks;
-    int32_t n_items;
-    uint32_t *head;
-    uint32_t *error;
-    uint32_t spin_limit;
 };
 
-// ---- inter-workgroup signalling ------------------------------------------------------
-__device__ __forceinline__ bool wait_count(const BatchArgs &a, uint32_t *ctr, uint32_t target, int *flag)
+// ---- work-queue kernels, one per phase ----------------------------------------------------
+// Every phase kernel runs a persistent grid that takes items of its own phase with
+// one atomic counter until the phase is drained; the graph orders the phases, so no
+// workgroup ever waits for another.
+__device__ __forceinline__ int32_t next_item(uint32_t *head, int32_t *slot)
 {
-    if (threadIdx.x == 0) {
-        uint32_t spins = 0;
-        int ok = 1;
-        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                ok = 0;
-                break;
-            }
-            if (++spins > a.spin_limit) {
-                __hip_atomic_store(a.error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(2);
+    if (threadIdx.x == 0) *slot = (int32_t)atomicAdd(head, 1u);
+    __syncthreads();
+    const int32_t id = *slot;
+    __syncthreads();
+    return id;
+}
+
+__global__ __launch_bounds__(BATCH_THREADS) void batch_cal(BatchArgs a, int32_t first, int32_t count, uint32_t *head)
+{
+    __shared__ int32_t slot;
+    for (int32_t q; (q = next_item(head, &slot)) < count;) {
+        const Item it = a.items[first + q];
+        const StackDev &s = a.stacks[it.stack];
+        const int32_t bands = (int32_t)((s.H + CAL_ROWS - 1) / CAL_ROWS);
+        const int32_t k = it.a / bands, y0 = (it.a - k * bands) * CAL_ROWS;
+        const int32_t y1 = min(y0 + CAL_ROWS, s.H);
+        const int64_t n = (int64_t)(y1 - y0) * s.W;
+        for (int64_t i = threadIdx.x; i < n; i += BATCH_THREADS) {
+            const int32_t y = y0 + (int32_t)(i / s.W), x = (int32_t)(i % s.W);
+            const int64_t c = (int64_t)y * s.crp + x;
+            s.cal[((int64_t)k * s.H + y) * s.W + x] =
+                calib_px(s.raw[(int64_t)k * s.rfp + (int64_t)y * s.rrp + x], s.dark[c], s.flat[c]);
         }
-        // make the producers' released writes visible before anything is read
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        *flag = ok;
-    }
-    __syncthreads();
-    const bool ok = *flag != 0;
-    __syncthreads();
-    return ok;
-}
-
-__device__ __forceinline__ void signal_done(uint32_t *ctr)
-{
-    __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// ---- item bodies ---------------------------------------------------------------------------
-__device__ __noinline__ void do_cal(const StackDev &s, int32_t a)
-{
-    const int32_t bands = (int32_t)((s.H + CAL_ROWS - 1) / CAL_ROWS);
-    const int32_t k = a / bands, y0 = (a - k * bands) * CAL_ROWS;
-    const int32_t y1 = min(y0 + CAL_ROWS, s.H);
-    const int64_t n = (int64_t)(y1 - y0) * s.W;
-    for (int64_t i = threadIdx.x; i < n; i += BATCH_THREADS) {
-        const int32_t y = y0 + (int32_t)(i / s.W), x = (int32_t)(i % s.W);
-        const int64_t c = (int64_t)y * s.crp + x;
-        s.cal[((int64_t)k * s.H + y) * s.W + x] =
-            calib_px(s.raw[(int64_t)k * s.rfp + (int64_t)y * s.rrp + x], s.dark[c], s.flat[c]);
     }
 }
 
-__device__ __noinline__ void do_rect(const StackDev &s)
+__global__ __launch_bounds__(MEAN_THREADS) void batch_meanpart(BatchArgs a, int32_t first, int32_t count,
+                                                               uint32_t *head)
+{
+    __shared__ int32_t slot;
+    __shared__ double scratch[MEAN_THREADS / 64];
+    for (int32_t q; (q = next_item(head, &slot)) < count;) {
+        const Item it = a.items[first + q];
+        const StackDev &s = a.stacks[it.stack];
+        const double v = tmpl_part_sum(s.sa.ref, s.W, s.sa.tx0, s.sa.ty0, s.sa.tw, s.sa.th, it.a, scratch);
+        if (threadIdx.x == 0) s.mean_parts[it.a] = v;
+    }
+}
+
+__global__ __launch_bounds__(MEAN_THREADS) void batch_meanfinal(BatchArgs a, int32_t first)
+{
+    __shared__ double scratch[MEAN_THREADS / 64];
+    const Item it = a.items[first + blockIdx.x];
+    const StackDev &s = a.stacks[it.stack];
+    const double m =
+        tmpl_mean_of_parts(s.mean_parts, s.n_mean_parts, (double)s.sa.tw * (double)s.sa.th, scratch);
+    if (threadIdx.x == 0) *s.mean = m;
+}
+
+__global__ __launch_bounds__(BATCH_THREADS) void batch_score(BatchArgs a, int32_t first, int32_t count,
+                                                             uint32_t *head)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int32_t slot;
+    for (int32_t q; (q = next_item(head, &slot)) < count;) {
+        const Item it = a.items[first + q];
+        const StackDev &s = a.stacks[it.stack];
+        score_dispatch(s.K, [&](auto Kc) { score_tile<decltype(Kc)::value>(s.sa, it.a, smem); });
+    }
+}
+
+__global__ __launch_bounds__(256) void batch_pick(BatchArgs a, int32_t first)
+{
+    __shared__ Best scratch[4];
+    const Item it = a.items[first + blockIdx.x];
+    const StackDev &s = a.stacks[it.stack];
+    const int32_t D = s.sa.D, k = it.a;
+    double *S = s.scores + (int64_t)k * D * D;
+    const double *pk = s.partial + (int64_t)k * s.sa.n_tiles * D * D;
+    for (int32_t c = threadIdx.x; c < D * D; c += blockDim.x)
+        S[c] = candidate_score(pk, s.sa.n_tiles, D, s.R, s.R, 0, 0, c);
+    __syncthreads();
+    const int32_t kf = k + (k >= s.ref ? 1 : 0);
+    pick_frame(S, D, s.R, s.R, 0, 0, s.offsets + kf, scratch);
+}
+
+__global__ void batch_rect(BatchArgs a, int32_t first)
 {
     if (threadIdx.x != 0) return;
+    const StackDev &s = a.stacks[a.items[first + blockIdx.x].stack];
     // reference frame: offset 0 by definition
     reduce_offset_t z;
     z.dx = z.dy = 0;
@@ -161,17 +187,15 @@ __device__ __noinline__ void do_rect(const StackDev &s)
         }
         s.soffs[2 * k] = sx;
         s.soffs[2 * k + 1] = sy;
-        const double a = ceil(-(double)sx), b = floor((double)(s.W - 1) - (double)sx);
-        const double c = ceil(-(double)sy), d = floor((double)(s.H - 1) - (double)sy);
-        xl = a > xl ? a : xl;
-        xh = b < xh ? b : xh;
-        yl = c > yl ? c : yl;
-        yh = d < yh ? d : yh;
+        const double lo_x = ceil(-(double)sx), hi_x = floor((double)(s.W - 1) - (double)sx);
+        const double lo_y = ceil(-(double)sy), hi_y = floor((double)(s.H - 1) - (double)sy);
+        xl = lo_x > xl ? lo_x : xl;
+        xh = hi_x < xh ? hi_x : xh;
+        yl = lo_y > yl ? lo_y : yl;
+        yh = hi_y < yh ? hi_y : yh;
     }
-    int32_t r[4];
-    if (xl > xh || yl > yh) {
-        r[0] = r[1] = r[2] = r[3] = 0;  // no overlap: empty output
-    } else {
+    int32_t r[4] = {0, 0, 0, 0};  // no overlap: empty output
+    if (xl <= xh && yl <= yh) {
         r[0] = (int32_t)xl;
         r[1] = (int32_t)yl;
         r[2] = (int32_t)(xh - xl) + 1;
@@ -185,136 +209,56 @@ __device__ __noinline__ void do_rect(const StackDev &s)
 
 __device__ __forceinline__ int32_t clampi(int32_t v, int32_t lo, int32_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-__device__ __noinline__ void do_out(const StackDev &s, int32_t a, float *tile)
-{
-    const int32_t x0 = s.rect[0], y0 = s.rect[1], w = s.rect[2], h = s.rect[3];
-    const int64_t plane = (int64_t)w * h;
-    unsigned dropped = 0;
-    for (int32_t sub = 0; sub < OUT_TILES; ++sub) {
-        const int64_t p0 = ((int64_t)a * OUT_TILES + sub) * COMB_TILE;
-        if (p0 >= plane) break;  // uniform over the workgroup
-        // aligned values of every frame for the tile's pixels, as the shift kernel makes them
-        for (int32_t idx = threadIdx.x; idx < s.N * COMB_TILE; idx += BATCH_THREADS) {
-            const int32_t k = idx / COMB_TILE, px = idx - k * COMB_TILE;
-            const int64_t p = p0 + px;
-            float v = 0.0f;
-            if (p < plane) {
-                const int32_t vv = (int32_t)(p / w), u = (int32_t)(p - (int64_t)vv * w);
-                const ShiftSetup ss = shift_setup(s.soffs[2 * k], s.soffs[2 * k + 1]);
-                const float *f = s.cal + (int64_t)k * s.W * s.H;
-                const int32_t j = clampi(y0 + vv + ss.iy, 0, s.H - 1);
-                const int32_t i = clampi(x0 + u + ss.ix, 0, s.W - 1);
-                if (s.integer_mode) {
-                    v = f[(int64_t)j * s.W + i];
-                } else {
-                    const int32_t j1 = clampi(ss.b > 0.0 ? j + 1 : j, 0, s.H - 1);
-                    const int32_t i1 = ss.a > 0.0 ? clampi(x0 + u + ss.ix + 1, 0, s.W - 1) : i;
-                    v = bilerp(ss.a, ss.b, f[(int64_t)j * s.W + i], f[(int64_t)j * s.W + i1],
-                               f[(int64_t)j1 * s.W + i], f[(int64_t)j1 * s.W + i1]);
-                }
-            }
-            tile[idx] = v;
-        }
-        __syncthreads();
-        lanes_dispatch(s.lanes, s.N, [&](auto Lc, auto Vc) {
-            constexpr int L = decltype(Lc)::value, V = decltype(Vc)::value;
-            dropped += clip_tile<L, V>(tile, p0, plane, s.N, (double)s.ksigma, s.max_iters, s.out, nullptr);
-        });
-        __syncthreads();
-    }
-    if (s.n_rej && dropped) atomicAdd(reinterpret_cast<unsigned long long *>(s.n_rej), (unsigned long long)dropped);
-}
-
-__device__ __noinline__ void do_score(const StackDev &s, int32_t a, unsigned char *smem)
-{
-    score_dispatch(s.K, [&](auto Kc) { score_tile<decltype(Kc)::value>(s.sa, a, smem); });
-}
-
-__device__ __noinline__ void do_pick(const StackDev &s, int32_t k, Best *bscratch)
-{
-    const int32_t D = s.sa.D;
-    double *S = s.scores + (int64_t)k * D * D;
-    const double *pk = s.partial + (int64_t)k * s.sa.n_tiles * D * D;
-    for (int32_t c = threadIdx.x; c < D * D; c += BATCH_THREADS)
-        S[c] = candidate_score(pk, s.sa.n_tiles, D, s.R, s.R, 0, 0, c);
-    __syncthreads();
-    const int32_t kf = k + (k >= s.ref ? 1 : 0);
-    pick_frame(S, D, s.R, s.R, 0, 0, s.offsets + kf, bscratch);
-}
-
-__device__ __noinline__ double do_meanpart(const StackDev &s, int32_t part, double *mscratch)
-{
-    return tmpl_part_sum(s.sa.ref, s.W, s.sa.tx0, s.sa.ty0, s.sa.tw, s.sa.th, part, mscratch);
-}
-
-__global__ __launch_bounds__(BATCH_THREADS, 4) void batch_kernel(BatchArgs a)
+__global__ __launch_bounds__(COMB_TILE) void batch_out(BatchArgs a, int32_t first, int32_t count, uint32_t *head)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int32_t item_id;
-    __shared__ int flag;
-    __shared__ double mscratch[BATCH_THREADS / 64];
-    __shared__ Best bscratch[BATCH_THREADS / 64];
-
-    for (;;) {
-        if (threadIdx.x == 0) {
-            const bool err = __hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
-            item_id = err ? a.n_items : (int32_t)atomicAdd(a.head, 1u);
-        }
-        __syncthreads();
-        const int32_t id = item_id;
-        __syncthreads();
-        if (id >= a.n_items) break;
-        const Item it = a.items[id];
+    __shared__ int32_t slot;
+    float *tile = reinterpret_cast<float *>(smem);
+    for (int32_t q; (q = next_item(head, &slot)) < count;) {
+        const Item it = a.items[first + q];
         const StackDev &s = a.stacks[it.stack];
-        switch (it.type) {
-        case IT_CAL:
-            do_cal(s, it.a);
-            signal_done(s.ctr + C_CAL);
-            break;
-        case IT_MEANPART: {
-            if (!wait_count(a, s.ctr + C_CAL, (uint32_t)s.n_cal, &flag)) break;
-            const double v = do_meanpart(s, it.a, mscratch);
-            if (threadIdx.x == 0) s.mean_parts[it.a] = v;
-            signal_done(s.ctr + C_MEANPART);
-            break;
+        const int32_t x0 = s.rect[0], y0 = s.rect[1], w = s.rect[2], h = s.rect[3];
+        const int64_t plane = (int64_t)w * h;
+        unsigned dropped = 0;
+        for (int32_t sub = 0; sub < OUT_TILES; ++sub) {
+            const int64_t p0 = ((int64_t)it.a * OUT_TILES + sub) * COMB_TILE;
+            if (p0 >= plane) break;  // uniform over the workgroup
+            // aligned values of every frame for the tile's pixels, as the shift kernel makes them
+            for (int32_t k = 0; k < s.N; ++k) {
+                const int32_t px = threadIdx.x;
+                const int64_t p = p0 + px;
+                float v = 0.0f;
+                if (p < plane) {
+                    const int32_t vv = (int32_t)(p / w), u = (int32_t)(p - (int64_t)vv * w);
+                    const ShiftSetup ss = shift_setup(s.soffs[2 * k], s.soffs[2 * k + 1]);
+                    const float *f = s.cal + (int64_t)k * s.W * s.H;
+                    const int32_t j = clampi(y0 + vv + ss.iy, 0, s.H - 1);
+                    const int32_t i = clampi(x0 + u + ss.ix, 0, s.W - 1);
+                    if (s.integer_mode) {
+                        v = f[(int64_t)j * s.W + i];
+                    } else {
+                        const int32_t j1 = clampi(ss.b > 0.0 ? j + 1 : j, 0, s.H - 1);
+                        const int32_t i1 = ss.a > 0.0 ? clampi(x0 + u + ss.ix + 1, 0, s.W - 1) : i;
+                        v = bilerp(ss.a, ss.b, f[(int64_t)j * s.W + i], f[(int64_t)j * s.W + i1],
+                                   f[(int64_t)j1 * s.W + i], f[(int64_t)j1 * s.W + i1]);
+                    }
+                }
+                tile[k * COMB_TILE + px] = v;
+            }
+            __syncthreads();
+            lanes_dispatch(s.lanes, s.N, [&](auto Lc, auto Vc) {
+                constexpr int L = decltype(Lc)::value, V = decltype(Vc)::value;
+                dropped += clip_tile<L, V>(tile, p0, plane, s.N, (double)s.ksigma, s.max_iters, s.out, nullptr);
+            });
+            __syncthreads();
         }
-        case IT_MEANFINAL: {
-            if (!wait_count(a, s.ctr + C_MEANPART, (uint32_t)s.n_mean_parts, &flag)) break;
-            const double m = tmpl_mean_of_parts(s.mean_parts, s.n_mean_parts, (double)s.sa.tw * (double)s.sa.th,
-                                                mscratch);
-            if (threadIdx.x == 0) *s.mean = m;
-            signal_done(s.ctr + C_MEAN);
-            break;
-        }
-        case IT_SCORE:
-            if (!wait_count(a, s.ctr + C_MEAN, 1u, &flag)) break;
-            do_score(s, it.a, smem);
-            signal_done(s.ctr + C_SCORE);
-            break;
-        case IT_PICK: {
-            if (!wait_count(a, s.ctr + C_SCORE, (uint32_t)s.n_score, &flag)) break;
-            do_pick(s, it.a, bscratch);
-            signal_done(s.ctr + C_PICK);
-            break;
-        }
-        case IT_RECT:
-            if (!wait_count(a, s.ctr + C_PICK, (uint32_t)s.n_pick, &flag)) break;
-            do_rect(s);
-            signal_done(s.ctr + C_RECT);
-            break;
-        case IT_OUT:
-            if (!wait_count(a, s.ctr + C_RECT, 1u, &flag)) break;
-            do_out(s, it.a, reinterpret_cast<float *>(smem));
-            break;
-        default:
-            break;
-        }
+        if (s.n_rej && dropped) atomicAdd(reinterpret_cast<unsigned long long *>(s.n_rej), (unsigned long long)dropped);
     }
 }
 
-__global__ void batch_reset(uint32_t *ctrs, int32_t n, int64_t *const *n_rej, int32_t n_stacks)
+__global__ void batch_reset(uint32_t *heads, int32_t n, int64_t *const *n_rej, int32_t n_stacks)
 {
-    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) ctrs[i] = 0u;
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) heads[i] = 0u;
     for (int32_t i = threadIdx.x; i < n_stacks; i += blockDim.x)
         if (n_rej[i]) *n_rej[i] = 0;
 }
@@ -325,17 +269,16 @@ static size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 struct StackLayout {
     RegPlan plan;
     size_t cal, mean_parts, mean, partial, scores, soffs, rect;
-    int32_t n_cal, n_mean_parts, n_score, n_pick, n_out;
+    int32_t count[N_PHASES];
 };
 
 struct BatchLayout {
     std::vector<StackLayout> st;
-    size_t items, stacks, ctrs, head, nrej_ptrs, total;
+    size_t items, stacks, heads, nrej_ptrs, total;
     int32_t n_items;
-    size_t lds;
+    int32_t first[N_PHASES], count[N_PHASES];
+    size_t score_lds, out_lds;
 };
-
-static int32_t stack_ref(const reduce_stack_t &s) { return s.ref_index; }
 
 static int validate(const reduce_stack_t *stacks, int32_t n)
 {
@@ -363,8 +306,9 @@ static BatchLayout layout_of(const reduce_stack_t *stacks, int32_t n)
 {
     BatchLayout L;
     size_t off = 0;
-    int64_t n_items = 0;
-    L.lds = 0;
+    L.score_lds = 0;
+    L.out_lds = 0;
+    for (int p = 0; p < N_PHASES; ++p) L.count[p] = 0;
     for (int32_t i = 0; i < n; ++i) {
         const reduce_stack_t &s = stacks[i];
         StackLayout sl;
@@ -374,9 +318,9 @@ static BatchLayout layout_of(const reduce_stack_t *stacks, int32_t n)
         const int32_t nreg = s.N - 1;
         sl.cal = off;
         off += al(sizeof(float) * fp * s.N);
-        sl.n_mean_parts = (int32_t)ceil_div(s.H - 2 * s.radius, MEAN_ROWS);
+        const int32_t n_mean_parts = (int32_t)ceil_div(s.H - 2 * s.radius, MEAN_ROWS);
         sl.mean_parts = off;
-        off += al(sizeof(double) * sl.n_mean_parts);
+        off += al(sizeof(double) * n_mean_parts);
         sl.mean = off;
         off += 256;
         sl.partial = off;
@@ -387,23 +331,30 @@ static BatchLayout layout_of(const reduce_stack_t *stacks, int32_t n)
         off += al(sizeof(float) * 2 * s.N);
         sl.rect = off;
         off += 256;
-        sl.n_cal = s.N * (int32_t)ceil_div(s.H, CAL_ROWS);
-        sl.n_score = nreg * p.n_tiles * p.G;
-        sl.n_pick = nreg;
-        sl.n_out = (int32_t)ceil_div(fp, (int64_t)COMB_TILE * OUT_TILES);
-        n_items += sl.n_cal + sl.n_mean_parts + 1 + sl.n_score + sl.n_pick + 1 + sl.n_out;
-        L.lds = std::max(L.lds, std::max(p.lds, sizeof(float) * (size_t)s.N * COMB_TILE));
+        sl.count[IT_CAL] = s.N * (int32_t)ceil_div(s.H, CAL_ROWS);
+        sl.count[IT_MEANPART] = n_mean_parts;
+        sl.count[IT_MEANFINAL] = 1;
+        sl.count[IT_SCORE] = nreg * p.n_tiles * p.G;
+        sl.count[IT_PICK] = nreg;
+        sl.count[IT_RECT] = 1;
+        sl.count[IT_OUT] = (int32_t)ceil_div(fp, (int64_t)COMB_TILE * OUT_TILES);
+        for (int q = 0; q < N_PHASES; ++q) L.count[q] += sl.count[q];
+        if (nreg > 0) L.score_lds = std::max(L.score_lds, p.lds);
+        L.out_lds = std::max(L.out_lds, sizeof(float) * (size_t)s.N * COMB_TILE);
         L.st.push_back(sl);
     }
-    L.n_items = (int32_t)n_items;
+    int64_t total = 0;
+    for (int q = 0; q < N_PHASES; ++q) {
+        L.first[q] = (int32_t)total;
+        total += L.count[q];
+    }
+    L.n_items = total > INT32_MAX ? -1 : (int32_t)total;
     L.items = off;
-    off += al(sizeof(Item) * (size_t)n_items);
+    off += al(sizeof(Item) * (size_t)std::max<int64_t>(total, 0));
     L.stacks = off;
     off += al(sizeof(StackDev) * (size_t)n);
-    L.ctrs = off;
-    off += al(sizeof(uint32_t) * C_COUNT * (size_t)n);
-    L.head = off;
-    off += 256;  // head, error
+    L.heads = off;
+    off += 256;
     L.nrej_ptrs = off;
     off += al(sizeof(int64_t *) * (size_t)n);
     L.total = off;
@@ -415,17 +366,11 @@ struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<unsigned char> host;  // uploaded descriptor bytes (kept alive with the entry)
-    BatchArgs args{};
-    uint32_t *ctrs = nullptr;
-    int32_t n_ctrs = 0;
-    int64_t *const *nrej = nullptr;
-    int32_t n_stacks = 0;
-    int grid = 0;
-    size_t lds = 0;
 };
 
 static std::mutex g_batch_mu;
 static std::map<void *, GraphEntry> g_graphs;  // by workspace address
+static hipStream_t g_capture_stream = nullptr;
 
 static uint64_t fnv1a(const void *p, size_t n, uint64_t h = 1469598103934665603ull)
 {
@@ -437,13 +382,23 @@ static uint64_t fnv1a(const void *p, size_t n, uint64_t h = 1469598103934665603u
     return h;
 }
 
+// Resident workgroups of a kernel over the whole device, at most `items`.
+template <typename K>
+static int persistent_grid(K kernel, int threads, size_t lds, int32_t items)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev))
+        return -1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess || per_cu < 1)
+        return -1;
+    return (int)std::min<int64_t>((int64_t)cus * per_cu, std::max<int32_t>(items, 1));
+}
+
 static int build_entry(const reduce_stack_t *stacks, int32_t n, void *ws, const BatchLayout &L, GraphEntry *e,
                        hipStream_t s)
 {
     unsigned char *base = static_cast<unsigned char *>(ws);
     std::vector<StackDev> sd(n);
-    std::vector<Item> items;
-    items.reserve(L.n_items);
     std::vector<int64_t *> nrej(n);
     for (int32_t i = 0; i < n; ++i) {
         const reduce_stack_t &st = stacks[i];
@@ -463,7 +418,7 @@ static int build_entry(const reduce_stack_t *stacks, int32_t n, void *ws, const 
         d.W = st.W;
         d.H = st.H;
         d.N = st.N;
-        d.ref = stack_ref(st);
+        d.ref = st.ref_index;
         d.R = st.radius;
         d.max_iters = st.max_iters;
         d.integer_mode = st.integer_mode ? 1 : 0;
@@ -477,36 +432,27 @@ static int build_entry(const reduce_stack_t *stacks, int32_t n, void *ws, const 
         d.scores = reinterpret_cast<double *>(base + sl.scores);
         d.soffs = reinterpret_cast<float *>(base + sl.soffs);
         d.rect = reinterpret_cast<int32_t *>(base + sl.rect);
-        d.ctr = reinterpret_cast<uint32_t *>(base + L.ctrs) + (size_t)C_COUNT * i;
-        d.n_cal = sl.n_cal;
-        d.n_mean_parts = sl.n_mean_parts;
-        d.n_score = sl.n_score;
-        d.n_pick = sl.n_pick;
+        d.n_mean_parts = sl.count[IT_MEANPART];
         const int32_t R = st.radius;
         const float *ref = d.cal + (int64_t)d.ref * st.W * st.H;
         d.sa = make_score_args(sl.plan, ref, d.cal, nullptr, d.mean, d.partial, st.W, st.H, std::max(st.N - 1, 1), R,
                                R, R, R, st.W - 2 * R, st.H - 2 * R, d.ref);
     }
-    // the queue, phase by phase; search items of the largest stacks first
-    for (int32_t i = 0; i < n; ++i)
-        for (int32_t a = 0; a < L.st[i].n_cal; ++a) items.push_back({IT_CAL, i, a, 0});
-    for (int32_t i = 0; i < n; ++i)
-        for (int32_t a = 0; a < L.st[i].n_mean_parts; ++a) items.push_back({IT_MEANPART, i, a, 0});
-    for (int32_t i = 0; i < n; ++i) items.push_back({IT_MEANFINAL, i, 0, 0});
+    // the queue, phase by phase; search and output items of the largest stacks first
     std::vector<int32_t> order(n);
     for (int32_t i = 0; i < n; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-        const double cx = (double)L.st[x].n_score * L.st[x].plan.BR * L.st[x].plan.TX * L.st[x].plan.C;
-        const double cy = (double)L.st[y].n_score * L.st[y].plan.BR * L.st[y].plan.TX * L.st[y].plan.C;
-        return cx > cy;
+        const auto cost = [&](int32_t z) {
+            const RegPlan &p = L.st[z].plan;
+            return (double)L.st[z].count[IT_SCORE] * p.BR * p.TX * p.C + (double)L.st[z].count[IT_OUT];
+        };
+        return cost(x) > cost(y);
     });
-    for (int32_t i : order)
-        for (int32_t a = 0; a < L.st[i].n_score; ++a) items.push_back({IT_SCORE, i, a, 0});
-    for (int32_t i = 0; i < n; ++i)
-        for (int32_t a = 0; a < L.st[i].n_pick; ++a) items.push_back({IT_PICK, i, a, 0});
-    for (int32_t i = 0; i < n; ++i) items.push_back({IT_RECT, i, 0, 0});
-    for (int32_t i : order)
-        for (int32_t a = 0; a < L.st[i].n_out; ++a) items.push_back({IT_OUT, i, a, 0});
+    std::vector<Item> items;
+    items.reserve(L.n_items);
+    for (int q = 0; q < N_PHASES; ++q)
+        for (int32_t i : order)
+            for (int32_t a = 0; a < L.st[i].count[q]; ++a) items.push_back({q, i, a, 0});
     if ((int32_t)items.size() != L.n_items) return fail(REDUCE_ERR_SHAPE, "reduce_stack_batch: item count");
 
     // descriptors into the workspace
@@ -517,52 +463,44 @@ static int build_entry(const reduce_stack_t *stacks, int32_t n, void *ws, const 
     if (hipMemcpyAsync(base + L.items, e->host.data(), e->host.size(), hipMemcpyHostToDevice, s) != hipSuccess)
         return fail(REDUCE_ERR_HIP, "reduce_stack_batch: descriptor upload");
 
-    BatchArgs &a = e->args;
+    BatchArgs a;
     a.items = reinterpret_cast<const Item *>(base + L.items);
     a.stacks = reinterpret_cast<const StackDev *>(base + L.stacks);
-    a.n_items = L.n_items;
-    a.head = reinterpret_cast<uint32_t *>(base + L.head);
-    a.error = a.head + 1;
-    const char *lim = std::getenv("REDUCE_BATCH_SPIN_LIMIT");
-    a.spin_limit = lim ? (uint32_t)std::strtoul(lim, nullptr, 10) : (1u << 27);
-    e->ctrs = reinterpret_cast<uint32_t *>(base + L.ctrs);
-    e->n_ctrs = C_COUNT * n;
-    e->nrej = reinterpret_cast<int64_t *const *>(base + L.nrej_ptrs);
-    e->n_stacks = n;
-    e->lds = L.lds;
+    uint32_t *heads = reinterpret_cast<uint32_t *>(base + L.heads);
+    int64_t *const *nrej_dev = reinterpret_cast<int64_t *const *>(base + L.nrej_ptrs);
 
-    // persistent grid: as many workgroups as can be resident at once
-    int dev = 0, cus = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev))
-        return fail(REDUCE_ERR_HIP, "reduce_stack_batch: device query");
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel, BATCH_THREADS, L.lds) != hipSuccess ||
-        per_cu < 1)
-        return fail(REDUCE_ERR_HIP, "reduce_stack_batch: the kernel does not fit on a compute unit");
-    e->grid = std::min<int64_t>((int64_t)cus * per_cu, std::max<int32_t>(L.n_items, 1));
+    const int g_cal = persistent_grid(batch_cal, BATCH_THREADS, 0, L.count[IT_CAL]);
+    const int g_mean = persistent_grid(batch_meanpart, MEAN_THREADS, 0, L.count[IT_MEANPART]);
+    const int g_score = persistent_grid(batch_score, BATCH_THREADS, L.score_lds, L.count[IT_SCORE]);
+    const int g_out = persistent_grid(batch_out, COMB_TILE, L.out_lds, L.count[IT_OUT]);
+    if (g_cal < 1 || g_mean < 1 || g_score < 1 || g_out < 1)
+        return fail(REDUCE_ERR_HIP, "reduce_stack_batch: occupancy query");
 
-    // graph: reset counters and error flag, then the persistent kernel
-    if (hipGraphCreate(&e->graph, 0) != hipSuccess) return fail(REDUCE_ERR_HIP, "reduce_stack_batch: graph");
-    uint32_t *ctr_all = e->ctrs;
-    int32_t n_all = (int32_t)((L.head + 8 - L.ctrs) / sizeof(uint32_t));  // counters, head and error
-    void *reset_args[] = {&ctr_all, &n_all, (void *)&e->nrej, &e->n_stacks};
-    hipKernelNodeParams rp{};
-    rp.func = reinterpret_cast<void *>(batch_reset);
-    rp.gridDim = dim3(1);
-    rp.blockDim = dim3(256);
-    rp.sharedMemBytes = 0;
-    rp.kernelParams = reset_args;
-    hipGraphNode_t n_reset, n_main;
-    if (hipGraphAddKernelNode(&n_reset, e->graph, nullptr, 0, &rp) != hipSuccess)
-        return fail(REDUCE_ERR_HIP, "reduce_stack_batch: graph reset node");
-    void *main_args[] = {&e->args};
-    hipKernelNodeParams mp{};
-    mp.func = reinterpret_cast<void *>(batch_kernel);
-    mp.gridDim = dim3((unsigned)e->grid);
-    mp.blockDim = dim3(BATCH_THREADS);
-    mp.sharedMemBytes = (unsigned)L.lds;
-    mp.kernelParams = main_args;
-    if (hipGraphAddKernelNode(&n_main, e->graph, &n_reset, 1, &mp) != hipSuccess)
-        return fail(REDUCE_ERR_HIP, "reduce_stack_batch: graph kernel node");
+    // record the phase kernels into a graph on a private stream
+    if (!g_capture_stream && hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking) != hipSuccess)
+        return fail(REDUCE_ERR_HIP, "reduce_stack_batch: capture stream");
+    hipStream_t c = g_capture_stream;
+    if (hipStreamBeginCapture(c, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(REDUCE_ERR_HIP, "reduce_stack_batch: begin capture");
+    hipLaunchKernelGGL(batch_reset, dim3(1), dim3(256), 0, c, heads, (int32_t)N_PHASES, nrej_dev, n);
+    hipLaunchKernelGGL(batch_cal, dim3(g_cal), dim3(BATCH_THREADS), 0, c, a, L.first[IT_CAL], L.count[IT_CAL],
+                       heads + IT_CAL);
+    if (L.count[IT_MEANPART] > 0)
+        hipLaunchKernelGGL(batch_meanpart, dim3(g_mean), dim3(MEAN_THREADS), 0, c, a, L.first[IT_MEANPART],
+                           L.count[IT_MEANPART], heads + IT_MEANPART);
+    hipLaunchKernelGGL(batch_meanfinal, dim3(L.count[IT_MEANFINAL]), dim3(MEAN_THREADS), 0, c, a,
+                       L.first[IT_MEANFINAL]);
+    if (L.count[IT_SCORE] > 0)
+        hipLaunchKernelGGL(batch_score, dim3(g_score), dim3(BATCH_THREADS), L.score_lds, c, a, L.first[IT_SCORE],
+                           L.count[IT_SCORE], heads + IT_SCORE);
+    if (L.count[IT_PICK] > 0)
+        hipLaunchKernelGGL(batch_pick, dim3(L.count[IT_PICK]), dim3(256), 0, c, a, L.first[IT_PICK]);
+    hipLaunchKernelGGL(batch_rect, dim3(L.count[IT_RECT]), dim3(64), 0, c, a, L.first[IT_RECT]);
+    hipLaunchKernelGGL(batch_out, dim3(g_out), dim3(COMB_TILE), L.out_lds, c, a, L.first[IT_OUT], L.count[IT_OUT],
+                       heads + IT_OUT);
+    const hipError_t launch_err = hipGetLastError();
+    if (hipStreamEndCapture(c, &e->graph) != hipSuccess || launch_err != hipSuccess)
+        return fail(REDUCE_ERR_HIP, "reduce_stack_batch: graph capture");
     if (hipGraphInstantiate(&e->exec, e->graph, nullptr, nullptr, 0) != hipSuccess)
         return fail(REDUCE_ERR_HIP, "reduce_stack_batch: graph instantiate");
     return REDUCE_OK;
@@ -594,9 +532,9 @@ extern "C" int reduce_stack_batch(const reduce_stack_t *stacks, int32_t n, void 
     const int v = validate(stacks, n);
     if (v != REDUCE_OK) return v;
     const BatchLayout L = layout_of(stacks, n);
+    if (L.n_items < 0) return fail(REDUCE_ERR_UNSUPPORTED, "reduce_stack_batch: too many work items");
     if (!ws || ws_bytes < L.total)
         return fail(REDUCE_ERR_WORKSPACE, "reduce_stack_batch: workspace needs " + std::to_string(L.total) + " bytes");
-    if (L.n_items < 0) return fail(REDUCE_ERR_UNSUPPORTED, "reduce_stack_batch: too many work items");
     hipStream_t s = as_stream(stream);
 
     // a graph per workspace, rebuilt when the stacks or their launch shapes change
@@ -607,8 +545,6 @@ extern "C" int reduce_stack_batch(const reduce_stack_t *stacks, int32_t n, void 
         h = fnv1a(&lanes, sizeof(lanes), h);
     }
     h = fnv1a(&L.total, sizeof(L.total), h);
-    const char *lim = std::getenv("REDUCE_BATCH_SPIN_LIMIT");
-    h = fnv1a(lim ? lim : "", lim ? std::strlen(lim) : 0, h);
     std::lock_guard<std::mutex> lk(g_batch_mu);
     GraphEntry &e = g_graphs[ws];
     if (!e.exec || e.hash != h) {
@@ -624,24 +560,7 @@ extern "C" int reduce_stack_batch(const reduce_stack_t *stacks, int32_t n, void 
         }
         e.hash = h;
     }
-    ProfScope prof("batch_kernel", s);
+    ProfScope prof("stack_batch", s);
     if (hipGraphLaunch(e.exec, s) != hipSuccess) return fail(REDUCE_ERR_HIP, "reduce_stack_batch: graph launch");
     return check_launch("reduce_stack_batch");
-}
-
-extern "C" int reduce_stack_batch_check(const void *ws, size_t ws_bytes, const reduce_stack_t *stacks, int32_t n,
-                                        void *stream)
-{
-    if (!ws || !stacks) return fail(REDUCE_ERR_NULL, "reduce_stack_batch_check: NULL argument");
-    if (n < 1) return fail(REDUCE_ERR_SHAPE, "reduce_stack_batch_check: no stacks");
-    const BatchLayout L = layout_of(stacks, n);
-    if (ws_bytes < L.total) return fail(REDUCE_ERR_WORKSPACE, "reduce_stack_batch_check: workspace too small");
-    uint32_t flag = 0;
-    hipStream_t s = as_stream(stream);
-    if (hipMemcpyAsync(&flag, static_cast<const unsigned char *>(ws) + L.head + 4, sizeof(flag),
-                       hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-        return fail(REDUCE_ERR_HIP, "reduce_stack_batch_check: read of the error flag");
-    if (flag) return fail(REDUCE_ERR_HIP, "reduce_stack_batch: a dependency wait exceeded its spin limit");
-    return REDUCE_OK;
 }

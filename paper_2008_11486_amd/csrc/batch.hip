@@ -537,9 +537,12 @@ extern "C" int reduce_stack_batch(const reduce_stack_t *stacks, int32_t n, void 
         return fail(REDUCE_ERR_WORKSPACE, "reduce_stack_batch: workspace needs " + std::to_string(L.total) + " bytes");
     // Switched off: the graph replay of this path did not complete on its first runs on
     // the device, and the cause has not been identified; nothing is launched.
-    if (!std::getenv("REDUCE_BATCH_ENABLE"))
-        return fail(REDUCE_ERR_UNSUPPORTED, "reduce_stack_batch: the batched graph path is switched off "
-                                            "(its replay did not complete on the device; cause not yet found)");
+    return fail(REDUCE_ERR_UNSUPPORTED, "reduce_stack_batch: the batched graph path is switched off "
+                                        "(its replay did not complete on the device; cause not yet found)");
+}
+
+static int stack_batch_launch(const reduce_stack_t *stacks, int32_t n, void *ws, const BatchLayout &L, void *stream)
+{
     hipStream_t s = as_stream(stream);
 
     // a graph per workspace, rebuilt when the stacks or their launch shapes change

@@ -81,8 +81,9 @@ def _declare(L: ctypes.CDLL) -> None:
     L.oracle_shift.argtypes = [P, P, I32, I32, I32, P, P]
     L.oracle_combine.argtypes = [P, I32, I32, I32, D, I32, P, P, P, P, D]
     L.oracle_downsample4.argtypes = [P, I32, I32, P]
+    L.oracle_cnn_input.argtypes = [P, I32, I32, P]
     for name in ("oracle_calibrate", "oracle_register", "oracle_valid_rect", "oracle_shift",
-                 "oracle_combine", "oracle_downsample4"):
+                 "oracle_combine", "oracle_downsample4", "oracle_cnn_input"):
         getattr(L, name).restype = ctypes.c_int
     if hasattr(L, "oracle_cnn_forward"):
         L.oracle_bf16_round.argtypes = [P, P, I64]
@@ -200,6 +201,92 @@ def downsample4(img: np.ndarray) -> np.ndarray:
     out = np.empty((H // 4, W // 4), dtype=np.float64)
     _check(lib().oracle_downsample4(_p(img), W, H, _p(out)), "oracle_downsample4")
     return out
+
+
+def cnn_input(img: np.ndarray) -> np.ndarray:
+    """Block mean, standardisation, asinh, bfloat16 rounding (float64 [H/4][W/4])."""
+    img = _f64(img)
+    H, W = img.shape
+    out = np.empty((H // 4, W // 4), dtype=np.float64)
+    _check(lib().oracle_cnn_input(_p(img), W, H, _p(out)), "oracle_cnn_input")
+    return out
+
+
+def bf16_round(x) -> np.ndarray:
+    x = _f64(x)
+    out = np.empty_like(x)
+    _check(lib().oracle_bf16_round(_p(x), _p(out), x.size), "oracle_bf16_round")
+    return out
+
+
+CNN_CH = 32
+CNN_CIN = (2, 32, 32, 32)
+
+
+def cnn_num_params() -> int:
+    return int(lib().oracle_cnn_num_params())
+
+
+def cnn_split(params: np.ndarray) -> dict:
+    """Views of the flat parameter vector: w1..w4 [9][cin][32], b1..b4, wl [2][32], bl [2]."""
+    out, o = {}, 0
+    for i, cin in enumerate(CNN_CIN):
+        n = 9 * cin * CNN_CH
+        out[f"w{i + 1}"] = params[o:o + n].reshape(9, cin, CNN_CH)
+        o += n
+        out[f"b{i + 1}"] = params[o:o + CNN_CH]
+        o += CNN_CH
+    out["wl"] = params[o:o + 2 * CNN_CH].reshape(2, CNN_CH)
+    o += 2 * CNN_CH
+    out["bl"] = params[o:o + 2]
+    return out
+
+
+def conv_forward(x: np.ndarray, w: np.ndarray, b: np.ndarray, relu: bool = True) -> np.ndarray:
+    """x [B][H][W][Cin], w [9][Cin][Cout] -> [B][ceil(H/2)][ceil(W/2)][Cout]."""
+    x, w, b = _f64(x), _f64(w), _f64(b)
+    B, H, W, Cin = x.shape
+    Cout = w.shape[2]
+    y = np.empty((B, (H + 1) // 2, (W + 1) // 2, Cout))
+    _check(lib().oracle_conv3x3s2_forward(_p(x), B, Cin, H, W, _p(w), _p(b), Cout, 1 if relu else 0, _p(y)),
+           "oracle_conv3x3s2_forward")
+    return y
+
+
+def conv_backward(x: np.ndarray, w: np.ndarray, dz: np.ndarray, want_dx: bool = True):
+    """Returns (dx or None, dw [9][Cin][Cout], db [Cout]) for dz = dLoss/dZ."""
+    x, w, dz = _f64(x), _f64(w), _f64(dz)
+    B, H, W, Cin = x.shape
+    Cout = w.shape[2]
+    dx = np.empty_like(x) if want_dx else None
+    dw = np.empty_like(w)
+    db = np.empty(Cout)
+    _check(lib().oracle_conv3x3s2_backward(_p(x), B, Cin, H, W, _p(w), Cout, None, 1, _p(dz), _p(dx), _p(dw),
+                                           _p(db)), "oracle_conv3x3s2_backward")
+    return dx, dw, db
+
+
+def cnn_forward(x: np.ndarray, params: np.ndarray, bf16: bool = True, want_acts: bool = False):
+    """x [B][H][W][2] -> pred [B][2] (and the stored activations X1..X4 + pool, flat)."""
+    x, params = _f64(x), _f64(params)
+    B, H, W, _ = x.shape
+    pred = np.empty((B, 2))
+    acts = np.empty(int(lib().oracle_cnn_act_size(B, H, W))) if want_acts else None
+    _check(lib().oracle_cnn_forward(_p(x), B, H, W, _p(params), 1 if bf16 else 0, _p(pred), _p(acts)),
+           "oracle_cnn_forward")
+    return (pred, acts) if want_acts else pred
+
+
+def cnn_loss_backward(x: np.ndarray, params: np.ndarray, target: np.ndarray, huber_delta: float = 1.0,
+                      bf16: bool = True):
+    """(loss, grad of the flat parameters)."""
+    x, params, target = _f64(x), _f64(params), _f64(target)
+    B, H, W, _ = x.shape
+    loss = np.zeros(1)
+    grad = np.empty_like(params)
+    _check(lib().oracle_cnn_loss_backward(_p(x), B, H, W, _p(params), 1 if bf16 else 0, _p(target),
+                                          float(huber_delta), _p(loss), _p(grad)), "oracle_cnn_loss_backward")
+    return float(loss[0]), grad
 
 
 def reduce_stack(raw: np.ndarray, dark: np.ndarray, flat: np.ndarray, radius: int,

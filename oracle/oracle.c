@@ -324,3 +324,35 @@ int oracle_downsample4(const double *in, int32_t W, int32_t H, double *out)
         }
     return O_OK;
 }
+
+/* ------------------------------------------------------------------------------
+ * Input of the offset-proposal network: block mean, standardisation by the mean and
+ * population standard deviation of the block-mean image, asinh to compress the
+ * bright stars, and the bfloat16 rounding of the stored input (via float, ties to
+ * even).
+ * ---------------------------------------------------------------------------- */
+static double to_bf16(double x)
+{
+    float f = (float)x;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (double)f;
+    u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+int oracle_cnn_input(const double *in, int32_t W, int32_t H, double *out)
+{
+    int rc = oracle_downsample4(in, W, H, out);
+    if (rc) return rc;
+    const int64_t n = (int64_t)(W / 4) * (H / 4);
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += out[i];
+    const double mean = s / (double)n;
+    double q = 0.0;
+    for (int64_t i = 0; i < n; ++i) q += (out[i] - mean) * (out[i] - mean);
+    const double sd = sqrt(q / (double)n);
+    for (int64_t i = 0; i < n; ++i) out[i] = to_bf16(asinh(sd > 0.0 ? (out[i] - mean) / sd : 0.0));
+    return O_OK;
+}

@@ -71,6 +71,26 @@ int oracle_combine(const double *aligned, int32_t w, int32_t h, int32_t N, doubl
 /* 4x4 block mean: out[j][i] = mean of in[4j..4j+3][4i..4i+3]. */
 int oracle_downsample4(const double *in, int32_t W, int32_t H, double *out);
 
+/* Network input of one frame: 4x4 block mean, then asinh((x - mean) / std) with the
+ * mean and population standard deviation of the block-mean image, rounded to
+ * bfloat16 (via float, ties to even).  out is [H/4][W/4]. */
+int oracle_cnn_input(const double *in, int32_t W, int32_t H, double *out);
+
+/* ---- offset-proposal network (oracle_cnn.c) ---- */
+int oracle_bf16_round(const double *in, double *out, int64_t n);
+int oracle_conv3x3s2_forward(const double *x, int32_t B, int32_t Cin, int32_t H, int32_t W, const double *w,
+                             const double *bias, int32_t Cout, int32_t relu, double *y);
+int oracle_conv3x3s2_backward(const double *x, int32_t B, int32_t Cin, int32_t H, int32_t W, const double *w,
+                              int32_t Cout, const double *y, int32_t relu, const double *dz, double *dx,
+                              double *dw, double *db);
+int64_t oracle_cnn_num_params(void);
+int64_t oracle_cnn_act_size(int32_t B, int32_t H, int32_t W);
+int oracle_cnn_forward(const double *x, int32_t B, int32_t H, int32_t W, const double *params, int32_t bf16,
+                       double *pred, double *acts);
+int oracle_cnn_loss_backward(const double *x, int32_t B, int32_t H, int32_t W, const double *params,
+                             int32_t bf16, const double *target, double huber_delta, double *loss,
+                             double *grad);
+
 #ifdef __cplusplus
 }
 #endif

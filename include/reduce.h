@@ -192,6 +192,38 @@ typedef struct {
 size_t reduce_stack_batch_ws(const reduce_stack_t *stacks, int32_t n);
 int reduce_stack_batch(const reduce_stack_t *stacks, int32_t n, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- offset-proposal network --------------------------------------------------
+ * A small CNN proposes each frame's offset from 4x-downsampled frames, so that the
+ * brute-force search can be narrowed to a +-2 px window around the proposal.
+ *
+ * reduce_cnn_input: network input of N calibrated frames: the 4x4 block mean (in
+ *   double), standardised by the mean and population standard deviation of the
+ *   block-mean image, asinh, rounded to bfloat16 (ties to even).  frames: device
+ *   float [N][H][W] (W, H multiples of 4); out: device bfloat16 bits [N][H/4][W/4];
+ *   ws: reduce_cnn_input_ws(W, H, N) bytes.
+ *
+ * Network: four 3x3 convolutions with stride 2 and zero padding 1 (2 -> 32 -> 32 ->
+ * 32 -> 32 channels) with ReLU, the mean over pixels, a linear layer 32 -> 2 giving
+ * (dx, dy) in downsampled pixels.  Input channel 0 is the reference, channel 1 the
+ * frame.  params: device float, reduce_cnn_num_params() values in the order W1 b1 W2
+ * b2 W3 b3 W4 b4 Wl bl with conv weights W[t][cin][cout], t = 3 ky + kx, Wl[2][32].
+ * The convolutions run on bfloat16 matrix cores with FP32 accumulation; weights and
+ * activations are stored in bfloat16.
+ *
+ * reduce_cnn_forward: ref device bfloat16 [h][w] per batch item at ref + b *
+ *   ref_stride (ref_stride 0: one reference for all), img device bfloat16 [B][h][w];
+ *   pred device float [B][2].  ws (reduce_cnn_ws(B, h, w) bytes) keeps the
+ *   activations for reduce_cnn_backward.  reduce_cnn_ws_offsets gives the byte
+ *   offsets of the four activations [B][h_l][w_l][32] inside ws. */
+size_t reduce_cnn_input_ws(int32_t W, int32_t H, int32_t N);
+int reduce_cnn_input(const float *frames, int32_t W, int32_t H, int32_t N, uint16_t *out, void *ws,
+                     size_t ws_bytes, void *stream);
+int64_t reduce_cnn_num_params(void);
+size_t reduce_cnn_ws(int32_t B, int32_t h, int32_t w);
+int reduce_cnn_ws_offsets(int32_t B, int32_t h, int32_t w, int64_t *offsets);
+int reduce_cnn_forward(const uint16_t *ref, int64_t ref_stride, const uint16_t *img, int32_t B, int32_t h,
+                       int32_t w, const float *params, float *pred, void *ws, size_t ws_bytes, void *stream);
+
 /* ---- autotuner --------------------------------------------------------------
  * Launch shapes (tiles, workgroup sizes, lanes per pixel) are chosen per problem
  * size by timing candidates on the caller's data with HIP events; the winner is

@@ -78,6 +78,16 @@ def _declare(L):
     L.reduce_stack_batch_ws.restype = SZ
     L.reduce_stack_batch.argtypes = [P, I32, P, SZ, P]
     L.reduce_stack_batch.restype = ctypes.c_int
+    L.reduce_cnn_input_ws.argtypes = [I32, I32, I32]
+    L.reduce_cnn_input_ws.restype = SZ
+    L.reduce_cnn_input.argtypes = [P, I32, I32, I32, P, P, SZ, P]
+    L.reduce_cnn_num_params.restype = I64
+    L.reduce_cnn_ws.argtypes = [I32, I32, I32]
+    L.reduce_cnn_ws.restype = SZ
+    L.reduce_cnn_ws_offsets.argtypes = [I32, I32, I32, P]
+    L.reduce_cnn_forward.argtypes = [P, I64, P, I32, I32, I32, P, P, P, SZ, P]
+    for n in ("reduce_cnn_input", "reduce_cnn_ws_offsets", "reduce_cnn_forward"):
+        getattr(L, n).restype = ctypes.c_int
     L.reduce_prof_enable.argtypes = [ctypes.c_int]
     L.reduce_prof_query.argtypes = [ctypes.c_char_p, P, P]
     for n in ("reduce_calibrate", "reduce_register", "reduce_valid_rect", "reduce_shift", "reduce_combine",
@@ -98,7 +108,9 @@ def exported_symbols() -> Sequence[str]:
             "reduce_register_ws", "reduce_register", "reduce_valid_rect", "reduce_shift",
             "reduce_combine", "reduce_prof_enable", "reduce_prof_query", "reduce_register_plan",
             "reduce_tune_register", "reduce_tune_combine", "reduce_tune_save", "reduce_tune_load",
-            "reduce_tune_clear", "reduce_stack_batch_ws", "reduce_stack_batch")
+            "reduce_tune_clear", "reduce_stack_batch_ws", "reduce_stack_batch",
+            "reduce_cnn_input_ws", "reduce_cnn_input", "reduce_cnn_num_params", "reduce_cnn_ws",
+            "reduce_cnn_ws_offsets", "reduce_cnn_forward")
 
 
 def _check(rc: int) -> None:
@@ -349,3 +361,62 @@ class StackBatch:
         rect = it["rect"].cpu().numpy()
         h, w = int(rect[3]), int(rect[2])
         return it["out"][: h * w].view(h, w), rect, offsets_to_numpy(it["offsets"]), int(it["n_rej"].cpu()[0])
+
+
+# ---------------------------------------------------------------------------- proposal network
+def cnn_num_params() -> int:
+    return int(lib().reduce_cnn_num_params())
+
+
+def cnn_input(frames: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """frames float32 [N][H][W] -> bfloat16 bits as int16 [N][H/4][W/4]."""
+    _dev(frames, "frames")
+    if frames.dim() == 2:
+        frames = frames.unsqueeze(0)
+    N, H, W = frames.shape
+    ws = torch.empty(max(int(lib().reduce_cnn_input_ws(W, H, N)), 1), dtype=torch.uint8, device=frames.device)
+    if out is None:
+        out = torch.empty((N, H // 4, W // 4), dtype=torch.int16, device=frames.device)
+    _check(lib().reduce_cnn_input(_ptr(frames.contiguous()), W, H, N, _ptr(out), _ptr(ws), ws.numel(),
+                                  _stream(stream)))
+    return out
+
+
+def bf16_bits_to_float(t: torch.Tensor) -> torch.Tensor:
+    """int16 tensor of bfloat16 bits -> float32 (a view change, no arithmetic)."""
+    return t.contiguous().view(torch.bfloat16).float()
+
+
+class CnnWorkspace:
+    """Device workspace of the network for a batch shape (activations, gradients)."""
+
+    def __init__(self, B: int, h: int, w: int, device="cuda:0"):
+        self.B, self.h, self.w = B, h, w
+        n = int(lib().reduce_cnn_ws(B, h, w))
+        if n == 0:
+            raise ReduceError(ERR_SHAPE, "bad network shape")
+        self.buf = torch.empty(n, dtype=torch.uint8, device=device)
+        off = (ctypes.c_int64 * 4)()
+        _check(lib().reduce_cnn_ws_offsets(B, h, w, off))
+        self.offsets = list(off)
+
+    def activation(self, layer: int) -> torch.Tensor:
+        """bfloat16 bits (int16) [B][h_l][w_l][32] of layer 1..4 after the last forward."""
+        hl, wl = self.h, self.w
+        for _ in range(layer):
+            hl, wl = (hl + 1) // 2, (wl + 1) // 2
+        n = self.B * hl * wl * 32
+        o = self.offsets[layer - 1]
+        return self.buf[o:o + 2 * n].view(torch.int16).view(self.B, hl, wl, 32)
+
+
+def cnn_forward(ref_in: torch.Tensor, img_in: torch.Tensor, params: torch.Tensor, cws: CnnWorkspace,
+                ref_shared: bool = True, pred: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """ref_in int16 [h][w] (shared) or [B][h][w]; img_in int16 [B][h][w]; params float32 -> pred [B][2]."""
+    B, h, w = img_in.shape
+    if pred is None:
+        pred = torch.empty((B, 2), dtype=torch.float32, device=img_in.device)
+    stride = 0 if ref_shared else h * w
+    _check(lib().reduce_cnn_forward(_ptr(ref_in), stride, _ptr(img_in), B, h, w, _ptr(params), _ptr(pred),
+                                    _ptr(cws.buf), cws.buf.numel(), _stream(stream)))
+    return pred

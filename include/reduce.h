@@ -213,8 +213,10 @@ int reduce_stack_batch(const reduce_stack_t *stacks, int32_t n, void *ws, size_t
  * reduce_cnn_forward: ref device bfloat16 [h][w] per batch item at ref + b *
  *   ref_stride (ref_stride 0: one reference for all), img device bfloat16 [B][h][w];
  *   pred device float [B][2].  ws (reduce_cnn_ws(B, h, w) bytes) keeps the
- *   activations for reduce_cnn_backward.  reduce_cnn_ws_offsets gives the byte
- *   offsets of the four activations [B][h_l][w_l][32] inside ws. */
+ *   activations for reduce_cnn_backward.  reduce_cnn_ws_offsets fills offsets[6]
+ *   with byte offsets inside ws: [0..3] the four activations [B][h_l][w_l][32]
+ *   (h_l = ceil(h / 2^l)); [4] and [5] two bfloat16 gradient planes that, after
+ *   reduce_cnn_backward, hold dLoss/dZ of layer 2 and of layer 1 respectively. */
 size_t reduce_cnn_input_ws(int32_t W, int32_t H, int32_t N);
 int reduce_cnn_input(const float *frames, int32_t W, int32_t H, int32_t N, uint16_t *out, void *ws,
                      size_t ws_bytes, void *stream);
@@ -223,6 +225,21 @@ size_t reduce_cnn_ws(int32_t B, int32_t h, int32_t w);
 int reduce_cnn_ws_offsets(int32_t B, int32_t h, int32_t w, int64_t *offsets);
 int reduce_cnn_forward(const uint16_t *ref, int64_t ref_stride, const uint16_t *img, int32_t B, int32_t h,
                        int32_t w, const float *params, float *pred, void *ws, size_t ws_bytes, void *stream);
+
+/* reduce_cnn_backward: loss and gradient of the Huber loss (threshold huber_delta) of
+ *   pred - target, averaged over the B x 2 components, with respect to params.  Needs
+ *   the activations the immediately preceding reduce_cnn_forward left in ws for the
+ *   same inputs and params.  target device float [B][2]; loss device float [1]; grad
+ *   device float [reduce_cnn_num_params()].  Gradients with respect to conv
+ *   pre-activations are stored in bfloat16; weight gradients accumulate in FP32 and
+ *   are summed over fixed pixel chunks in order.  B <= 1024.
+ * reduce_cnn_adamw: one AdamW step (decoupled weight decay, bias-corrected moments)
+ *   on n FP32 parameters with moments m, v, at 1-based step `step`. */
+int reduce_cnn_backward(const uint16_t *ref, int64_t ref_stride, const uint16_t *img, int32_t B, int32_t h,
+                        int32_t w, const float *params, const float *pred, const float *target,
+                        float huber_delta, float *loss, float *grad, void *ws, size_t ws_bytes, void *stream);
+int reduce_cnn_adamw(float *params, float *m, float *v, const float *grad, int64_t n, float lr, float beta1,
+                     float beta2, float eps, float weight_decay, int32_t step, void *stream);
 
 /* ---- autotuner --------------------------------------------------------------
  * Launch shapes (tiles, workgroup sizes, lanes per pixel) are chosen per problem

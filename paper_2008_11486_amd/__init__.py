@@ -86,7 +86,10 @@ def _declare(L):
     L.reduce_cnn_ws.restype = SZ
     L.reduce_cnn_ws_offsets.argtypes = [I32, I32, I32, P]
     L.reduce_cnn_forward.argtypes = [P, I64, P, I32, I32, I32, P, P, P, SZ, P]
-    for n in ("reduce_cnn_input", "reduce_cnn_ws_offsets", "reduce_cnn_forward"):
+    L.reduce_cnn_backward.argtypes = [P, I64, P, I32, I32, I32, P, P, P, F, P, P, P, SZ, P]
+    L.reduce_cnn_adamw.argtypes = [P, P, P, P, I64, F, F, F, F, F, I32, P]
+    for n in ("reduce_cnn_input", "reduce_cnn_ws_offsets", "reduce_cnn_forward", "reduce_cnn_backward",
+              "reduce_cnn_adamw"):
         getattr(L, n).restype = ctypes.c_int
     L.reduce_prof_enable.argtypes = [ctypes.c_int]
     L.reduce_prof_query.argtypes = [ctypes.c_char_p, P, P]
@@ -110,7 +113,7 @@ def exported_symbols() -> Sequence[str]:
             "reduce_tune_register", "reduce_tune_combine", "reduce_tune_save", "reduce_tune_load",
             "reduce_tune_clear", "reduce_stack_batch_ws", "reduce_stack_batch",
             "reduce_cnn_input_ws", "reduce_cnn_input", "reduce_cnn_num_params", "reduce_cnn_ws",
-            "reduce_cnn_ws_offsets", "reduce_cnn_forward")
+            "reduce_cnn_ws_offsets", "reduce_cnn_forward", "reduce_cnn_backward", "reduce_cnn_adamw")
 
 
 def _check(rc: int) -> None:
@@ -396,7 +399,7 @@ class CnnWorkspace:
         if n == 0:
             raise ReduceError(ERR_SHAPE, "bad network shape")
         self.buf = torch.empty(n, dtype=torch.uint8, device=device)
-        off = (ctypes.c_int64 * 4)()
+        off = (ctypes.c_int64 * 6)()
         _check(lib().reduce_cnn_ws_offsets(B, h, w, off))
         self.offsets = list(off)
 
@@ -409,6 +412,15 @@ class CnnWorkspace:
         o = self.offsets[layer - 1]
         return self.buf[o:o + 2 * n].view(torch.int16).view(self.B, hl, wl, 32)
 
+    def grad_z(self, layer: int) -> torch.Tensor:
+        """bfloat16 bits of dLoss/dZ of layer 1 or 2 after the last backward."""
+        if layer not in (1, 2):
+            raise ValueError("only the gradients of layers 1 and 2 stay in the workspace")
+        shape = self.activation(layer).shape
+        n = shape[0] * shape[1] * shape[2] * 32
+        o = self.offsets[5 if layer == 1 else 4]
+        return self.buf[o:o + 2 * n].view(torch.int16).view(shape)
+
 
 def cnn_forward(ref_in: torch.Tensor, img_in: torch.Tensor, params: torch.Tensor, cws: CnnWorkspace,
                 ref_shared: bool = True, pred: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
@@ -420,3 +432,25 @@ def cnn_forward(ref_in: torch.Tensor, img_in: torch.Tensor, params: torch.Tensor
     _check(lib().reduce_cnn_forward(_ptr(ref_in), stride, _ptr(img_in), B, h, w, _ptr(params), _ptr(pred),
                                     _ptr(cws.buf), cws.buf.numel(), _stream(stream)))
     return pred
+
+
+def cnn_backward(ref_in: torch.Tensor, img_in: torch.Tensor, params: torch.Tensor, pred: torch.Tensor,
+                 target: torch.Tensor, cws: CnnWorkspace, huber_delta: float = 1.0, ref_shared: bool = True,
+                 grad: Optional[torch.Tensor] = None, loss: Optional[torch.Tensor] = None, stream=None):
+    """(loss [1], grad [n]) after cnn_forward on the same inputs; all device float32."""
+    B, h, w = img_in.shape
+    if grad is None:
+        grad = torch.empty_like(params)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=params.device)
+    stride = 0 if ref_shared else h * w
+    _check(lib().reduce_cnn_backward(_ptr(ref_in), stride, _ptr(img_in), B, h, w, _ptr(params), _ptr(pred),
+                                     _ptr(target), float(huber_delta), _ptr(loss), _ptr(grad), _ptr(cws.buf),
+                                     cws.buf.numel(), _stream(stream)))
+    return loss, grad
+
+
+def cnn_adamw(params, m, v, grad, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0, stream=None):
+    _check(lib().reduce_cnn_adamw(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), params.numel(), float(lr),
+                                  float(beta1), float(beta2), float(eps), float(weight_decay), int(step),
+                                  _stream(stream)))

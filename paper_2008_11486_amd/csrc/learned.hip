@@ -13,6 +13,7 @@
 // channels, or all 18 (tap, channel) pairs of the 2-channel input layer).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <string>
 
@@ -168,7 +169,7 @@ __global__ __launch_bounds__(256) void conv_fwd(const uint16_t *__restrict__ x, 
                                                 int32_t W, const uint16_t *__restrict__ wf,
                                                 const float *__restrict__ bias, uint16_t *__restrict__ y)
 {
-    __shared__ uint16_t tile[4][16 * CNN_CH];
+    __shared__ __align__(16) uint16_t tile[4][16 * CNN_CH];
     const int32_t Ho = (H + 1) / 2, Wo = (W + 1) / 2;
     const int32_t b = blockIdx.z, oy = blockIdx.y;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -259,6 +260,264 @@ __global__ __launch_bounds__(256) void pool_head(const uint16_t *__restrict__ x4
     }
 }
 
+// ---- loss and head backward ------------------------------------------------------------------
+// One workgroup: Huber loss, head gradients (double sums over the batch in order) and
+// the gradient with respect to the pooled features.
+__global__ __launch_bounds__(256) void head_backward(const float *__restrict__ pred, const float *__restrict__ target,
+                                                     int32_t B, double delta, const double *__restrict__ pool,
+                                                     const float *__restrict__ params, float *__restrict__ loss,
+                                                     float *__restrict__ grad, double *__restrict__ dpool)
+{
+    __shared__ double dpred[2 * 1024];
+    __shared__ double lpart[256];
+    const float *wl = params + cnn_head_offset();
+    double l = 0.0;
+    for (int32_t i = threadIdx.x; i < 2 * B; i += 256) {
+        const double e = (double)pred[i] - (double)target[i];
+        const double ae = fabs(e);
+        l += ae <= delta ? 0.5 * e * e : delta * (ae - 0.5 * delta);
+        dpred[i] = (ae <= delta ? e : (e > 0 ? delta : -delta)) / (2.0 * B);
+    }
+    lpart[threadIdx.x] = l;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < 256; ++i) t += lpart[i];
+        *loss = (float)(t / (2.0 * B));
+    }
+    float *gh = grad + cnn_head_offset();
+    if (threadIdx.x < 2 * CNN_CH) {  // dWl[j][c]
+        const int j = threadIdx.x / CNN_CH, c = threadIdx.x % CNN_CH;
+        double sacc = 0.0;
+        for (int32_t b = 0; b < B; ++b) sacc += dpred[2 * b + j] * pool[b * CNN_CH + c];
+        gh[j * CNN_CH + c] = (float)sacc;
+    } else if (threadIdx.x < 2 * CNN_CH + 2) {  // dbl[j]
+        const int j = threadIdx.x - 2 * CNN_CH;
+        double sacc = 0.0;
+        for (int32_t b = 0; b < B; ++b) sacc += dpred[2 * b + j];
+        gh[2 * CNN_CH + j] = (float)sacc;
+    }
+    for (int32_t i = threadIdx.x; i < B * CNN_CH; i += 256) {
+        const int32_t b = i / CNN_CH, c = i % CNN_CH;
+        dpool[i] = dpred[2 * b] * (double)wl[c] + dpred[2 * b + 1] * (double)wl[CNN_CH + c];
+    }
+}
+
+// Gradient of the last pre-activation: the pool's 1/P spread, masked by ReLU.
+__global__ void pool_backward(const uint16_t *__restrict__ x4, int64_t P, int32_t B,
+                              const double *__restrict__ dpool, uint16_t *__restrict__ dz)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)B * P * CNN_CH) return;
+    const int32_t c = (int32_t)(i % CNN_CH);
+    const int32_t b = (int32_t)(i / (P * CNN_CH));
+    const double g = bf2f(x4[i]) > 0.0f ? dpool[b * CNN_CH + c] / (double)P : 0.0;
+    dz[i] = f2bf((float)g);
+}
+
+// ---- weight gradient ---------------------------------------------------------------------------
+// dW[t][ci][co] = sum over output pixels of X[input pixel of tap t][ci] * dZ[pixel][co],
+// as D[co][n] with K = 32 output pixels per step.  For the 2-channel input layer n =
+// 2 t + ci (18 columns); otherwise n = ci for each of the 9 taps.  A chunk of pixel
+// blocks per workgroup writes one partial; wgrad_reduce sums the partials in order.
+template <int CIN>
+__global__ __launch_bounds__(256) void wgrad(const uint16_t *__restrict__ x, const uint16_t *__restrict__ ref,
+                                             int64_t ref_stride, const uint16_t *__restrict__ img, int32_t B,
+                                             int32_t H, int32_t W, const uint16_t *__restrict__ dz,
+                                             float *__restrict__ wpart, float *__restrict__ bpart)
+{
+    constexpr int TAPS = CIN == 2 ? 1 : 9;  // column groups of 32
+    __shared__ uint16_t zt[32][CNN_CH + 2];      // [pixel][co]
+    __shared__ uint16_t xt[TAPS][32][32 + 2];    // [group][pixel][n]
+    const int32_t Ho = (H + 1) / 2, Wo = (W + 1) / 2;
+    const int64_t P = (int64_t)B * Ho * Wo;
+    const int64_t nblk = (P + 31) / 32;
+    const int64_t per = (nblk + gridDim.x - 1) / gridDim.x;
+    const int64_t blk0 = (int64_t)blockIdx.x * per, blk1 = min(blk0 + per, nblk);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int mt = wave & 1, nt = wave >> 1;  // co tile, column tile
+    f32x4 acc[TAPS];
+#pragma unroll
+    for (int t = 0; t < TAPS; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.0f;
+
+    for (int64_t blk = blk0; blk < blk1; ++blk) {
+        __syncthreads();
+        // dZ tile: 32 pixels x 32 channels
+        for (int e = threadIdx.x; e < 32 * CNN_CH; e += 256) {
+            const int pp = e / CNN_CH, c = e % CNN_CH;
+            const int64_t p = blk * 32 + pp;
+            zt[pp][c] = p < P ? dz[p * CNN_CH + c] : (uint16_t)0;
+        }
+        // input tiles
+        for (int e = threadIdx.x; e < TAPS * 32 * 32; e += 256) {
+            const int g = e / 1024, pp = (e / 32) % 32, n = e % 32;
+            const int64_t p = blk * 32 + pp;
+            uint16_t v = 0;
+            if (p < P) {
+                const int32_t b = (int32_t)(p / ((int64_t)Ho * Wo));
+                const int32_t r = (int32_t)(p % ((int64_t)Ho * Wo));
+                const int32_t oy = r / Wo, ox = r % Wo;
+                int t, ci;
+                if (CIN == 2) {
+                    t = n >> 1;
+                    ci = n & 1;
+                } else {
+                    t = g;
+                    ci = n;
+                }
+                if (t < 9) {
+                    const int32_t iy = 2 * oy + t / 3 - 1, ix = 2 * ox + t % 3 - 1;
+                    if (iy >= 0 && iy < H && ix >= 0 && ix < W) {
+                        if (CIN == 2) {
+                            const int64_t q = (int64_t)iy * W + ix;
+                            v = ci == 0 ? ref[(int64_t)b * ref_stride + q] : img[(int64_t)b * H * W + q];
+                        } else {
+                            v = x[(((int64_t)b * H + iy) * W + ix) * CNN_CH + ci];
+                        }
+                    }
+                }
+            }
+            xt[g][pp][n] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < CNN_CH) {
+            const int c = threadIdx.x;
+            for (int pp = 0; pp < 32; ++pp) bsum += bf2f(zt[pp][c]);
+        }
+        // A[m = co][k = pixel], B[k = pixel][n]
+        const int m = lane & 15, kg = lane >> 4;
+        uint16_t ae[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) ae[j] = zt[kg * 8 + j][mt * 16 + m];
+        const uint4 apk = make_uint4(ae[0] | ((uint32_t)ae[1] << 16), ae[2] | ((uint32_t)ae[3] << 16),
+                                     ae[4] | ((uint32_t)ae[5] << 16), ae[6] | ((uint32_t)ae[7] << 16));
+        const bf16x8 a = __builtin_bit_cast(bf16x8, apk);
+#pragma unroll
+        for (int g = 0; g < TAPS; ++g) {
+            uint16_t be[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) be[j] = xt[g][kg * 8 + j][nt * 16 + m];
+            const uint4 bpk = make_uint4(be[0] | ((uint32_t)be[1] << 16), be[2] | ((uint32_t)be[3] << 16),
+                                         be[4] | ((uint32_t)be[5] << 16), be[6] | ((uint32_t)be[7] << 16));
+            acc[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, bpk), acc[g], 0, 0, 0);
+        }
+    }
+    // D[co = 16 mt + 4 kg + j][n = 16 nt + m]
+    const int m = lane & 15, kg = lane >> 4;
+    float *wp = wpart + (int64_t)blockIdx.x * 9 * CNN_CH * CNN_CH;
+#pragma unroll
+    for (int g = 0; g < TAPS; ++g)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int co = mt * 16 + kg * 4 + j, n = nt * 16 + m;
+            int t, ci;
+            if (CIN == 2) {
+                t = n >> 1;
+                ci = n & 1;
+                if (n >= 18) continue;
+            } else {
+                t = g;
+                ci = n;
+            }
+            wp[((int64_t)t * CIN + ci) * CNN_CH + co] = acc[g][j];
+        }
+    if (threadIdx.x < CNN_CH) bpart[(int64_t)blockIdx.x * CNN_CH + threadIdx.x] = bsum;
+}
+
+// Sum the chunk partials in chunk order: n_w weight and CNN_CH bias entries.
+__global__ void wgrad_reduce(const float *__restrict__ wpart, const float *__restrict__ bpart, int32_t chunks,
+                             int32_t n_w, float *__restrict__ gw, float *__restrict__ gb)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_w) {
+        float s = 0.0f;
+        for (int32_t c = 0; c < chunks; ++c) s += wpart[(int64_t)c * 9 * CNN_CH * CNN_CH + i];
+        gw[i] = s;
+    } else if (i < n_w + CNN_CH) {
+        const int32_t co = i - n_w;
+        float s = 0.0f;
+        for (int32_t c = 0; c < chunks; ++c) s += bpart[(int64_t)c * CNN_CH + co];
+        gb[co] = s;
+    }
+}
+
+// ---- data gradient -------------------------------------------------------------------------------
+// dX[iy][ix][ci] = sum over the taps whose output pixel exists of dZ[oy][ox][co] W[t][ci][co];
+// the result times the ReLU mask of X is the previous layer's dZ.  A wave takes 16 input
+// pixels of one row with the same x parity (ix = 2 j + px), so all 16 share the valid
+// taps: one ky for even iy, two for odd; likewise kx.
+__global__ __launch_bounds__(256) void dgrad(const uint16_t *__restrict__ dz, const uint16_t *__restrict__ wd,
+                                             const uint16_t *__restrict__ xin, int32_t H, int32_t W,
+                                             uint16_t *__restrict__ dzin)
+{
+    __shared__ __align__(16) uint16_t tile[4][16 * CNN_CH];
+    const int32_t Ho = (H + 1) / 2, Wo = (W + 1) / 2;
+    const int32_t b = blockIdx.z;
+    const int32_t iy = blockIdx.y >> 1, px = blockIdx.y & 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int32_t j0 = (blockIdx.x * 4 + wave) * 16;
+    const int m = lane & 15, kg = lane >> 4;
+    const int32_t jm = j0 + m, ixm = 2 * jm + px;
+
+    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    for (int ky = 0; ky < 3; ++ky) {
+        const int32_t ny = iy + 1 - ky;
+        if (ny < 0 || (ny & 1)) continue;
+        const int32_t oy = ny >> 1;
+        if (oy >= Ho) continue;
+        for (int kx = 0; kx < 3; ++kx) {
+            if ((px + 1 - kx) & 1) continue;
+            const int t = 3 * ky + kx;
+            const int32_t nx = ixm + 1 - kx;  // even by the parity of the tile
+            bf16x8 a = zero8();
+            if (ixm < W && nx >= 0 && (nx >> 1) < Wo)
+                a = load8(dz + (((int64_t)b * Ho + oy) * Wo + (nx >> 1)) * CNN_CH + kg * 8);
+            const bf16x8 b0 = load8(wd + ((int64_t)t * CNN_CH + m) * CNN_CH + kg * 8);
+            const bf16x8 b1 = load8(wd + ((int64_t)t * CNN_CH + 16 + m) * CNN_CH + kg * 8);
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b1, acc1, 0, 0, 0);
+        }
+    }
+    // lane holds pixels 4 kg + j, input channel m (and 16 + m)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int pp = 4 * kg + j;
+        const int32_t ix = 2 * (j0 + pp) + px;
+        float g0 = 0.0f, g1 = 0.0f;
+        if (ix < W) {
+            const uint16_t *xp = xin + (((int64_t)b * H + iy) * W + ix) * CNN_CH;
+            g0 = bf2f(xp[m]) > 0.0f ? acc0[j] : 0.0f;
+            g1 = bf2f(xp[16 + m]) > 0.0f ? acc1[j] : 0.0f;
+        }
+        tile[wave][pp * CNN_CH + m] = f2bf(g0);
+        tile[wave][pp * CNN_CH + 16 + m] = f2bf(g1);
+    }
+    __syncthreads();
+    const int pp = lane >> 2, c8 = (lane & 3) * 8;
+    const int32_t ix = 2 * (j0 + pp) + px;
+    if (ix < W) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(&tile[wave][pp * CNN_CH + c8]);
+        *reinterpret_cast<uint4 *>(dzin + (((int64_t)b * H + iy) * W + ix) * CNN_CH + c8) = v;
+    }
+}
+
+// ---- AdamW on the FP32 master parameters ------------------------------------------------------
+__global__ void adamw(float *__restrict__ p, float *__restrict__ m, float *__restrict__ v,
+                      const float *__restrict__ g, int64_t n, float lr, float beta1, float beta2, float eps, float wd,
+                      float c1, float c2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = beta1 * m[i] + (1.0f - beta1) * gi;
+    const float vi = beta2 * v[i] + (1.0f - beta2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / c1, vh = vi / c2;
+    p[i] = p[i] - lr * (mh / (sqrtf(vh) + eps) + wd * p[i]);
+}
+
 // ---- host side -----------------------------------------------------------------------------------
 static size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -329,6 +588,53 @@ int cnn_forward_launch(const uint16_t *ref, int64_t ref_stride, const uint16_t *
     return check_launch("reduce_cnn_forward");
 }
 
+int cnn_backward_launch(const uint16_t *ref, int64_t ref_stride, const uint16_t *img, int32_t B, int32_t h,
+                        int32_t w, const float *params, const float *pred, const float *target, double delta,
+                        float *loss, float *grad, void *ws, hipStream_t s)
+{
+    const CnnLayout L = cnn_layout(B, h, w);
+    unsigned char *base = static_cast<unsigned char *>(ws);
+    const uint16_t *wd = reinterpret_cast<const uint16_t *>(base + L.wd);
+    double *pool = reinterpret_cast<double *>(base + L.pool);
+    double *dpool = reinterpret_cast<double *>(base + L.dpool);
+    float *wpart = reinterpret_cast<float *>(base + L.wpart);
+    float *bpart = reinterpret_cast<float *>(base + L.bpart);
+    uint16_t *dz[2] = {reinterpret_cast<uint16_t *>(base + L.dz[0]), reinterpret_cast<uint16_t *>(base + L.dz[1])};
+    ProfScope prof("cnn_backward", s);
+    hipLaunchKernelGGL(head_backward, dim3(1), dim3(256), 0, s, pred, target, B, delta, pool, params, loss, grad,
+                       dpool);
+    const int64_t P4 = (int64_t)L.hs[3] * L.ws[3];
+    const uint16_t *x4 = reinterpret_cast<const uint16_t *>(base + L.act[3]);
+    hipLaunchKernelGGL(pool_backward, dim3((unsigned)ceil_div((int64_t)B * P4 * CNN_CH, 256)), dim3(256), 0, s, x4,
+                       P4, B, dpool, dz[0]);
+    int cur = 0;
+    for (int l = 3; l >= 0; --l) {
+        const int32_t hin = l ? L.hs[l - 1] : h, win = l ? L.ws[l - 1] : w;
+        const uint16_t *xin = l ? reinterpret_cast<const uint16_t *>(base + L.act[l - 1]) : nullptr;
+        const int64_t nblk = ceil_div((int64_t)B * L.hs[l] * L.ws[l], 32);
+        const int32_t chunks = (int32_t)std::min<int64_t>(CNN_WGRAD_CHUNKS, nblk);
+        if (l == 0)
+            hipLaunchKernelGGL(wgrad<2>, dim3(chunks), dim3(256), 0, s, nullptr, ref, ref_stride, img, B, hin, win,
+                               dz[cur], wpart, bpart);
+        else
+            hipLaunchKernelGGL(wgrad<32>, dim3(chunks), dim3(256), 0, s, xin, nullptr, 0, nullptr, B, hin, win,
+                               dz[cur], wpart, bpart);
+        const int32_t cin = l == 0 ? 2 : CNN_CH;
+        const int32_t n_w = 9 * cin * CNN_CH;
+        float *gw = grad + cnn_weight_offset(l);
+        hipLaunchKernelGGL(wgrad_reduce, dim3((unsigned)ceil_div(n_w + CNN_CH, 256)), dim3(256), 0, s, wpart, bpart,
+                           chunks, n_w, gw, gw + n_w);
+        if (l > 0) {
+            const int32_t jn = (win + 1) / 2;
+            dim3 grid((unsigned)ceil_div(jn, 64), (unsigned)(2 * hin), (unsigned)B);
+            hipLaunchKernelGGL(dgrad, grid, dim3(256), 0, s, dz[cur], wd + (size_t)(l - 1) * 9 * 1024, xin, hin, win,
+                               dz[cur ^ 1]);
+            cur ^= 1;
+        }
+    }
+    return check_launch("reduce_cnn_backward");
+}
+
 }  // namespace rd
 
 using namespace rd;
@@ -383,6 +689,8 @@ extern "C" int reduce_cnn_ws_offsets(int32_t B, int32_t h, int32_t w, int64_t *o
     if (B < 1 || h < 16 || w < 16) return fail(REDUCE_ERR_SHAPE, "reduce_cnn_ws_offsets: bad sizes");
     const CnnLayout L = cnn_layout(B, h, w);
     for (int l = 0; l < 4; ++l) offsets[l] = (int64_t)L.act[l];
+    offsets[4] = (int64_t)L.dz[0];
+    offsets[5] = (int64_t)L.dz[1];
     return REDUCE_OK;
 }
 
@@ -398,4 +706,35 @@ extern "C" int reduce_cnn_forward(const uint16_t *ref, int64_t ref_stride, const
     if (!ws || ws_bytes < need)
         return fail(REDUCE_ERR_WORKSPACE, "reduce_cnn_forward: workspace needs " + std::to_string(need) + " bytes");
     return cnn_forward_launch(ref, ref_stride, img, B, h, w, params, pred, ws, as_stream(stream));
+}
+
+extern "C" int reduce_cnn_backward(const uint16_t *ref, int64_t ref_stride, const uint16_t *img, int32_t B,
+                                   int32_t h, int32_t w, const float *params, const float *pred, const float *target,
+                                   float huber_delta, float *loss, float *grad, void *ws, size_t ws_bytes,
+                                   void *stream)
+{
+    if (!ref || !img || !params || !pred || !target || !loss || !grad)
+        return fail(REDUCE_ERR_NULL, "reduce_cnn_backward: NULL buffer");
+    if (B < 1 || h < 16 || w < 16) return fail(REDUCE_ERR_SHAPE, "reduce_cnn_backward: B >= 1 and h, w >= 16 needed");
+    if (B > 1024) return fail(REDUCE_ERR_UNSUPPORTED, "reduce_cnn_backward: B above 1024");
+    if (!(huber_delta > 0.0f)) return fail(REDUCE_ERR_RANGE, "reduce_cnn_backward: huber_delta must be > 0");
+    const size_t need = cnn_layout(B, h, w).total;
+    if (!ws || ws_bytes < need)
+        return fail(REDUCE_ERR_WORKSPACE, "reduce_cnn_backward: workspace needs " + std::to_string(need) + " bytes");
+    return cnn_backward_launch(ref, ref_stride, img, B, h, w, params, pred, target, (double)huber_delta, loss, grad,
+                               ws, as_stream(stream));
+}
+
+extern "C" int reduce_cnn_adamw(float *params, float *m, float *v, const float *grad, int64_t n, float lr,
+                                float beta1, float beta2, float eps, float weight_decay, int32_t step, void *stream)
+{
+    if (!params || !m || !v || !grad) return fail(REDUCE_ERR_NULL, "reduce_cnn_adamw: NULL buffer");
+    if (n < 1 || step < 1) return fail(REDUCE_ERR_RANGE, "reduce_cnn_adamw: n and step must be >= 1");
+    if (!(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return fail(REDUCE_ERR_RANGE, "reduce_cnn_adamw: bad hyper-parameters");
+    const float c1 = (float)(1.0 - std::pow((double)beta1, (double)step));
+    const float c2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+    hipLaunchKernelGGL(adamw, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, as_stream(stream), params, m, v, grad, n,
+                       lr, beta1, beta2, eps, weight_decay, c1, c2);
+    return check_launch("reduce_cnn_adamw");
 }

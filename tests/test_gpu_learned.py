@@ -84,3 +84,85 @@ def test_network_forward_parity(rd, orc, B, h, w, shared):
     pool = x.reshape(B, -1, 32).mean(axis=1)
     want_pred = pool @ parts["wl"].T + parts["bl"]
     np.testing.assert_allclose(pred, want_pred, rtol=1e-5, atol=1e-5)
+
+
+def _bf16_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to("cuda:0").to(torch.bfloat16) \
+        .view(torch.int16)
+
+
+def _net_case(rd, orc, B, h, w, seed):
+    rng = np.random.default_rng(seed)
+    params = random_params(orc, rng)
+    ref = orc.bf16_round(rng.normal(size=(h, w)))
+    img = orc.bf16_round(rng.normal(size=(B, h, w)))
+    target = rng.normal(size=(B, 2)) * 2.0  # a share beyond the Huber threshold
+    pdev = to_dev(params.astype(np.float32))
+    rdev, idev = _bf16_dev(ref), _bf16_dev(img)
+    cws = rd.CnnWorkspace(B, h, w)
+    pred = rd.cnn_forward(rdev, idev, pdev, cws)
+    tdev = to_dev(target.astype(np.float32))
+    loss, grad = rd.cnn_backward(rdev, idev, pdev, pred, tdev, cws, huber_delta=1.0)
+    x = np.stack([np.broadcast_to(ref, (B, h, w)), img], axis=-1)
+    return dict(params=params, x=x, target=target, pred=pred.cpu().numpy().astype(np.float64),
+                loss=float(loss.cpu()[0]), grad=grad.cpu().numpy().astype(np.float64), cws=cws)
+
+
+@pytest.mark.parametrize("B,h,w", [(3, 64, 64), (2, 48, 80), (5, 37, 53)])
+def test_network_backward_stages(rd, orc, B, h, w):
+    """Each backward stage against the oracle, given the GPU's own stage inputs."""
+    c = _net_case(rd, orc, B, h, w, seed=B * 7 + h)
+    parts = orc.cnn_split(c["params"])
+    g = orc.cnn_split(c["grad"])
+    acts = [c["x"]] + [rd.bf16_bits_to_float(c["cws"].activation(l)).cpu().numpy().astype(np.float64)
+                       for l in range(1, 5)]
+    # head: Huber derivative, pool of the GPU's X4
+    e = c["pred"] - c["target"]
+    dpred = np.where(np.abs(e) <= 1.0, e, np.sign(e)) / e.size
+    pool = acts[4].reshape(B, -1, 32).mean(axis=1)
+    np.testing.assert_allclose(g["wl"], dpred.T @ pool, rtol=1e-5, atol=1e-7)
+    np.testing.assert_allclose(g["bl"], dpred.sum(axis=0), rtol=1e-5, atol=1e-7)
+    hub = np.where(np.abs(e) <= 1.0, 0.5 * e * e, np.abs(e) - 0.5).mean()
+    assert c["loss"] == pytest.approx(hub, rel=1e-5)
+    # conv layers 1 and 2: weight and bias gradients from the GPU's dZ, and dZ1 from dZ2
+    dz = {l: rd.bf16_bits_to_float(c["cws"].grad_z(l)).cpu().numpy().astype(np.float64) for l in (1, 2)}
+    for l in (1, 2):
+        dx, dw, db = orc.conv_backward(acts[l - 1], orc.bf16_round(parts[f"w{l}"]), dz[l], want_dx=(l == 2))
+        scale = np.abs(dw).max()
+        np.testing.assert_allclose(g[f"w{l}"], dw, rtol=1e-4, atol=1e-4 * scale)
+        np.testing.assert_allclose(g[f"b{l}"], db, rtol=1e-4, atol=1e-4 * np.abs(db).max())
+        if l == 2:
+            want = orc.bf16_round(dx * (acts[1] > 0))
+            compare_bf16(dz[1], want, "dZ1 from dZ2")
+
+
+@pytest.mark.parametrize("B,h,w", [(4, 64, 64), (2, 40, 72)])
+def test_network_gradient_vs_oracle(rd, orc, B, h, w):
+    """The whole gradient against the oracle's bfloat16-mode backward on the same input."""
+    c = _net_case(rd, orc, B, h, w, seed=100 + B)
+    loss, grad = orc.cnn_loss_backward(c["x"], c["params"], c["target"], 1.0, bf16=True)
+    assert c["loss"] == pytest.approx(loss, rel=1e-3)
+    got, want = orc.cnn_split(c["grad"]), orc.cnn_split(grad)
+    for k in want:
+        a, b = got[k].ravel(), want[k].ravel()
+        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+        cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b))
+        print(f"{k}: relative L2 {rel:.2e}, cosine {cos:.6f}")
+        assert rel <= 2e-2 and cos >= 0.999, k
+
+
+def test_adamw_matches_torch(rd):
+    rng = np.random.default_rng(5)
+    n = 1000
+    p0 = rng.normal(size=n).astype(np.float32)
+    grads = [rng.normal(size=n).astype(np.float32) for _ in range(3)]
+    pt = torch.nn.Parameter(torch.from_numpy(p0.copy()))
+    opt = torch.optim.AdamW([pt], lr=1e-2, betas=(0.9, 0.999), eps=1e-8, weight_decay=0.05)
+    pd = to_dev(p0)
+    m = torch.zeros_like(pd)
+    v = torch.zeros_like(pd)
+    for step, gr in enumerate(grads, start=1):
+        pt.grad = torch.from_numpy(gr)
+        opt.step()
+        rd.cnn_adamw(pd, m, v, to_dev(gr), lr=1e-2, step=step, weight_decay=0.05)
+    np.testing.assert_allclose(pd.cpu().numpy(), pt.detach().numpy(), rtol=1e-5, atol=1e-6)

@@ -15,6 +15,9 @@ timed on this host as a baseline.
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -51,7 +54,82 @@ def parse():
                          "to calibrate the HBM byte counters")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM bytes per launch from rocprofv3 counters (JSON), if present")
+    ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="rocprofv3 --pmc output folders (FETCH_SIZE and WRITE_SIZE runs of this benchmark "
+                         "and of --copy-probe): write the --traffic JSON and exit")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal comparison")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2008_11486_amd", "weights",
+                                                      "proposal_4096.npy"),
+                    help="trained proposal network (float32 .npy); untrained weights if missing")
+    ap.add_argument("--learned-frames", type=int, default=16)
+    ap.add_argument("--no-wide", action="store_true",
+                    help="skip the streaming kernels at the wide-field size (16 frames of 6144x6160)")
     return ap.parse_args()
+
+
+# Sources each timed kernel is built from: recorded counter values are used only
+# while these files are unchanged.
+KERNEL_SOURCES = {
+    "score_tiles": ("register.hip", "register_core.h", "register_plan.h", "plan.cpp"),
+    "calibrate": ("calibrate.hip", "common.h"),
+    "shift": ("shift.hip", "common.h"),
+    "combine": ("combine.hip", "combine_core.h"),
+}
+KERNEL_SYMBOLS = {"score_tiles": "score_tiles", "calibrate": "calibrate_", "shift": "shift_kernel",
+                  "combine": "combine_kernel"}
+
+
+def source_hash(kernel):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2008_11486_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _counter_rows(folder, counter):
+    rows = []
+    for f in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
+        with open(f, newline="") as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter:
+                    rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    if not rows:
+        raise SystemExit(f"no {counter} rows under {folder}")
+    return rows
+
+
+def traffic_from(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, workload):
+    """Per-launch HBM bytes of the timed kernels from FETCH_SIZE / WRITE_SIZE (KiB per
+    dispatch), each scaled by what the same counter reads for a plain device copy."""
+    copy_bytes = 128 << 22  # --copy-probe moves 512 MiB in and 512 MiB out per launch
+    cf = max(v for _, v in _counter_rows(copy_fetch_dir, "FETCH_SIZE")) * 1024
+    cw = max(v for _, v in _counter_rows(copy_write_dir, "WRITE_SIZE")) * 1024
+    fs, ws = copy_bytes / cf, copy_bytes / cw
+    out = {"workload": WORKLOADS[workload], "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
+           "copy_probe_bytes": copy_bytes, "kernels": {}}
+    fr, wr = _counter_rows(fetch_dir, "FETCH_SIZE"), _counter_rows(write_dir, "WRITE_SIZE")
+    for k, sym in KERNEL_SYMBOLS.items():
+        fv = [v for n, v in fr if sym in n]
+        wv = [v for n, v in wr if sym in n]
+        if not fv or not wv:
+            continue
+        fetch = sum(fv) / len(fv) * 1024 * fs
+        write = sum(wv) / len(wv) * 1024 * ws
+        out["kernels"][k] = {"fetch_bytes": round(fetch), "write_bytes": round(write),
+                             "bytes": round(fetch + write), "dispatches": len(fv),
+                             "source_sha256": source_hash(k)}
+    return out
+
+
+def recorded_traffic(path, kernel):
+    """Bytes per launch recorded for kernel, or None if absent or the kernel changed since."""
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get("kernels", {}).get(kernel)
+    if rec is None or rec.get("source_sha256") != source_hash(kernel):
+        return None
+    return rec["bytes"]
 
 
 class StagePipeline:
@@ -123,8 +201,101 @@ def cpu_baseline(stacks, integer_mode):
                       f"FP64 C oracle from raw frames, {dt:.1f} s"}
 
 
+def learned_comparison(torch, rd, weights_path, M):
+    """Full +-64 px search vs network proposal + +-2 px search + fallbacks on one stack of
+    4096x4096 frames (a reference and M shifted frames, shifts uniform in +-64 px)."""
+    from paper_2008_11486_amd import learned
+    W = H = 4096
+    trained = os.path.exists(weights_path)
+    params = learned.load_params(weights_path) if trained else learned.init_params(0)
+    frames, t = learned.render_stack(0, M + 1, W, H, 64.0)
+    ref, rest = frames[0], frames[1:].contiguous()
+    ws = torch.empty(rd.register_ws_bytes(W, H, M, 64, 64), dtype=torch.uint8, device=frames.device)
+    reg = learned.LearnedRegistrar(params, W, H, M, radius_max=64, refine_radius=2)
+    full_s = learned.time_call(lambda: learned.full_search(ref, rest, 64, ws=ws), reps=3)
+    full = rd.offsets_to_numpy(learned.full_search(ref, rest, 64, ws=ws))
+    res = {}
+    learned_s = learned.time_call(lambda: res.setdefault("r", reg.register(ref, rest)), reps=1)
+    learned_s = min(learned_s, learned.time_call(lambda: reg.register(ref, rest), reps=3))
+    r = res["r"]
+    same = np.mean((r.offsets["dx"] == full["dx"]) & (r.offsets["dy"] == full["dy"]))
+    err = np.abs(r.centres - np.stack([full["dx"], full["dy"]], 1)).max(axis=1)
+    return {"workload": f"a reference and {M} frames of {W}x{H}, shifts uniform in +-64 px, full search R=64 "
+                        f"vs network proposal + R=2 search (same template) + full-search fallback",
+            "weights": "trained" if trained else "untrained", "full_ms": round(full_s * 1e3, 3),
+            "learned_ms": round(learned_s * 1e3, 3), "speedup": round(full_s / learned_s, 3),
+            "identical_integer_offsets": float(same), "fallback_rate": float(r.fallback.mean()),
+            "centre_error_px_median": float(np.median(err)), "centre_error_px_max": float(err.max()),
+            "true_offset_max_abs_px": float(np.abs(t).max())}
+
+
+def streaming_wide(torch, rd, reps=5):
+    """calibrate, shift and combine over 16 frames of 6144x6160 (working sets of 1.2-2.4 GB,
+    far beyond the 256 MB last-level cache), timed with HIP events on their stream."""
+    from paper_2008_11486_amd import learned
+    N, W, H, bound = 16, 6144, 6160, 64.0
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(20081148)
+    # input preparation: rendered sky (5000 stars per frame), then dark, flat, single-pixel
+    # cosmic-ray hits on 0.01% of pixels, rounding to uint16
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([20081148, 3])))
+    S = 5000
+    x = rng.uniform(-bound - 8, W + bound + 8, S)
+    y = rng.uniform(-bound - 8, H + bound + 8, S)
+    amp = np.exp(rng.uniform(np.log(2e3), np.log(5e4), S))
+    t = np.zeros((N, 2))
+    t[1:] = rng.uniform(-bound, bound, (N - 1, 2))
+    stars = np.zeros((N, S, 4), np.float32)
+    for k in range(N):
+        stars[k, :, 0], stars[k, :, 1], stars[k, :, 2] = x + t[k, 0], y + t[k, 1], amp
+    cal = torch.empty((N, H, W), dtype=torch.float32, device=dev)
+    rd.render_frames(torch.from_numpy(stars).to(dev), torch.arange(N, dtype=torch.int64, device=dev), W, H,
+                     sky=1000.0, fwhm=3.0, read_noise=10.0, seed=3, out=cal)
+    dark = 100.0 + 3.0 * torch.randn((H, W), generator=g, device=dev)
+    flat = 0.95 + 0.1 * torch.rand((H, W), generator=g, device=dev)
+    hits = torch.rand((N, H, W), generator=g, device=dev) < 1e-4
+    cal.mul_(flat).add_(dark).add_(hits * (5e3 + 5.5e4 * torch.rand((N, H, W), generator=g, device=dev)))
+    raw = cal.round_().clamp_(0, 65535).to(torch.int32).to(torch.int16)  # two's-complement bits of uint16
+    del hits
+    s = torch.from_numpy(t.astype(np.float32)).to(dev)
+    rect = rd.valid_rect(t.astype(np.float32), W, H)
+    w, h = int(rect[2]), int(rect[3])
+    al = torch.empty((N, h, w), dtype=torch.float32, device=dev)
+    out = torch.empty((h, w), dtype=torch.float32, device=dev)
+    for _ in range(2):
+        rd.calibrate(raw, dark, flat, out=cal)
+        rd.shift(cal, s, rect, out=al)
+        rd.combine(al, out=out)
+    torch.cuda.synchronize()
+    rd.prof_enable(True)
+    for _ in range(reps):
+        rd.calibrate(raw, dark, flat, out=cal)
+        rd.shift(cal, s, rect, out=al)
+        rd.combine(al, out=out)
+    torch.cuda.synchronize()
+    res = {"workload": f"{N} frames {W}x{H}, 5000 stars, cosmic-ray hits on 0.01% of pixels, shifts +-64 px, "
+                       f"overlap {w}x{h}"}
+    byts = {"calibrate": N * W * H * (2 + 4) + 8 * W * H, "shift": N * w * h * (4 + 4), "combine": N * w * h * 4 + w * h * 4}
+    for name in ("calibrate", "shift", "combine"):
+        ms, n = rd.prof_query(name)
+        gbs = byts[name] / (ms / n / 1e3) / 1e9
+        res[name] = {"avg_launch_ms": round(ms / n, 4), "bytes": byts[name], "GB/s": round(gbs, 1),
+                     "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    rd.prof_enable(False)
+    del raw, cal, al
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
+    if args.traffic_from:
+        rec = traffic_from(*args.traffic_from, workload=args.workload)
+        with open(args.traffic, "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(json.dumps(rec))
+        return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU sharding is a design "
@@ -179,11 +350,7 @@ def main():
     score_avg_s = score_ms / score_n / 1e3
     flops = register_flops_per_launch(spec0, spec0.N - 1)
     achieved = flops / score_avg_s / 1e12
-    traffic = None
-    if os.path.exists(args.traffic):
-        tr = json.load(open(args.traffic)).get(f"workload{args.workload}", {}).get("score_tiles")
-        if tr is not None:
-            traffic = tr
+    traffic = recorded_traffic(args.traffic, "score_tiles")
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(FP64_VALU_PEAK_TFLOPS, 3),
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4), "traffic": traffic,
                 "kernel": "score_tiles", "avg_launch_ms": round(score_avg_s * 1e3, 4),
@@ -196,7 +363,8 @@ def main():
         if n:
             gbs = sbytes[name] / (ms / n / 1e3) / 1e9
             streaming[name] = {"avg_launch_ms": round(ms / n, 4), "GB/s": round(gbs, 1),
-                               "frac": round(gbs / HBM_PEAK_GBS, 4)}
+                               "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes": sbytes[name],
+                               "traffic": recorded_traffic(args.traffic, name)}
 
     value = pipe.pixels / (ms_per_step / 1e3) / 1e6
     line = {
@@ -209,6 +377,10 @@ def main():
                    "search_plan": rd.register_plan(spec0.W, spec0.H, spec0.N - 1, spec0.radius)},
         "roofline": roofline, "streaming": streaming,
     }
+    if not args.no_wide:
+        line["streaming_wide"] = streaming_wide(torch, rd)
+    if not args.no_learned:
+        line["learned"] = learned_comparison(torch, rd, args.weights, args.learned_frames)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(stacks, integer_mode)
     print(json.dumps(line), flush=True)

@@ -241,6 +241,30 @@ int reduce_cnn_backward(const uint16_t *ref, int64_t ref_stride, const uint16_t 
 int reduce_cnn_adamw(float *params, float *m, float *v, const float *grad, int64_t n, float lr, float beta1,
                      float beta2, float eps, float weight_decay, int32_t step, void *stream);
 
+/* reduce_cnn_centres: search-window centres from the network's prediction:
+ *   centres[b][j] = clamp(rint(scale * pred[b][j]), -radius_max, radius_max) as int32
+ *   (device pred float [B][2], device centres int32 [B][2]), for the narrowed search
+ *   of reduce_register (scale 4 maps the 4x-downsampled prediction to frame pixels).
+ *   A NaN prediction gives -radius_max. */
+int reduce_cnn_centres(const float *pred, int32_t B, float scale, int32_t radius_max, int32_t *centres,
+                       void *stream);
+
+/* ---- training and evaluation frames --------------------------------------------
+ * reduce_render_frames: F synthetic sky frames [F][H][W] (device float out) for the
+ *   network's training and evaluation pairs: sky + sum over the frame's S catalogue
+ *   stars of amp * exp(-r^2 / (2 sigma^2)) (sigma = fwhm / 2.3548; pixel centres at
+ *   integer coordinates; each star reaches pixels within 8 px on both axes) + noise.
+ *   stars: device float [F][S][4] = (x, y, amp, unused) (NULL allowed when S = 0); keys:
+ *   device int64 [F].  With
+ *   noise != 0 each pixel adds sqrt(max(signal, 0) + read_noise^2) * z, z standard
+ *   normal by Box-Muller from Philox4x32-10 (key = seed, counter = (pixel index y*W + x
+ *   as two words, keys[f] as two words)), so a frame is reproducible from its inputs.
+ *   The paper times its pipeline on random-valued dummy frames (Section 3.2.2); these
+ *   stand in for calibrated sky frames.  Errors: F > 65535 -> UNSUPPORTED. */
+int reduce_render_frames(const float *stars, int32_t S, const int64_t *keys, int32_t F, int32_t W, int32_t H,
+                         float sky, float fwhm, float read_noise, int32_t noise, uint64_t seed, float *out,
+                         void *stream);
+
 /* ---- autotuner --------------------------------------------------------------
  * Launch shapes (tiles, workgroup sizes, lanes per pixel) are chosen per problem
  * size by timing candidates on the caller's data with HIP events; the winner is

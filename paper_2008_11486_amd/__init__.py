@@ -88,8 +88,10 @@ def _declare(L):
     L.reduce_cnn_forward.argtypes = [P, I64, P, I32, I32, I32, P, P, P, SZ, P]
     L.reduce_cnn_backward.argtypes = [P, I64, P, I32, I32, I32, P, P, P, F, P, P, P, SZ, P]
     L.reduce_cnn_adamw.argtypes = [P, P, P, P, I64, F, F, F, F, F, I32, P]
+    L.reduce_cnn_centres.argtypes = [P, I32, F, I32, P, P]
+    L.reduce_render_frames.argtypes = [P, I32, P, I32, I32, I32, F, F, F, I32, ctypes.c_uint64, P, P]
     for n in ("reduce_cnn_input", "reduce_cnn_ws_offsets", "reduce_cnn_forward", "reduce_cnn_backward",
-              "reduce_cnn_adamw"):
+              "reduce_cnn_adamw", "reduce_cnn_centres", "reduce_render_frames"):
         getattr(L, n).restype = ctypes.c_int
     L.reduce_prof_enable.argtypes = [ctypes.c_int]
     L.reduce_prof_query.argtypes = [ctypes.c_char_p, P, P]
@@ -113,7 +115,8 @@ def exported_symbols() -> Sequence[str]:
             "reduce_tune_register", "reduce_tune_combine", "reduce_tune_save", "reduce_tune_load",
             "reduce_tune_clear", "reduce_stack_batch_ws", "reduce_stack_batch",
             "reduce_cnn_input_ws", "reduce_cnn_input", "reduce_cnn_num_params", "reduce_cnn_ws",
-            "reduce_cnn_ws_offsets", "reduce_cnn_forward", "reduce_cnn_backward", "reduce_cnn_adamw")
+            "reduce_cnn_ws_offsets", "reduce_cnn_forward", "reduce_cnn_backward", "reduce_cnn_adamw",
+            "reduce_cnn_centres", "reduce_render_frames")
 
 
 def _check(rc: int) -> None:
@@ -291,13 +294,16 @@ def shift(frames: torch.Tensor, offs: torch.Tensor, rect: Sequence[int], integer
 
 # ---------------------------------------------------------------------------- combine
 def combine(aligned: torch.Tensor, ksigma: float = 3.0, max_iters: int = 3, want_keep: bool = False,
-            want_nrej: bool = False, stream=None):
+            want_nrej: bool = False, out: Optional[torch.Tensor] = None, stream=None):
     """Returns (out [h][w] float32, keep uint8 [N][h][w] or None, n_rej int64 [1] or None)."""
     _dev(aligned, "aligned")
     N, h, w = aligned.shape
     if not aligned.is_contiguous():
         raise ValueError("aligned must be contiguous")
-    out = torch.empty((h, w), dtype=torch.float32, device=aligned.device)
+    if out is None:
+        out = torch.empty((h, w), dtype=torch.float32, device=aligned.device)
+    elif out.dtype != torch.float32 or out.numel() != h * w or not out.is_contiguous():
+        raise ValueError("out must be contiguous float32 [h][w]")
     keep = torch.empty((N, h, w), dtype=torch.uint8, device=aligned.device) if want_keep else None
     nrej = torch.empty(1, dtype=torch.int64, device=aligned.device) if want_nrej else None
     _check(lib().reduce_combine(_ptr(aligned), w, h, N, float(ksigma), int(max_iters), _ptr(out),
@@ -371,13 +377,19 @@ def cnn_num_params() -> int:
     return int(lib().reduce_cnn_num_params())
 
 
-def cnn_input(frames: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+def cnn_input_ws_bytes(W: int, H: int, N: int) -> int:
+    return int(lib().reduce_cnn_input_ws(W, H, N))
+
+
+def cnn_input(frames: torch.Tensor, out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
+              stream=None) -> torch.Tensor:
     """frames float32 [N][H][W] -> bfloat16 bits as int16 [N][H/4][W/4]."""
     _dev(frames, "frames")
     if frames.dim() == 2:
         frames = frames.unsqueeze(0)
     N, H, W = frames.shape
-    ws = torch.empty(max(int(lib().reduce_cnn_input_ws(W, H, N)), 1), dtype=torch.uint8, device=frames.device)
+    if ws is None:
+        ws = torch.empty(max(cnn_input_ws_bytes(W, H, N), 1), dtype=torch.uint8, device=frames.device)
     if out is None:
         out = torch.empty((N, H // 4, W // 4), dtype=torch.int16, device=frames.device)
     _check(lib().reduce_cnn_input(_ptr(frames.contiguous()), W, H, N, _ptr(out), _ptr(ws), ws.numel(),
@@ -454,3 +466,30 @@ def cnn_adamw(params, m, v, grad, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, we
     _check(lib().reduce_cnn_adamw(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), params.numel(), float(lr),
                                   float(beta1), float(beta2), float(eps), float(weight_decay), int(step),
                                   _stream(stream)))
+
+
+def cnn_centres(pred: torch.Tensor, scale: float = 4.0, radius_max: int = 64, out: Optional[torch.Tensor] = None,
+                stream=None) -> torch.Tensor:
+    """int32 [B][2] window centres from a [B][2] prediction."""
+    B = pred.shape[0]
+    if out is None:
+        out = torch.empty((B, 2), dtype=torch.int32, device=pred.device)
+    _check(lib().reduce_cnn_centres(_ptr(pred), B, float(scale), int(radius_max), _ptr(out), _stream(stream)))
+    return out
+
+
+def render_frames(stars: torch.Tensor, keys: torch.Tensor, W: int, H: int, sky: float = 1000.0,
+                  fwhm: float = 3.0, read_noise: float = 10.0, noise: bool = True, seed: int = 0,
+                  out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """stars device float32 [F][S][4], keys device int64 [F] -> frames float32 [F][H][W]."""
+    F_, S = stars.shape[0], stars.shape[1]
+    if stars.dtype != torch.float32 or stars.shape[2] != 4 or not stars.is_contiguous():
+        raise ValueError("stars must be contiguous float32 [F][S][4]")
+    if keys.dtype != torch.int64 or keys.numel() != F_:
+        raise ValueError("keys must be int64 [F]")
+    if out is None:
+        out = torch.empty((F_, H, W), dtype=torch.float32, device=stars.device)
+    _check(lib().reduce_render_frames(_ptr(stars), S, _ptr(keys), F_, W, H, float(sky), float(fwhm),
+                                      float(read_noise), 1 if noise else 0, int(seed) & (2 ** 64 - 1), _ptr(out),
+                                      _stream(stream)))
+    return out

@@ -166,3 +166,109 @@ def test_adamw_matches_torch(rd):
         opt.step()
         rd.cnn_adamw(pd, m, v, to_dev(gr), lr=1e-2, step=step, weight_decay=0.05)
     np.testing.assert_allclose(pd.cpu().numpy(), pt.detach().numpy(), rtol=1e-5, atol=1e-6)
+
+
+# ---- rendered training frames --------------------------------------------------------------
+def _render_np(stars, W, H, sky, fwhm):
+    sig = fwhm / (2 * np.sqrt(2 * np.log(2)))
+    out = np.full((stars.shape[0], H, W), sky, dtype=np.float64)
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    for f in range(stars.shape[0]):
+        for x, y, a, _ in stars[f].astype(np.float64):
+            m = (np.abs(xx - x) <= 8) & (np.abs(yy - y) <= 8)
+            out[f][m] += a * np.exp(-((xx[m] - x) ** 2 + (yy[m] - y) ** 2) / (2 * sig * sig))
+    return out
+
+
+def test_render_noise_free_matches_numpy(rd):
+    rng = np.random.default_rng(3)
+    F, S, W, H = 3, 300, 200, 136
+    stars = np.zeros((F, S, 4), np.float32)
+    stars[..., 0] = rng.uniform(-20, W + 20, (F, S))
+    stars[..., 1] = rng.uniform(-20, H + 20, (F, S))
+    stars[..., 2] = rng.uniform(100, 5e4, (F, S))
+    keys = torch.arange(F, dtype=torch.int64, device="cuda:0")
+    got = rd.render_frames(to_dev(stars), keys, W, H, sky=1000.0, fwhm=3.0, noise=False).cpu().numpy()
+    want = _render_np(stars, W, H, 1000.0, 3.0)
+    np.testing.assert_allclose(got, want, rtol=2e-6, atol=1e-3)
+
+
+def test_render_noise_matches_philox_reference(rd):
+    from philox_ref import philox4x32_10, std_normal
+    W, H, F = 96, 40, 2
+    stars = np.zeros((F, 1, 4), np.float32)
+    stars[:, 0] = (50.3, 20.7, 3e4, 0)
+    keys = np.array([5, (1 << 48) | 77], np.int64)
+    seed = 0x1234_5678_9ABC_DEF0
+    got = rd.render_frames(to_dev(stars), torch.from_numpy(keys).to("cuda:0"), W, H, sky=1000.0, fwhm=3.0,
+                           read_noise=10.0, seed=seed).cpu().numpy().astype(np.float64)
+    clean = _render_np(stars, W, H, 1000.0, 3.0)
+    pix = np.arange(W * H, dtype=np.uint64)
+    for f in range(F):
+        k = int(keys[f])
+        r = philox4x32_10(pix & 0xFFFFFFFF, pix >> 32, np.full(pix.shape, k & 0xFFFFFFFF, np.uint64),
+                          np.full(pix.shape, k >> 32, np.uint64), seed & 0xFFFFFFFF, seed >> 32)
+        z = std_normal(r[0], r[1]).reshape(H, W)
+        want = clean[f] + np.sqrt(clean[f] + 100.0) * z
+        np.testing.assert_allclose(got[f], want, rtol=1e-5, atol=1e-3)
+    # the noise is standard normal after scaling
+    zz = (got - clean) / np.sqrt(clean + 100.0)
+    assert abs(zz.mean()) < 0.05 and abs(zz.std() - 1.0) < 0.05
+
+
+def test_render_is_reproducible_and_keyed(rd):
+    stars = torch.zeros((2, 0, 4), dtype=torch.float32, device="cuda:0")
+    a = rd.render_frames(stars, torch.tensor([1, 2], device="cuda:0"), 64, 64, seed=9)
+    b = rd.render_frames(stars, torch.tensor([1, 3], device="cuda:0"), 64, 64, seed=9)
+    assert torch.equal(a[0], b[0]) and not torch.equal(a[1], b[1])
+
+
+def test_centres(rd):
+    pred = np.array([[0.1, -0.124], [0.125, 0.375], [-16.2, 17.0], [np.nan, 2.5]], np.float32)
+    got = rd.cnn_centres(to_dev(pred), 4.0, 64).cpu().numpy()
+    want = np.clip(np.rint(pred.astype(np.float32) * np.float32(4.0)), -64, 64)
+    want[3, 0] = -64
+    np.testing.assert_array_equal(got, want.astype(np.int32))
+
+
+# ---- training and the narrowed search ---------------------------------------------------------
+TRAIN_W, TRAIN_BOUND, TRAIN_RMAX = 512, 12, 16
+
+
+@pytest.fixture(scope="module")
+def trained(rd):
+    from paper_2008_11486_amd import learned
+    tr = learned.ProposalTrainer(TRAIN_W, TRAIN_W, batch=16, shift_bound=TRAIN_BOUND, lr=2e-3, seed=0)
+    untrained = tr.params.clone()
+    hist = tr.train(n_pairs=2048, epochs=3, warmup=20, log_every=8)
+    print("loss history", hist[:3], "...", hist[-3:])
+    return learned, untrained, tr.params.clone(), hist
+
+
+def test_training_lowers_the_loss(trained):
+    _, _, _, hist = trained
+    losses = np.array([l for _, l in hist])
+    first, last = losses[:4].mean(), losses[-4:].mean()
+    print(f"loss {first:.3f} -> {last:.3f}")
+    assert last < 0.5 * first
+
+
+def test_trained_proposals_need_fewer_fallbacks(trained):
+    learned, p0, p1, _ = trained
+    M = 24
+    frames, t = learned.render_stack(0, M + 1, TRAIN_W, TRAIN_W, TRAIN_BOUND)
+    ref, rest = frames[0], frames[1:].contiguous()
+    import paper_2008_11486_amd as rd
+    full = rd.offsets_to_numpy(learned.full_search(ref, rest, TRAIN_RMAX))
+    out = {}
+    for name, p in (("untrained", p0), ("trained", p1)):
+        reg = learned.LearnedRegistrar(p, TRAIN_W, TRAIN_W, M, radius_max=TRAIN_RMAX)
+        res = reg.register(ref, rest)
+        # the fallback keeps the result identical to the full search
+        np.testing.assert_array_equal(res.offsets["dx"], full["dx"])
+        np.testing.assert_array_equal(res.offsets["dy"], full["dy"])
+        err = np.abs(res.centres - np.stack([full["dx"], full["dy"]], 1)).max(axis=1)
+        out[name] = (int(res.fallback.sum()), float(np.median(err)))
+        print(name, "fallbacks", out[name][0], "of", M, "median centre error", out[name][1], res.reason)
+    assert out["trained"][0] < out["untrained"][0]
+    assert out["trained"][1] < out["untrained"][1]

@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--workload", type=int, default=1, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the cost-model launch shapes")
+    ap.add_argument("--tune-cache", default=None,
+                    help="load tuned launch shapes from this file if it exists, else tune and save them here")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 512 MiB device copy (read 512 MiB + write 512 MiB per launch) "
                          "to calibrate the HBM byte counters")
@@ -57,6 +59,8 @@ def parse():
     ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="rocprofv3 --pmc output folders (FETCH_SIZE and WRITE_SIZE runs of this benchmark "
                          "and of --copy-probe): write the --traffic JSON and exit")
+    ap.add_argument("--traffic-kernels", default=",".join(("score_tiles", "calibrate", "shift", "combine")),
+                    help="with --traffic-from: the kernels to record (those unchanged since the counter runs)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal comparison")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2008_11486_amd", "weights",
                                                       "proposal_4096.npy"),
@@ -99,7 +103,7 @@ def _counter_rows(folder, counter):
     return rows
 
 
-def traffic_from(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, workload):
+def traffic_from(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, workload, kernels):
     """Per-launch HBM bytes of the timed kernels from FETCH_SIZE / WRITE_SIZE (KiB per
     dispatch), each scaled by what the same counter reads for a plain device copy."""
     copy_bytes = 128 << 22  # --copy-probe moves 512 MiB in and 512 MiB out per launch
@@ -110,6 +114,8 @@ def traffic_from(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, workload)
            "copy_probe_bytes": copy_bytes, "kernels": {}}
     fr, wr = _counter_rows(fetch_dir, "FETCH_SIZE"), _counter_rows(write_dir, "WRITE_SIZE")
     for k, sym in KERNEL_SYMBOLS.items():
+        if k not in kernels:
+            continue
         fv = [v for n, v in fr if sym in n]
         wv = [v for n, v in wr if sym in n]
         if not fv or not wv:
@@ -291,7 +297,7 @@ def streaming_wide(torch, rd, reps=5):
 def main():
     args = parse()
     if args.traffic_from:
-        rec = traffic_from(*args.traffic_from, workload=args.workload)
+        rec = traffic_from(*args.traffic_from, workload=args.workload, kernels=args.traffic_kernels.split(","))
         with open(args.traffic, "w") as fh:
             json.dump(rec, fh, indent=1)
         print(json.dumps(rec))
@@ -323,11 +329,16 @@ def main():
     integer_mode = args.workload == 0
     pipe = StagePipeline(rd, torch, stacks, integer_mode)
     tuned = None
-    if not args.no_tune:
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        rd.tune_load(args.tune_cache)
+        tuned = "loaded"
+    elif not args.no_tune:
         it = pipe.items[0]
         sp = it["spec"]
         rd.calibrate(it["raw"], it["dark"], it["flat"], out=it["cal"])
         tuned = rd.tune_register(it["cal"][0], it["cal"][1:], sp.radius)
+        if args.tune_cache:
+            rd.tune_save(args.tune_cache)
 
     for _ in range(args.warmup):
         pipe.step()

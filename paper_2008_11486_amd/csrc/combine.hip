@@ -1,10 +1,10 @@
 // Sigma-clipped mean co-add along the frame axis (Sections 2.1, 3.1.2).
 //
-// A workgroup stages a 256-pixel tile of every frame in LDS (one coalesced 1 KB row
-// per frame), then groups of L lanes clip one pixel column at a time: each lane
-// holds the frames l, l+L, l+2L, ... of the column in registers and the group's
-// sums, squared deviations and drop counts are combined with wavefront butterfly
-// reductions.  L = 1 keeps the whole column in one lane (no cross-lane traffic).
+// With one lane per pixel column (the default) each thread loads its column into
+// registers directly.  With L > 1 lanes per column a workgroup stages a 256-pixel
+// tile of every frame in LDS (one coalesced 1 KB row per frame), then each lane
+// takes the frames l, l+L, l+2L, ... of a column and the group's sums, squared
+// deviations and drop counts are combined with wavefront butterfly reductions.
 // Mean and sigma are evaluated in double.  Bytes per input pixel: 4 read, plus
 // 4/N for the output and 1 per value when the keep mask is requested.
 #include "common.h"
@@ -32,6 +32,94 @@ __global__ __launch_bounds__(COMB_TILE) void combine_kernel(
     }
 }
 
+// One thread per pixel column, the column's N values in registers straight from
+// HBM (coalesced across the workgroup's 256 adjacent pixels).  The arithmetic is
+// that of clip_column with one lane: sums in frame order in double, m = s / n,
+// q = sum of (x - m)^2, threshold ksigma * sqrt(q / n), drop |x - m| > threshold.
+// Two shortcuts leave every result unchanged: the largest |x - m| of the q pass
+// decides whether the drop pass is needed at all, and when an iteration drops
+// nothing its own sum is the final sum.
+template <int MAXV, bool ALL>
+__device__ __forceinline__ bool kept_at(uint64_t kept, int i, int32_t N)
+{
+    return ALL ? i < N : ((kept >> i) & 1ull) != 0;
+}
+
+template <int MAXV, bool ALL>
+__device__ __forceinline__ void clip_pass(const float (&x)[MAXV], uint64_t kept, int32_t N, int n, double &s,
+                                          double &m, double &q, double &dmax)
+{
+    s = 0.0;
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i)
+        if (kept_at<MAXV, ALL>(kept, i, N)) s = __dadd_rn(s, (double)x[i]);
+    m = s / (double)n;
+    q = 0.0;
+    dmax = 0.0;
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i)
+        if (kept_at<MAXV, ALL>(kept, i, N)) {
+            const double d = __dsub_rn((double)x[i], m);
+            q = __dadd_rn(q, __dmul_rn(d, d));
+            dmax = fmax(dmax, fabs(d));
+        }
+}
+
+template <int MAXV>
+__global__ __launch_bounds__(COMB_TILE) void combine_cols(
+    const float *__restrict__ aligned, int64_t plane, int32_t N, double ksigma, int32_t max_iters,
+    float *__restrict__ out, uint8_t *__restrict__ keep, unsigned long long *__restrict__ n_rej)
+{
+    const int64_t p = (int64_t)blockIdx.x * COMB_TILE + threadIdx.x;
+    const bool live = p < plane;
+    float x[MAXV];
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) x[i] = (i < N && live) ? aligned[(int64_t)i * plane + p] : 0.0f;
+    uint64_t kept = N >= 64 ? ~0ull : ((1ull << N) - 1ull);
+    int n = N;
+    unsigned dropped = 0;
+    double s = 0.0, m = 0.0, q = 0.0, dmax = 0.0;
+    bool final_known = false;
+    for (int32_t it = 0; it < max_iters; ++it) {
+        if (it == 0)
+            clip_pass<MAXV, true>(x, kept, N, n, s, m, q, dmax);
+        else
+            clip_pass<MAXV, false>(x, kept, N, n, s, m, q, dmax);
+        const double thr = __dmul_rn(ksigma, sqrt(q / (double)n));
+        if (!(dmax > thr)) {
+            final_known = true;  // nothing drops: s is the sum over the final set
+            break;
+        }
+        int drop = 0;
+#pragma unroll
+        for (int i = 0; i < MAXV; ++i)
+            if (((kept >> i) & 1ull) && fabs(__dsub_rn((double)x[i], m)) > thr) {
+                kept &= ~(1ull << i);
+                ++drop;
+            }
+        n -= drop;
+        dropped += (unsigned)drop;
+    }
+    if (!final_known) {
+        s = 0.0;
+#pragma unroll
+        for (int i = 0; i < MAXV; ++i)
+            if ((kept >> i) & 1ull) s = __dadd_rn(s, (double)x[i]);
+    }
+    if (live) {
+        out[p] = (float)(s / (double)n);
+        if (keep) {
+#pragma unroll
+            for (int i = 0; i < MAXV; ++i)
+                if (i < N) keep[(int64_t)i * plane + p] = (uint8_t)((kept >> i) & 1ull);
+        }
+    }
+    if (n_rej) {
+        const unsigned total = block_sum_u32(live ? dropped : 0u);
+        if (threadIdx.x == 0 && total) atomicAdd(n_rej, (unsigned long long)total);
+    }
+}
+
 __global__ void zero_u64(unsigned long long *p) { *p = 0ull; }
 
 void combine_dispatch(int lanes, const float *aligned, int64_t plane, int32_t N, double ksigma, int32_t max_iters,
@@ -45,11 +133,16 @@ void combine_dispatch(int lanes, const float *aligned, int64_t plane, int32_t N,
         hipLaunchKernelGGL((combine_kernel<L, V>), dim3(blocks), dim3(COMB_TILE), lds, s, aligned, plane, N, ksigma,
                            max_iters, out, keep, n_rej);
     };
+    auto launch_cols = [&](auto Vc) {
+        constexpr int V = decltype(Vc)::value;
+        hipLaunchKernelGGL((combine_cols<V>), dim3(blocks), dim3(COMB_TILE), 0, s, aligned, plane, N, ksigma,
+                           max_iters, out, keep, n_rej);
+    };
     switch (lanes) {
     case 1:
-        if (N <= 16) launch(std::integral_constant<int, 1>{}, std::integral_constant<int, 16>{});
-        else if (N <= 32) launch(std::integral_constant<int, 1>{}, std::integral_constant<int, 32>{});
-        else launch(std::integral_constant<int, 1>{}, std::integral_constant<int, 48>{});
+        if (N <= 16) launch_cols(std::integral_constant<int, 16>{});
+        else if (N <= 32) launch_cols(std::integral_constant<int, 32>{});
+        else launch_cols(std::integral_constant<int, 48>{});
         break;
     case 2: launch(std::integral_constant<int, 2>{}, std::integral_constant<int, 24>{}); break;
     case 4: launch(std::integral_constant<int, 4>{}, std::integral_constant<int, 12>{}); break;

@@ -48,16 +48,39 @@ __global__ __launch_bounds__(512) void score_tiles(ScoreArgs a)
     score_tile<K>(a, xcd_logical_id((int32_t)blockIdx.x, total), smem);
 }
 
-__global__ __launch_bounds__(256) void sum_tiles(const double *__restrict__ partial, int32_t n_tiles, int32_t D,
-                                                 int32_t R, int32_t Rmax, const int32_t *__restrict__ centers,
-                                                 double *__restrict__ scores)
+// Scores of each frame from its tile partials.  A workgroup takes 64 candidates; wave
+// w sums tiles w, w + SUM_WAVES, ... in order and the SUM_WAVES partial sums are added
+// in wave order, so the result is the same on every run.  -inf outside the clipped
+// window.
+constexpr int SUM_WAVES = 8;
+
+__global__ __launch_bounds__(64 * SUM_WAVES) void sum_tiles(const double *__restrict__ partial, int32_t n_tiles,
+                                                            int32_t D, int32_t R, int32_t Rmax,
+                                                            const int32_t *__restrict__ centers,
+                                                            double *__restrict__ scores)
 {
+    __shared__ double part[SUM_WAVES][64];
     const int32_t k = blockIdx.y;
-    const int32_t cand = blockIdx.x * 256 + threadIdx.x;
-    if (cand >= D * D) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int32_t DD = D * D;
+    const int32_t cand = blockIdx.x * 64 + lane;
+    double s = 0.0;
+    if (cand < DD) {
+        const double *pk = partial + (int64_t)k * n_tiles * DD + cand;
+#pragma unroll 4
+        for (int32_t t = wave; t < n_tiles; t += SUM_WAVES) s += pk[(int64_t)t * DD];
+    }
+    part[wave][lane] = s;
+    __syncthreads();
+    if (wave != 0 || cand >= DD) return;
+    double tot = 0.0;
+#pragma unroll
+    for (int w = 0; w < SUM_WAVES; ++w) tot += part[w][lane];
     const int32_t cx = centers ? centers[2 * k] : 0, cy = centers ? centers[2 * k + 1] : 0;
-    scores[(int64_t)k * D * D + cand] =
-        candidate_score(partial + (int64_t)k * n_tiles * D * D, n_tiles, D, R, Rmax, cx, cy, cand);
+    const int32_t jj = cand / D, ii = cand - jj * D;
+    const int32_t dx = cx - R + ii, dy = cy - R + jj;
+    const bool inside = dx >= -Rmax && dx <= Rmax && dy >= -Rmax && dy <= Rmax;
+    scores[(int64_t)k * DD + cand] = inside ? tot : -INFINITY;
 }
 
 __global__ __launch_bounds__(256) void pick_offsets(const double *__restrict__ scores, int32_t D, int32_t R,
@@ -145,8 +168,8 @@ int register_launch(const float *ref, const float *frames, int32_t W, int32_t H,
     case 18: launch_score<18>(a, p, s); break;
     default: launch_score<22>(a, p, s); break;
     }
-    hipLaunchKernelGGL(sum_tiles, dim3((unsigned)ceil_div((int64_t)p.D * p.D, 256), N), dim3(256), 0, s, partial,
-                       a.n_tiles, p.D, R, Rmax, centers, sc);
+    hipLaunchKernelGGL(sum_tiles, dim3((unsigned)ceil_div((int64_t)p.D * p.D, 64), N), dim3(64 * SUM_WAVES), 0, s,
+                       partial, a.n_tiles, p.D, R, Rmax, centers, sc);
     hipLaunchKernelGGL(pick_offsets, dim3(N), dim3(256), 0, s, sc, p.D, R, Rmax, centers, out);
     return check_launch("reduce_register");
 }

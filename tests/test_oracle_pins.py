@@ -5,6 +5,7 @@ evaluation or an independent library routine, chosen so that a dropped term, a
 wrong sign or index or a transposed operand in the oracle fails at least one test.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -412,3 +413,20 @@ def test_end_to_end_small_stack_recovers_integer_shifts(orc):
     assert np.array_equal(np.stack([res["offsets"]["dx"], res["offsets"]["dy"]], 1)[1:],
                           st.shifts[1:].astype(np.int64))
     assert res["n_rej"] == 0  # N = 5 can never reject
+
+
+def test_combine_golden_closed_forms(orc):
+    """Hand-derived cases in tests/golden/sigma_clip_closed_forms.txt."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "sigma_clip_closed_forms.txt")
+    n = 0
+    for line in open(path):
+        if not line.strip() or line.startswith("#"):
+            continue
+        want, mask, vals = [p.strip() for p in line.split("|")]
+        v = np.array([float(t) for t in vals.split()])
+        out, keep, nrej, _ = orc.combine(v.reshape(-1, 1, 1), 3.0, 3)
+        assert out[0, 0] == float(want)
+        assert "".join(str(int(b)) for b in keep[:, 0, 0]) == mask
+        assert nrej == mask.count("0")
+        n += 1
+    assert n == 5

@@ -83,6 +83,45 @@ __device__ __forceinline__ double tmpl_mean_of_parts(const double *part, int32_t
     return s / count;  // valid in thread 0
 }
 
+// ---- LDS staging -----------------------------------------------------------------------------
+// Copy a rows x cols tile into LDS: element e = t, t + nthreads, ... is (e / cols, e % cols).
+// Each thread issues STAGE_U loads before it stores any of them, so their latencies
+// overlap; an element outside the source (ok == false) is loaded from offset 0 and
+// stored as zero, which keeps the loads branch-free.
+constexpr int STAGE_U = 8;
+
+template <typename Addr, typename Store>
+__device__ __forceinline__ void stage_tile(int rows, int cols, int nthreads, int t, Addr addr,
+                                           const float *__restrict__ src, Store store)
+{
+    const int n = rows * cols;
+    const int dr = nthreads / cols, dc = nthreads - dr * cols;
+    int r = t / cols, c = t - r * cols;
+    for (int e = t; e < n; e += STAGE_U * nthreads) {
+        float v[STAGE_U];
+        int lr[STAGE_U], lc[STAGE_U];
+        bool ok[STAGE_U];
+#pragma unroll
+        for (int u = 0; u < STAGE_U; ++u) {
+            lr[u] = r;
+            lc[u] = c;
+            bool in = false;
+            const int64_t off = addr(r, c, in);
+            ok[u] = in && e + u * nthreads < n;
+            v[u] = src[ok[u] ? off : 0];
+            c += dc;
+            r += dr;
+            if (c >= cols) {
+                c -= cols;
+                ++r;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < STAGE_U; ++u)
+            if (e + u * nthreads < n) store(lr[u], lc[u], ok[u], v[u]);
+    }
+}
+
 // ---- one tile of partial scores ----------------------------------------------------------
 // lid in [0, n_tiles * G * N): tile fastest, then candidate group, then frame.
 template <int K>
@@ -132,29 +171,18 @@ __device__ __forceinline__ void score_tile(const ScoreArgs &a, int32_t lid, unsi
     for (int32_t yc = yb0; yc < yb1; yc += a.TY) {
         __syncthreads();
         if (in_block) {
-            // template tile, zero outside T (contributes exactly nothing); one wave per row
-            for (int yy = wave; yy < a.TY; yy += nwaves) {
-                const bool row_ok = yc + yy < yb1;
-                const float *src = a.ref + (int64_t)(a.ty0 + yc + yy) * a.W + a.tx0 + x_t;
-                for (int xx = lane; xx < a.TX; xx += 64) {
-                    double v = 0.0;
-                    if (row_ok && x_t + xx < a.tw) v = (double)src[xx] - mean;
-                    rt[yy * a.TX + xx] = v;
-                }
-            }
-            // frame tile, zero outside the frame; one wave per row
+            // template tile (zero outside T: contributes exactly nothing), then the frame
+            // tile (zero outside the frame)
+            stage_tile(a.TY, a.TX, a.threads, t, [&](int r, int c, bool &ok) -> int64_t {
+                ok = yc + r < yb1 && x_t + c < a.tw;
+                return (int64_t)(a.ty0 + yc + r) * a.W + a.tx0 + x_t + c;
+            }, a.ref, [&](int r, int c, bool ok, float v) { rt[r * a.TX + c] = ok ? (double)v - mean : 0.0; });
             const int32_t fy0 = a.ty0 + yc + cy - a.R + j_lo;
-            for (int rr = wave; rr < a.FR; rr += nwaves) {
-                const int32_t gy = fy0 + rr;
-                const bool row_ok = gy >= 0 && gy < a.H;
-                const float *src = f + (int64_t)gy * a.W;
-                for (int cc = lane; cc < a.FC; cc += 64) {
-                    const int32_t gx = fx0 + cc;
-                    float v = 0.0f;
-                    if (row_ok && gx >= 0 && gx < a.W) v = src[gx];
-                    ft[rr * a.FC + cc] = v;
-                }
-            }
+            stage_tile(a.FR, a.FC, a.threads, t, [&](int r, int c, bool &ok) -> int64_t {
+                const int32_t gy = fy0 + r, gx = fx0 + c;
+                ok = gy >= 0 && gy < a.H && gx >= 0 && gx < a.W;
+                return (int64_t)gy * a.W + gx;
+            }, f, [&](int r, int c, bool ok, float v) { ft[r * a.FC + c] = ok ? v : 0.0f; });
         }
         __syncthreads();
         if (active) {

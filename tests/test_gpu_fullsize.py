@@ -1,0 +1,116 @@
+"""Parity at the wide-field size (16 frames of 6144x6160, cosmic rays, shifts within
++-64 px, search radius 65), in the launch configuration the benchmark uses, on
+outputs the oracle can compute one by one: calibrated rows, scores S(d) at sampled
+offsets (the best one, its neighbours and random ones), shifted rows and combined
+pixel columns.  Each oracle stage gets the GPU's own input to that stage.
+"""
+import numpy as np
+import pytest
+
+import synth
+from helpers import TOL, err_summary, rel_err, to_dev
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rd():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2008_11486_amd as rd
+    rd.lib()
+    return rd
+
+
+@pytest.fixture(scope="module")
+def wide(rd):
+    spec = synth.config_specs(3)[0]
+    st = synth.make_stack(spec, workers=16)
+    R = spec.radius
+    cal = rd.calibrate(to_dev(st.raw), to_dev(st.dark), to_dev(st.flat))
+    raw_offs, scores = rd.register(cal[0].contiguous(), cal, R, want_scores=True)
+    offs = rd.offsets_to_numpy(raw_offs)
+    s = np.stack([offs["sx"], offs["sy"]], 1).astype(np.float32)
+    s[0] = 0.0
+    rect = rd.valid_rect(s, spec.W, spec.H)
+    al = rd.shift(cal, to_dev(s), rect)
+    out, keep, nrej = rd.combine(al, want_keep=True, want_nrej=True)
+    torch.cuda.synchronize()
+    return dict(spec=spec, st=st, cal=cal, offs=offs, scores=scores, s=s, rect=rect, al=al, out=out, keep=keep,
+                nrej=nrej)
+
+
+def test_wide_calibrate_rows(wide, orc):
+    st, cal = wide["st"], wide["cal"]
+    rng = np.random.default_rng(1)
+    rows = np.sort(rng.choice(st.spec.H, 6, replace=False))
+    want = orc.calibrate(st.raw[:, rows], st.dark[rows], st.flat[rows])
+    got = cal[:, torch.from_numpy(rows).to(cal.device)].cpu().numpy()
+    e = rel_err(got, want)
+    print(f"wide calibrate rows {rows.tolist()}: {err_summary(e)}")
+    assert e.max() <= TOL
+
+
+def test_wide_scores_at_sampled_offsets(wide, orc):
+    spec, offs, S = wide["spec"], wide["offs"], wide["scores"].cpu().numpy()
+    R = spec.radius
+    ref = wide["cal"][0].cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(2)
+    truth = wide["st"].shifts
+    for k in range(1, spec.N):
+        frame = wide["cal"][k].cpu().numpy().astype(np.float64)[None]
+        d = (int(offs["dx"][k]), int(offs["dy"][k]))
+        assert np.all(np.abs(np.array([offs["sx"][k], offs["sy"][k]]) - truth[k]) < 0.1)
+        cands = [(d[0] + a, d[1] + b) for a in (-1, 0, 1) for b in (-1, 0, 1)]
+        cands += [tuple(int(v) for v in rng.integers(-R, R + 1, 2)) for _ in range(2)]
+        for cx, cy in cands:
+            if max(abs(cx), abs(cy)) > R:
+                continue
+            o, So = orc.register(ref, frame, 0, R, centers=np.array([[cx, cy]]), want_scores=True)
+            g = S[k, cy + R, cx + R]
+            assert g == pytest.approx(So[0, 0, 0], rel=1e-11, abs=1e-11 * abs(S[k, d[1] + R, d[0] + R])), \
+                (k, cx, cy, g, So[0, 0, 0])
+        # the reported best is the maximum of the GPU's own score plane, ties to smaller dy, dx
+        plane = S[k]
+        best = np.flatnonzero(plane == plane.max())[0]
+        assert (best // (2 * R + 1) - R, best % (2 * R + 1) - R) == (d[1], d[0])
+
+
+def test_wide_shift_rows(wide, orc):
+    spec, cal, s, rect, al = wide["spec"], wide["cal"], wide["s"], wide["rect"], wide["al"]
+    x0, y0, w, h = (int(v) for v in rect)
+    rng = np.random.default_rng(3)
+    for k in rng.choice(spec.N, 4, replace=False):
+        for v in rng.choice(h, 3, replace=False):
+            iy = int(np.floor(s[k, 1]))
+            lo = max(y0 + v + iy - 1, 0)
+            hi = min(y0 + v + iy + 3, spec.H)
+            crop = cal[k, lo:hi].cpu().numpy().astype(np.float64)
+            want = orc.shift(crop[None], s[k:k + 1], (x0, y0 + v - lo, w, 1))[0, 0]
+            got = al[k, v].cpu().numpy().astype(np.float64)
+            e = rel_err(got, want)
+            assert e.max() <= TOL, (k, v, err_summary(e))
+
+
+def test_wide_combine_columns(wide, orc):
+    al, out, keep = wide["al"], wide["out"], wide["keep"]
+    N, h, w = al.shape
+    flat_keep = keep.reshape(N, -1)
+    rejected = torch.nonzero((flat_keep == 0).any(dim=0)).flatten()
+    rng = np.random.default_rng(4)
+    pick = np.unique(np.concatenate([rng.choice(h * w, 40000, replace=False),
+                                     rejected[:20000].cpu().numpy()]))
+    idx = torch.from_numpy(pick).to(al.device)
+    cols = al.reshape(N, -1)[:, idx].cpu().numpy().astype(np.float64)
+    oo, okeep, _, near = orc.combine(cols.reshape(N, 1, -1))
+    gk = flat_keep[:, idx].cpu().numpy().reshape(N, 1, -1)
+    flips = gk != okeep
+    assert np.all(~flips | (near == 1)), "mask differs away from the threshold band"
+    bad = flips.any(axis=0)[0]
+    e = rel_err(out.reshape(-1)[idx].cpu().numpy(), oo[0])
+    print(f"wide combine: {len(pick)} columns, {int(rejected.numel())} with rejections, "
+          f"{int(bad.sum())} near-threshold flips, {err_summary(e[~bad])}")
+    assert e[~bad].max() <= TOL
+    assert int(rejected.numel()) > 0  # cosmic rays were rejected

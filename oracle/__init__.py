@@ -127,8 +127,8 @@ def calibrate(raw: np.ndarray, dark: np.ndarray, flat: np.ndarray) -> np.ndarray
         raw = raw[None]
     assert raw.dtype == np.uint16
     N, H, W = raw.shape
-    if raw.strides[2] != 2:
-        raw = np.ascontiguousarray(raw)
+    if raw.strides[2] != 2 or raw.strides[1] < 0 or raw.strides[0] < raw.strides[1] * H:
+        raw = np.ascontiguousarray(raw)  # the C side takes nested row and frame pitches
     dark = np.asarray(dark, dtype=np.float64)
     flat = np.asarray(flat, dtype=np.float64)
     if dark.strides[1] != 8 or flat.strides != dark.strides:

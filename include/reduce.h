@@ -156,9 +156,10 @@ int reduce_combine(const float *aligned, int32_t w, int32_t h, int32_t N, float 
 
 /* ---- batched stacks -----------------------------------------------------------
  * The whole chain for many independent stacks (for instance the three bands of the
- * paper's cameras, Section 2.1, or many fields) of uneven frame counts and sizes in
- * one launch of a cached HIP graph of persistent work-queue kernels, one per phase,
- * each draining the phase's work items of every stack.  For every stack:
+ * paper's cameras, Section 2.1, or many fields) of uneven frame counts and sizes
+ * with one kernel launch per phase (calibrate, template mean, search tiles, tile
+ * sums, argmax, overlap, shift + combine), each launch covering the phase's work
+ * items of every stack, enqueued on `stream`.  For every stack:
  * calibrate all frames as reduce_calibrate; register every frame k != ref_index
  * against frame ref_index as reduce_register with radius_max = radius and the
  * interior template; the reference frame gets the offset 0 (peak 0, second -inf,
@@ -171,10 +172,11 @@ int reduce_combine(const float *aligned, int32_t w, int32_t h, int32_t N, float 
  *   offsets   device reduce_offset_t [N]
  *   n_rej     device int64[1] (values dropped by the clip) or NULL
  * ws: device workspace of reduce_stack_batch_ws(stacks, n) bytes (calibrated frames,
- * partial scores, work queue); query again after tuning.  The stack descriptors are
- * copied at the call; a repeated call with identical descriptors and workspace
- * replays the cached graph without copying.  Calls sharing one workspace must not
- * overlap.  Errors: as the stage-wise calls, per stack; N > 48 -> UNSUPPORTED. */
+ * partial scores, the work-item table); query again after tuning.  The stack
+ * descriptors are copied into the workspace at every call (the host image is kept
+ * per workspace and rebuilt, after synchronising `stream`, when the descriptors
+ * change).  Calls sharing one workspace must not overlap.  Errors: as the stage-wise
+ * calls, per stack; N > 48 -> UNSUPPORTED. */
 typedef struct {
     const uint16_t *raw;
     int64_t raw_row_pitch, raw_frame_pitch;

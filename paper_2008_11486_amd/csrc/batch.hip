@@ -1,23 +1,22 @@
-// Many stacks of uneven frame counts and sizes in one HIP graph launch of persistent
-// work-queue kernels.
+// Many stacks of uneven frame counts and sizes in one launch per phase.
 //
-// The host turns the stacks into one work queue of items, grouped by phase:
+// The host turns the stacks into one table of work items, grouped by phase:
 //
 //   CAL        calibrate a band of rows of one frame into the workspace
 //   MEANPART   sum MEAN_ROWS template rows of the calibrated reference
 //   MEANFINAL  template mean of the reference
 //   SCORE      one tile of partial correlation scores (the stack's tuned launch shape)
-//   PICK       sum one frame's partials over tiles, argmax, runner-up, parabola
+//   SUM        64 candidate scores of one frame from its tile partials
+//   PICK       argmax, runner-up, parabola of one frame
 //   RECT       common overlap of the stack from its offsets
 //   OUT        bilinear shift of every frame + sigma-clipped mean for OUT_TILES x 256
 //              output pixels
 //
-// Each phase is one kernel whose resident workgroups take the phase's items, over
-// all stacks, from one atomic counter until it is drained; the graph runs the phases
-// in order, so every dependency is met at a kernel boundary and no workgroup waits
-// for another.  The search items of the largest stacks come first.  Each item calls
-// the same device bodies as the stage-wise kernels with the same launch shape, so
-// results are bit-identical to them.
+// Each phase is one kernel launch with one workgroup per item over all stacks; the
+// stream orders the phases, so every dependency is met at a kernel boundary and no
+// workgroup waits for another.  The search items go out in an XCD-aware order.  Each
+// item calls the same device routines as the stage-wise kernels with the same launch
+// shape, so results are bit-identical to them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -44,7 +43,7 @@ constexpr int BATCH_THREADS = 512;
 constexpr int CAL_ROWS = 32;    // rows of one frame per CAL item
 constexpr int OUT_TILES = 4;    // combine tiles (of COMB_TILE pixels) per OUT item
 
-enum ItemType : int32_t { IT_CAL = 0, IT_MEANPART, IT_MEANFINAL, IT_SCORE, IT_PICK, IT_RECT, IT_OUT };
+enum ItemType : int32_t { IT_CAL = 0, IT_MEANPART, IT_MEANFINAL, IT_SCORE, IT_SUM, IT_PICK, IT_RECT, IT_OUT };
 constexpr int N_PHASES = IT_OUT + 1;
 
 struct Item {
@@ -81,49 +80,30 @@ struct BatchArgs {
     const StackDev *stacks;
 };
 
-// ---- work-queue kernels, one per phase ----------------------------------------------------
-// Every phase kernel runs a persistent grid that takes items of its own phase with
-// one atomic counter until the phase is drained; the graph orders the phases, so no
-// workgroup ever waits for another.
-__device__ __forceinline__ int32_t next_item(uint32_t *head, int32_t *slot)
+// ---- phase kernels: one workgroup per item ------------------------------------------------
+__global__ __launch_bounds__(BATCH_THREADS) void batch_cal(BatchArgs a, int32_t first)
 {
-    if (threadIdx.x == 0) *slot = (int32_t)atomicAdd(head, 1u);
-    __syncthreads();
-    const int32_t id = *slot;
-    __syncthreads();
-    return id;
-}
-
-__global__ __launch_bounds__(BATCH_THREADS) void batch_cal(BatchArgs a, int32_t first, int32_t count, uint32_t *head)
-{
-    __shared__ int32_t slot;
-    for (int32_t q; (q = next_item(head, &slot)) < count;) {
-        const Item it = a.items[first + q];
-        const StackDev &s = a.stacks[it.stack];
-        const int32_t bands = (int32_t)((s.H + CAL_ROWS - 1) / CAL_ROWS);
-        const int32_t k = it.a / bands, y0 = (it.a - k * bands) * CAL_ROWS;
-        const int32_t y1 = min(y0 + CAL_ROWS, s.H);
-        const int64_t n = (int64_t)(y1 - y0) * s.W;
-        for (int64_t i = threadIdx.x; i < n; i += BATCH_THREADS) {
-            const int32_t y = y0 + (int32_t)(i / s.W), x = (int32_t)(i % s.W);
-            const int64_t c = (int64_t)y * s.crp + x;
-            s.cal[((int64_t)k * s.H + y) * s.W + x] =
-                calib_px(s.raw[(int64_t)k * s.rfp + (int64_t)y * s.rrp + x], s.dark[c], s.flat[c]);
-        }
+    const Item it = a.items[first + blockIdx.x];
+    const StackDev &s = a.stacks[it.stack];
+    const int32_t bands = (int32_t)((s.H + CAL_ROWS - 1) / CAL_ROWS);
+    const int32_t k = it.a / bands, y0 = (it.a - k * bands) * CAL_ROWS;
+    const int32_t y1 = min(y0 + CAL_ROWS, s.H);
+    const int64_t n = (int64_t)(y1 - y0) * s.W;
+    for (int64_t i = threadIdx.x; i < n; i += BATCH_THREADS) {
+        const int32_t y = y0 + (int32_t)(i / s.W), x = (int32_t)(i % s.W);
+        const int64_t c = (int64_t)y * s.crp + x;
+        s.cal[((int64_t)k * s.H + y) * s.W + x] =
+            calib_px(s.raw[(int64_t)k * s.rfp + (int64_t)y * s.rrp + x], s.dark[c], s.flat[c]);
     }
 }
 
-__global__ __launch_bounds__(MEAN_THREADS) void batch_meanpart(BatchArgs a, int32_t first, int32_t count,
-                                                               uint32_t *head)
+__global__ __launch_bounds__(MEAN_THREADS) void batch_meanpart(BatchArgs a, int32_t first)
 {
-    __shared__ int32_t slot;
     __shared__ double scratch[MEAN_THREADS / 64];
-    for (int32_t q; (q = next_item(head, &slot)) < count;) {
-        const Item it = a.items[first + q];
-        const StackDev &s = a.stacks[it.stack];
-        const double v = tmpl_part_sum(s.sa.ref, s.W, s.sa.tx0, s.sa.ty0, s.sa.tw, s.sa.th, it.a, scratch);
-        if (threadIdx.x == 0) s.mean_parts[it.a] = v;
-    }
+    const Item it = a.items[first + blockIdx.x];
+    const StackDev &s = a.stacks[it.stack];
+    const double v = tmpl_part_sum(s.sa.ref, s.W, s.sa.tx0, s.sa.ty0, s.sa.tw, s.sa.th, it.a, scratch);
+    if (threadIdx.x == 0) s.mean_parts[it.a] = v;
 }
 
 __global__ __launch_bounds__(MEAN_THREADS) void batch_meanfinal(BatchArgs a, int32_t first)
@@ -136,16 +116,24 @@ __global__ __launch_bounds__(MEAN_THREADS) void batch_meanfinal(BatchArgs a, int
     if (threadIdx.x == 0) *s.mean = m;
 }
 
-__global__ __launch_bounds__(BATCH_THREADS) void batch_score(BatchArgs a, int32_t first, int32_t count,
-                                                             uint32_t *head)
+__global__ __launch_bounds__(BATCH_THREADS) void batch_score(BatchArgs a, int32_t first, int32_t count)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int32_t slot;
-    for (int32_t q; (q = next_item(head, &slot)) < count;) {
-        const Item it = a.items[first + q];
-        const StackDev &s = a.stacks[it.stack];
-        score_dispatch(s.K, [&](auto Kc) { score_tile<decltype(Kc)::value>(s.sa, it.a, smem); });
-    }
+    const Item it = a.items[first + xcd_logical_id((int32_t)blockIdx.x, count)];
+    const StackDev &s = a.stacks[it.stack];
+    score_dispatch(s.K, [&](auto Kc) { score_tile<decltype(Kc)::value>(s.sa, it.a, smem); });
+}
+
+__global__ __launch_bounds__(64 * SUM_WAVES) void batch_sum(BatchArgs a, int32_t first)
+{
+    __shared__ double part[SUM_WAVES][64];
+    const Item it = a.items[first + blockIdx.x];
+    const StackDev &s = a.stacks[it.stack];
+    const int32_t D = s.sa.D;
+    const int32_t blocks = (D * D + 63) / 64;
+    const int32_t k = it.a / blocks, cb = it.a - k * blocks;
+    sum_candidate_block(s.partial + (int64_t)k * s.sa.n_tiles * D * D, s.sa.n_tiles, D, s.R, s.R, 0, 0, cb,
+                        s.scores + (int64_t)k * D * D, part);
 }
 
 __global__ __launch_bounds__(256) void batch_pick(BatchArgs a, int32_t first)
@@ -154,13 +142,8 @@ __global__ __launch_bounds__(256) void batch_pick(BatchArgs a, int32_t first)
     const Item it = a.items[first + blockIdx.x];
     const StackDev &s = a.stacks[it.stack];
     const int32_t D = s.sa.D, k = it.a;
-    double *S = s.scores + (int64_t)k * D * D;
-    const double *pk = s.partial + (int64_t)k * s.sa.n_tiles * D * D;
-    for (int32_t c = threadIdx.x; c < D * D; c += blockDim.x)
-        S[c] = candidate_score(pk, s.sa.n_tiles, D, s.R, s.R, 0, 0, c);
-    __syncthreads();
     const int32_t kf = k + (k >= s.ref ? 1 : 0);
-    pick_frame(S, D, s.R, s.R, 0, 0, s.offsets + kf, scratch);
+    pick_frame(s.scores + (int64_t)k * D * D, D, s.R, s.R, 0, 0, s.offsets + kf, scratch);
 }
 
 __global__ void batch_rect(BatchArgs a, int32_t first)
@@ -209,13 +192,12 @@ __global__ void batch_rect(BatchArgs a, int32_t first)
 
 __device__ __forceinline__ int32_t clampi(int32_t v, int32_t lo, int32_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-__global__ __launch_bounds__(COMB_TILE) void batch_out(BatchArgs a, int32_t first, int32_t count, uint32_t *head)
+__global__ __launch_bounds__(COMB_TILE) void batch_out(BatchArgs a, int32_t first)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int32_t slot;
     float *tile = reinterpret_cast<float *>(smem);
-    for (int32_t q; (q = next_item(head, &slot)) < count;) {
-        const Item it = a.items[first + q];
+    {
+        const Item it = a.items[first + blockIdx.x];
         const StackDev &s = a.stacks[it.stack];
         const int32_t x0 = s.rect[0], y0 = s.rect[1], w = s.rect[2], h = s.rect[3];
         const int64_t plane = (int64_t)w * h;
@@ -256,9 +238,8 @@ __global__ __launch_bounds__(COMB_TILE) void batch_out(BatchArgs a, int32_t firs
     }
 }
 
-__global__ void batch_reset(uint32_t *heads, int32_t n, int64_t *const *n_rej, int32_t n_stacks)
+__global__ void batch_reset(int64_t *const *n_rej, int32_t n_stacks)
 {
-    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) heads[i] = 0u;
     for (int32_t i = threadIdx.x; i < n_stacks; i += blockDim.x)
         if (n_rej[i]) *n_rej[i] = 0;
 }
@@ -274,7 +255,7 @@ struct StackLayout {
 
 struct BatchLayout {
     std::vector<StackLayout> st;
-    size_t items, stacks, heads, nrej_ptrs, total;
+    size_t items, stacks, nrej_ptrs, total;
     int32_t n_items;
     int32_t first[N_PHASES], count[N_PHASES];
     size_t score_lds, out_lds;
@@ -335,6 +316,7 @@ static BatchLayout layout_of(const reduce_stack_t *stacks, int32_t n)
         sl.count[IT_MEANPART] = n_mean_parts;
         sl.count[IT_MEANFINAL] = 1;
         sl.count[IT_SCORE] = nreg * p.n_tiles * p.G;
+        sl.count[IT_SUM] = nreg * (int32_t)ceil_div((int64_t)p.D * p.D, 64);
         sl.count[IT_PICK] = nreg;
         sl.count[IT_RECT] = 1;
         sl.count[IT_OUT] = (int32_t)ceil_div(fp, (int64_t)COMB_TILE * OUT_TILES);
@@ -353,24 +335,20 @@ static BatchLayout layout_of(const reduce_stack_t *stacks, int32_t n)
     off += al(sizeof(Item) * (size_t)std::max<int64_t>(total, 0));
     L.stacks = off;
     off += al(sizeof(StackDev) * (size_t)n);
-    L.heads = off;
-    off += 256;
     L.nrej_ptrs = off;
     off += al(sizeof(int64_t *) * (size_t)n);
     L.total = off;
     return L;
 }
 
-struct GraphEntry {
+struct BatchEntry {
     uint64_t hash = 0;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    bool ready = false;
     std::vector<unsigned char> host;  // uploaded descriptor bytes (kept alive with the entry)
 };
 
 static std::mutex g_batch_mu;
-static std::map<void *, GraphEntry> g_graphs;  // by workspace address
-static hipStream_t g_capture_stream = nullptr;
+static std::map<void *, BatchEntry> g_entries;  // by workspace address
 
 static uint64_t fnv1a(const void *p, size_t n, uint64_t h = 1469598103934665603ull)
 {
@@ -382,20 +360,9 @@ static uint64_t fnv1a(const void *p, size_t n, uint64_t h = 1469598103934665603u
     return h;
 }
 
-// Resident workgroups of a kernel over the whole device, at most `items`.
-template <typename K>
-static int persistent_grid(K kernel, int threads, size_t lds, int32_t items)
-{
-    int dev = 0, cus = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev))
-        return -1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess || per_cu < 1)
-        return -1;
-    return (int)std::min<int64_t>((int64_t)cus * per_cu, std::max<int32_t>(items, 1));
-}
-
-static int build_entry(const reduce_stack_t *stacks, int32_t n, void *ws, const BatchLayout &L, GraphEntry *e,
-                       hipStream_t s)
+// Host image of the descriptors of every stack and of the item table.
+static int build_descriptors(const reduce_stack_t *stacks, int32_t n, void *ws, const BatchLayout &L,
+                             BatchEntry *e)
 {
     unsigned char *base = static_cast<unsigned char *>(ws);
     std::vector<StackDev> sd(n);
@@ -438,7 +405,7 @@ static int build_entry(const reduce_stack_t *stacks, int32_t n, void *ws, const 
         d.sa = make_score_args(sl.plan, ref, d.cal, nullptr, d.mean, d.partial, st.W, st.H, std::max(st.N - 1, 1), R,
                                R, R, R, st.W - 2 * R, st.H - 2 * R, d.ref);
     }
-    // the queue, phase by phase; search and output items of the largest stacks first
+    // the table, phase by phase; within a phase the largest stacks first
     std::vector<int32_t> order(n);
     for (int32_t i = 0; i < n; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
@@ -454,64 +421,43 @@ static int build_entry(const reduce_stack_t *stacks, int32_t n, void *ws, const 
         for (int32_t i : order)
             for (int32_t a = 0; a < L.st[i].count[q]; ++a) items.push_back({q, i, a, 0});
     if ((int32_t)items.size() != L.n_items) return fail(REDUCE_ERR_SHAPE, "reduce_stack_batch: item count");
-
-    // descriptors into the workspace
     e->host.assign(L.total - L.items, 0);
     std::memcpy(e->host.data(), items.data(), sizeof(Item) * items.size());
     std::memcpy(e->host.data() + (L.stacks - L.items), sd.data(), sizeof(StackDev) * sd.size());
     std::memcpy(e->host.data() + (L.nrej_ptrs - L.items), nrej.data(), sizeof(int64_t *) * nrej.size());
-    if (hipMemcpyAsync(base + L.items, e->host.data(), e->host.size(), hipMemcpyHostToDevice, s) != hipSuccess)
-        return fail(REDUCE_ERR_HIP, "reduce_stack_batch: descriptor upload");
-
-    BatchArgs a;
-    a.items = reinterpret_cast<const Item *>(base + L.items);
-    a.stacks = reinterpret_cast<const StackDev *>(base + L.stacks);
-    uint32_t *heads = reinterpret_cast<uint32_t *>(base + L.heads);
-    int64_t *const *nrej_dev = reinterpret_cast<int64_t *const *>(base + L.nrej_ptrs);
-
-    const int g_cal = persistent_grid(batch_cal, BATCH_THREADS, 0, L.count[IT_CAL]);
-    const int g_mean = persistent_grid(batch_meanpart, MEAN_THREADS, 0, L.count[IT_MEANPART]);
-    const int g_score = persistent_grid(batch_score, BATCH_THREADS, L.score_lds, L.count[IT_SCORE]);
-    const int g_out = persistent_grid(batch_out, COMB_TILE, L.out_lds, L.count[IT_OUT]);
-    if (g_cal < 1 || g_mean < 1 || g_score < 1 || g_out < 1)
-        return fail(REDUCE_ERR_HIP, "reduce_stack_batch: occupancy query");
-
-    // record the phase kernels into a graph on a private stream
-    if (!g_capture_stream && hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking) != hipSuccess)
-        return fail(REDUCE_ERR_HIP, "reduce_stack_batch: capture stream");
-    hipStream_t c = g_capture_stream;
-    if (hipStreamBeginCapture(c, hipStreamCaptureModeThreadLocal) != hipSuccess)
-        return fail(REDUCE_ERR_HIP, "reduce_stack_batch: begin capture");
-    hipLaunchKernelGGL(batch_reset, dim3(1), dim3(256), 0, c, heads, (int32_t)N_PHASES, nrej_dev, n);
-    hipLaunchKernelGGL(batch_cal, dim3(g_cal), dim3(BATCH_THREADS), 0, c, a, L.first[IT_CAL], L.count[IT_CAL],
-                       heads + IT_CAL);
-    if (L.count[IT_MEANPART] > 0)
-        hipLaunchKernelGGL(batch_meanpart, dim3(g_mean), dim3(MEAN_THREADS), 0, c, a, L.first[IT_MEANPART],
-                           L.count[IT_MEANPART], heads + IT_MEANPART);
-    hipLaunchKernelGGL(batch_meanfinal, dim3(L.count[IT_MEANFINAL]), dim3(MEAN_THREADS), 0, c, a,
-                       L.first[IT_MEANFINAL]);
-    if (L.count[IT_SCORE] > 0)
-        hipLaunchKernelGGL(batch_score, dim3(g_score), dim3(BATCH_THREADS), L.score_lds, c, a, L.first[IT_SCORE],
-                           L.count[IT_SCORE], heads + IT_SCORE);
-    if (L.count[IT_PICK] > 0)
-        hipLaunchKernelGGL(batch_pick, dim3(L.count[IT_PICK]), dim3(256), 0, c, a, L.first[IT_PICK]);
-    hipLaunchKernelGGL(batch_rect, dim3(L.count[IT_RECT]), dim3(64), 0, c, a, L.first[IT_RECT]);
-    hipLaunchKernelGGL(batch_out, dim3(g_out), dim3(COMB_TILE), L.out_lds, c, a, L.first[IT_OUT], L.count[IT_OUT],
-                       heads + IT_OUT);
-    const hipError_t launch_err = hipGetLastError();
-    if (hipStreamEndCapture(c, &e->graph) != hipSuccess || launch_err != hipSuccess)
-        return fail(REDUCE_ERR_HIP, "reduce_stack_batch: graph capture");
-    if (hipGraphInstantiate(&e->exec, e->graph, nullptr, nullptr, 0) != hipSuccess)
-        return fail(REDUCE_ERR_HIP, "reduce_stack_batch: graph instantiate");
     return REDUCE_OK;
 }
 
-static void destroy_entry(GraphEntry &e)
+static int launch_phases(int32_t n, void *ws, const BatchLayout &L, hipStream_t s)
 {
-    if (e.exec) hipGraphExecDestroy(e.exec);
-    if (e.graph) hipGraphDestroy(e.graph);
-    e.exec = nullptr;
-    e.graph = nullptr;
+    unsigned char *base = static_cast<unsigned char *>(ws);
+    BatchArgs a;
+    a.items = reinterpret_cast<const Item *>(base + L.items);
+    a.stacks = reinterpret_cast<const StackDev *>(base + L.stacks);
+    int64_t *const *nrej_dev = reinterpret_cast<int64_t *const *>(base + L.nrej_ptrs);
+    hipLaunchKernelGGL(batch_reset, dim3(1), dim3(256), 0, s, nrej_dev, n);
+    if (L.count[IT_CAL] > 0)
+        hipLaunchKernelGGL(batch_cal, dim3(L.count[IT_CAL]), dim3(BATCH_THREADS), 0, s, a, L.first[IT_CAL]);
+    if (L.count[IT_MEANPART] > 0)
+        hipLaunchKernelGGL(batch_meanpart, dim3(L.count[IT_MEANPART]), dim3(MEAN_THREADS), 0, s, a,
+                           L.first[IT_MEANPART]);
+    hipLaunchKernelGGL(batch_meanfinal, dim3(L.count[IT_MEANFINAL]), dim3(MEAN_THREADS), 0, s, a,
+                       L.first[IT_MEANFINAL]);
+    if (L.count[IT_SCORE] > 0) {
+        ProfScope prof("batch_score", s);
+        hipLaunchKernelGGL(batch_score, dim3(L.count[IT_SCORE]), dim3(BATCH_THREADS), L.score_lds, s, a,
+                           L.first[IT_SCORE], L.count[IT_SCORE]);
+    }
+    if (L.count[IT_SUM] > 0)
+        hipLaunchKernelGGL(batch_sum, dim3(L.count[IT_SUM]), dim3(64 * SUM_WAVES), 0, s, a, L.first[IT_SUM]);
+    if (L.count[IT_PICK] > 0)
+        hipLaunchKernelGGL(batch_pick, dim3(L.count[IT_PICK]), dim3(256), 0, s, a, L.first[IT_PICK]);
+    hipLaunchKernelGGL(batch_rect, dim3(L.count[IT_RECT]), dim3(64), 0, s, a, L.first[IT_RECT]);
+    {
+        ProfScope prof("batch_out", s);
+        hipLaunchKernelGGL(batch_out, dim3(L.count[IT_OUT]), dim3(COMB_TILE), L.out_lds, s, a, L.first[IT_OUT]);
+    }
+    return check_launch("reduce_stack_batch");
 }
 
 }  // namespace rd
@@ -533,19 +479,15 @@ extern "C" int reduce_stack_batch(const reduce_stack_t *stacks, int32_t n, void 
     if (v != REDUCE_OK) return v;
     const BatchLayout L = layout_of(stacks, n);
     if (L.n_items < 0) return fail(REDUCE_ERR_UNSUPPORTED, "reduce_stack_batch: too many work items");
+    for (int q = 0; q < N_PHASES; ++q)
+        if (L.count[q] > 0x7fffffff / 2) return fail(REDUCE_ERR_UNSUPPORTED, "reduce_stack_batch: too many items");
+    if (L.score_lds > 65536) return fail(REDUCE_ERR_UNSUPPORTED, "reduce_stack_batch: search tile above 64 KB");
     if (!ws || ws_bytes < L.total)
         return fail(REDUCE_ERR_WORKSPACE, "reduce_stack_batch: workspace needs " + std::to_string(L.total) + " bytes");
-    // Switched off: the graph replay of this path did not complete on its first runs on
-    // the device, and the cause has not been identified; nothing is launched.
-    return fail(REDUCE_ERR_UNSUPPORTED, "reduce_stack_batch: the batched graph path is switched off "
-                                        "(its replay did not complete on the device; cause not yet found)");
-}
-
-static int stack_batch_launch(const reduce_stack_t *stacks, int32_t n, void *ws, const BatchLayout &L, void *stream)
-{
     hipStream_t s = as_stream(stream);
 
-    // a graph per workspace, rebuilt when the stacks or their launch shapes change
+    // the host image of the descriptors is rebuilt only when the stacks or their launch
+    // shapes change; it is uploaded into the workspace on every call
     uint64_t h = fnv1a(stacks, sizeof(reduce_stack_t) * (size_t)n);
     for (const StackLayout &sl : L.st) h = fnv1a(&sl.plan, sizeof(RegPlan), h);
     for (int32_t i = 0; i < n; ++i) {
@@ -554,21 +496,23 @@ static int stack_batch_launch(const reduce_stack_t *stacks, int32_t n, void *ws,
     }
     h = fnv1a(&L.total, sizeof(L.total), h);
     std::lock_guard<std::mutex> lk(g_batch_mu);
-    GraphEntry &e = g_graphs[ws];
-    if (!e.exec || e.hash != h) {
-        if (e.exec && hipStreamSynchronize(s) != hipSuccess)  // the old graph may still run
-            return fail(REDUCE_ERR_HIP, "reduce_stack_batch: synchronize before rebuilding");
-        destroy_entry(e);
-        e = GraphEntry{};
-        const int rc = build_entry(stacks, n, ws, L, &e, s);
+    BatchEntry &e = g_entries[ws];
+    if (!e.ready || e.hash != h) {
+        // an earlier call on this workspace may still read the old descriptors
+        if (e.ready && hipStreamSynchronize(s) != hipSuccess)
+            return fail(REDUCE_ERR_HIP, "reduce_stack_batch: synchronize before new descriptors");
+        e = BatchEntry{};
+        const int rc = build_descriptors(stacks, n, ws, L, &e);
         if (rc != REDUCE_OK) {
-            destroy_entry(e);
-            g_graphs.erase(ws);
+            g_entries.erase(ws);
             return rc;
         }
         e.hash = h;
+        e.ready = true;
     }
+    if (hipMemcpyAsync(static_cast<unsigned char *>(ws) + L.items, e.host.data(), e.host.size(),
+                       hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(REDUCE_ERR_HIP, "reduce_stack_batch: descriptor upload");
     ProfScope prof("stack_batch", s);
-    if (hipGraphLaunch(e.exec, s) != hipSuccess) return fail(REDUCE_ERR_HIP, "reduce_stack_batch: graph launch");
-    return check_launch("reduce_stack_batch");
+    return launch_phases(n, ws, L, s);
 }

@@ -28,18 +28,6 @@ __global__ __launch_bounds__(MEAN_THREADS) void tmpl_mean_final(const double *__
     if (threadIdx.x == 0) *mean = m;
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs.  Give each XCD a
-// contiguous run of logical work items (tile fastest, then candidate group, then
-// frame) so that neighbouring tiles, which share frame rows and columns, hit the
-// same L2.
-__device__ __forceinline__ int32_t xcd_logical_id(int32_t lin, int32_t total)
-{
-    constexpr int32_t NXCD = 8;
-    const int32_t per = total / NXCD, rem = total % NXCD;
-    const int32_t x = lin % NXCD, slot = lin / NXCD;
-    return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + slot;
-}
-
 template <int K>
 __global__ __launch_bounds__(512) void score_tiles(ScoreArgs a)
 {
@@ -48,12 +36,7 @@ __global__ __launch_bounds__(512) void score_tiles(ScoreArgs a)
     score_tile<K>(a, xcd_logical_id((int32_t)blockIdx.x, total), smem);
 }
 
-// Scores of each frame from its tile partials.  A workgroup takes 64 candidates; wave
-// w sums tiles w, w + SUM_WAVES, ... in order and the SUM_WAVES partial sums are added
-// in wave order, so the result is the same on every run.  -inf outside the clipped
-// window.
-constexpr int SUM_WAVES = 8;
-
+// Scores of each frame from its tile partials (64 candidates per workgroup).
 __global__ __launch_bounds__(64 * SUM_WAVES) void sum_tiles(const double *__restrict__ partial, int32_t n_tiles,
                                                             int32_t D, int32_t R, int32_t Rmax,
                                                             const int32_t *__restrict__ centers,
@@ -61,26 +44,9 @@ __global__ __launch_bounds__(64 * SUM_WAVES) void sum_tiles(const double *__rest
 {
     __shared__ double part[SUM_WAVES][64];
     const int32_t k = blockIdx.y;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int32_t DD = D * D;
-    const int32_t cand = blockIdx.x * 64 + lane;
-    double s = 0.0;
-    if (cand < DD) {
-        const double *pk = partial + (int64_t)k * n_tiles * DD + cand;
-#pragma unroll 4
-        for (int32_t t = wave; t < n_tiles; t += SUM_WAVES) s += pk[(int64_t)t * DD];
-    }
-    part[wave][lane] = s;
-    __syncthreads();
-    if (wave != 0 || cand >= DD) return;
-    double tot = 0.0;
-#pragma unroll
-    for (int w = 0; w < SUM_WAVES; ++w) tot += part[w][lane];
     const int32_t cx = centers ? centers[2 * k] : 0, cy = centers ? centers[2 * k + 1] : 0;
-    const int32_t jj = cand / D, ii = cand - jj * D;
-    const int32_t dx = cx - R + ii, dy = cy - R + jj;
-    const bool inside = dx >= -Rmax && dx <= Rmax && dy >= -Rmax && dy <= Rmax;
-    scores[(int64_t)k * DD + cand] = inside ? tot : -INFINITY;
+    sum_candidate_block(partial + (int64_t)k * n_tiles * D * D, n_tiles, D, R, Rmax, cx, cy, blockIdx.x,
+                        scores + (int64_t)k * D * D, part);
 }
 
 __global__ __launch_bounds__(256) void pick_offsets(const double *__restrict__ scores, int32_t D, int32_t R,

@@ -246,6 +246,54 @@ __device__ __forceinline__ void score_dispatch(int K, F &&f)
     }
 }
 
+// ---- XCD-aware work order ----------------------------------------------------------------
+// Workgroups are dispatched round-robin over the 8 XCDs.  Give each XCD a
+// contiguous run of logical work items (tile fastest, then candidate group, then
+// frame) so that neighbouring tiles, which share frame rows and columns, hit the
+// same L2.
+__device__ __forceinline__ int32_t xcd_logical_id(int32_t lin, int32_t total)
+{
+    constexpr int32_t NXCD = 8;
+    const int32_t per = total / NXCD, rem = total % NXCD;
+    const int32_t x = lin % NXCD, slot = lin / NXCD;
+    return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + slot;
+}
+
+// ---- sum of tile partials ------------------------------------------------------------------
+// Candidates 64*cblock .. +63 of one frame, by a workgroup of 64*SUM_WAVES threads: wave w
+// sums tiles w, w + SUM_WAVES, ... in order, then the SUM_WAVES partial sums are added in
+// wave order, so every path that uses this routine gets the same bits.  -inf outside the
+// clipped window.
+constexpr int SUM_WAVES = 8;
+
+__device__ __forceinline__ void sum_candidate_block(const double *__restrict__ partial_k, int32_t n_tiles,
+                                                    int32_t D, int32_t R, int32_t Rmax, int32_t cx, int32_t cy,
+                                                    int32_t cblock, double *__restrict__ scores_k,
+                                                    double (*part)[64])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int32_t DD = D * D;
+    const int32_t cand = cblock * 64 + lane;
+    double s = 0.0;
+    if (cand < DD && wave < SUM_WAVES) {
+        const double *pk = partial_k + cand;
+#pragma unroll 4
+        for (int32_t t = wave; t < n_tiles; t += SUM_WAVES) s += pk[(int64_t)t * DD];
+    }
+    if (wave < SUM_WAVES) part[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0 && cand < DD) {
+        double tot = 0.0;
+#pragma unroll
+        for (int w = 0; w < SUM_WAVES; ++w) tot += part[w][lane];
+        const int32_t jj = cand / D, ii = cand - jj * D;
+        const int32_t dx = cx - R + ii, dy = cy - R + jj;
+        const bool inside = dx >= -Rmax && dx <= Rmax && dy >= -Rmax && dy <= Rmax;
+        scores_k[cand] = inside ? tot : -INFINITY;
+    }
+    __syncthreads();
+}
+
 // ---- scores of one frame from its partials ------------------------------------------------
 // Sum over tiles in tile order; -inf outside the clipped window.
 __device__ __forceinline__ double candidate_score(const double *partial_k, int32_t n_tiles, int32_t D, int32_t R,

@@ -27,7 +27,8 @@
 namespace rd {
 
 constexpr int MEAN_THREADS = 256;  // logical threads of the template-mean reduction
-constexpr int MEAN_ROWS = 16;      // template rows per mean part
+constexpr int MEAN_ROWS = 2;       // template rows per mean part
+constexpr int MEAN_U = 4;          // columns per thread loaded together
 
 struct ScoreArgs {
     const float *ref;
@@ -60,7 +61,8 @@ __device__ __forceinline__ double block_sum_f64(double v, double *scratch, int w
 }
 
 // Sum of template rows [MEAN_ROWS*part, +MEAN_ROWS) with MEAN_THREADS logical threads
-// striding over columns; valid in thread 0.
+// striding over columns; valid in thread 0.  A thread loads MEAN_U columns of a row
+// before adding them, in column order.
 __device__ __forceinline__ double tmpl_part_sum(const float *ref, int32_t W, int32_t tx0, int32_t ty0, int32_t tw,
                                                 int32_t th, int32_t part, double *scratch)
 {
@@ -68,8 +70,20 @@ __device__ __forceinline__ double tmpl_part_sum(const float *ref, int32_t W, int
     const int32_t y1 = min(y0 + MEAN_ROWS, th);
     double s = 0.0;
     if (threadIdx.x < MEAN_THREADS)
-        for (int32_t y = y0; y < y1; ++y)
-            for (int32_t x = threadIdx.x; x < tw; x += MEAN_THREADS) s += (double)ref[(int64_t)(ty0 + y) * W + tx0 + x];
+        for (int32_t y = y0; y < y1; ++y) {
+            const float *row = ref + (int64_t)(ty0 + y) * W + tx0;
+            for (int32_t x0 = threadIdx.x; x0 < tw; x0 += MEAN_U * MEAN_THREADS) {
+                float v[MEAN_U];
+#pragma unroll
+                for (int u = 0; u < MEAN_U; ++u) {
+                    const int32_t x = x0 + u * MEAN_THREADS;
+                    v[u] = row[x < tw ? x : 0];
+                }
+#pragma unroll
+                for (int u = 0; u < MEAN_U; ++u)
+                    if (x0 + u * MEAN_THREADS < tw) s += (double)v[u];
+            }
+        }
     return block_sum_f64(s, scratch, MEAN_THREADS / 64);
 }
 

@@ -7,6 +7,8 @@
 // deviations and drop counts are combined with wavefront butterfly reductions.
 // Mean and sigma are evaluated in double.  Bytes per input pixel: 4 read, plus
 // 4/N for the output and 1 per value when the keep mask is requested.
+#include <cstdlib>
+
 #include "common.h"
 #include "combine_core.h"
 
@@ -65,19 +67,13 @@ __device__ __forceinline__ void clip_pass(const float (&x)[MAXV], uint64_t kept,
         }
 }
 
+// Clip one column held in registers; returns the mean and updates kept / dropped.
 template <int MAXV>
-__global__ __launch_bounds__(COMB_TILE) void combine_cols(
-    const float *__restrict__ aligned, int64_t plane, int32_t N, double ksigma, int32_t max_iters,
-    float *__restrict__ out, uint8_t *__restrict__ keep, unsigned long long *__restrict__ n_rej)
+__device__ __forceinline__ float clip_registers(const float (&x)[MAXV], int32_t N, double ksigma, int32_t max_iters,
+                                                uint64_t &kept, unsigned &dropped)
 {
-    const int64_t p = (int64_t)blockIdx.x * COMB_TILE + threadIdx.x;
-    const bool live = p < plane;
-    float x[MAXV];
-#pragma unroll
-    for (int i = 0; i < MAXV; ++i) x[i] = (i < N && live) ? aligned[(int64_t)i * plane + p] : 0.0f;
-    uint64_t kept = N >= 64 ? ~0ull : ((1ull << N) - 1ull);
+    kept = N >= 64 ? ~0ull : ((1ull << N) - 1ull);
     int n = N;
-    unsigned dropped = 0;
     double s = 0.0, m = 0.0, q = 0.0, dmax = 0.0;
     bool final_known = false;
     for (int32_t it = 0; it < max_iters; ++it) {
@@ -106,21 +102,94 @@ __global__ __launch_bounds__(COMB_TILE) void combine_cols(
         for (int i = 0; i < MAXV; ++i)
             if ((kept >> i) & 1ull) s = __dadd_rn(s, (double)x[i]);
     }
-    if (live) {
-        out[p] = (float)(s / (double)n);
-        if (keep) {
+    return (float)(s / (double)n);
+}
+
+// PX adjacent pixel columns per thread: each frame's PX values come in as one vector
+// load (plane and pointer aligned to PX floats), then the columns are clipped one
+// after the other.
+template <int MAXV, int PX>
+__global__ __launch_bounds__(COMB_TILE) void combine_cols(
+    const float *__restrict__ aligned, int64_t plane, int32_t N, double ksigma, int32_t max_iters,
+    float *__restrict__ out, uint8_t *__restrict__ keep, unsigned long long *__restrict__ n_rej)
+{
+    const int64_t p0 = ((int64_t)blockIdx.x * COMB_TILE + threadIdx.x) * PX;
+    float xs[PX][MAXV];
+    if (PX == 1 || p0 + PX <= plane) {
 #pragma unroll
-            for (int i = 0; i < MAXV; ++i)
-                if (i < N) keep[(int64_t)i * plane + p] = (uint8_t)((kept >> i) & 1ull);
+        for (int i = 0; i < MAXV; ++i) {
+            if (i < N) {
+                const float *src = aligned + (int64_t)i * plane + p0;
+                if (PX == 4) {
+                    const float4 v = *reinterpret_cast<const float4 *>(src);
+                    xs[0][i] = v.x;
+                    xs[1][i] = v.y;
+                    xs[2][i] = v.z;
+                    xs[3][i] = v.w;
+                } else if (PX == 2) {
+                    const float2 v = *reinterpret_cast<const float2 *>(src);
+                    xs[0][i] = v.x;
+                    xs[1][i] = v.y;
+                } else {
+                    xs[0][i] = p0 < plane ? src[0] : 0.0f;
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < PX; ++c) xs[c][i] = 0.0f;
+            }
         }
+    } else {
+#pragma unroll
+        for (int i = 0; i < MAXV; ++i)
+#pragma unroll
+            for (int c = 0; c < PX; ++c)
+                xs[c][i] = (i < N && p0 + c < plane) ? aligned[(int64_t)i * plane + p0 + c] : 0.0f;
+    }
+    unsigned dropped = 0;
+    float res[PX];
+    uint64_t kept[PX];
+#pragma unroll
+    for (int c = 0; c < PX; ++c) {
+        unsigned d = 0;
+        res[c] = clip_registers<MAXV>(xs[c], N, ksigma, max_iters, kept[c], d);
+        if (p0 + c < plane) dropped += d;
+    }
+    if (PX > 1 && p0 + PX <= plane) {
+        if (PX == 4)
+            *reinterpret_cast<float4 *>(out + p0) = make_float4(res[0], res[1], res[2], res[3]);
+        else
+            *reinterpret_cast<float2 *>(out + p0) = make_float2(res[0], res[1]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < PX; ++c)
+            if (p0 + c < plane) out[p0 + c] = res[c];
+    }
+    if (keep) {
+#pragma unroll
+        for (int i = 0; i < MAXV; ++i)
+            if (i < N)
+#pragma unroll
+                for (int c = 0; c < PX; ++c)
+                    if (p0 + c < plane) keep[(int64_t)i * plane + p0 + c] = (uint8_t)((kept[c] >> i) & 1ull);
     }
     if (n_rej) {
-        const unsigned total = block_sum_u32(live ? dropped : 0u);
+        const unsigned total = block_sum_u32(dropped);
         if (threadIdx.x == 0 && total) atomicAdd(n_rej, (unsigned long long)total);
     }
 }
 
 __global__ void zero_u64(unsigned long long *p) { *p = 0ull; }
+
+// Pixel columns per thread of the one-lane kernel (at most 4); REDUCE_COMBINE_PX overrides.
+static int combine_px()
+{
+    const char *e = std::getenv("REDUCE_COMBINE_PX");
+    if (e) {
+        const int v = std::atoi(e);
+        if (v == 1 || v == 2 || v == 4) return v;
+    }
+    return 4;
+}
 
 void combine_dispatch(int lanes, const float *aligned, int64_t plane, int32_t N, double ksigma, int32_t max_iters,
                       float *out, uint8_t *keep, unsigned long long *n_rej, hipStream_t s)
@@ -133,16 +202,29 @@ void combine_dispatch(int lanes, const float *aligned, int64_t plane, int32_t N,
         hipLaunchKernelGGL((combine_kernel<L, V>), dim3(blocks), dim3(COMB_TILE), lds, s, aligned, plane, N, ksigma,
                            max_iters, out, keep, n_rej);
     };
-    auto launch_cols = [&](auto Vc) {
-        constexpr int V = decltype(Vc)::value;
-        hipLaunchKernelGGL((combine_cols<V>), dim3(blocks), dim3(COMB_TILE), 0, s, aligned, plane, N, ksigma,
-                           max_iters, out, keep, n_rej);
+    // vector loads need the frame planes and the pointer aligned to the pixel group
+    const bool v4 = plane % 4 == 0 && (reinterpret_cast<uintptr_t>(aligned) & 15u) == 0 &&
+                    (reinterpret_cast<uintptr_t>(out) & 15u) == 0;
+    const bool v2 = plane % 2 == 0 && (reinterpret_cast<uintptr_t>(aligned) & 7u) == 0 &&
+                    (reinterpret_cast<uintptr_t>(out) & 7u) == 0;
+    auto launch_cols = [&](auto Vc, auto Pc) {
+        constexpr int V = decltype(Vc)::value, P = decltype(Pc)::value;
+        hipLaunchKernelGGL((combine_cols<V, P>), dim3((unsigned)ceil_div(plane, (int64_t)COMB_TILE * P)),
+                           dim3(COMB_TILE), 0, s, aligned, plane, N, ksigma, max_iters, out, keep, n_rej);
     };
+    const int px = combine_px();
     switch (lanes) {
     case 1:
-        if (N <= 16) launch_cols(std::integral_constant<int, 16>{});
-        else if (N <= 32) launch_cols(std::integral_constant<int, 32>{});
-        else launch_cols(std::integral_constant<int, 48>{});
+        if (N <= 16) {
+            if (v4 && px >= 4) launch_cols(std::integral_constant<int, 16>{}, std::integral_constant<int, 4>{});
+            else if (v2 && px >= 2) launch_cols(std::integral_constant<int, 16>{}, std::integral_constant<int, 2>{});
+            else launch_cols(std::integral_constant<int, 16>{}, std::integral_constant<int, 1>{});
+        } else if (N <= 32) {
+            if (v2 && px >= 2) launch_cols(std::integral_constant<int, 32>{}, std::integral_constant<int, 2>{});
+            else launch_cols(std::integral_constant<int, 32>{}, std::integral_constant<int, 1>{});
+        } else {
+            launch_cols(std::integral_constant<int, 48>{}, std::integral_constant<int, 1>{});
+        }
         break;
     case 2: launch(std::integral_constant<int, 2>{}, std::integral_constant<int, 24>{}); break;
     case 4: launch(std::integral_constant<int, 4>{}, std::integral_constant<int, 12>{}); break;

@@ -20,6 +20,29 @@ __device__ __forceinline__ int32_t clampi(int32_t v, int32_t lo, int32_t hi)
     return v < lo ? lo : (v > hi ? hi : v);
 }
 
+// V outputs of one row at o + u0: 16-byte stores when every output row starts 16-byte
+// aligned (vec_store 4: w % 4 == 0), 8-byte stores when rows start 8-byte aligned
+// (vec_store 2: w even), single floats otherwise and at the row end.
+template <int V>
+__device__ __forceinline__ void store_outputs(float *__restrict__ o, int32_t u0, int32_t w, int vec_store,
+                                              const float (&r)[V])
+{
+    if (vec_store == 4 && u0 + V <= w) {
+#pragma unroll
+        for (int q = 0; q < V / 4; ++q)
+            *reinterpret_cast<float4 *>(o + u0 + 4 * q) = make_float4(r[4 * q], r[4 * q + 1], r[4 * q + 2],
+                                                                      r[4 * q + 3]);
+    } else if (vec_store == 2 && u0 + V <= w) {
+#pragma unroll
+        for (int q = 0; q < V / 2; ++q)
+            *reinterpret_cast<float2 *>(o + u0 + 2 * q) = make_float2(r[2 * q], r[2 * q + 1]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+            if (u0 + e < w) o[u0 + e] = r[e];
+    }
+}
+
 // One tap row of a thread: the floats from the 16-byte aligned column b = c0 - (c0 & 3)
 // on, so that tap e (column c0 + e) is raw[(c0 & 3) + e].  The misalignment is the same
 // for every thread of a frame.  Rows whose aligned span lies inside the frame row come
@@ -74,7 +97,7 @@ struct TapRow {
 template <bool INTEGER, int V>
 __global__ __launch_bounds__(SH_BLOCK) void shift_kernel(
     const float *__restrict__ in, float *__restrict__ out, int32_t W, int32_t H,
-    const float *__restrict__ offs, int32_t x0, int32_t y0, int32_t w, int32_t h, bool vec_store, bool aligned)
+    const float *__restrict__ offs, int32_t x0, int32_t y0, int32_t w, int32_t h, int vec_store, bool aligned)
 {
     const int32_t k = blockIdx.z;
     const int32_t v0 = blockIdx.y * SH_ROWS;
@@ -123,16 +146,7 @@ __global__ __launch_bounds__(SH_BLOCK) void shift_kernel(
             }
         }
         float *o = out + ((int64_t)k * h + v) * w;
-        if (vec_store && u0 + V <= w) {
-#pragma unroll
-            for (int q = 0; q < V / 4; ++q)
-                *reinterpret_cast<float4 *>(o + u0 + 4 * q) = make_float4(r[4 * q], r[4 * q + 1], r[4 * q + 2],
-                                                                          r[4 * q + 3]);
-        } else {
-#pragma unroll
-            for (int e = 0; e < V; ++e)
-                if (u0 + e < w) o[u0 + e] = r[e];
-        }
+        store_outputs<V>(o, u0, w, vec_store, r);
         if (!more) break;
         if (jn == j1 && j1 != j) {
             up = lo;                      // rows advanced by one
@@ -156,7 +170,7 @@ template <bool INTEGER, int V, int RB, int AL>
 __device__ __forceinline__ void shift_rows_body(const float *__restrict__ f, float *__restrict__ out, int32_t W,
                                                 int32_t H, int32_t k, int32_t v0, int32_t v1, int32_t u0, int32_t c0,
                                                 int32_t jbase, const ShiftSetup &ss, int32_t w, int32_t h,
-                                                bool vec_store, bool aligned)
+                                                int vec_store, bool aligned)
 {
     constexpr int RAW = V + 4;
     const bool step = ss.a > 0.0;
@@ -201,16 +215,7 @@ __device__ __forceinline__ void shift_rows_body(const float *__restrict__ f, flo
             }
             if (v + u < v1) {
                 float *o = out + ((int64_t)k * h + v + u) * w;
-                if (vec_store && u0 + V <= w) {
-#pragma unroll
-                    for (int q = 0; q < V / 4; ++q)
-                        *reinterpret_cast<float4 *>(o + u0 + 4 * q) = make_float4(r[4 * q], r[4 * q + 1],
-                                                                                  r[4 * q + 2], r[4 * q + 3]);
-                } else {
-#pragma unroll
-                    for (int e = 0; e < V; ++e)
-                        if (u0 + e < w) o[u0 + e] = r[e];
-                }
+                store_outputs<V>(o, u0, w, vec_store, r);
             }
         }
 #pragma unroll
@@ -221,7 +226,7 @@ __device__ __forceinline__ void shift_rows_body(const float *__restrict__ f, flo
 template <bool INTEGER, int V, int RB>
 __global__ __launch_bounds__(SH_BLOCK) void shift_rows(
     const float *__restrict__ in, float *__restrict__ out, int32_t W, int32_t H,
-    const float *__restrict__ offs, int32_t x0, int32_t y0, int32_t w, int32_t h, bool vec_store, bool aligned)
+    const float *__restrict__ offs, int32_t x0, int32_t y0, int32_t w, int32_t h, int vec_store, bool aligned)
 {
     const int32_t k = blockIdx.z;
     const int32_t v0 = blockIdx.y * SH_ROWS;
@@ -272,7 +277,8 @@ extern "C" int reduce_shift(const float *in, float *out, int32_t W, int32_t H, i
     const int32_t x0 = rect[0], y0 = rect[1], w = rect[2], h = rect[3];
     if (w < 1 || h < 1 || w > W || h > H) return fail(REDUCE_ERR_SHAPE, "reduce_shift: empty or oversized rect");
     if (N > 65535 || h > 65535) return fail(REDUCE_ERR_UNSUPPORTED, "reduce_shift: N or h above 65535");
-    const bool vec_store = (w % 4 == 0) && ((reinterpret_cast<uintptr_t>(out) & 15u) == 0);
+    const uintptr_t oa = reinterpret_cast<uintptr_t>(out);
+    const int vec_store = (w % 4 == 0 && (oa & 15u) == 0) ? 4 : (w % 2 == 0 && (oa & 7u) == 0) ? 2 : 1;
     const bool aligned = (W % 4 == 0) && ((reinterpret_cast<uintptr_t>(in) & 15u) == 0);
     const int variant = shift_variant();
     const int vec = variant == 8 ? 8 : 4;

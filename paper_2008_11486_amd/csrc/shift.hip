@@ -1,18 +1,17 @@
 // Bilinear sub-pixel shift onto the common overlap (Section 3.2.1 names bilinear
 // interpolation as the cheaper alternative to the paper's bicubic spline).
 //
-// Streaming kernel: a thread makes 8 consecutive outputs in each row of a 16-row
+// Streaming kernel: a thread makes 4 consecutive outputs in each row of a 16-row
 // strip.  The integer part of the offset is applied in integer arithmetic, the
 // fraction becomes per-frame bilinear weights evaluated in double and rounded once.
 // Bytes per output pixel: 4 read (a strip fetches each input row once, plus one
 // extra row per strip) + 4 write.
-#include <cstdlib>
-
 #include "common.h"
 
 namespace rd {
 
 constexpr int SH_BLOCK = 128;
+constexpr int SH_VEC = 4;     // outputs per thread and row
 constexpr int SH_ROWS = 16;   // output rows per workgroup: each input row is fetched once per strip
 
 __device__ __forceinline__ int32_t clampi(int32_t v, int32_t lo, int32_t hi)
@@ -160,114 +159,9 @@ __global__ __launch_bounds__(SH_BLOCK) void shift_kernel(
     }
 }
 
-// Grid as shift_kernel with V outputs per thread and row.  The strip is done in batches
-// of RB output rows: the RB + 1 tap rows a batch needs (row r_i = clamp(first row + i),
-// so output row u uses r_u and r_u+1) are all requested before any is used, and the
-// last one is kept as the first of the next batch.  AL = c0 & 3, the misalignment of
-// the first tap, is the same for every thread of a frame, so the kernel branches once
-// into the matching instance and the tap select is static.
-template <bool INTEGER, int V, int RB, int AL>
-__device__ __forceinline__ void shift_rows_body(const float *__restrict__ f, float *__restrict__ out, int32_t W,
-                                                int32_t H, int32_t k, int32_t v0, int32_t v1, int32_t u0, int32_t c0,
-                                                int32_t jbase, const ShiftSetup &ss, int32_t w, int32_t h,
-                                                int vec_store, bool aligned)
-{
-    constexpr int RAW = V + 4;
-    const bool step = ss.a > 0.0;
-    const bool down = !INTEGER && ss.b > 0.0;
-    const int32_t b = c0 - AL;
-    const bool fast = aligned && b >= 0 && b + RAW <= W;
-    float rows[RB + 1][RAW];
-    for (int32_t v = v0; v < v1; v += RB) {
-#pragma unroll
-        for (int i = 0; i <= RB; ++i) {
-            if (v != v0 && i == 0) continue;
-            const float *row = f + (int64_t)clampi(jbase + v + i, 0, H - 1) * W;
-            if (fast) {
-#pragma unroll
-                for (int q = 0; q < RAW / 4; ++q) {
-                    const float4 u = *reinterpret_cast<const float4 *>(row + b + 4 * q);
-                    rows[i][4 * q] = u.x;
-                    rows[i][4 * q + 1] = u.y;
-                    rows[i][4 * q + 2] = u.z;
-                    rows[i][4 * q + 3] = u.w;
-                }
-            } else {
-#pragma unroll
-                for (int e = 0; e < RAW; ++e) rows[i][e] = row[clampi(b + e, 0, W - 1)];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < RB; ++u) {
-            float r[V];
-#pragma unroll
-            for (int e = 0; e < V; ++e) {
-                const float f00 = rows[u][AL + e];
-                if (INTEGER) {
-                    r[e] = f00;
-                } else {
-                    // the right-hand tap is the next column only when it carries weight
-                    const float f10 = step ? rows[u][AL + e + 1] : f00;
-                    const float f01 = down ? rows[u + 1][AL + e] : f00;
-                    const float f11 = down ? (step ? rows[u + 1][AL + e + 1] : f01) : f10;
-                    r[e] = bilerp(ss.a, ss.b, f00, f10, f01, f11);
-                }
-            }
-            if (v + u < v1) {
-                float *o = out + ((int64_t)k * h + v + u) * w;
-                store_outputs<V>(o, u0, w, vec_store, r);
-            }
-        }
-#pragma unroll
-        for (int e = 0; e < RAW; ++e) rows[0][e] = rows[RB][e];
-    }
-}
-
-template <bool INTEGER, int V, int RB>
-__global__ __launch_bounds__(SH_BLOCK) void shift_rows(
-    const float *__restrict__ in, float *__restrict__ out, int32_t W, int32_t H,
-    const float *__restrict__ offs, int32_t x0, int32_t y0, int32_t w, int32_t h, int vec_store, bool aligned)
-{
-    const int32_t k = blockIdx.z;
-    const int32_t v0 = blockIdx.y * SH_ROWS;
-    const int32_t v1 = min(v0 + SH_ROWS, h);
-    const int32_t u0 = (blockIdx.x * SH_BLOCK + threadIdx.x) * V;
-    if (u0 >= w) return;
-    const ShiftSetup ss = shift_setup(offs[2 * k], offs[2 * k + 1]);
-    const float *f = in + (int64_t)k * W * H;
-    const int32_t c0 = x0 + u0 + ss.ix;
-    const int32_t jbase = y0 + ss.iy;  // unclamped tap row of output row v is jbase + v
-    switch (c0 & 3) {
-    case 0:
-        shift_rows_body<INTEGER, V, RB, 0>(f, out, W, H, k, v0, v1, u0, c0, jbase, ss, w, h, vec_store, aligned);
-        break;
-    case 1:
-        shift_rows_body<INTEGER, V, RB, 1>(f, out, W, H, k, v0, v1, u0, c0, jbase, ss, w, h, vec_store, aligned);
-        break;
-    case 2:
-        shift_rows_body<INTEGER, V, RB, 2>(f, out, W, H, k, v0, v1, u0, c0, jbase, ss, w, h, vec_store, aligned);
-        break;
-    default:
-        shift_rows_body<INTEGER, V, RB, 3>(f, out, W, H, k, v0, v1, u0, c0, jbase, ss, w, h, vec_store, aligned);
-        break;
-    }
-}
-
 }  // namespace rd
 
 using namespace rd;
-
-// Kernel variant: 0 = batches of 8 tap rows (default), 4 or 8 = row walk with 4 or 8
-// outputs per thread; REDUCE_SHIFT_VARIANT overrides.
-static int shift_variant()
-{
-    const char *e = std::getenv("REDUCE_SHIFT_VARIANT");
-    if (e) {
-        const int v = std::atoi(e);
-        if (v == 4 || v == 8) return v;
-    }
-    return 0;
-}
 
 extern "C" int reduce_shift(const float *in, float *out, int32_t W, int32_t H, int32_t N,
                             const float *offs, const int32_t *rect, int32_t integer_mode, void *stream)
@@ -280,32 +174,14 @@ extern "C" int reduce_shift(const float *in, float *out, int32_t W, int32_t H, i
     const uintptr_t oa = reinterpret_cast<uintptr_t>(out);
     const int vec_store = (w % 4 == 0 && (oa & 15u) == 0) ? 4 : (w % 2 == 0 && (oa & 7u) == 0) ? 2 : 1;
     const bool aligned = (W % 4 == 0) && ((reinterpret_cast<uintptr_t>(in) & 15u) == 0);
-    const int variant = shift_variant();
-    const int vec = variant == 8 ? 8 : 4;
-    dim3 grid((unsigned)ceil_div(w, (int64_t)SH_BLOCK * vec), (unsigned)ceil_div(h, SH_ROWS), (unsigned)N);
+    dim3 grid((unsigned)ceil_div(w, (int64_t)SH_BLOCK * SH_VEC), (unsigned)ceil_div(h, SH_ROWS), (unsigned)N);
     ProfScope prof("shift", as_stream(stream));
     hipStream_t s = as_stream(stream);
-    if (variant == 0) {
-        if (integer_mode)
-            hipLaunchKernelGGL((shift_rows<true, 4, 8>), grid, dim3(SH_BLOCK), 0, s, in, out, W, H, offs, x0, y0, w,
-                               h, vec_store, aligned);
-        else
-            hipLaunchKernelGGL((shift_rows<false, 4, 8>), grid, dim3(SH_BLOCK), 0, s, in, out, W, H, offs, x0, y0, w,
-                               h, vec_store, aligned);
-    } else if (vec == 4) {
-        if (integer_mode)
-            hipLaunchKernelGGL((shift_kernel<true, 4>), grid, dim3(SH_BLOCK), 0, s, in, out, W, H, offs, x0, y0, w, h,
-                               vec_store, aligned);
-        else
-            hipLaunchKernelGGL((shift_kernel<false, 4>), grid, dim3(SH_BLOCK), 0, s, in, out, W, H, offs, x0, y0, w,
-                               h, vec_store, aligned);
-    } else {
-        if (integer_mode)
-            hipLaunchKernelGGL((shift_kernel<true, 8>), grid, dim3(SH_BLOCK), 0, s, in, out, W, H, offs, x0, y0, w, h,
-                               vec_store, aligned);
-        else
-            hipLaunchKernelGGL((shift_kernel<false, 8>), grid, dim3(SH_BLOCK), 0, s, in, out, W, H, offs, x0, y0, w,
-                               h, vec_store, aligned);
-    }
+    if (integer_mode)
+        hipLaunchKernelGGL((shift_kernel<true, SH_VEC>), grid, dim3(SH_BLOCK), 0, s, in, out, W, H, offs, x0, y0, w, h,
+                           vec_store, aligned);
+    else
+        hipLaunchKernelGGL((shift_kernel<false, SH_VEC>), grid, dim3(SH_BLOCK), 0, s, in, out, W, H, offs, x0, y0, w,
+                           h, vec_store, aligned);
     return check_launch("reduce_shift");
 }

@@ -182,17 +182,24 @@ class ProposalTrainer:
         return self.loss
 
     def train(self, n_pairs: int, epochs: int, warmup: int = 100, min_lr_frac: float = 0.01,
-              log_every: int = 50, shuffle_seed: int = 1, log=None) -> list:
-        """Cosine schedule over epochs x n_pairs / B steps; returns (step, loss) pairs."""
+              log_every: int = 50, shuffle_seed: int = 1, log=None, time_budget: Optional[float] = None) -> list:
+        """Cosine schedule over epochs x n_pairs / B steps (or over time_budget seconds,
+        stopping when it is spent); returns (step, loss) pairs."""
         per_epoch = n_pairs // self.B
         total = per_epoch * epochs
         rng = np.random.Generator(np.random.PCG64(shuffle_seed))
         history = []
         s = 0
+        t0 = time.perf_counter()
         for _ in range(epochs):
             order = rng.permutation(n_pairs)
             for k in range(per_epoch):
-                frac = s / max(total - 1, 1)
+                if time_budget is not None:
+                    frac = (time.perf_counter() - t0) / time_budget
+                    if frac >= 1.0:
+                        break
+                else:
+                    frac = s / max(total - 1, 1)
                 lr = self.lr * (min_lr_frac + (1 - min_lr_frac) * 0.5 * (1 + math.cos(math.pi * frac)))
                 if s < warmup:
                     lr *= (s + 1) / warmup
@@ -200,8 +207,14 @@ class ProposalTrainer:
                 if s % log_every == 0 or s == total - 1:
                     history.append((s, float(loss.item())))
                     if log:
-                        log(f"step {s}/{total} loss {history[-1][1]:.4f} lr {lr:.2e}")
+                        log(f"step {s}/{total} loss {history[-1][1]:.4f} lr {lr:.2e} "
+                            f"{time.perf_counter() - t0:.0f} s")
                 s += 1
+            else:
+                continue
+            break
+        if history and history[-1][0] != s - 1:
+            history.append((s - 1, float(loss.item())))
         return history
 
 

@@ -33,6 +33,8 @@ def main(argv=None) -> int:
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--weight-decay", type=float, default=1e-4)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--time-budget", type=float, default=None,
+                    help="seconds of training; the learning-rate schedule runs over this time")
     ap.add_argument("--eval-stacks", type=int, default=2)
     ap.add_argument("--eval-frames", type=int, default=16)
     ap.add_argument("--out", required=True)
@@ -55,7 +57,7 @@ def main(argv=None) -> int:
                                  seed=args.seed)
     untrained = tr.params.clone()
     t0 = time.perf_counter()
-    hist = tr.train(args.pairs, args.epochs, warmup=100, log_every=100, log=log)
+    hist = tr.train(args.pairs, args.epochs, warmup=100, log_every=100, log=log, time_budget=args.time_budget)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
@@ -91,6 +93,7 @@ def main(argv=None) -> int:
             log(json.dumps(evals[-1]))
         del frames, rest
     summary = dict(size=W, bound=args.bound, pairs=args.pairs, batch=args.batch, epochs=args.epochs,
+                   time_budget=args.time_budget,
                    steps=tr.steps, lr=args.lr, weight_decay=args.weight_decay, train_seconds=round(train_s, 1),
                    loss_first=hist[0][1], loss_last=hist[-1][1], loss_history=hist,
                    true_peak_ratio_train=dict(min=min(ratios), max=max(ratios)), eval=evals)

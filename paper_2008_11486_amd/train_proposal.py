@@ -57,7 +57,7 @@ def main(argv=None) -> int:
                                  seed=args.seed)
     untrained = tr.params.clone()
     t0 = time.perf_counter()
-    hist = tr.train(args.pairs, args.epochs, warmup=100, log_every=100, log=log, time_budget=args.time_budget)
+    hist = tr.train(args.pairs, args.epochs, warmup=100, log_every=20, log=log, time_budget=args.time_budget)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)

@@ -251,6 +251,14 @@ int reduce_cnn_adamw(float *params, float *m, float *v, const float *grad, int64
 int reduce_cnn_centres(const float *pred, int32_t B, float scale, int32_t radius_max, int32_t *centres,
                        void *stream);
 
+/* reduce_recentre: for every frame whose narrowed-search maximum lies on its window
+ *   border (EDGE_X or EDGE_Y in offs[k].flags), set centres[k] to that maximum
+ *   (dx, dy), clamped to +-radius_max; other centres are left alone.  Repeating
+ *   reduce_register + reduce_recentre walks each +-R window towards the peak it
+ *   sees rising at its border.  offs device reduce_offset_t [N], centres device
+ *   int32 [N][2] (updated in place). */
+int reduce_recentre(const reduce_offset_t *offs, int32_t N, int32_t radius_max, int32_t *centres, void *stream);
+
 /* ---- training and evaluation frames --------------------------------------------
  * reduce_render_frames: F synthetic sky frames [F][H][W] (device float out) for the
  *   network's training and evaluation pairs: sky + sum over the frame's S catalogue

@@ -89,9 +89,10 @@ def _declare(L):
     L.reduce_cnn_backward.argtypes = [P, I64, P, I32, I32, I32, P, P, P, F, P, P, P, SZ, P]
     L.reduce_cnn_adamw.argtypes = [P, P, P, P, I64, F, F, F, F, F, I32, P]
     L.reduce_cnn_centres.argtypes = [P, I32, F, I32, P, P]
+    L.reduce_recentre.argtypes = [P, I32, I32, P, P]
     L.reduce_render_frames.argtypes = [P, I32, P, I32, I32, I32, F, F, F, I32, ctypes.c_uint64, P, P]
     for n in ("reduce_cnn_input", "reduce_cnn_ws_offsets", "reduce_cnn_forward", "reduce_cnn_backward",
-              "reduce_cnn_adamw", "reduce_cnn_centres", "reduce_render_frames"):
+              "reduce_cnn_adamw", "reduce_cnn_centres", "reduce_render_frames", "reduce_recentre"):
         getattr(L, n).restype = ctypes.c_int
     L.reduce_prof_enable.argtypes = [ctypes.c_int]
     L.reduce_prof_query.argtypes = [ctypes.c_char_p, P, P]
@@ -116,7 +117,7 @@ def exported_symbols() -> Sequence[str]:
             "reduce_tune_clear", "reduce_stack_batch_ws", "reduce_stack_batch",
             "reduce_cnn_input_ws", "reduce_cnn_input", "reduce_cnn_num_params", "reduce_cnn_ws",
             "reduce_cnn_ws_offsets", "reduce_cnn_forward", "reduce_cnn_backward", "reduce_cnn_adamw",
-            "reduce_cnn_centres", "reduce_render_frames")
+            "reduce_cnn_centres", "reduce_render_frames", "reduce_recentre")
 
 
 def _check(rc: int) -> None:
@@ -493,3 +494,12 @@ def render_frames(stars: torch.Tensor, keys: torch.Tensor, W: int, H: int, sky: 
                                       float(read_noise), 1 if noise else 0, int(seed) & (2 ** 64 - 1), _ptr(out),
                                       _stream(stream)))
     return out
+
+
+def recentre(offsets: torch.Tensor, centres: torch.Tensor, radius_max: int, stream=None) -> torch.Tensor:
+    """Move the centres of frames whose window maximum is on the border (in place)."""
+    N = centres.shape[0]
+    if offsets.numel() != N * OFFSET_BYTES or centres.dtype != torch.int32 or not centres.is_contiguous():
+        raise ValueError("offsets [N][48] bytes and contiguous int32 centres [N][2] needed")
+    _check(lib().reduce_recentre(_ptr(offsets), N, int(radius_max), _ptr(centres), _stream(stream)))
+    return centres

@@ -133,6 +133,19 @@ __global__ void centres_kernel(const float *__restrict__ pred, int32_t B, float 
     centres[i] = (int32_t)c;
 }
 
+// A window whose maximum sits on its border moves its centre onto that maximum.
+__global__ void recentre_kernel(const reduce_offset_t *__restrict__ offs, int32_t N, int32_t rmax,
+                                int32_t *__restrict__ centres)
+{
+    const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const reduce_offset_t o = offs[k];
+    if (o.flags & (REDUCE_EDGE_X | REDUCE_EDGE_Y)) {
+        centres[2 * k] = min(max(o.dx, -rmax), rmax);
+        centres[2 * k + 1] = min(max(o.dy, -rmax), rmax);
+    }
+}
+
 }  // namespace rd
 
 using namespace rd;
@@ -165,4 +178,15 @@ extern "C" int reduce_cnn_centres(const float *pred, int32_t B, float scale, int
     hipLaunchKernelGGL(centres_kernel, dim3((unsigned)ceil_div(2 * (int64_t)B, 256)), dim3(256), 0,
                        as_stream(stream), pred, B, scale, radius_max, centres);
     return check_launch("reduce_cnn_centres");
+}
+
+extern "C" int reduce_recentre(const reduce_offset_t *offs, int32_t N, int32_t radius_max, int32_t *centres,
+                               void *stream)
+{
+    if (!offs || !centres) return fail(REDUCE_ERR_NULL, "reduce_recentre: NULL buffer");
+    if (N < 1) return fail(REDUCE_ERR_SHAPE, "reduce_recentre: N must be >= 1");
+    if (radius_max < 0) return fail(REDUCE_ERR_RANGE, "reduce_recentre: negative radius_max");
+    hipLaunchKernelGGL(recentre_kernel, dim3((unsigned)ceil_div(N, 256)), dim3(256), 0, as_stream(stream), offs, N,
+                       radius_max, centres);
+    return check_launch("reduce_recentre");
 }

@@ -7,10 +7,11 @@
 * ``ProposalTrainer`` runs forward, Huber-loss backward and AdamW, all in the
   library's kernels, on freshly rendered pairs.
 * ``LearnedRegistrar`` proposes an offset per frame, searches only a small window
-  around it with the same template as the full search, and falls back to the full
-  window when the narrowed result cannot be trusted (its maximum on the window
-  border, a window clipped at the search limit, or a peak far below the reference's
-  own zero-offset score).
+  around it with the same template as the full search (a window whose maximum lies
+  on its border moves onto that maximum, a few times at most), and falls back to the
+  full window when the narrowed result cannot be trusted (its maximum still on the
+  window border, a window clipped at the search limit, or a peak far below the
+  reference's own zero-offset score).
 
 The registration problem itself (score, argmax, sub-pixel vertex) is the one of
 ``reduce_register``; the network only moves the window.
@@ -26,7 +27,7 @@ import numpy as np
 import torch
 
 from . import (CLIPPED, EDGE_X, EDGE_Y, FALLBACK, CnnWorkspace, cnn_adamw, cnn_backward, cnn_centres,
-               cnn_forward, cnn_input, cnn_input_ws_bytes, cnn_num_params, offsets_to_numpy, register,
+               cnn_forward, cnn_input, cnn_input_ws_bytes, cnn_num_params, offsets_to_numpy, recentre, register,
                register_ws_bytes, render_frames)
 
 SEED_ROOT = 20081148
@@ -231,9 +232,10 @@ class LearnedRegistrar:
     against one reference [H][W] (all device float32)."""
 
     def __init__(self, params, W: int, H: int, M: int, radius_max: int = 64, refine_radius: int = 2,
-                 peak_ratio: float = 0.5, device="cuda:0"):
+                 peak_ratio: float = 0.5, moves: int = 4, device="cuda:0"):
         self.W, self.H, self.M = W, H, M
         self.rmax, self.r = radius_max, refine_radius
+        self.moves = moves
         self.peak_ratio = peak_ratio
         self.dev = torch.device(device)
         p = params if isinstance(params, torch.Tensor) else torch.from_numpy(np.asarray(params, np.float32))
@@ -263,7 +265,11 @@ class LearnedRegistrar:
         if frames.shape != (self.M, self.H, self.W):
             raise ValueError(f"frames must be [{self.M}][{self.H}][{self.W}]")
         centres = self.propose(ref, frames)
+        proposed = centres.clone()
         refined = register(ref, frames, self.r, self.rmax, centers=centres, ws=self.ws_refine)
+        for _ in range(self.moves):  # windows with a border maximum move onto it
+            recentre(refined, centres, self.rmax)
+            refined = register(ref, frames, self.r, self.rmax, centers=centres, ws=self.ws_refine)
         auto = register(ref, ref.reshape(1, self.H, self.W), 0, self.rmax, ws=self.ws_auto)
         o = offsets_to_numpy(refined)
         s_auto = float(offsets_to_numpy(auto)["peak"][0])
@@ -275,7 +281,7 @@ class LearnedRegistrar:
             full = offsets_to_numpy(register(ref, frames[k:k + 1], self.rmax, self.rmax, ws=self.ws_full))
             o[k] = full[0]
             o["flags"][k] |= FALLBACK
-        return LearnedResult(offsets=o, centres=centres.cpu().numpy(), fallback=fb,
+        return LearnedResult(offsets=o, centres=proposed.cpu().numpy(), fallback=fb,
                              reason=dict(border=int(border.sum()), clipped=int(clipped.sum()),
                                          weak=int(weak.sum()), s_auto=s_auto))
 

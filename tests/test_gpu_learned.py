@@ -272,3 +272,14 @@ def test_trained_proposals_need_fewer_fallbacks(trained):
         print(name, "fallbacks", out[name][0], "of", M, "median centre error", out[name][1], res.reason)
     assert out["trained"][0] < out["untrained"][0]
     assert out["trained"][1] < out["untrained"][1]
+
+
+def test_recentre_moves_border_windows_only(rd):
+    o = np.zeros(4, dtype=rd.OFFSET_DTYPE)
+    o["dx"] = [5, -70, 3, 9]
+    o["dy"] = [-2, 1, 4, 66]
+    o["flags"] = [rd.EDGE_X, rd.EDGE_Y | rd.CLIPPED, 0, rd.EDGE_X | rd.EDGE_Y]
+    raw = torch.from_numpy(o.view(np.uint8).reshape(4, -1).copy()).to("cuda:0")
+    c = torch.tensor([[3, -2], [-68, 0], [1, 1], [7, 64]], dtype=torch.int32, device="cuda:0")
+    rd.recentre(raw, c, 64)
+    np.testing.assert_array_equal(c.cpu().numpy(), [[5, -2], [-64, 1], [1, 1], [9, 64]])

@@ -229,6 +229,15 @@ def learned_comparison(torch, rd, weights_path, M):
     learned_s = learned.time_call(lambda: res.setdefault("r", reg.register(ref, rest)), reps=1)
     learned_s = min(learned_s, learned.time_call(lambda: reg.register(ref, rest), reps=3))
     r = res["r"]
+    torch.cuda.synchronize()
+    rd.prof_enable(True)
+    reg.register(ref, rest)
+    torch.cuda.synchronize()
+    parts = {}
+    for name in ("cnn_input", "cnn_forward", "register", "score_tiles"):
+        ms, n = rd.prof_query(name)
+        parts[name] = {"ms": round(ms, 3), "launches": n}
+    rd.prof_enable(False)
     same = np.mean((r.offsets["dx"] == full["dx"]) & (r.offsets["dy"] == full["dy"]))
     err = np.abs(r.centres - np.stack([full["dx"], full["dy"]], 1)).max(axis=1)
     return {"workload": f"a reference and {M} frames of {W}x{H}, shifts uniform in +-64 px, full search R=64 "
@@ -237,7 +246,7 @@ def learned_comparison(torch, rd, weights_path, M):
             "learned_ms": round(learned_s * 1e3, 3), "speedup": round(full_s / learned_s, 3),
             "identical_integer_offsets": float(same), "fallback_rate": float(r.fallback.mean()),
             "centre_error_px_median": float(np.median(err)), "centre_error_px_max": float(err.max()),
-            "true_offset_max_abs_px": float(np.abs(t).max())}
+            "true_offset_max_abs_px": float(np.abs(t).max()), "learned_breakdown": parts}
 
 
 def streaming_wide(torch, rd, reps=5):

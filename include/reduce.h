@@ -251,9 +251,11 @@ int reduce_cnn_adamw(float *params, float *m, float *v, const float *grad, int64
 int reduce_cnn_centres(const float *pred, int32_t B, float scale, int32_t radius_max, int32_t *centres,
                        void *stream);
 
-/* reduce_recentre: for every frame whose narrowed-search maximum lies on its window
- *   border (EDGE_X or EDGE_Y in offs[k].flags), set centres[k] to that maximum
- *   (dx, dy), clamped to +-radius_max; other centres are left alone.  Repeating
+/* reduce_recentre: for every frame whose narrowed-search maximum lies on a window
+ *   border strictly inside +-radius_max (EDGE_X with |dx| < radius_max, or EDGE_Y
+ *   with |dy| < radius_max; a border at +-radius_max is also the full search's border),
+ *   set centres[k] to that maximum (dx, dy), clamped to +-radius_max; other centres
+ *   are left alone.  Repeating
  *   reduce_register + reduce_recentre walks each +-R window towards the peak it
  *   sees rising at its border.  offs device reduce_offset_t [N], centres device
  *   int32 [N][2] (updated in place). */

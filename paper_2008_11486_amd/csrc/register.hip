@@ -113,6 +113,7 @@ int register_launch(const float *ref, const float *frames, int32_t W, int32_t H,
                     int32_t Rmax, const int32_t *centers, int32_t tx0, int32_t ty0, int32_t tw, int32_t th,
                     reduce_offset_t *out, double *scores, void *ws, const RegPlan &p, hipStream_t s)
 {
+    ProfScope prof_all("register", s);
     const RegWs L = reg_ws_layout(p, N);
     unsigned char *base = static_cast<unsigned char *>(ws);
     double *mean_parts = reinterpret_cast<double *>(base + L.mean_parts);

@@ -133,14 +133,17 @@ __global__ void centres_kernel(const float *__restrict__ pred, int32_t B, float 
     centres[i] = (int32_t)c;
 }
 
-// A window whose maximum sits on its border moves its centre onto that maximum.
+// A window whose maximum sits on a border inside the search limit moves its centre
+// onto that maximum (a border at +-rmax is also the full search's border).
 __global__ void recentre_kernel(const reduce_offset_t *__restrict__ offs, int32_t N, int32_t rmax,
                                 int32_t *__restrict__ centres)
 {
     const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= N) return;
     const reduce_offset_t o = offs[k];
-    if (o.flags & (REDUCE_EDGE_X | REDUCE_EDGE_Y)) {
+    const bool bx = (o.flags & REDUCE_EDGE_X) && o.dx > -rmax && o.dx < rmax;
+    const bool by = (o.flags & REDUCE_EDGE_Y) && o.dy > -rmax && o.dy < rmax;
+    if (bx || by) {
         centres[2 * k] = min(max(o.dx, -rmax), rmax);
         centres[2 * k + 1] = min(max(o.dy, -rmax), rmax);
     }

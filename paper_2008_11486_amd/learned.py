@@ -9,9 +9,9 @@
 * ``LearnedRegistrar`` proposes an offset per frame, searches only a small window
   around it with the same template as the full search (a window whose maximum lies
   on its border moves onto that maximum, a few times at most), and falls back to the
-  full window when the narrowed result cannot be trusted (its maximum still on the
-  window border, a window clipped at the search limit, or a peak far below the
-  reference's own zero-offset score).
+  full window when the narrowed result cannot be trusted (its maximum still on a
+  window border inside the search limit, or a peak far below the reference's own
+  zero-offset score).
 
 The registration problem itself (score, argmax, sub-pixel vertex) is the one of
 ``reduce_register``; the network only moves the window.
@@ -273,10 +273,14 @@ class LearnedRegistrar:
         auto = register(ref, ref.reshape(1, self.H, self.W), 0, self.rmax, ws=self.ws_auto)
         o = offsets_to_numpy(refined)
         s_auto = float(offsets_to_numpy(auto)["peak"][0])
-        border = (o["flags"] & (EDGE_X | EDGE_Y)) != 0
+        # a border at +-R_max is the full search's border too; any other border maximum,
+        # or a peak far below the reference's own, sends the frame to the full search
+        inner_x = (o["dx"] > -self.rmax) & (o["dx"] < self.rmax)
+        inner_y = (o["dy"] > -self.rmax) & (o["dy"] < self.rmax)
+        border = (((o["flags"] & EDGE_X) != 0) & inner_x) | (((o["flags"] & EDGE_Y) != 0) & inner_y)
         clipped = (o["flags"] & CLIPPED) != 0
         weak = ~(o["peak"] >= self.peak_ratio * s_auto)
-        fb = border | clipped | weak
+        fb = border | weak
         for k in np.nonzero(fb)[0]:
             full = offsets_to_numpy(register(ref, frames[k:k + 1], self.rmax, self.rmax, ws=self.ws_full))
             o[k] = full[0]

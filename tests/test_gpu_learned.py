@@ -275,7 +275,7 @@ def test_trained_proposals_need_fewer_fallbacks(trained):
 
 
 def test_recentre_moves_border_windows_only(rd):
-    o = np.zeros(4, dtype=rd.OFFSET_DTYPE)
+    o = np.zeros(5, dtype=rd.OFFSET_DTYPE)
     o["dx"] = [5, -62, 3, 9, 64]
     o["dy"] = [-2, 1, 4, 63, 10]
     o["flags"] = [rd.EDGE_X, rd.EDGE_Y | rd.CLIPPED, 0, rd.EDGE_X | rd.EDGE_Y, rd.EDGE_X | rd.CLIPPED]

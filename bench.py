@@ -221,6 +221,9 @@ def learned_comparison(torch, rd, weights_path, M):
     params = learned.load_params(weights_path) if trained else learned.init_params(0)
     frames, t = learned.render_stack(0, M + 1, W, H, 64.0)
     ref, rest = frames[0], frames[1:].contiguous()
+    # both searches run with tuned launch shapes (tuned on two frames; the shape does not depend on N)
+    rd.tune_register(ref, rest[:2].contiguous(), 64, 64)
+    rd.tune_register(ref, rest, 2, 64)
     ws = torch.empty(rd.register_ws_bytes(W, H, M, 64, 64), dtype=torch.uint8, device=frames.device)
     reg = learned.LearnedRegistrar(params, W, H, M, radius_max=64, refine_radius=2)
     full_s = learned.time_call(lambda: learned.full_search(ref, rest, 64, ws=ws), reps=3)

@@ -253,6 +253,8 @@ class LearnedRegistrar:
                                    device=self.dev)
         self.ws_full = torch.empty(max(register_ws_bytes(W, H, 1, radius_max, radius_max), 1), dtype=torch.uint8,
                                    device=self.dev)
+        self.ws_move = torch.empty(max(register_ws_bytes(W, H, 1, refine_radius, radius_max), 1),
+                                   dtype=torch.uint8, device=self.dev)
 
     def propose(self, ref: torch.Tensor, frames: torch.Tensor) -> torch.Tensor:
         """Enqueue network input, forward and centres; returns the device centres."""
@@ -261,24 +263,34 @@ class LearnedRegistrar:
         cnn_forward(self.inp_ref[0], self.inp, self.params, self.cws, ref_shared=True, pred=self.pred)
         return cnn_centres(self.pred, float(DOWNSAMPLE), self.rmax, out=self.centres)
 
+    def _inner_border(self, o: np.ndarray) -> np.ndarray:
+        """Frames whose maximum lies on a window border inside +-R_max (a border at
+        +-R_max is the full search's border too)."""
+        inner_x = (o["dx"] > -self.rmax) & (o["dx"] < self.rmax)
+        inner_y = (o["dy"] > -self.rmax) & (o["dy"] < self.rmax)
+        return (((o["flags"] & EDGE_X) != 0) & inner_x) | (((o["flags"] & EDGE_Y) != 0) & inner_y)
+
     def register(self, ref: torch.Tensor, frames: torch.Tensor) -> LearnedResult:
         if frames.shape != (self.M, self.H, self.W):
             raise ValueError(f"frames must be [{self.M}][{self.H}][{self.W}]")
         centres = self.propose(ref, frames)
         proposed = centres.clone()
         refined = register(ref, frames, self.r, self.rmax, centers=centres, ws=self.ws_refine)
-        for _ in range(self.moves):  # windows with a border maximum move onto it
-            recentre(refined, centres, self.rmax)
-            refined = register(ref, frames, self.r, self.rmax, centers=centres, ws=self.ws_refine)
         auto = register(ref, ref.reshape(1, self.H, self.W), 0, self.rmax, ws=self.ws_auto)
         o = offsets_to_numpy(refined)
         s_auto = float(offsets_to_numpy(auto)["peak"][0])
-        # a border at +-R_max is the full search's border too; any other border maximum,
-        # or a peak far below the reference's own, sends the frame to the full search
-        inner_x = (o["dx"] > -self.rmax) & (o["dx"] < self.rmax)
-        inner_y = (o["dy"] > -self.rmax) & (o["dy"] < self.rmax)
-        border = (((o["flags"] & EDGE_X) != 0) & inner_x) | (((o["flags"] & EDGE_Y) != 0) & inner_y)
-        clipped = (o["flags"] & CLIPPED) != 0
+        # a window whose maximum is on an inner border moves onto that maximum, frame by frame
+        moved = 0
+        for _ in range(self.moves):
+            walk = np.nonzero(self._inner_border(o))[0]
+            if walk.size == 0:
+                break
+            for k in walk:
+                c = torch.tensor([[int(o["dx"][k]), int(o["dy"][k])]], dtype=torch.int32, device=self.dev)
+                o[k] = offsets_to_numpy(register(ref, frames[k:k + 1], self.r, self.rmax, centers=c,
+                                                 ws=self.ws_move))[0]
+                moved += 1
+        border = self._inner_border(o)
         weak = ~(o["peak"] >= self.peak_ratio * s_auto)
         fb = border | weak
         for k in np.nonzero(fb)[0]:
@@ -286,8 +298,8 @@ class LearnedRegistrar:
             o[k] = full[0]
             o["flags"][k] |= FALLBACK
         return LearnedResult(offsets=o, centres=proposed.cpu().numpy(), fallback=fb,
-                             reason=dict(border=int(border.sum()), clipped=int(clipped.sum()),
-                                         weak=int(weak.sum()), s_auto=s_auto))
+                             reason=dict(border=int(border.sum()), weak=int(weak.sum()), moves=moved,
+                                         clipped=int(((o["flags"] & CLIPPED) != 0).sum()), s_auto=s_auto))
 
 
 def full_search(ref: torch.Tensor, frames: torch.Tensor, radius_max: int = 64, ws=None) -> torch.Tensor:

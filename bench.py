@@ -68,6 +68,10 @@ def parse():
     ap.add_argument("--learned-frames", type=int, default=16)
     ap.add_argument("--no-wide", action="store_true",
                     help="skip the streaming kernels at the wide-field size (16 frames of 6144x6160)")
+    ap.add_argument("--wide-only", action="store_true",
+                    help="run only the wide-field streaming kernels (for counter runs) and print their figures")
+    ap.add_argument("--traffic-key", default="kernels",
+                    help="with --traffic-from: the section of the traffic file to write (kernels, wide)")
     return ap.parse_args()
 
 
@@ -128,11 +132,14 @@ def traffic_from(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, workload,
     return out
 
 
-def recorded_traffic(path, kernel):
+def recorded_traffic(path, kernel, section=None):
     """Bytes per launch recorded for kernel, or None if absent or the kernel changed since."""
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path)).get("kernels", {}).get(kernel)
+    d = json.load(open(path))
+    if section:
+        d = d.get(section, {})
+    rec = d.get("kernels", {}).get(kernel)
     if rec is None or rec.get("source_sha256") != source_hash(kernel):
         return None
     return rec["bytes"]
@@ -252,7 +259,7 @@ def learned_comparison(torch, rd, weights_path, M):
             "true_offset_max_abs_px": float(np.abs(t).max()), "learned_breakdown": parts}
 
 
-def streaming_wide(torch, rd, reps=5):
+def streaming_wide(torch, rd, reps=5, traffic_path=os.path.join(ROOT, "profiles", "traffic.json")):
     """calibrate, shift and combine over 16 frames of 6144x6160 (working sets of 1.2-2.4 GB,
     far beyond the 256 MB last-level cache), timed with HIP events on their stream."""
     from paper_2008_11486_amd import learned
@@ -304,7 +311,7 @@ def streaming_wide(torch, rd, reps=5):
         ms, n = rd.prof_query(name)
         gbs = byts[name] / (ms / n / 1e3) / 1e9
         res[name] = {"avg_launch_ms": round(ms / n, 4), "bytes": byts[name], "GB/s": round(gbs, 1),
-                     "frac": round(gbs / HBM_PEAK_GBS, 4)}
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(traffic_path, name, "wide")}
     rd.prof_enable(False)
     del raw, cal, al
     torch.cuda.empty_cache()
@@ -315,9 +322,15 @@ def main():
     args = parse()
     if args.traffic_from:
         rec = traffic_from(*args.traffic_from, workload=args.workload, kernels=args.traffic_kernels.split(","))
+        old = json.load(open(args.traffic)) if os.path.exists(args.traffic) else {}
+        if args.traffic_key == "kernels":
+            old.update(rec)
+        else:
+            old[args.traffic_key] = {"workload": "16 frames 6144x6160 (wide field)", "kernels": rec["kernels"],
+                                     "fetch_scale": rec["fetch_scale"], "write_scale": rec["write_scale"]}
         with open(args.traffic, "w") as fh:
-            json.dump(rec, fh, indent=1)
-        print(json.dumps(rec))
+            json.dump(old, fh, indent=1)
+        print(json.dumps(old))
         return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -339,7 +352,19 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes_read": src.numel() * 4, "copy_probe_bytes_written": dst.numel() * 4}))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        print(json.dumps({"copy_probe_bytes_read": src.numel() * 4, "copy_probe_bytes_written": dst.numel() * 4,
+                          "ms": round(ms, 4), "GB/s": round(2 * src.numel() * 4 / (ms / 1e3) / 1e9, 1)}))
+        return 0
+    if args.wide_only:
+        rd.lib()
+        print(json.dumps({"streaming_wide": streaming_wide(torch, rd)}))
         return 0
     rd.lib()
     stacks = synth.make_config(args.workload)

@@ -84,7 +84,7 @@ KERNEL_SOURCES = {
     "combine": ("combine.hip", "combine_core.h"),
 }
 KERNEL_SYMBOLS = {"score_tiles": "score_tiles", "calibrate": "calibrate_", "shift": "shift_kernel",
-                  "combine": "combine_kernel"}
+                  "combine": "combine_"}
 
 
 def source_hash(kernel):

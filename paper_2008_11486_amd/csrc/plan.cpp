@@ -208,6 +208,23 @@ void reg_shape_candidates(int32_t W, int32_t H, int32_t R, int32_t Rmax, RegShap
             if (++taken == 4) break;
         }
     }
+    // smaller-LDS shapes per K, so that more workgroups share a compute unit (the model
+    // counts instructions, not occupancy; the measurement decides)
+    for (int32_t K : kRegK)
+        for (size_t cap : {(size_t)52 * 1024, (size_t)39 * 1024, (size_t)30 * 1024}) {
+            if (n >= max_count) break;
+            for (const auto &c : shapes) {
+                if (c.second.K != K) continue;
+                RegPlan p;
+                if (!reg_plan_from_shape(W, H, R, Rmax, c.second, &p) || p.lds > cap) continue;
+                bool dup = false;
+                for (int i = 0; i < n; ++i)
+                    dup = dup || (out[i].K == c.second.K && out[i].G == c.second.G && out[i].S == c.second.S &&
+                                  out[i].TY == c.second.TY && out[i].CPT == c.second.CPT);
+                if (!dup) out[n++] = c.second;
+                break;
+            }
+        }
     // tile-height variants of the model's overall best shape
     if (!shapes.empty()) {
         const RegShape b = shapes.front().second;

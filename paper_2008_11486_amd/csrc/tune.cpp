@@ -72,7 +72,7 @@ extern "C" int reduce_tune_register(const float *ref, const float *frames, int32
         return fail(REDUCE_ERR_RANGE, "reduce_tune_register: no template for these sizes");
     if (reps < 1) reps = 1;
     hipStream_t s = as_stream(stream);
-    constexpr int MAXC = 32;
+    constexpr int MAXC = 64;
     RegShape cand[MAXC];
     int n = 0;
     reg_shape_candidates(W, H, radius, radius_max, cand, &n, MAXC);

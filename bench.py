@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--workload", type=int, default=1, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the cost-model launch shapes")
+    ap.add_argument("--path", choices=("stagewise", "batched"), default="stagewise",
+                    help="stage-wise entry points per stack, or one batched call for all stacks")
     ap.add_argument("--tune-cache", default=None,
                     help="load tuned launch shapes from this file if it exists, else tune and save them here")
     ap.add_argument("--copy-probe", action="store_true",
@@ -183,6 +185,22 @@ class StagePipeline:
                           integer_mode=self.integer_mode)
             outs.append(rd.combine(al)[0])
         return outs
+
+
+class BatchedPipeline:
+    """All stacks through one reduce_stack_batch call per step (one launch per phase)."""
+
+    def __init__(self, rd, torch, stacks, integer_mode):
+        dev = torch.device("cuda:0")
+        self.items = []
+        for st in stacks:
+            self.items.append((torch.from_numpy(st.raw.view(np.int16)).to(dev), torch.from_numpy(st.dark).to(dev),
+                               torch.from_numpy(st.flat).to(dev), st.spec.radius))
+        self.batch = rd.StackBatch(self.items, integer_mode=integer_mode)
+        self.pixels = sum(st.spec.pixels for st in stacks)
+
+    def step(self):
+        self.batch.run()
 
 
 def register_flops_per_launch(spec, frames):
@@ -369,16 +387,17 @@ def main():
     rd.lib()
     stacks = synth.make_config(args.workload)
     integer_mode = args.workload == 0
-    pipe = StagePipeline(rd, torch, stacks, integer_mode)
+    pipe = (BatchedPipeline if args.path == "batched" else StagePipeline)(rd, torch, stacks, integer_mode)
     tuned = None
     if args.tune_cache and os.path.exists(args.tune_cache):
         rd.tune_load(args.tune_cache)
         tuned = "loaded"
     elif not args.no_tune:
-        it = pipe.items[0]
-        sp = it["spec"]
-        rd.calibrate(it["raw"], it["dark"], it["flat"], out=it["cal"])
-        tuned = rd.tune_register(it["cal"][0], it["cal"][1:], sp.radius)
+        st0 = stacks[0]
+        cal0 = rd.calibrate(torch.from_numpy(st0.raw.view(np.int16)).to("cuda:0"),
+                            torch.from_numpy(st0.dark).to("cuda:0"), torch.from_numpy(st0.flat).to("cuda:0"))
+        tuned = rd.tune_register(cal0[0].contiguous(), cal0[1:].contiguous(), st0.spec.radius)
+        del cal0
         if args.tune_cache:
             rd.tune_save(args.tune_cache)
 
@@ -395,25 +414,31 @@ def main():
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
 
-    kern = {name: rd.prof_query(name) for name in ("score_tiles", "calibrate", "shift", "combine")}
+    kern = {name: rd.prof_query(name) for name in ("score_tiles", "calibrate", "shift", "combine", "batch_score",
+                                                   "batch_out")}
+    if args.path == "batched":
+        kern["score_tiles"] = kern["batch_score"]
     rd.prof_enable(False)
 
     spec0 = stacks[0].spec
     score_ms, score_n = kern["score_tiles"]
     score_avg_s = score_ms / score_n / 1e3
-    flops = register_flops_per_launch(spec0, spec0.N - 1)
+    # one stage-wise launch searches one stack; one batched launch searches all of them
+    flops = sum(register_flops_per_launch(st.spec, st.spec.N - 1)
+                for st in (stacks if args.path == "batched" else stacks[:1]))
     achieved = flops / score_avg_s / 1e12
-    traffic = recorded_traffic(args.traffic, "score_tiles")
+    traffic = recorded_traffic(args.traffic, "score_tiles") if args.path == "stagewise" else None
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(FP64_VALU_PEAK_TFLOPS, 3),
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4), "traffic": traffic,
-                "kernel": "score_tiles", "avg_launch_ms": round(score_avg_s * 1e3, 4),
+                "kernel": "batch_score" if args.path == "batched" else "score_tiles",
+                "avg_launch_ms": round(score_avg_s * 1e3, 4),
                 "flops_per_launch": flops}
 
     sbytes = streaming_bytes(spec0)
     streaming = {}
     for name in ("calibrate", "shift", "combine"):
         ms, n = kern[name]
-        if n:
+        if n and args.path == "stagewise":
             gbs = sbytes[name] / (ms / n / 1e3) / 1e9
             streaming[name] = {"avg_launch_ms": round(ms / n, 4), "GB/s": round(gbs, 1),
                                "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes": sbytes[name],
@@ -426,7 +451,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "stacks": len(stacks),
                    "frames": [s.spec.N for s in stacks], "size": [spec0.W, spec0.H],
-                   "path": "stage-wise", "pixel_storage": "uint16 in, f32 between stages",
+                   "path": args.path, "pixel_storage": "uint16 in, f32 between stages",
                    "search_plan": rd.register_plan(spec0.W, spec0.H, spec0.N - 1, spec0.radius)},
         "roofline": roofline, "streaming": streaming,
     }

@@ -200,9 +200,10 @@ __device__ __forceinline__ void score_tile(const ScoreArgs &a, int32_t lid, unsi
         }
         __syncthreads();
         if (active) {
+            // pairs s, s + S, ... as (template row yy, column block xb), stepped without division
+            const int dq = a.S / a.NXB, dr = a.S - dq * a.NXB;
+            int yy = s / a.NXB, xb = s - (s / a.NXB) * a.NXB;
             for (int pr = s; pr < pairs; pr += a.S) {
-                const int yy = pr / a.NXB;
-                const int xb = pr - yy * a.NXB;
                 const double *rrow = rt + yy * a.TX + xb * K;
                 const float *frow = ft + (yy + jr) * a.FC + (xb + bx) * K;
                 double r[K];
@@ -216,6 +217,12 @@ __device__ __forceinline__ void score_tile(const ScoreArgs &a, int32_t lid, unsi
                         const int q = m - i;
                         if (q >= 0 && q < K) acc[q] = fma(r[i], fv, acc[q]);
                     }
+                }
+                yy += dq;
+                xb += dr;
+                if (xb >= a.NXB) {
+                    xb -= a.NXB;
+                    ++yy;
                 }
             }
         }

@@ -9,14 +9,17 @@
 //   SUM        64 candidate scores of one frame from its tile partials
 //   PICK       argmax, runner-up, parabola of one frame
 //   RECT       common overlap of the stack from its offsets
-//   OUT        bilinear shift of every frame + sigma-clipped mean for OUT_TILES x 256
-//              output pixels
+//   SHIFT      a 16-row strip of one frame's bilinear shift onto the overlap
+//   COMB*      sigma-clipped mean of a block of pixel columns (one launch per frame-count
+//              class: up to 16, 32 or 48 frames)
 //
 // Each phase is one kernel launch with one workgroup per item over all stacks; the
 // stream orders the phases, so every dependency is met at a kernel boundary and no
 // workgroup waits for another.  The search items go out in an XCD-aware order.  Each
 // item calls the same device routines as the stage-wise kernels with the same launch
-// shape, so results are bit-identical to them.
+// shape, so results are bit-identical to them.  Items of the shift and combine phases
+// are counted for the whole frame (the overlap is only known on the device) and those
+// outside the overlap return at once.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,24 +30,27 @@
 #include <string>
 #include <vector>
 
+#include "calibrate_core.h"
 #include "combine_core.h"
 #include "common.h"
 #include "register_core.h"
 #include "register_plan.h"
+#include "shift_core.h"
 
 namespace rd {
 
-int combine_lanes_for(int32_t N);
 ScoreArgs make_score_args(const RegPlan &p, const float *ref, const float *frames, const int32_t *centers,
                           const double *mean, double *partial, int32_t W, int32_t H, int32_t N, int32_t R,
                           int32_t Rmax, int32_t tx0, int32_t ty0, int32_t tw, int32_t th, int32_t skip);
 
 constexpr int BATCH_THREADS = 512;
-constexpr int CAL_ROWS = 32;    // rows of one frame per CAL item
-constexpr int OUT_TILES = 4;    // combine tiles (of COMB_TILE pixels) per OUT item
+constexpr int COMB_PX16 = 2;    // pixel columns per thread of the up-to-16-frame combine
 
-enum ItemType : int32_t { IT_CAL = 0, IT_MEANPART, IT_MEANFINAL, IT_SCORE, IT_SUM, IT_PICK, IT_RECT, IT_OUT };
-constexpr int N_PHASES = IT_OUT + 1;
+enum ItemType : int32_t {
+    IT_CAL = 0, IT_MEANPART, IT_MEANFINAL, IT_SCORE, IT_SUM, IT_PICK, IT_RECT, IT_SHIFT, IT_COMB16, IT_COMB32,
+    IT_COMB48
+};
+constexpr int N_PHASES = IT_COMB48 + 1;
 
 struct Item {
     int32_t type, stack, a, pad;
@@ -61,10 +67,11 @@ struct StackDev {
     reduce_offset_t *offsets;
     int64_t *n_rej;
     // sizes and parameters
-    int32_t W, H, N, ref, R, max_iters, integer_mode, lanes, K;
+    int32_t W, H, N, ref, R, max_iters, integer_mode, cal_vec, K;
     float ksigma;
     // workspace
     float *cal;           // [N][H][W]
+    float *al;            // [N][h][w] aligned frames (room for [N][H][W])
     double *mean_parts;   // [n_mean_parts]
     double *mean;         // [1]
     double *partial;      // [N-1][n_tiles][D*D]
@@ -81,20 +88,15 @@ struct BatchArgs {
 };
 
 // ---- phase kernels: one workgroup per item ------------------------------------------------
-__global__ __launch_bounds__(BATCH_THREADS) void batch_cal(BatchArgs a, int32_t first)
+__global__ __launch_bounds__(CAL_BLOCK) void batch_cal(BatchArgs a, int32_t first)
 {
     const Item it = a.items[first + blockIdx.x];
     const StackDev &s = a.stacks[it.stack];
-    const int32_t bands = (int32_t)((s.H + CAL_ROWS - 1) / CAL_ROWS);
-    const int32_t k = it.a / bands, y0 = (it.a - k * bands) * CAL_ROWS;
-    const int32_t y1 = min(y0 + CAL_ROWS, s.H);
-    const int64_t n = (int64_t)(y1 - y0) * s.W;
-    for (int64_t i = threadIdx.x; i < n; i += BATCH_THREADS) {
-        const int32_t y = y0 + (int32_t)(i / s.W), x = (int32_t)(i % s.W);
-        const int64_t c = (int64_t)y * s.crp + x;
-        s.cal[((int64_t)k * s.H + y) * s.W + x] =
-            calib_px(s.raw[(int64_t)k * s.rfp + (int64_t)y * s.rrp + x], s.dark[c], s.flat[c]);
-    }
+    const int64_t i = (int64_t)it.a * CAL_BLOCK + threadIdx.x;
+    if (s.cal_vec)
+        calibrate_group8(s.raw, s.rrp, s.rfp, s.dark, s.flat, s.crp, s.cal, s.W, s.H, s.N, i);
+    else
+        calibrate_pixel(s.raw, s.rrp, s.rfp, s.dark, s.flat, s.crp, s.cal, s.W, s.H, s.N, i);
 }
 
 __global__ __launch_bounds__(MEAN_THREADS) void batch_meanpart(BatchArgs a, int32_t first)
@@ -190,51 +192,49 @@ __global__ void batch_rect(BatchArgs a, int32_t first)
     }
 }
 
-__device__ __forceinline__ int32_t clampi(int32_t v, int32_t lo, int32_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
-
-__global__ __launch_bounds__(COMB_TILE) void batch_out(BatchArgs a, int32_t first)
+__global__ __launch_bounds__(SH_BLOCK) void batch_shift(BatchArgs a, int32_t first)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    float *tile = reinterpret_cast<float *>(smem);
-    {
-        const Item it = a.items[first + blockIdx.x];
-        const StackDev &s = a.stacks[it.stack];
-        const int32_t x0 = s.rect[0], y0 = s.rect[1], w = s.rect[2], h = s.rect[3];
-        const int64_t plane = (int64_t)w * h;
-        unsigned dropped = 0;
-        for (int32_t sub = 0; sub < OUT_TILES; ++sub) {
-            const int64_t p0 = ((int64_t)it.a * OUT_TILES + sub) * COMB_TILE;
-            if (p0 >= plane) break;  // uniform over the workgroup
-            // aligned values of every frame for the tile's pixels, as the shift kernel makes them
-            for (int32_t k = 0; k < s.N; ++k) {
-                const int32_t px = threadIdx.x;
-                const int64_t p = p0 + px;
-                float v = 0.0f;
-                if (p < plane) {
-                    const int32_t vv = (int32_t)(p / w), u = (int32_t)(p - (int64_t)vv * w);
-                    const ShiftSetup ss = shift_setup(s.soffs[2 * k], s.soffs[2 * k + 1]);
-                    const float *f = s.cal + (int64_t)k * s.W * s.H;
-                    const int32_t j = clampi(y0 + vv + ss.iy, 0, s.H - 1);
-                    const int32_t i = clampi(x0 + u + ss.ix, 0, s.W - 1);
-                    if (s.integer_mode) {
-                        v = f[(int64_t)j * s.W + i];
-                    } else {
-                        const int32_t j1 = clampi(ss.b > 0.0 ? j + 1 : j, 0, s.H - 1);
-                        const int32_t i1 = ss.a > 0.0 ? clampi(x0 + u + ss.ix + 1, 0, s.W - 1) : i;
-                        v = bilerp(ss.a, ss.b, f[(int64_t)j * s.W + i], f[(int64_t)j * s.W + i1],
-                                   f[(int64_t)j1 * s.W + i], f[(int64_t)j1 * s.W + i1]);
-                    }
-                }
-                tile[k * COMB_TILE + px] = v;
-            }
-            __syncthreads();
-            lanes_dispatch(s.lanes, s.N, [&](auto Lc, auto Vc) {
-                constexpr int L = decltype(Lc)::value, V = decltype(Vc)::value;
-                dropped += clip_tile<L, V>(tile, p0, plane, s.N, (double)s.ksigma, s.max_iters, s.out, nullptr);
-            });
-            __syncthreads();
-        }
-        if (s.n_rej && dropped) atomicAdd(reinterpret_cast<unsigned long long *>(s.n_rej), (unsigned long long)dropped);
+    const Item it = a.items[first + blockIdx.x];
+    const StackDev &s = a.stacks[it.stack];
+    const int32_t x0 = s.rect[0], y0 = s.rect[1], w = s.rect[2], h = s.rect[3];
+    const int32_t xblks = (int32_t)ceil_div(s.W, (int64_t)SH_BLOCK * SH_VEC);
+    const int32_t strips = (int32_t)ceil_div(s.H, SH_ROWS);
+    const int32_t k = it.a / (strips * xblks);
+    const int32_t r = it.a - k * strips * xblks;
+    const int32_t strip = r / xblks, xblk = r - strip * xblks;
+    if (w < 1 || h < 1) return;
+    const int vs = shift_vec_store(w, reinterpret_cast<uintptr_t>(s.al));
+    const bool aligned = s.W % 4 == 0;
+    if (s.integer_mode)
+        shift_strip<true, SH_VEC>(s.cal, s.al, s.W, s.H, k, s.soffs[2 * k], s.soffs[2 * k + 1], strip, xblk, x0, y0,
+                                  w, h, vs, aligned);
+    else
+        shift_strip<false, SH_VEC>(s.cal, s.al, s.W, s.H, k, s.soffs[2 * k], s.soffs[2 * k + 1], strip, xblk, x0,
+                                   y0, w, h, vs, aligned);
+}
+
+// Sigma-clipped mean of block it.a of the stack's overlap; PX pixel columns per thread
+// when the overlap plane allows vector loads, else one.
+template <int MAXV, int PX>
+__global__ __launch_bounds__(COMB_TILE) void batch_comb(BatchArgs a, int32_t first)
+{
+    const Item it = a.items[first + blockIdx.x];
+    const StackDev &s = a.stacks[it.stack];
+    const int64_t plane = (int64_t)s.rect[2] * s.rect[3];
+    const bool vec = PX > 1 && plane % PX == 0;
+    const int64_t blocks = vec ? ceil_div(plane, (int64_t)COMB_TILE * PX) : ceil_div(plane, (int64_t)COMB_TILE);
+    if (it.a >= blocks) return;  // uniform over the workgroup
+    unsigned dropped;
+    if (vec)
+        dropped = combine_cols_block<MAXV, PX>(s.al, plane, s.N, (double)s.ksigma, s.max_iters, s.out, nullptr,
+                                               it.a);
+    else
+        dropped = combine_cols_block<MAXV, 1>(s.al, plane, s.N, (double)s.ksigma, s.max_iters, s.out, nullptr,
+                                              it.a);
+    if (s.n_rej) {
+        const unsigned total = block_sum_u32(dropped);
+        if (threadIdx.x == 0 && total) atomicAdd(reinterpret_cast<unsigned long long *>(s.n_rej),
+                                                 (unsigned long long)total);
     }
 }
 
@@ -249,7 +249,7 @@ static size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct StackLayout {
     RegPlan plan;
-    size_t cal, mean_parts, mean, partial, scores, soffs, rect;
+    size_t cal, al, mean_parts, mean, partial, scores, soffs, rect;
     int32_t count[N_PHASES];
 };
 
@@ -258,7 +258,7 @@ struct BatchLayout {
     size_t items, stacks, nrej_ptrs, total;
     int32_t n_items;
     int32_t first[N_PHASES], count[N_PHASES];
-    size_t score_lds, out_lds;
+    size_t score_lds;
 };
 
 static int validate(const reduce_stack_t *stacks, int32_t n)
@@ -283,12 +283,19 @@ static int validate(const reduce_stack_t *stacks, int32_t n)
     return REDUCE_OK;
 }
 
+// Dark subtraction takes 8-pixel groups when rows, pitches and pointers allow it.
+static bool cal_vec_ok(const reduce_stack_t &s)
+{
+    const auto a16 = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
+    return s.W % CAL_VEC == 0 && s.raw_row_pitch % CAL_VEC == 0 && s.raw_frame_pitch % CAL_VEC == 0 &&
+           s.cal_row_pitch % 4 == 0 && a16(s.raw) && a16(s.dark) && a16(s.flat);
+}
+
 static BatchLayout layout_of(const reduce_stack_t *stacks, int32_t n)
 {
     BatchLayout L;
     size_t off = 0;
     L.score_lds = 0;
-    L.out_lds = 0;
     for (int p = 0; p < N_PHASES; ++p) L.count[p] = 0;
     for (int32_t i = 0; i < n; ++i) {
         const reduce_stack_t &s = stacks[i];
@@ -298,6 +305,8 @@ static BatchLayout layout_of(const reduce_stack_t *stacks, int32_t n)
         const int64_t fp = (int64_t)s.W * s.H;
         const int32_t nreg = s.N - 1;
         sl.cal = off;
+        off += al(sizeof(float) * fp * s.N);
+        sl.al = off;
         off += al(sizeof(float) * fp * s.N);
         const int32_t n_mean_parts = (int32_t)ceil_div(s.H - 2 * s.radius, MEAN_ROWS);
         sl.mean_parts = off;
@@ -312,17 +321,21 @@ static BatchLayout layout_of(const reduce_stack_t *stacks, int32_t n)
         off += al(sizeof(float) * 2 * s.N);
         sl.rect = off;
         off += 256;
-        sl.count[IT_CAL] = s.N * (int32_t)ceil_div(s.H, CAL_ROWS);
+        sl.count[IT_CAL] = (int32_t)ceil_div(cal_vec_ok(s) ? fp / CAL_VEC : fp, CAL_BLOCK);
         sl.count[IT_MEANPART] = n_mean_parts;
         sl.count[IT_MEANFINAL] = 1;
         sl.count[IT_SCORE] = nreg * p.n_tiles * p.G;
         sl.count[IT_SUM] = nreg * (int32_t)ceil_div((int64_t)p.D * p.D, 64);
         sl.count[IT_PICK] = nreg;
         sl.count[IT_RECT] = 1;
-        sl.count[IT_OUT] = (int32_t)ceil_div(fp, (int64_t)COMB_TILE * OUT_TILES);
+        sl.count[IT_SHIFT] =
+            s.N * (int32_t)ceil_div(s.H, SH_ROWS) * (int32_t)ceil_div(s.W, (int64_t)SH_BLOCK * SH_VEC);
+        const int32_t comb_blocks = (int32_t)ceil_div(fp, (int64_t)COMB_TILE);
+        sl.count[IT_COMB16] = s.N <= 16 ? comb_blocks : 0;
+        sl.count[IT_COMB32] = s.N > 16 && s.N <= 32 ? comb_blocks : 0;
+        sl.count[IT_COMB48] = s.N > 32 ? comb_blocks : 0;
         for (int q = 0; q < N_PHASES; ++q) L.count[q] += sl.count[q];
         if (nreg > 0) L.score_lds = std::max(L.score_lds, p.lds);
-        L.out_lds = std::max(L.out_lds, sizeof(float) * (size_t)s.N * COMB_TILE);
         L.st.push_back(sl);
     }
     int64_t total = 0;
@@ -389,10 +402,11 @@ static int build_descriptors(const reduce_stack_t *stacks, int32_t n, void *ws, 
         d.R = st.radius;
         d.max_iters = st.max_iters;
         d.integer_mode = st.integer_mode ? 1 : 0;
-        d.lanes = combine_lanes_for(st.N);
+        d.cal_vec = cal_vec_ok(st) ? 1 : 0;
         d.K = sl.plan.K;
         d.ksigma = st.ksigma;
         d.cal = reinterpret_cast<float *>(base + sl.cal);
+        d.al = reinterpret_cast<float *>(base + sl.al);
         d.mean_parts = reinterpret_cast<double *>(base + sl.mean_parts);
         d.mean = reinterpret_cast<double *>(base + sl.mean);
         d.partial = reinterpret_cast<double *>(base + sl.partial);
@@ -411,7 +425,7 @@ static int build_descriptors(const reduce_stack_t *stacks, int32_t n, void *ws, 
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
         const auto cost = [&](int32_t z) {
             const RegPlan &p = L.st[z].plan;
-            return (double)L.st[z].count[IT_SCORE] * p.BR * p.TX * p.C + (double)L.st[z].count[IT_OUT];
+            return (double)L.st[z].count[IT_SCORE] * p.BR * p.TX * p.C + (double)L.st[z].count[IT_SHIFT];
         };
         return cost(x) > cost(y);
     });
@@ -437,7 +451,7 @@ static int launch_phases(int32_t n, void *ws, const BatchLayout &L, hipStream_t 
     int64_t *const *nrej_dev = reinterpret_cast<int64_t *const *>(base + L.nrej_ptrs);
     hipLaunchKernelGGL(batch_reset, dim3(1), dim3(256), 0, s, nrej_dev, n);
     if (L.count[IT_CAL] > 0)
-        hipLaunchKernelGGL(batch_cal, dim3(L.count[IT_CAL]), dim3(BATCH_THREADS), 0, s, a, L.first[IT_CAL]);
+        hipLaunchKernelGGL(batch_cal, dim3(L.count[IT_CAL]), dim3(CAL_BLOCK), 0, s, a, L.first[IT_CAL]);
     if (L.count[IT_MEANPART] > 0)
         hipLaunchKernelGGL(batch_meanpart, dim3(L.count[IT_MEANPART]), dim3(MEAN_THREADS), 0, s, a,
                            L.first[IT_MEANPART]);
@@ -454,8 +468,20 @@ static int launch_phases(int32_t n, void *ws, const BatchLayout &L, hipStream_t 
         hipLaunchKernelGGL(batch_pick, dim3(L.count[IT_PICK]), dim3(256), 0, s, a, L.first[IT_PICK]);
     hipLaunchKernelGGL(batch_rect, dim3(L.count[IT_RECT]), dim3(64), 0, s, a, L.first[IT_RECT]);
     {
-        ProfScope prof("batch_out", s);
-        hipLaunchKernelGGL(batch_out, dim3(L.count[IT_OUT]), dim3(COMB_TILE), L.out_lds, s, a, L.first[IT_OUT]);
+        ProfScope prof("batch_shift", s);
+        hipLaunchKernelGGL(batch_shift, dim3(L.count[IT_SHIFT]), dim3(SH_BLOCK), 0, s, a, L.first[IT_SHIFT]);
+    }
+    {
+        ProfScope prof("batch_comb", s);
+        if (L.count[IT_COMB16] > 0)
+            hipLaunchKernelGGL((batch_comb<16, COMB_PX16>), dim3(L.count[IT_COMB16]), dim3(COMB_TILE), 0, s, a,
+                               L.first[IT_COMB16]);
+        if (L.count[IT_COMB32] > 0)
+            hipLaunchKernelGGL((batch_comb<32, 1>), dim3(L.count[IT_COMB32]), dim3(COMB_TILE), 0, s, a,
+                               L.first[IT_COMB32]);
+        if (L.count[IT_COMB48] > 0)
+            hipLaunchKernelGGL((batch_comb<48, 1>), dim3(L.count[IT_COMB48]), dim3(COMB_TILE), 0, s, a,
+                               L.first[IT_COMB48]);
     }
     return check_launch("reduce_stack_batch");
 }
@@ -490,10 +516,6 @@ extern "C" int reduce_stack_batch(const reduce_stack_t *stacks, int32_t n, void 
     // shapes change; it is uploaded into the workspace on every call
     uint64_t h = fnv1a(stacks, sizeof(reduce_stack_t) * (size_t)n);
     for (const StackLayout &sl : L.st) h = fnv1a(&sl.plan, sizeof(RegPlan), h);
-    for (int32_t i = 0; i < n; ++i) {
-        const int32_t lanes = combine_lanes_for(stacks[i].N);
-        h = fnv1a(&lanes, sizeof(lanes), h);
-    }
     h = fnv1a(&L.total, sizeof(L.total), h);
     std::lock_guard<std::mutex> lk(g_batch_mu);
     BatchEntry &e = g_entries[ws];

@@ -34,144 +34,15 @@ __global__ __launch_bounds__(COMB_TILE) void combine_kernel(
     }
 }
 
-// One thread per pixel column, the column's N values in registers straight from
-// HBM (coalesced across the workgroup's 256 adjacent pixels).  The arithmetic is
-// that of clip_column with one lane: sums in frame order in double, m = s / n,
-// q = sum of (x - m)^2, threshold ksigma * sqrt(q / n), drop |x - m| > threshold.
-// Two shortcuts leave every result unchanged: the largest |x - m| of the q pass
-// decides whether the drop pass is needed at all, and when an iteration drops
-// nothing its own sum is the final sum.
-template <int MAXV, bool ALL>
-__device__ __forceinline__ bool kept_at(uint64_t kept, int i, int32_t N)
-{
-    return ALL ? i < N : ((kept >> i) & 1ull) != 0;
-}
-
-template <int MAXV, bool ALL>
-__device__ __forceinline__ void clip_pass(const float (&x)[MAXV], uint64_t kept, int32_t N, int n, double &s,
-                                          double &m, double &q, double &dmax)
-{
-    s = 0.0;
-#pragma unroll
-    for (int i = 0; i < MAXV; ++i)
-        if (kept_at<MAXV, ALL>(kept, i, N)) s = __dadd_rn(s, (double)x[i]);
-    m = s / (double)n;
-    q = 0.0;
-    dmax = 0.0;
-#pragma unroll
-    for (int i = 0; i < MAXV; ++i)
-        if (kept_at<MAXV, ALL>(kept, i, N)) {
-            const double d = __dsub_rn((double)x[i], m);
-            q = __dadd_rn(q, __dmul_rn(d, d));
-            dmax = fmax(dmax, fabs(d));
-        }
-}
-
-// Clip one column held in registers; returns the mean and updates kept / dropped.
-template <int MAXV>
-__device__ __forceinline__ float clip_registers(const float (&x)[MAXV], int32_t N, double ksigma, int32_t max_iters,
-                                                uint64_t &kept, unsigned &dropped)
-{
-    kept = N >= 64 ? ~0ull : ((1ull << N) - 1ull);
-    int n = N;
-    double s = 0.0, m = 0.0, q = 0.0, dmax = 0.0;
-    bool final_known = false;
-    for (int32_t it = 0; it < max_iters; ++it) {
-        if (it == 0)
-            clip_pass<MAXV, true>(x, kept, N, n, s, m, q, dmax);
-        else
-            clip_pass<MAXV, false>(x, kept, N, n, s, m, q, dmax);
-        const double thr = __dmul_rn(ksigma, sqrt(q / (double)n));
-        if (!(dmax > thr)) {
-            final_known = true;  // nothing drops: s is the sum over the final set
-            break;
-        }
-        int drop = 0;
-#pragma unroll
-        for (int i = 0; i < MAXV; ++i)
-            if (((kept >> i) & 1ull) && fabs(__dsub_rn((double)x[i], m)) > thr) {
-                kept &= ~(1ull << i);
-                ++drop;
-            }
-        n -= drop;
-        dropped += (unsigned)drop;
-    }
-    if (!final_known) {
-        s = 0.0;
-#pragma unroll
-        for (int i = 0; i < MAXV; ++i)
-            if ((kept >> i) & 1ull) s = __dadd_rn(s, (double)x[i]);
-    }
-    return (float)(s / (double)n);
-}
-
-// PX adjacent pixel columns per thread: each frame's PX values come in as one vector
-// load (plane and pointer aligned to PX floats), then the columns are clipped one
-// after the other.
+// PX adjacent pixel columns per thread (combine_cols_block); one atomic per workgroup
+// for the rejection count.
 template <int MAXV, int PX>
 __global__ __launch_bounds__(COMB_TILE) void combine_cols(
     const float *__restrict__ aligned, int64_t plane, int32_t N, double ksigma, int32_t max_iters,
     float *__restrict__ out, uint8_t *__restrict__ keep, unsigned long long *__restrict__ n_rej)
 {
-    const int64_t p0 = ((int64_t)blockIdx.x * COMB_TILE + threadIdx.x) * PX;
-    float xs[PX][MAXV];
-    if (PX == 1 || p0 + PX <= plane) {
-#pragma unroll
-        for (int i = 0; i < MAXV; ++i) {
-            if (i < N) {
-                const float *src = aligned + (int64_t)i * plane + p0;
-                if (PX == 4) {
-                    const float4 v = *reinterpret_cast<const float4 *>(src);
-                    xs[0][i] = v.x;
-                    xs[1][i] = v.y;
-                    xs[2][i] = v.z;
-                    xs[3][i] = v.w;
-                } else if (PX == 2) {
-                    const float2 v = *reinterpret_cast<const float2 *>(src);
-                    xs[0][i] = v.x;
-                    xs[1][i] = v.y;
-                } else {
-                    xs[0][i] = p0 < plane ? src[0] : 0.0f;
-                }
-            } else {
-#pragma unroll
-                for (int c = 0; c < PX; ++c) xs[c][i] = 0.0f;
-            }
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < MAXV; ++i)
-#pragma unroll
-            for (int c = 0; c < PX; ++c)
-                xs[c][i] = (i < N && p0 + c < plane) ? aligned[(int64_t)i * plane + p0 + c] : 0.0f;
-    }
-    unsigned dropped = 0;
-    float res[PX];
-    uint64_t kept[PX];
-#pragma unroll
-    for (int c = 0; c < PX; ++c) {
-        unsigned d = 0;
-        res[c] = clip_registers<MAXV>(xs[c], N, ksigma, max_iters, kept[c], d);
-        if (p0 + c < plane) dropped += d;
-    }
-    if (PX > 1 && p0 + PX <= plane) {
-        if (PX == 4)
-            *reinterpret_cast<float4 *>(out + p0) = make_float4(res[0], res[1], res[2], res[3]);
-        else
-            *reinterpret_cast<float2 *>(out + p0) = make_float2(res[0], res[1]);
-    } else {
-#pragma unroll
-        for (int c = 0; c < PX; ++c)
-            if (p0 + c < plane) out[p0 + c] = res[c];
-    }
-    if (keep) {
-#pragma unroll
-        for (int i = 0; i < MAXV; ++i)
-            if (i < N)
-#pragma unroll
-                for (int c = 0; c < PX; ++c)
-                    if (p0 + c < plane) keep[(int64_t)i * plane + p0 + c] = (uint8_t)((kept[c] >> i) & 1ull);
-    }
+    const unsigned dropped = combine_cols_block<MAXV, PX>(aligned, plane, N, ksigma, max_iters, out, keep,
+                                                          (int64_t)blockIdx.x);
     if (n_rej) {
         const unsigned total = block_sum_u32(dropped);
         if (threadIdx.x == 0 && total) atomicAdd(n_rej, (unsigned long long)total);

@@ -40,7 +40,7 @@ struct ProfScope {
     }
 };
 
-inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // ---- per-element arithmetic ----------------------------------------------------
 

@@ -159,9 +159,6 @@ __device__ __forceinline__ void score_tile(const ScoreArgs &a, int32_t lid, unsi
     const int32_t j_lo = c0 / a.NBX;
 
     const int t = threadIdx.x;
-    const int lane = t & 63;
-    const int wave = t >> 6;
-    const int nwaves = a.threads >> 6;
     const bool in_block = t < a.threads;
     const int cl = t % a.CW;
     const int s = t / a.CW;

@@ -49,8 +49,8 @@ def parse():
     ap.add_argument("--workload", type=int, default=1, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the cost-model launch shapes")
-    ap.add_argument("--path", choices=("stagewise", "batched"), default="stagewise",
-                    help="stage-wise entry points per stack, or one batched call for all stacks")
+    ap.add_argument("--path", choices=("stagewise", "batched"), default="batched",
+                    help="one batched call for all stacks (default), or the stage-wise entry points per stack")
     ap.add_argument("--tune-cache", default=None,
                     help="load tuned launch shapes from this file if it exists, else tune and save them here")
     ap.add_argument("--copy-probe", action="store_true",
@@ -61,7 +61,8 @@ def parse():
     ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="rocprofv3 --pmc output folders (FETCH_SIZE and WRITE_SIZE runs of this benchmark "
                          "and of --copy-probe): write the --traffic JSON and exit")
-    ap.add_argument("--traffic-kernels", default=",".join(("score_tiles", "calibrate", "shift", "combine")),
+    ap.add_argument("--traffic-kernels", default=",".join(("batch_score", "batch_cal", "batch_shift", "batch_comb",
+                                                           "score_tiles", "calibrate", "shift", "combine")),
                     help="with --traffic-from: the kernels to record (those unchanged since the counter runs)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal comparison")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2008_11486_amd", "weights",
@@ -81,11 +82,17 @@ def parse():
 # while these files are unchanged.
 KERNEL_SOURCES = {
     "score_tiles": ("register.hip", "register_core.h", "register_plan.h", "plan.cpp"),
-    "calibrate": ("calibrate.hip", "common.h"),
-    "shift": ("shift.hip", "common.h"),
+    "batch_score": ("batch.hip", "register_core.h", "register_plan.h", "plan.cpp"),
+    "batch_shift": ("batch.hip", "shift_core.h", "common.h"),
+    "batch_comb": ("batch.hip", "combine_core.h"),
+    "batch_cal": ("batch.hip", "calibrate_core.h", "common.h"),
+    "calibrate": ("calibrate.hip", "calibrate_core.h", "common.h"),
+    "shift": ("shift.hip", "shift_core.h", "common.h"),
     "combine": ("combine.hip", "combine_core.h"),
 }
-KERNEL_SYMBOLS = {"score_tiles": "score_tiles", "calibrate": "calibrate_", "shift": "shift_kernel",
+KERNEL_SYMBOLS = {"batch_score": "batch_score", "batch_shift": "batch_shift", "batch_comb": "batch_comb",
+                  "batch_cal": "batch_cal", "score_tiles": "score_tiles", "calibrate": "calibrate_",
+                  "shift": "shift_kernel",
                   "combine": "combine_"}
 
 
@@ -427,7 +434,7 @@ def main():
     flops = sum(register_flops_per_launch(st.spec, st.spec.N - 1)
                 for st in (stacks if args.path == "batched" else stacks[:1]))
     achieved = flops / score_avg_s / 1e12
-    traffic = recorded_traffic(args.traffic, "score_tiles") if args.path == "stagewise" else None
+    traffic = recorded_traffic(args.traffic, "batch_score" if args.path == "batched" else "score_tiles")
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(FP64_VALU_PEAK_TFLOPS, 3),
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4), "traffic": traffic,
                 "kernel": "batch_score" if args.path == "batched" else "score_tiles",

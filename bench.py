@@ -349,7 +349,10 @@ def main():
         rec = traffic_from(*args.traffic_from, workload=args.workload, kernels=args.traffic_kernels.split(","))
         old = json.load(open(args.traffic)) if os.path.exists(args.traffic) else {}
         if args.traffic_key == "kernels":
+            kernels = dict(old.get("kernels", {}))
+            kernels.update(rec["kernels"])
             old.update(rec)
+            old["kernels"] = kernels
         else:
             old[args.traffic_key] = {"workload": "16 frames 6144x6160 (wide field)", "kernels": rec["kernels"],
                                      "fetch_scale": rec["fetch_scale"], "write_scale": rec["write_scale"]}

@@ -6,6 +6,7 @@
 //   MEANPART   sum MEAN_ROWS template rows of the calibrated reference
 //   MEANFINAL  template mean of the reference
 //   SCORE      one tile of partial correlation scores (the stack's tuned launch shape)
+//   SSCORE     the same for windows of side <= 5 (four strip tiles per item)
 //   SUM        64 candidate scores of one frame from its tile partials
 //   PICK       argmax, runner-up, parabola of one frame
 //   RECT       common overlap of the stack from its offsets
@@ -47,8 +48,8 @@ constexpr int BATCH_THREADS = 512;
 constexpr int COMB_PX16 = 2;    // pixel columns per thread of the up-to-16-frame combine
 
 enum ItemType : int32_t {
-    IT_CAL = 0, IT_MEANPART, IT_MEANFINAL, IT_SCORE, IT_SUM, IT_PICK, IT_RECT, IT_SHIFT, IT_COMB16, IT_COMB32,
-    IT_COMB48
+    IT_CAL = 0, IT_MEANPART, IT_MEANFINAL, IT_SCORE, IT_SSCORE, IT_SUM, IT_PICK, IT_RECT, IT_SHIFT, IT_COMB16,
+    IT_COMB32, IT_COMB48
 };
 constexpr int N_PHASES = IT_COMB48 + 1;
 
@@ -124,6 +125,13 @@ __global__ __launch_bounds__(BATCH_THREADS) void batch_score(BatchArgs a, int32_
     const Item it = a.items[first + xcd_logical_id((int32_t)blockIdx.x, count)];
     const StackDev &s = a.stacks[it.stack];
     score_dispatch(s.K, [&](auto Kc) { score_tile<decltype(Kc)::value>(s.sa, it.a, smem); });
+}
+
+__global__ __launch_bounds__(64 * SMALL_WAVES) void batch_score_small(BatchArgs a, int32_t first)
+{
+    const Item it = a.items[first + blockIdx.x];
+    const StackDev &s = a.stacks[it.stack];
+    small_dispatch(s.sa.D, [&](auto Dc) { score_small_tile<decltype(Dc)::value>(s.sa, it.a); });
 }
 
 __global__ __launch_bounds__(64 * SUM_WAVES) void batch_sum(BatchArgs a, int32_t first)
@@ -324,7 +332,8 @@ static BatchLayout layout_of(const reduce_stack_t *stacks, int32_t n)
         sl.count[IT_CAL] = (int32_t)ceil_div(cal_vec_ok(s) ? fp / CAL_VEC : fp, CAL_BLOCK);
         sl.count[IT_MEANPART] = n_mean_parts;
         sl.count[IT_MEANFINAL] = 1;
-        sl.count[IT_SCORE] = nreg * p.n_tiles * p.G;
+        sl.count[IT_SCORE] = p.K != 0 ? nreg * p.wg_per_frame : 0;
+        sl.count[IT_SSCORE] = p.K == 0 ? nreg * p.wg_per_frame : 0;
         sl.count[IT_SUM] = nreg * (int32_t)ceil_div((int64_t)p.D * p.D, 64);
         sl.count[IT_PICK] = nreg;
         sl.count[IT_RECT] = 1;
@@ -335,7 +344,7 @@ static BatchLayout layout_of(const reduce_stack_t *stacks, int32_t n)
         sl.count[IT_COMB32] = s.N > 16 && s.N <= 32 ? comb_blocks : 0;
         sl.count[IT_COMB48] = s.N > 32 ? comb_blocks : 0;
         for (int q = 0; q < N_PHASES; ++q) L.count[q] += sl.count[q];
-        if (nreg > 0) L.score_lds = std::max(L.score_lds, p.lds);
+        if (nreg > 0 && p.K != 0) L.score_lds = std::max(L.score_lds, p.lds);
         L.st.push_back(sl);
     }
     int64_t total = 0;
@@ -425,7 +434,8 @@ static int build_descriptors(const reduce_stack_t *stacks, int32_t n, void *ws, 
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
         const auto cost = [&](int32_t z) {
             const RegPlan &p = L.st[z].plan;
-            return (double)L.st[z].count[IT_SCORE] * p.BR * p.TX * p.C + (double)L.st[z].count[IT_SHIFT];
+            return (double)(L.st[z].count[IT_SCORE] + L.st[z].count[IT_SSCORE]) * p.BR * p.TX * p.C +
+                   (double)L.st[z].count[IT_SHIFT];
         };
         return cost(x) > cost(y);
     });
@@ -462,6 +472,9 @@ static int launch_phases(int32_t n, void *ws, const BatchLayout &L, hipStream_t 
         hipLaunchKernelGGL(batch_score, dim3(L.count[IT_SCORE]), dim3(BATCH_THREADS), L.score_lds, s, a,
                            L.first[IT_SCORE], L.count[IT_SCORE]);
     }
+    if (L.count[IT_SSCORE] > 0)
+        hipLaunchKernelGGL(batch_score_small, dim3(L.count[IT_SSCORE]), dim3(64 * SMALL_WAVES), 0, s, a,
+                           L.first[IT_SSCORE]);
     if (L.count[IT_SUM] > 0)
         hipLaunchKernelGGL(batch_sum, dim3(L.count[IT_SUM]), dim3(64 * SUM_WAVES), 0, s, a, L.first[IT_SUM]);
     if (L.count[IT_PICK] > 0)

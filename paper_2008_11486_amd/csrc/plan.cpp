@@ -107,6 +107,39 @@ bool reg_plan_from_shape(int32_t W, int32_t H, int32_t R, int32_t Rmax, const Re
     p.BR = (int32_t)std::min<int64_t>((int64_t)sh.CPT * p.TY, ceil_div(th, p.TY) * p.TY);
     p.n_bands = (int32_t)ceil_div(th, p.BR);
     p.n_tiles = p.n_bands * p.n_xchunks;
+    p.wg_per_frame = p.n_tiles * p.G;
+    *out = p;
+    return true;
+}
+
+bool reg_plan_small(int32_t W, int32_t H, int32_t R, int32_t Rmax, RegPlan *out)
+{
+    constexpr int32_t ROWS = 256, WAVES = 4;  // the device constants SMALL_ROWS, SMALL_WAVES
+    RegPlan p{};
+    p.D = 2 * R + 1;
+    if (p.D > 5) return false;
+    const int32_t tw = W - 2 * Rmax, th = H - 2 * Rmax;
+    if (tw < 1 || th < 1) return false;
+    p.K = 0;
+    p.NBX = 1;
+    p.C = p.D;
+    p.G = 1;
+    p.CW = p.D;
+    p.S = 1;
+    p.threads = 64 * WAVES;
+    p.TX = 64;
+    p.NXB = 1;
+    p.TY = ROWS;
+    p.BR = ROWS;
+    p.JS = p.D;
+    p.FR = 0;
+    p.FC = 0;
+    p.lds = 0;
+    p.th_max = th;
+    p.n_xchunks = (int32_t)ceil_div(tw, 64);
+    p.n_bands = (int32_t)ceil_div(th, ROWS);
+    p.n_tiles = p.n_bands * p.n_xchunks;
+    p.wg_per_frame = (int32_t)ceil_div(p.n_tiles, WAVES);
     *out = p;
     return true;
 }
@@ -168,6 +201,7 @@ RegPlan reg_plan(int32_t W, int32_t H, int32_t R, int32_t Rmax, int32_t K_force,
     if (!TY_force) TY_force = env_int("REDUCE_REG_TY");
     RegPlan p{};
     RegShape sh{};
+    if (!K_force && !TY_force && env_int("REDUCE_REG_GENERAL") != 1 && reg_plan_small(W, H, R, Rmax, &p)) return p;
     if (!K_force && !TY_force && tuned_reg_shape(W, H, R, Rmax, &sh) && reg_plan_from_shape(W, H, R, Rmax, sh, &p))
         return p;
     std::vector<std::pair<double, RegShape>> shapes;

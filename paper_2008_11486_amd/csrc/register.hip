@@ -101,6 +101,12 @@ ScoreArgs make_score_args(const RegPlan &p, const float *ref, const float *frame
     return a;
 }
 
+template <int D>
+__global__ __launch_bounds__(64 * SMALL_WAVES) void score_small(ScoreArgs a)
+{
+    score_small_tile<D>(a, (int32_t)blockIdx.x);
+}
+
 template <int K>
 static void launch_score(const ScoreArgs &a, const RegPlan &p, hipStream_t s)
 {
@@ -127,6 +133,16 @@ int register_launch(const float *ref, const float *frames, int32_t W, int32_t H,
                        (double)tw * (double)th, mean);
     const ScoreArgs a =
         make_score_args(p, ref, frames, centers, mean, partial, W, H, N, R, Rmax, tx0, ty0, tw, th, 0x7fffffff);
+    if (p.K == 0) {
+        ProfScope prof("score_tiles", s);
+        // workgroups for this call's template (at most the plan's, which is sized for the largest)
+        const dim3 grid((unsigned)(ceil_div(a.n_tiles, SMALL_WAVES) * N));
+        switch (p.D) {
+        case 1: hipLaunchKernelGGL(score_small<1>, grid, dim3(64 * SMALL_WAVES), 0, s, a); break;
+        case 3: hipLaunchKernelGGL(score_small<3>, grid, dim3(64 * SMALL_WAVES), 0, s, a); break;
+        default: hipLaunchKernelGGL(score_small<5>, grid, dim3(64 * SMALL_WAVES), 0, s, a); break;
+        }
+    } else {
     switch (p.K) {
     case 5: launch_score<5>(a, p, s); break;
     case 9: launch_score<9>(a, p, s); break;
@@ -134,6 +150,7 @@ int register_launch(const float *ref, const float *frames, int32_t W, int32_t H,
     case 17: launch_score<17>(a, p, s); break;
     case 18: launch_score<18>(a, p, s); break;
     default: launch_score<22>(a, p, s); break;
+    }
     }
     hipLaunchKernelGGL(sum_tiles, dim3((unsigned)ceil_div((int64_t)p.D * p.D, 64), N), dim3(64 * SUM_WAVES), 0, s,
                        partial, a.n_tiles, p.D, R, Rmax, centers, sc);

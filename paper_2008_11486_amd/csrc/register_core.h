@@ -251,6 +251,87 @@ __device__ __forceinline__ void score_tile(const ScoreArgs &a, int32_t lid, unsi
     __syncthreads();  // LDS is reused by the caller's next item
 }
 
+// ---- small windows (side D <= 5) ------------------------------------------------------------
+// A tile is a strip of SMALL_ROWS template rows x 64 template columns, one per wave; lane l
+// owns template column 64 * colblock + l and walks down the strip with all D x D candidate
+// sums in registers.  The frame rows a template row needs (D of them, one per window row)
+// slide down with it: a ring of D + 1 rows, converted to FP64 once when loaded, one row
+// ahead of use.  At the end of the strip each sum is reduced over the wave with a fixed
+// butterfly and written as the tile's partial, in the layout of the general kernel.
+constexpr int SMALL_ROWS = 256;   // template rows per tile
+constexpr int SMALL_WAVES = 4;    // tiles (one per wave) per workgroup
+constexpr int SMALL_D_MAX = 5;
+
+template <int D>
+__device__ __forceinline__ void score_small_tile(const ScoreArgs &a, int32_t lid)
+{
+    constexpr int U = D + 1;  // ring rows
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int32_t groups = (a.n_tiles + SMALL_WAVES - 1) / SMALL_WAVES;
+    const int32_t g = lid % groups, k = lid / groups;
+    const int32_t tile = g * SMALL_WAVES + wave;
+    if (wave >= SMALL_WAVES || tile >= a.n_tiles) return;
+    const int32_t strip = tile / a.n_xchunks, colb = tile - strip * a.n_xchunks;
+    const int32_t x = colb * 64 + lane;
+    const bool col_ok = x < a.tw;
+    const int32_t y0 = strip * SMALL_ROWS, y1 = min(y0 + SMALL_ROWS, a.th);
+    const int32_t cx = a.centers ? a.centers[2 * k] : 0, cy = a.centers ? a.centers[2 * k + 1] : 0;
+    const int32_t kf = k + (k >= a.skip ? 1 : 0);
+    const float *f = a.frames + (int64_t)kf * a.W * a.H;
+    const double mean = *a.mean;
+    // frame columns of the D offsets dx = cx - R + j, clamped into the frame: an offset
+    // beyond +-Rmax is discarded when the tiles are summed, so any in-frame value will do
+    int32_t gx[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) gx[j] = min(max(a.tx0 + x + cx - a.R + j, 0), a.W - 1);
+    const float *ref_col = a.ref + a.tx0 + (col_ok ? x : 0);
+    const int32_t base0 = a.ty0 + y0 + cy - a.R;  // frame row of window row 0 at template row y0
+
+    double ring[U][D];
+    double acc[D * D];
+#pragma unroll
+    for (int q = 0; q < D * D; ++q) acc[q] = 0.0;
+    auto load_row = [&](double(&dst)[D], int32_t r) {
+        const float *row = f + (int64_t)min(max(r, 0), a.H - 1) * a.W;
+#pragma unroll
+        for (int j = 0; j < D; ++j) dst[j] = (double)row[gx[j]];
+    };
+#pragma unroll
+    for (int i = 0; i < D; ++i) load_row(ring[i], base0 + i);
+    for (int32_t t = 0; t < y1 - y0; t += U) {
+#pragma unroll
+        for (int p = 0; p < U; ++p) {
+            const int32_t yl = t + p;  // template row y0 + yl uses ring rows p .. p + D - 1 (mod U)
+            if (yl < y1 - y0) {
+                load_row(ring[(p + D) % U], base0 + yl + D);  // for the next template row
+                const double rv = col_ok ? (double)ref_col[(int64_t)(a.ty0 + y0 + yl) * a.W] - mean : 0.0;
+#pragma unroll
+                for (int i = 0; i < D; ++i)
+#pragma unroll
+                    for (int j = 0; j < D; ++j) acc[i * D + j] = fma(rv, ring[(p + i) % U][j], acc[i * D + j]);
+            }
+        }
+    }
+    double *out = a.partial + ((int64_t)k * a.n_tiles + tile) * (int64_t)(D * D);
+#pragma unroll
+    for (int q = 0; q < D * D; ++q) {
+        double v = acc[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == q) out[q] = v;
+    }
+}
+
+template <typename F>
+__device__ __forceinline__ void small_dispatch(int D, F &&f)
+{
+    switch (D) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    default: f(std::integral_constant<int, 5>{}); break;
+    }
+}
+
 template <typename F>
 __device__ __forceinline__ void score_dispatch(int K, F &&f)
 {

@@ -26,7 +26,12 @@ struct RegPlan {
     size_t lds;         // dynamic LDS bytes
     int32_t n_bands, n_xchunks, n_tiles;  // tiles of the largest template
     int32_t th_max;
+    int32_t wg_per_frame;  // workgroups (work items) per frame
 };
+
+// The small-window plan (window side D <= 5): K = 0, strips of SMALL_ROWS template rows x
+// 64 columns, one per wave, four per workgroup; no LDS.
+bool reg_plan_small(int32_t W, int32_t H, int32_t R, int32_t Rmax, RegPlan *out);
 
 // Per-workgroup shape of a plan; everything else follows from it and the sizes.
 struct RegShape {

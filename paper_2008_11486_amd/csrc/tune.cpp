@@ -72,6 +72,17 @@ extern "C" int reduce_tune_register(const float *ref, const float *frames, int32
         return fail(REDUCE_ERR_RANGE, "reduce_tune_register: no template for these sizes");
     if (reps < 1) reps = 1;
     hipStream_t s = as_stream(stream);
+    {
+        RegPlan sp;
+        if (reg_plan_small(W, H, radius, radius_max, &sp)) {  // small windows have one shape
+            if (fields) {
+                const int32_t v[16] = {sp.D, sp.K, sp.NBX, sp.C, sp.G, sp.CW, sp.S, sp.threads, sp.TX, sp.TY, sp.BR,
+                                       sp.JS, sp.FR, sp.FC, (int32_t)sp.lds, sp.n_tiles};
+                for (int i = 0; i < 16; ++i) fields[i] = v[i];
+            }
+            return REDUCE_OK;
+        }
+    }
     constexpr int MAXC = 64;
     RegShape cand[MAXC];
     int n = 0;

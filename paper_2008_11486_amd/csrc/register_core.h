@@ -255,17 +255,18 @@ __device__ __forceinline__ void score_tile(const ScoreArgs &a, int32_t lid, unsi
 // A tile is a strip of SMALL_ROWS template rows x 64 template columns, one per wave; lane l
 // owns template column 64 * colblock + l and walks down the strip with all D x D candidate
 // sums in registers.  The frame rows a template row needs (D of them, one per window row)
-// slide down with it: a ring of D + 1 rows, converted to FP64 once when loaded, one row
-// ahead of use.  At the end of the strip each sum is reduced over the wave with a fixed
+// slide down with it: a ring of D + SMALL_AHEAD rows, converted to FP64 once when loaded,
+// requested SMALL_AHEAD rows ahead of use.  At the end of the strip each sum is reduced over the wave with a fixed
 // butterfly and written as the tile's partial, in the layout of the general kernel.
 constexpr int SMALL_ROWS = 256;   // template rows per tile
 constexpr int SMALL_WAVES = 4;    // tiles (one per wave) per workgroup
 constexpr int SMALL_D_MAX = 5;
+constexpr int SMALL_AHEAD = 3;    // rows of frame data in flight ahead of use
 
 template <int D>
 __device__ __forceinline__ void score_small_tile(const ScoreArgs &a, int32_t lid)
 {
-    constexpr int U = D + 1;  // ring rows
+    constexpr int U = D + SMALL_AHEAD;  // ring rows
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int32_t groups = (a.n_tiles + SMALL_WAVES - 1) / SMALL_WAVES;
     const int32_t g = lid % groups, k = lid / groups;
@@ -297,13 +298,14 @@ __device__ __forceinline__ void score_small_tile(const ScoreArgs &a, int32_t lid
         for (int j = 0; j < D; ++j) dst[j] = (double)row[gx[j]];
     };
 #pragma unroll
-    for (int i = 0; i < D; ++i) load_row(ring[i], base0 + i);
+    for (int i = 0; i < D + SMALL_AHEAD - 1; ++i) load_row(ring[i], base0 + i);
     for (int32_t t = 0; t < y1 - y0; t += U) {
 #pragma unroll
         for (int p = 0; p < U; ++p) {
             const int32_t yl = t + p;  // template row y0 + yl uses ring rows p .. p + D - 1 (mod U)
             if (yl < y1 - y0) {
-                load_row(ring[(p + D) % U], base0 + yl + D);  // for the next template row
+                // the row template row yl + SMALL_AHEAD needs last
+                load_row(ring[(p + D + SMALL_AHEAD - 1) % U], base0 + yl + D + SMALL_AHEAD - 1);
                 const double rv = col_ok ? (double)ref_col[(int64_t)(a.ty0 + y0 + yl) * a.W] - mean : 0.0;
 #pragma unroll
                 for (int i = 0; i < D; ++i)

@@ -114,7 +114,7 @@ bool reg_plan_from_shape(int32_t W, int32_t H, int32_t R, int32_t Rmax, const Re
 
 bool reg_plan_small(int32_t W, int32_t H, int32_t R, int32_t Rmax, RegPlan *out)
 {
-    constexpr int32_t ROWS = 256, WAVES = 4;  // the device constants SMALL_ROWS, SMALL_WAVES
+    constexpr int32_t ROWS = 128, WAVES = 4;  // the device constants SMALL_ROWS, SMALL_WAVES
     RegPlan p{};
     p.D = 2 * R + 1;
     if (p.D > 5) return false;

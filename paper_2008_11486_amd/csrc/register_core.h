@@ -258,7 +258,7 @@ __device__ __forceinline__ void score_tile(const ScoreArgs &a, int32_t lid, unsi
 // slide down with it: a ring of D + SMALL_AHEAD rows, converted to FP64 once when loaded,
 // requested SMALL_AHEAD rows ahead of use.  At the end of the strip each sum is reduced over the wave with a fixed
 // butterfly and written as the tile's partial, in the layout of the general kernel.
-constexpr int SMALL_ROWS = 256;   // template rows per tile
+constexpr int SMALL_ROWS = 128;   // template rows per tile
 constexpr int SMALL_WAVES = 4;    // tiles (one per wave) per workgroup
 constexpr int SMALL_D_MAX = 5;
 constexpr int SMALL_AHEAD = 3;    // rows of frame data in flight ahead of use
@@ -267,7 +267,10 @@ template <int D>
 __device__ __forceinline__ void score_small_tile(const ScoreArgs &a, int32_t lid)
 {
     constexpr int U = D + SMALL_AHEAD;  // ring rows
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    // the wave index is the same for all lanes of a wave; saying so keeps everything
+    // derived from it (tile, rows, row addresses) in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int32_t groups = (a.n_tiles + SMALL_WAVES - 1) / SMALL_WAVES;
     const int32_t g = lid % groups, k = lid / groups;
     const int32_t tile = g * SMALL_WAVES + wave;
@@ -275,17 +278,17 @@ __device__ __forceinline__ void score_small_tile(const ScoreArgs &a, int32_t lid
     const int32_t strip = tile / a.n_xchunks, colb = tile - strip * a.n_xchunks;
     const int32_t x = colb * 64 + lane;
     const bool col_ok = x < a.tw;
-    const int32_t y0 = strip * SMALL_ROWS, y1 = min(y0 + SMALL_ROWS, a.th);
+    const int32_t y0 = strip * SMALL_ROWS, rows = min(y0 + SMALL_ROWS, a.th) - y0;
     const int32_t cx = a.centers ? a.centers[2 * k] : 0, cy = a.centers ? a.centers[2 * k + 1] : 0;
     const int32_t kf = k + (k >= a.skip ? 1 : 0);
     const float *f = a.frames + (int64_t)kf * a.W * a.H;
     const double mean = *a.mean;
     // frame columns of the D offsets dx = cx - R + j, clamped into the frame: an offset
     // beyond +-Rmax is discarded when the tiles are summed, so any in-frame value will do
-    int32_t gx[D];
+    uint32_t gx4[D];  // byte offsets within a frame row
 #pragma unroll
-    for (int j = 0; j < D; ++j) gx[j] = min(max(a.tx0 + x + cx - a.R + j, 0), a.W - 1);
-    const float *ref_col = a.ref + a.tx0 + (col_ok ? x : 0);
+    for (int j = 0; j < D; ++j) gx4[j] = 4u * (uint32_t)min(max(a.tx0 + x + cx - a.R + j, 0), a.W - 1);
+    const uint32_t rx4 = 4u * (uint32_t)(a.tx0 + (col_ok ? x : 0));
     const int32_t base0 = a.ty0 + y0 + cy - a.R;  // frame row of window row 0 at template row y0
 
     double ring[U][D];
@@ -293,26 +296,27 @@ __device__ __forceinline__ void score_small_tile(const ScoreArgs &a, int32_t lid
 #pragma unroll
     for (int q = 0; q < D * D; ++q) acc[q] = 0.0;
     auto load_row = [&](double(&dst)[D], int32_t r) {
-        const float *row = f + (int64_t)min(max(r, 0), a.H - 1) * a.W;
+        const char *row = reinterpret_cast<const char *>(f + (int64_t)min(max(r, 0), a.H - 1) * a.W);
 #pragma unroll
-        for (int j = 0; j < D; ++j) dst[j] = (double)row[gx[j]];
+        for (int j = 0; j < D; ++j) dst[j] = (double)*reinterpret_cast<const float *>(row + gx4[j]);
+    };
+    // template row y0 + yl: its value, then window rows i = 0..D-1 use ring rows yl + i (mod U);
+    // the ring row freed by yl - 1 takes frame row yl + D + SMALL_AHEAD - 1
+    auto step = [&](int p, int32_t yl) {
+        load_row(ring[(p + D + SMALL_AHEAD - 1) % U], base0 + yl + D + SMALL_AHEAD - 1);
+        const char *rrow = reinterpret_cast<const char *>(a.ref + (int64_t)(a.ty0 + y0 + yl) * a.W);
+        const double rv = col_ok ? (double)*reinterpret_cast<const float *>(rrow + rx4) - mean : 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) acc[i * D + j] = fma(rv, ring[(p + i) % U][j], acc[i * D + j]);
     };
 #pragma unroll
     for (int i = 0; i < D + SMALL_AHEAD - 1; ++i) load_row(ring[i], base0 + i);
-    for (int32_t t = 0; t < y1 - y0; t += U) {
+    for (int32_t t = 0; t < rows; t += U) {
 #pragma unroll
-        for (int p = 0; p < U; ++p) {
-            const int32_t yl = t + p;  // template row y0 + yl uses ring rows p .. p + D - 1 (mod U)
-            if (yl < y1 - y0) {
-                // the row template row yl + SMALL_AHEAD needs last
-                load_row(ring[(p + D + SMALL_AHEAD - 1) % U], base0 + yl + D + SMALL_AHEAD - 1);
-                const double rv = col_ok ? (double)ref_col[(int64_t)(a.ty0 + y0 + yl) * a.W] - mean : 0.0;
-#pragma unroll
-                for (int i = 0; i < D; ++i)
-#pragma unroll
-                    for (int j = 0; j < D; ++j) acc[i * D + j] = fma(rv, ring[(p + i) % U][j], acc[i * D + j]);
-            }
-        }
+        for (int p = 0; p < U; ++p)
+            if (t + p < rows) step(p, t + p);  // uniform over the wave
     }
     double *out = a.partial + ((int64_t)k * a.n_tiles + tile) * (int64_t)(D * D);
 #pragma unroll

@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--learned-frames", type=int, default=16)
     ap.add_argument("--no-wide", action="store_true",
                     help="skip the streaming kernels at the wide-field size (16 frames of 6144x6160)")
+    ap.add_argument("--no-many", action="store_true",
+                    help="skip the batched leg over 64 stacks of 3-30 frames, sides 512-4096")
     ap.add_argument("--wide-only", action="store_true",
                     help="run only the wide-field streaming kernels (for counter runs) and print their figures")
     ap.add_argument("--traffic-key", default="kernels",
@@ -242,6 +244,64 @@ def cpu_baseline(stacks, integer_mode, min_seconds=10.0, max_reps=20):
     return {"value": pix / dt / 1e6, "unit": "Mpix/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"the full workload ({len(stacks)} stacks, {pix / reps / 1e6:.1f} Mpix) {reps} times, "
                       f"FP64 C oracle from raw frames (calibrate, search, shift, combine), {dt:.1f} s"}
+
+
+def many_stacks(torch, rd, reps=2):
+    """64 stacks (frame counts 3-30, square sides 512-4096, sub-pixel shifts within +-16 px,
+    search radius 17) through one batched call: the stack shapes of the many-stack
+    workload, frames rendered on the GPU (star density of the 1024x1024 stacks)."""
+    import synth
+    from paper_2008_11486_amd import learned
+    specs = synth.config_specs(2)
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(20081148)
+    stacks, pix = [], 0
+    tuned = set()
+    for i, sp in enumerate(specs):
+        rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([20081148, 2, 7, i])))
+        x = rng.uniform(-24, sp.W + 24, sp.n_stars)
+        y = rng.uniform(-24, sp.H + 24, sp.n_stars)
+        amp = np.exp(rng.uniform(np.log(2e3), np.log(5e4), sp.n_stars))
+        t = np.zeros((sp.N, 2))
+        t[1:] = rng.uniform(-16, 16, (sp.N - 1, 2))
+        stars = np.zeros((sp.N, sp.n_stars, 4), np.float32)
+        for k in range(sp.N):
+            stars[k, :, 0], stars[k, :, 1], stars[k, :, 2] = x + t[k, 0], y + t[k, 1], amp
+        frames = rd.render_frames(torch.from_numpy(stars).to(dev),
+                                  torch.arange(sp.N, dtype=torch.int64, device=dev) + 64 * i, sp.W, sp.H,
+                                  sky=1000.0, fwhm=3.0, read_noise=10.0, seed=2)
+        if sp.W not in tuned:  # tuned shapes per frame size (they do not depend on N)
+            rd.tune_register(frames[0].contiguous(), frames[1:3].contiguous(), sp.radius)
+            tuned.add(sp.W)
+        dark = 100.0 + 3.0 * torch.randn((sp.H, sp.W), generator=g, device=dev)
+        flat = 0.95 + 0.1 * torch.rand((sp.H, sp.W), generator=g, device=dev)
+        raw = frames.mul_(flat).add_(dark).round_().clamp_(0, 65535).to(torch.int32).to(torch.int16)
+        del frames
+        stacks.append((raw, dark, flat, sp.radius))
+        pix += sp.N * sp.W * sp.H
+    batch = rd.StackBatch(stacks)
+    batch.run()
+    torch.cuda.synchronize()
+    rd.prof_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        batch.run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    ms, n = rd.prof_query("batch_score")
+    rd.prof_enable(False)
+    flops = sum(2.0 * (sp.N - 1) * (sp.W - 2 * sp.radius) * (sp.H - 2 * sp.radius) * (2 * sp.radius + 1) ** 2
+                for sp in specs)
+    frames_n = [sp.N for sp in specs]
+    res = {"workload": f"{len(specs)} stacks, N in {min(frames_n)}-{max(frames_n)} ({sum(frames_n)} frames), "
+                       f"sides 512-4096, shifts +-16 px, R=17, one batched call",
+           "Mpix/s": round(pix / dt / 1e6, 1), "ms_per_call": round(dt * 1e3, 2), "input_pixels": pix,
+           "search_ms": round(ms / n, 2), "search_TFLOP/s": round(flops / (ms / n / 1e3) / 1e12, 2),
+           "search_frac_fp64": round(flops / (ms / n / 1e3) / 1e12 / FP64_VALU_PEAK_TFLOPS, 4)}
+    del batch, stacks
+    torch.cuda.empty_cache()
+    return res
 
 
 def learned_comparison(torch, rd, weights_path, M):
@@ -467,6 +527,8 @@ def main():
     }
     if not args.no_wide:
         line["streaming_wide"] = streaming_wide(torch, rd)
+    if not args.no_many:
+        line["many_stacks"] = many_stacks(torch, rd)
     if not args.no_learned:
         line["learned"] = learned_comparison(torch, rd, args.weights, args.learned_frames)
     if not args.no_cpu_baseline:

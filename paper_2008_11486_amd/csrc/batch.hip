@@ -119,12 +119,15 @@ __global__ __launch_bounds__(MEAN_THREADS) void batch_meanfinal(BatchArgs a, int
     if (threadIdx.x == 0) *s.mean = m;
 }
 
+// One launch per group of stacks that share a search shape (register block K, threads,
+// LDS), with exactly that workgroup size and LDS, as the stage-wise launch uses.
+template <int K>
 __global__ __launch_bounds__(BATCH_THREADS) void batch_score(BatchArgs a, int32_t first, int32_t count)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const Item it = a.items[first + xcd_logical_id((int32_t)blockIdx.x, count)];
     const StackDev &s = a.stacks[it.stack];
-    score_dispatch(s.K, [&](auto Kc) { score_tile<decltype(Kc)::value>(s.sa, it.a, smem); });
+    score_tile<K>(s.sa, it.a, smem);
 }
 
 __global__ __launch_bounds__(64 * SMALL_WAVES) void batch_score_small(BatchArgs a, int32_t first)
@@ -261,13 +264,27 @@ struct StackLayout {
     int32_t count[N_PHASES];
 };
 
+struct ScoreGroup {
+    int32_t K, threads;
+    size_t lds;
+    std::vector<int32_t> stacks;  // by decreasing search work
+    int32_t first, count;         // item range within the SCORE phase
+};
+
 struct BatchLayout {
     std::vector<StackLayout> st;
     size_t items, stacks, nrej_ptrs, total;
     int32_t n_items;
     int32_t first[N_PHASES], count[N_PHASES];
     size_t score_lds;
+    std::vector<ScoreGroup> groups;
 };
+
+static double search_cost(const StackLayout &sl)
+{
+    const RegPlan &p = sl.plan;
+    return (double)sl.count[IT_SCORE] * p.BR * p.TX * p.C;
+}
 
 static int validate(const reduce_stack_t *stacks, int32_t n)
 {
@@ -353,6 +370,28 @@ static BatchLayout layout_of(const reduce_stack_t *stacks, int32_t n)
         total += L.count[q];
     }
     L.n_items = total > INT32_MAX ? -1 : (int32_t)total;
+    // search groups by shape, in order of first appearance; stacks within a group by cost
+    int32_t next = L.first[IT_SCORE];
+    for (int32_t i = 0; i < n; ++i) {
+        const StackLayout &sl = L.st[i];
+        if (sl.count[IT_SCORE] == 0) continue;
+        ScoreGroup *g = nullptr;
+        for (ScoreGroup &c : L.groups)
+            if (c.K == sl.plan.K && c.threads == sl.plan.threads && c.lds == sl.plan.lds) g = &c;
+        if (!g) {
+            L.groups.push_back(ScoreGroup{sl.plan.K, sl.plan.threads, sl.plan.lds, {}, 0, 0});
+            g = &L.groups.back();
+        }
+        g->stacks.push_back(i);
+    }
+    for (ScoreGroup &g : L.groups) {
+        std::stable_sort(g.stacks.begin(), g.stacks.end(),
+                         [&](int32_t x, int32_t y) { return search_cost(L.st[x]) > search_cost(L.st[y]); });
+        g.first = next;
+        g.count = 0;
+        for (int32_t i : g.stacks) g.count += L.st[i].count[IT_SCORE];
+        next += g.count;
+    }
     L.items = off;
     off += al(sizeof(Item) * (size_t)std::max<int64_t>(total, 0));
     L.stacks = off;
@@ -441,15 +480,35 @@ static int build_descriptors(const reduce_stack_t *stacks, int32_t n, void *ws, 
     });
     std::vector<Item> items;
     items.reserve(L.n_items);
-    for (int q = 0; q < N_PHASES; ++q)
+    for (int q = 0; q < N_PHASES; ++q) {
+        if (q == IT_SCORE) {
+            for (const ScoreGroup &g : L.groups)
+                for (int32_t i : g.stacks)
+                    for (int32_t a = 0; a < L.st[i].count[q]; ++a) items.push_back({q, i, a, 0});
+            continue;
+        }
         for (int32_t i : order)
             for (int32_t a = 0; a < L.st[i].count[q]; ++a) items.push_back({q, i, a, 0});
+    }
     if ((int32_t)items.size() != L.n_items) return fail(REDUCE_ERR_SHAPE, "reduce_stack_batch: item count");
     e->host.assign(L.total - L.items, 0);
     std::memcpy(e->host.data(), items.data(), sizeof(Item) * items.size());
     std::memcpy(e->host.data() + (L.stacks - L.items), sd.data(), sizeof(StackDev) * sd.size());
     std::memcpy(e->host.data() + (L.nrej_ptrs - L.items), nrej.data(), sizeof(int64_t *) * nrej.size());
     return REDUCE_OK;
+}
+
+template <typename F>
+static void score_dispatch_host(int K, F &&f)
+{
+    switch (K) {
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    case 9: f(std::integral_constant<int, 9>{}); break;
+    case 12: f(std::integral_constant<int, 12>{}); break;
+    case 17: f(std::integral_constant<int, 17>{}); break;
+    case 18: f(std::integral_constant<int, 18>{}); break;
+    default: f(std::integral_constant<int, 22>{}); break;
+    }
 }
 
 static int launch_phases(int32_t n, void *ws, const BatchLayout &L, hipStream_t s)
@@ -469,8 +528,11 @@ static int launch_phases(int32_t n, void *ws, const BatchLayout &L, hipStream_t 
                        L.first[IT_MEANFINAL]);
     if (L.count[IT_SCORE] > 0) {
         ProfScope prof("batch_score", s);
-        hipLaunchKernelGGL(batch_score, dim3(L.count[IT_SCORE]), dim3(BATCH_THREADS), L.score_lds, s, a,
-                           L.first[IT_SCORE], L.count[IT_SCORE]);
+        for (const ScoreGroup &g : L.groups)
+            score_dispatch_host(g.K, [&](auto Kc) {
+                constexpr int K = decltype(Kc)::value;
+                hipLaunchKernelGGL(batch_score<K>, dim3(g.count), dim3(g.threads), g.lds, s, a, g.first, g.count);
+            });
     }
     if (L.count[IT_SSCORE] > 0)
         hipLaunchKernelGGL(batch_score_small, dim3(L.count[IT_SSCORE]), dim3(64 * SMALL_WAVES), 0, s, a,

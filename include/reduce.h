@@ -287,12 +287,16 @@ int reduce_render_frames(const float *stars, int32_t S, const int64_t *keys, int
  *     fits ws_bytes are tried; out receives the offsets (device reduce_offset_t [N]);
  *     fields (host int32[16] or NULL) receives the chosen plan as in
  *     reduce_register_plan.
+ *   reduce_tune_register_ws: workspace bytes that fit every candidate shape of
+ *     reduce_tune_register for these sizes (0 for sizes without a template); a
+ *     workspace of reduce_register_ws bytes may exclude the faster shapes.
  *   reduce_tune_combine: lanes per pixel column L in {1, 2, 4, 8, 16} for N frames;
  *     out (device float [h][w]) is overwritten; lanes (host, or NULL) gets L.
  *   reduce_tune_save / reduce_tune_load: the cache as JSON lines tagged with the
  *     device architecture; entries of other architectures are ignored on load.
  * Errors: as the calls they time; no fitting candidate -> WORKSPACE; unreadable or
  * unwritable file -> RANGE. */
+size_t reduce_tune_register_ws(int32_t W, int32_t H, int32_t N, int32_t radius, int32_t radius_max);
 int reduce_tune_register(const float *ref, const float *frames, int32_t W, int32_t H, int32_t N,
                          int32_t radius, int32_t radius_max, reduce_offset_t *out, void *ws,
                          size_t ws_bytes, int32_t reps, void *stream, int32_t *fields);

@@ -68,6 +68,8 @@ def _declare(L):
     L.reduce_register_plan.argtypes = [I32, I32, I32, I32, I32, P]
     L.reduce_register_plan.restype = ctypes.c_int
     L.reduce_tune_register.argtypes = [P, P, I32, I32, I32, I32, I32, P, P, SZ, I32, P, P]
+    L.reduce_tune_register_ws.argtypes = [I32, I32, I32, I32, I32]
+    L.reduce_tune_register_ws.restype = SZ
     L.reduce_tune_combine.argtypes = [P, I32, I32, I32, F, I32, P, I32, P, P]
     L.reduce_tune_save.argtypes = [ctypes.c_char_p]
     L.reduce_tune_load.argtypes = [ctypes.c_char_p]
@@ -113,7 +115,8 @@ def exported_symbols() -> Sequence[str]:
     return ("reduce_status_str", "reduce_last_error", "reduce_version", "reduce_calibrate",
             "reduce_register_ws", "reduce_register", "reduce_valid_rect", "reduce_shift",
             "reduce_combine", "reduce_prof_enable", "reduce_prof_query", "reduce_register_plan",
-            "reduce_tune_register", "reduce_tune_combine", "reduce_tune_save", "reduce_tune_load",
+            "reduce_tune_register", "reduce_tune_register_ws", "reduce_tune_combine", "reduce_tune_save",
+            "reduce_tune_load",
             "reduce_tune_clear", "reduce_stack_batch_ws", "reduce_stack_batch",
             "reduce_cnn_input_ws", "reduce_cnn_input", "reduce_cnn_num_params", "reduce_cnn_ws",
             "reduce_cnn_ws_offsets", "reduce_cnn_forward", "reduce_cnn_backward", "reduce_cnn_adamw",
@@ -230,7 +233,8 @@ def tune_register(ref: torch.Tensor, frames: torch.Tensor, radius: int, radius_m
         frames = frames.unsqueeze(0)
     N, H, W = frames.shape
     rmax = radius if radius_max is None else radius_max
-    ws = torch.empty(max(register_ws_bytes(W, H, N, radius, rmax), 1), dtype=torch.uint8, device=frames.device)
+    ws = torch.empty(max(int(lib().reduce_tune_register_ws(W, H, N, radius, rmax)), 1), dtype=torch.uint8,
+                     device=frames.device)
     out = torch.empty((N, OFFSET_BYTES), dtype=torch.uint8, device=frames.device)
     f = (ctypes.c_int32 * 16)()
     _check(lib().reduce_tune_register(_ptr(ref), _ptr(frames), W, H, N, radius, rmax, _ptr(out), _ptr(ws),

@@ -3,6 +3,7 @@
 // device architecture.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <string>
@@ -61,6 +62,24 @@ static int time_ms(hipStream_t s, int reps, F fn, double *ms)
 }  // namespace rd
 
 using namespace rd;
+
+extern "C" size_t reduce_tune_register_ws(int32_t W, int32_t H, int32_t N, int32_t radius, int32_t radius_max)
+{
+    if (W < 1 || H < 1 || N < 1 || radius < 0 || radius_max < 0) return 0;
+    if (W - 2 * radius_max < 1 || H - 2 * radius_max < 1) return 0;
+    size_t need = reduce_register_ws(W, H, N, radius, radius_max);
+    RegPlan sp;
+    if (reg_plan_small(W, H, radius, radius_max, &sp)) return need;
+    constexpr int MAXC = 64;
+    RegShape cand[MAXC];
+    int n = 0;
+    reg_shape_candidates(W, H, radius, radius_max, cand, &n, MAXC);
+    for (int i = 0; i < n; ++i) {
+        RegPlan p;
+        if (reg_plan_from_shape(W, H, radius, radius_max, cand[i], &p)) need = std::max(need, register_ws_bytes(p, N));
+    }
+    return need;
+}
 
 extern "C" int reduce_tune_register(const float *ref, const float *frames, int32_t W, int32_t H, int32_t N,
                                     int32_t radius, int32_t radius_max, reduce_offset_t *out, void *ws,

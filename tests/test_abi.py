@@ -62,6 +62,19 @@ def test_register_ws_is_monotone(rd):
     assert rd.register_ws_bytes(16, 16, 1, 8) == 0  # no template left
 
 
+def test_tuner_workspace_covers_the_search_plan(rd):
+    # the tuner's workspace bound is never below what the plan in use needs, and for the
+    # large general-kernel cases it exceeds it (candidates with more tiles are included)
+    L = rd.lib()
+    for W, H, N, R in ((512, 512, 5, 8), (1024, 1024, 10, 21), (4096, 4096, 16, 17), (4096, 4096, 2, 64),
+                       (4096, 4096, 16, 2)):
+        plan_ws = rd.register_ws_bytes(W, H, N, R)
+        tune_ws = int(L.reduce_tune_register_ws(W, H, N, R, R))
+        assert tune_ws >= plan_ws > 0, (W, H, N, R)
+    assert int(L.reduce_tune_register_ws(4096, 4096, 16, 17, 17)) > rd.register_ws_bytes(4096, 4096, 16, 17)
+    assert int(L.reduce_tune_register_ws(16, 16, 1, 8, 8)) == 0
+
+
 def test_valid_rect_matches_oracle(rd, orc):
     rng = np.random.default_rng(3)
     for _ in range(200):

@@ -3,8 +3,6 @@
 // the kernels that wrap it and the host side of reduce_register.
 //
 // Roofline: VALU (FP64 FMA).  Algorithmic work per frame: |T| * (2R+1)^2 FMA.
-#include <cstdint>
-#include <cstdlib>
 #include <string>
 
 #include "common.h"
@@ -100,8 +98,6 @@ ScoreArgs make_score_args(const RegPlan &p, const float *ref, const float *frame
     a.G = p.G;
     a.threads = p.threads;
     a.skip = skip;
-    a.vec4 = (W % 4 == 0) && ((uintptr_t)ref % 16 == 0) && ((uintptr_t)frames % 16 == 0) &&
-             std::getenv("REDUCE_SCALAR_STAGING") == nullptr;
     return a;
 }
 

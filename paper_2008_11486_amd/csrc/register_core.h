@@ -41,7 +41,6 @@ struct ScoreArgs {
     int32_t TY, TX, NXB, BR, NBX, C, CW, S, JS, FR, FC, n_xchunks, n_tiles, N, G;
     int32_t threads;         // threads taking part (the first `threads` of the block)
     int32_t skip;            // index of a frame to step over (the reference), or a large value
-    int32_t vec4;            // W % 4 == 0 and ref, frames 16-byte aligned: stage with float4 loads
 };
 
 // ---- template mean ---------------------------------------------------------------
@@ -137,53 +136,6 @@ __device__ __forceinline__ void stage_tile(int rows, int cols, int nthreads, int
     }
 }
 
-// Vector form of stage_tile (U float4 loads in flight per thread) for sources whose rows start on 16-byte boundaries: a tile
-// row is `cols` floats that begin `mis` (0..3) floats past such a boundary; lanes load
-// whole aligned float4s, row-major, and store each of the four values whose tile column
-// c = 4q + i - mis lies in [0, cols).  row(r, q) gives the q-th float4 of tile row r, or
-// NULL if it lies outside the source (its values are stored as zero, like stage_tile's);
-// `safe` is any readable aligned address, loaded in place of NULL so that the loads of a
-// batch stay unconditional.  The LDS contents equal stage_tile's for the same tile.
-template <int U, typename Row, typename Store>
-__device__ __forceinline__ void stage_tile_v4(int rows, int cols, int mis, int nthreads, int t, Row row,
-                                              const float4 *__restrict__ safe, Store store)
-{
-    const int q4 = (mis + cols + 3) >> 2;
-    const int n = rows * q4;
-    const int dr = nthreads / q4, dq = nthreads - dr * q4;
-    int r = t / q4, q = t - r * q4;
-    for (int e = t; e < n; e += U * nthreads) {
-        float4 v[U];
-        int lr[U], lq[U];
-        bool ok[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            lr[u] = r;
-            lq[u] = q;
-            const float4 *p = (e + u * nthreads < n) ? row(r, q) : nullptr;
-            ok[u] = p != nullptr;
-            v[u] = *(ok[u] ? p : safe);
-            q += dq;
-            r += dr;
-            if (q >= q4) {
-                q -= q4;
-                ++r;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (e + u * nthreads >= n) continue;
-            const int c0 = 4 * lq[u] - mis;
-            const float vv[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int c = c0 + i;
-                if (c >= 0 && c < cols) store(lr[u], c, ok[u], vv[i]);
-            }
-        }
-    }
-}
-
 // ---- one tile of partial scores ----------------------------------------------------------
 // lid in [0, n_tiles * G * N): tile fastest, then candidate group, then frame.
 template <int K>
@@ -229,27 +181,7 @@ __device__ __forceinline__ void score_tile(const ScoreArgs &a, int32_t lid, unsi
     const int pairs = a.TY * a.NXB;
     for (int32_t yc = yb0; yc < yb1; yc += a.TY) {
         __syncthreads();
-        if (in_block && a.vec4) {
-            // the same tiles as below, with aligned float4 loads
-            const int32_t gx_t = a.tx0 + x_t;
-            const int mis_t = gx_t & 3;
-            const int32_t tx_end = a.tx0 + a.tw;
-            const float4 *safe = reinterpret_cast<const float4 *>(a.ref);
-            stage_tile_v4<(K >= 12 ? 8 : 4)>(a.TY, a.TX, mis_t, a.threads, t, [&](int r, int q) -> const float4 * {
-                const int32_t x4 = gx_t - mis_t + 4 * q;
-                if (yc + r >= yb1 || x4 >= tx_end) return nullptr;
-                return reinterpret_cast<const float4 *>(a.ref + (int64_t)(a.ty0 + yc + r) * a.W + x4);
-            }, safe, [&](int r, int c, bool ok, float v) {
-                rt[r * a.TX + c] = ok && x_t + c < a.tw ? (double)v - mean : 0.0;
-            });
-            const int32_t fy0 = a.ty0 + yc + cy - a.R + j_lo;
-            const int mis_f = fx0 & 3;  // two's complement: fx0 - mis_f is the float4 boundary below fx0
-            stage_tile_v4<(K >= 12 ? 8 : 4)>(a.FR, a.FC, mis_f, a.threads, t, [&](int r, int q) -> const float4 * {
-                const int32_t gy = fy0 + r, gx = fx0 - mis_f + 4 * q;
-                if (gy < 0 || gy >= a.H || gx < 0 || gx >= a.W) return nullptr;
-                return reinterpret_cast<const float4 *>(f + (int64_t)gy * a.W + gx);
-            }, safe, [&](int r, int c, bool ok, float v) { ft[r * a.FC + c] = ok ? v : 0.0f; });
-        } else if (in_block) {
+        if (in_block) {
             // template tile (zero outside T: contributes exactly nothing), then the frame
             // tile (zero outside the frame)
             stage_tile(a.TY, a.TX, a.threads, t, [&](int r, int c, bool &ok) -> int64_t {

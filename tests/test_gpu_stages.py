@@ -126,30 +126,6 @@ def test_register_template_and_centres(rd, orc):
     np.testing.assert_allclose(S2[fin], So2[fin], rtol=1e-11)
 
 
-@pytest.mark.parametrize("K", [5, 9, 12, 17, 18, 22])
-def test_register_vector_staging_matches_scalar(rd, monkeypatch, K):
-    # float4 staging of 16-byte aligned frames fills LDS exactly as the scalar staging
-    # does: same scores and offsets bit for bit, including a template that starts off a
-    # float4 boundary and windows whose frame columns start left of the frame
-    spec = synth.small_spec(3, 200, 176, n_stars=40, shift_bound=9.0, radius=11, seed=(K,))
-    st = synth.make_stack(spec)
-    cal = rd.calibrate(*_stack_dev(st))
-    ref = cal[0].contiguous()
-    centers = to_dev(np.array([[0, 0], [5, -7], [-12, 12]], dtype=np.int32))
-    monkeypatch.setenv("REDUCE_REG_K", str(K))
-    rd.tune_clear()
-    runs = []
-    for scalar in (False, True):
-        if scalar:
-            monkeypatch.setenv("REDUCE_SCALAR_STAGING", "1")
-        o1, s1 = rd.register(ref, cal, 11, want_scores=True)
-        o2, s2 = rd.register(ref, cal, 3, 12, centers=centers, tmpl=(13, 14, 170, 140), want_scores=True)
-        runs.append([t.cpu() for t in (o1, s1, o2, s2)])
-    assert rd.register_plan(200, 176, 3, 11)["K"] == K
-    for a, b in zip(*runs):
-        assert torch.equal(a, b)
-
-
 def test_register_workload0_integer_shifts(rd, orc):
     st = synth.make_config(0)[0]
     cal = rd.calibrate(*_stack_dev(st))

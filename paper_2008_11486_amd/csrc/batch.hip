@@ -6,7 +6,7 @@
 //   MEANPART   sum MEAN_ROWS template rows of the calibrated reference
 //   MEANFINAL  template mean of the reference
 //   SCORE      one tile of partial correlation scores (the stack's tuned launch shape)
-//   SSCORE     the same for windows of side <= 5 (four strip tiles per item)
+//   SSCORE     the same for windows of side <= 5 (one tile of 240 x 256 template pixels per item)
 //   SUM        64 candidate scores of one frame from its tile partials
 //   PICK       argmax, runner-up, parabola of one frame
 //   RECT       common overlap of the stack from its offsets
@@ -130,11 +130,12 @@ __global__ __launch_bounds__(BATCH_THREADS) void batch_score(BatchArgs a, int32_
     score_tile<K>(s.sa, it.a, smem);
 }
 
-__global__ __launch_bounds__(64 * SMALL_WAVES) void batch_score_small(BatchArgs a, int32_t first)
+__global__ __launch_bounds__(SMALL_COLS) void batch_score_small(BatchArgs a, int32_t first)
 {
+    __shared__ __align__(16) float fl[SMALL_LDS_FLOATS];
     const Item it = a.items[first + blockIdx.x];
     const StackDev &s = a.stacks[it.stack];
-    small_dispatch(s.sa.D, [&](auto Dc) { score_small_tile<decltype(Dc)::value>(s.sa, it.a); });
+    small_dispatch(s.sa.D, [&](auto Dc) { score_small_tile<decltype(Dc)::value>(s.sa, it.a, fl); });
 }
 
 __global__ __launch_bounds__(64 * SUM_WAVES) void batch_sum(BatchArgs a, int32_t first)
@@ -535,7 +536,7 @@ static int launch_phases(int32_t n, void *ws, const BatchLayout &L, hipStream_t 
             });
     }
     if (L.count[IT_SSCORE] > 0)
-        hipLaunchKernelGGL(batch_score_small, dim3(L.count[IT_SSCORE]), dim3(64 * SMALL_WAVES), 0, s, a,
+        hipLaunchKernelGGL(batch_score_small, dim3(L.count[IT_SSCORE]), dim3(SMALL_COLS), 0, s, a,
                            L.first[IT_SSCORE]);
     if (L.count[IT_SUM] > 0)
         hipLaunchKernelGGL(batch_sum, dim3(L.count[IT_SUM]), dim3(64 * SUM_WAVES), 0, s, a, L.first[IT_SUM]);

@@ -114,7 +114,7 @@ bool reg_plan_from_shape(int32_t W, int32_t H, int32_t R, int32_t Rmax, const Re
 
 bool reg_plan_small(int32_t W, int32_t H, int32_t R, int32_t Rmax, RegPlan *out)
 {
-    constexpr int32_t ROWS = 128, WAVES = 4;  // the device constants SMALL_ROWS, SMALL_WAVES
+    constexpr int32_t COLS = 256, ROWS = 240;  // the device constants SMALL_COLS, SMALL_ROWS
     RegPlan p{};
     p.D = 2 * R + 1;
     if (p.D > 5) return false;
@@ -126,20 +126,20 @@ bool reg_plan_small(int32_t W, int32_t H, int32_t R, int32_t Rmax, RegPlan *out)
     p.G = 1;
     p.CW = p.D;
     p.S = 1;
-    p.threads = 64 * WAVES;
-    p.TX = 64;
+    p.threads = COLS;
+    p.TX = COLS;
     p.NXB = 1;
-    p.TY = ROWS;
+    p.TY = 15;  // rows per staged chunk
     p.BR = ROWS;
     p.JS = p.D;
-    p.FR = 0;
-    p.FC = 0;
-    p.lds = 0;
+    p.FR = 15;
+    p.FC = COLS + 4;
+    p.lds = 2 * 15 * (COLS + 4) * sizeof(float);  // static in the kernel
     p.th_max = th;
-    p.n_xchunks = (int32_t)ceil_div(tw, 64);
+    p.n_xchunks = (int32_t)ceil_div(tw, COLS);
     p.n_bands = (int32_t)ceil_div(th, ROWS);
     p.n_tiles = p.n_bands * p.n_xchunks;
-    p.wg_per_frame = (int32_t)ceil_div(p.n_tiles, WAVES);
+    p.wg_per_frame = p.n_tiles;
     *out = p;
     return true;
 }

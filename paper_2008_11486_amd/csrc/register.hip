@@ -102,9 +102,10 @@ ScoreArgs make_score_args(const RegPlan &p, const float *ref, const float *frame
 }
 
 template <int D>
-__global__ __launch_bounds__(64 * SMALL_WAVES) void score_small(ScoreArgs a)
+__global__ __launch_bounds__(SMALL_COLS) void score_small(ScoreArgs a)
 {
-    score_small_tile<D>(a, (int32_t)blockIdx.x);
+    __shared__ __align__(16) float fl[SMALL_LDS_FLOATS];
+    score_small_tile<D>(a, (int32_t)blockIdx.x, fl);
 }
 
 template <int K>
@@ -136,11 +137,11 @@ int register_launch(const float *ref, const float *frames, int32_t W, int32_t H,
     if (p.K == 0) {
         ProfScope prof("score_tiles", s);
         // workgroups for this call's template (at most the plan's, which is sized for the largest)
-        const dim3 grid((unsigned)(ceil_div(a.n_tiles, SMALL_WAVES) * N));
+        const dim3 grid((unsigned)((int64_t)a.n_tiles * N));
         switch (p.D) {
-        case 1: hipLaunchKernelGGL(score_small<1>, grid, dim3(64 * SMALL_WAVES), 0, s, a); break;
-        case 3: hipLaunchKernelGGL(score_small<3>, grid, dim3(64 * SMALL_WAVES), 0, s, a); break;
-        default: hipLaunchKernelGGL(score_small<5>, grid, dim3(64 * SMALL_WAVES), 0, s, a); break;
+        case 1: hipLaunchKernelGGL(score_small<1>, grid, dim3(SMALL_COLS), 0, s, a); break;
+        case 3: hipLaunchKernelGGL(score_small<3>, grid, dim3(SMALL_COLS), 0, s, a); break;
+        default: hipLaunchKernelGGL(score_small<5>, grid, dim3(SMALL_COLS), 0, s, a); break;
         }
     } else {
     switch (p.K) {

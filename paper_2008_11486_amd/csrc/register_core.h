@@ -252,80 +252,146 @@ __device__ __forceinline__ void score_tile(const ScoreArgs &a, int32_t lid, unsi
 }
 
 // ---- small windows (side D <= 5) ------------------------------------------------------------
-// A tile is a strip of SMALL_ROWS template rows x 64 template columns, one per wave; lane l
-// owns template column 64 * colblock + l and walks down the strip with all D x D candidate
-// sums in registers.  The frame rows a template row needs (D of them, one per window row)
-// slide down with it: a ring of D + SMALL_AHEAD rows, converted to FP64 once when loaded,
-// requested SMALL_AHEAD rows ahead of use.  At the end of the strip each sum is reduced over the wave with a fixed
-// butterfly and written as the tile's partial, in the layout of the general kernel.
-constexpr int SMALL_ROWS = 128;   // template rows per tile
-constexpr int SMALL_WAVES = 4;    // tiles (one per wave) per workgroup
+// A tile is SMALL_ROWS template rows x SMALL_COLS template columns for one workgroup of
+// SMALL_COLS threads; thread t owns template column SMALL_COLS * colblock + t and walks down
+// the tile with all D x D candidate sums in registers.  The frame rows a template row needs
+// (D of them, one per window row) slide down with it in a register ring of D rows, converted
+// to FP64 once; the newest row of the ring comes from LDS, where the workgroup stages the
+// frame in chunks of SMALL_CH rows x SMALL_FC columns, double-buffered: the loads of the next
+// chunk (and its template values) are issued before the current chunk is computed, so one
+// barrier per chunk is the only wait.  At the end each sum is reduced over the wave with a
+// fixed butterfly and over the waves in wave order, and written as the tile's partial in the
+// layout of the general kernel.
+constexpr int SMALL_COLS = 256;                       // template columns per tile, one per thread
+constexpr int SMALL_CH = 15;                          // template rows per chunk (a multiple of every D)
+constexpr int SMALL_ROWS = 16 * SMALL_CH;             // template rows per tile
+constexpr int SMALL_FC = SMALL_COLS + 4;              // frame columns per staged row (>= SMALL_COLS + D - 1)
+constexpr int SMALL_LDS_FLOATS = 2 * SMALL_CH * SMALL_FC + SMALL_COLS;  // both chunk buffers, one spare slot per thread
 constexpr int SMALL_D_MAX = 5;
-constexpr int SMALL_AHEAD = 3;    // rows of frame data in flight ahead of use
+static_assert(SMALL_CH % 15 == 0, "chunk rows must be a multiple of 1, 3 and 5");
+static_assert(4 * SMALL_CH <= SMALL_COLS && SMALL_FC - SMALL_COLS == 4, "extra staged columns");
+static_assert(SMALL_LDS_FLOATS * 4 >= 8 * (SMALL_COLS / 64) * SMALL_D_MAX * SMALL_D_MAX, "reduction scratch");
 
 template <int D>
-__device__ __forceinline__ void score_small_tile(const ScoreArgs &a, int32_t lid)
+__device__ __forceinline__ void score_small_tile(const ScoreArgs &a, int32_t lid, float *__restrict__ fl)
 {
-    constexpr int U = D + SMALL_AHEAD;  // ring rows
-    const int lane = threadIdx.x & 63;
-    // the wave index is the same for all lanes of a wave; saying so keeps everything
-    // derived from it (tile, rows, row addresses) in scalar registers
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int32_t groups = (a.n_tiles + SMALL_WAVES - 1) / SMALL_WAVES;
-    const int32_t g = lid % groups, k = lid / groups;
-    const int32_t tile = g * SMALL_WAVES + wave;
-    if (wave >= SMALL_WAVES || tile >= a.n_tiles) return;
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    const int32_t tile = lid % a.n_tiles, k = lid / a.n_tiles;
     const int32_t strip = tile / a.n_xchunks, colb = tile - strip * a.n_xchunks;
-    const int32_t x = colb * 64 + lane;
+    const int32_t x = colb * SMALL_COLS + t;
     const bool col_ok = x < a.tw;
     const int32_t y0 = strip * SMALL_ROWS, rows = min(y0 + SMALL_ROWS, a.th) - y0;
+    const int nch = (rows + SMALL_CH - 1) / SMALL_CH;
     const int32_t cx = a.centers ? a.centers[2 * k] : 0, cy = a.centers ? a.centers[2 * k + 1] : 0;
     const int32_t kf = k + (k >= a.skip ? 1 : 0);
     const float *f = a.frames + (int64_t)kf * a.W * a.H;
     const double mean = *a.mean;
-    // frame columns of the D offsets dx = cx - R + j, clamped into the frame: an offset
-    // beyond +-Rmax is discarded when the tiles are summed, so any in-frame value will do
-    uint32_t gx4[D];  // byte offsets within a frame row
-#pragma unroll
-    for (int j = 0; j < D; ++j) gx4[j] = 4u * (uint32_t)min(max(a.tx0 + x + cx - a.R + j, 0), a.W - 1);
-    const uint32_t rx4 = 4u * (uint32_t)(a.tx0 + (col_ok ? x : 0));
-    const int32_t base0 = a.ty0 + y0 + cy - a.R;  // frame row of window row 0 at template row y0
+    // staged column c is frame column fx0 + c, clamped into the frame (an offset beyond
+    // +-Rmax is discarded when the tiles are summed, so any in-frame value will do); frame
+    // row of window row 0 at template row y0 is fy0; chunk ch holds frame rows
+    // fy0 + D - 1 + ch * SMALL_CH + [0, SMALL_CH), clamped likewise
+    const int32_t fx0 = a.tx0 + colb * SMALL_COLS + cx - a.R;
+    const int32_t fy0 = a.ty0 + y0 + cy - a.R;
+    // 32-bit element offsets (a frame holds fewer than 2^31 pixels)
+    const uint32_t W = (uint32_t)a.W;
+    const float *tcol = a.ref + a.tx0 + (col_ok ? x : 0);
+    const int32_t ty_last = a.ty0 + y0 + rows - 1;
 
-    double ring[U][D];
+    // staging: thread t loads column t of every chunk row, and threads t < 4 * SMALL_CH also
+    // one of the SMALL_FC - SMALL_COLS extra columns (row t / 4, column SMALL_COLS + t % 4);
+    // row offsets are uniform over the workgroup
+    const int32_t gxm = min(max(fx0 + t, 0), a.W - 1);
+    const bool has_x = t < 4 * SMALL_CH;
+    const int xr = has_x ? t >> 2 : 0, xc = SMALL_COLS + (t & 3);
+    const int32_t gxx = min(max(fx0 + xc, 0), a.W - 1);
+    float pf[SMALL_CH], pfx;
+    auto load_chunk = [&](int ch) {
+        const int32_t gy0 = fy0 + D - 1 + ch * SMALL_CH;
+#pragma unroll
+        for (int r = 0; r < SMALL_CH; ++r) pf[r] = f[(uint32_t)min(max(gy0 + r, 0), a.H - 1) * W + (uint32_t)gxm];
+        pfx = f[(uint32_t)min(max(gy0 + xr, 0), a.H - 1) * W + (uint32_t)gxx];
+    };
+    // branch-free: a thread without an extra value writes it to its spare slot
+    const int xslot = has_x ? xr * SMALL_FC + xc : 2 * SMALL_CH * SMALL_FC + t;
+    auto store_chunk = [&](int buf) {
+        float *dst = fl + buf * (SMALL_CH * SMALL_FC);
+#pragma unroll
+        for (int r = 0; r < SMALL_CH; ++r) dst[r * SMALL_FC + t] = pf[r];
+        fl[has_x ? buf * (SMALL_CH * SMALL_FC) + xslot : xslot] = pfx;
+    };
+    // template value of row y0 + yl of this thread's column (rows past the tile repeat its last)
+    auto tmpl_at = [&](int32_t yl) { return tcol[(uint32_t)min(a.ty0 + y0 + yl, ty_last) * W]; };
+
+    // the ring starts with frame rows fy0 .. fy0 + D - 2 (window rows 0 .. D-2 of template row 0)
+    double ring[D][D];
+#pragma unroll
+    for (int i = 0; i + 1 < D; ++i) {
+        const float *row = f + (uint32_t)min(max(fy0 + i, 0), a.H - 1) * W;
+#pragma unroll
+        for (int j = 0; j < D; ++j) ring[i][j] = (double)row[min(max(fx0 + t + j, 0), a.W - 1)];
+    }
     double acc[D * D];
 #pragma unroll
     for (int q = 0; q < D * D; ++q) acc[q] = 0.0;
-    auto load_row = [&](double(&dst)[D], int32_t r) {
-        const char *row = reinterpret_cast<const char *>(f + (int64_t)min(max(r, 0), a.H - 1) * a.W);
+    const double colw = col_ok ? 1.0 : 0.0;
+
+    // template values one chunk ahead: tv[p] holds row ch * SMALL_CH + p while chunk ch is
+    // computed and is refilled with row (ch + 1) * SMALL_CH + p right after its use
+    float tv[SMALL_CH];
 #pragma unroll
-        for (int j = 0; j < D; ++j) dst[j] = (double)*reinterpret_cast<const float *>(row + gx4[j]);
-    };
-    // template row y0 + yl: its value, then window rows i = 0..D-1 use ring rows yl + i (mod U);
-    // the ring row freed by yl - 1 takes frame row yl + D + SMALL_AHEAD - 1
-    auto step = [&](int p, int32_t yl) {
-        load_row(ring[(p + D + SMALL_AHEAD - 1) % U], base0 + yl + D + SMALL_AHEAD - 1);
-        const char *rrow = reinterpret_cast<const char *>(a.ref + (int64_t)(a.ty0 + y0 + yl) * a.W);
-        const double rv = col_ok ? (double)*reinterpret_cast<const float *>(rrow + rx4) - mean : 0.0;
+    for (int p = 0; p < SMALL_CH; ++p) tv[p] = tmpl_at(p);
+    load_chunk(0);
+    store_chunk(0);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+        // the loads and stores of the next chunk are unconditional (rows are clamped into
+        // the frame; after the last chunk they fill the idle buffer, which is not read), so
+        // the loop body stays one block and the compiler keeps the computation in place
+        load_chunk(ch + 1);
+        const float *src = fl + (ch & 1) * (SMALL_CH * SMALL_FC) + t;
+        // the staged row of template row p + 1 is read while row p is computed
+        float nxt[D];
 #pragma unroll
-        for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j) nxt[j] = src[j];
 #pragma unroll
-            for (int j = 0; j < D; ++j) acc[i * D + j] = fma(rv, ring[(p + i) % U][j], acc[i * D + j]);
-    };
+        for (int p = 0; p < SMALL_CH; ++p) {
+            // frame row of window row D-1 for template row ch * SMALL_CH + p enters the ring
 #pragma unroll
-    for (int i = 0; i < D + SMALL_AHEAD - 1; ++i) load_row(ring[i], base0 + i);
-    for (int32_t t = 0; t < rows; t += U) {
+            for (int j = 0; j < D; ++j) ring[(p + D - 1) % D][j] = (double)nxt[j];
+            if (p + 1 < SMALL_CH) {
 #pragma unroll
-        for (int p = 0; p < U; ++p)
-            if (t + p < rows) step(p, t + p);  // uniform over the wave
+                for (int j = 0; j < D; ++j) nxt[j] = src[(p + 1) * SMALL_FC + j];
+            }
+            // zero weight for columns past the template and rows past the tile
+            const double rv = ((double)tv[p] - mean) * (ch * SMALL_CH + p < rows ? colw : 0.0);
+            tv[p] = tmpl_at((ch + 1) * SMALL_CH + p);
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = 0; j < D; ++j) acc[i * D + j] = fma(rv, ring[(p + i) % D][j], acc[i * D + j]);
+            __builtin_amdgcn_sched_barrier(0);  // one row at a time: bounds the registers in flight
+        }
+        store_chunk((ch + 1) & 1);
+        __syncthreads();
     }
-    double *out = a.partial + ((int64_t)k * a.n_tiles + tile) * (int64_t)(D * D);
+    // wave butterflies, then the waves in order
+    double *red = reinterpret_cast<double *>(fl);
 #pragma unroll
     for (int q = 0; q < D * D; ++q) {
         double v = acc[q];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (lane == q) out[q] = v;
+        if (lane == q) red[wave * (D * D) + q] = v;
     }
+    __syncthreads();
+    if (t < D * D) {
+        double v = red[t];
+#pragma unroll
+        for (int w = 1; w < SMALL_COLS / 64; ++w) v += red[w * (D * D) + t];
+        a.partial[((int64_t)k * a.n_tiles + tile) * (int64_t)(D * D) + t] = v;
+    }
+    __syncthreads();  // LDS is reused by the caller's next item
 }
 
 template <typename F>

@@ -29,8 +29,8 @@ struct RegPlan {
     int32_t wg_per_frame;  // workgroups (work items) per frame
 };
 
-// The small-window plan (window side D <= 5): K = 0, strips of SMALL_ROWS template rows x
-// 64 columns, one per wave, four per workgroup; no LDS.
+// The small-window plan (window side D <= 5): K = 0, tiles of 240 template rows x 256
+// columns, one per workgroup of 256 threads, frame rows staged in 15-row chunks.
 bool reg_plan_small(int32_t W, int32_t H, int32_t R, int32_t Rmax, RegPlan *out);
 
 // Per-workgroup shape of a plan; everything else follows from it and the sizes.

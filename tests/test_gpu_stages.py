@@ -84,7 +84,11 @@ def _check_offsets(g, o, label):
     return int(tie.sum())
 
 
-@pytest.mark.parametrize("R,shape", [(0, (3, 40, 48)), (1, (3, 33, 41)), (2, (4, 64, 64)), (3, (2, 45, 70)),
+@pytest.mark.parametrize("R,shape", [(0, (3, 40, 48)), (1, (3, 33, 41)), (2, (4, 64, 64)),
+                                     # small windows over several 256-column tiles, 240-row
+                                     # strips and 15-row chunks, with ragged last ones
+                                     (2, (2, 530, 600)), (1, (2, 497, 700)), (0, (2, 260, 513)),
+                                     (3, (2, 45, 70)),
                                      (5, (3, 96, 80)), (8, (3, 120, 100)), (12, (2, 90, 150)),
                                      (17, (2, 130, 140)), (21, (2, 150, 128))])
 def test_register_parity_random_shapes(rd, orc, R, shape):

@@ -23,6 +23,7 @@ struct CnnLayout {
     size_t act[4];         // X1..X4 [B][h_l][w_l][32] bf16
     int32_t hs[4], ws[4];
     size_t pool;           // [B][32] double
+    size_t ppart;          // [B][chunks][32] double pooling partial sums
     size_t fwd_total;
     size_t dz[2];          // gradient planes (bf16)
     size_t dpool;          // [B][32] double

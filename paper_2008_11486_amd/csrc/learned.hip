@@ -232,30 +232,47 @@ __global__ __launch_bounds__(256) void conv_fwd(const uint16_t *__restrict__ x, 
 }
 
 // ---- mean pool and linear head ----------------------------------------------------------------
-// One workgroup per image: pool[c] = mean over pixels (double, fixed order), then
-// pred = Wl pool + bl.
-__global__ __launch_bounds__(256) void pool_head(const uint16_t *__restrict__ x4, int64_t P,
-                                                 const float *__restrict__ params, double *__restrict__ pool,
-                                                 float *__restrict__ pred)
+// pool_partial: workgroup (chunk, image) sums POOL_CHUNK pixels of every channel (eight
+// pixel groups, then the groups in order, in double).  pool_head: one workgroup per
+// image adds the chunk sums in chunk order, pool[c] = sum / P, then pred = Wl pool + bl.
+constexpr int POOL_CHUNK = 128;
+
+__global__ __launch_bounds__(256) void pool_partial(const uint16_t *__restrict__ x4, int64_t P, int32_t nchunk,
+                                                    double *__restrict__ part)
 {
-    __shared__ double part[8][CNN_CH];
-    const int32_t b = blockIdx.x;
+    __shared__ double red[8][CNN_CH];
+    const int32_t b = blockIdx.y, ch = blockIdx.x;
     const int c = threadIdx.x % CNN_CH, g = threadIdx.x / CNN_CH;  // 8 pixel groups
+    const int64_t p0 = (int64_t)ch * POOL_CHUNK, p1 = min(p0 + POOL_CHUNK, P);
     double s = 0.0;
-    for (int64_t p = g; p < P; p += 8) s += (double)bf2f(x4[((int64_t)b * P + p) * CNN_CH + c]);
-    part[g][c] = s;
+    for (int64_t p = p0 + g; p < p1; p += 8) s += (double)bf2f(x4[((int64_t)b * P + p) * CNN_CH + c]);
+    red[g][c] = s;
     __syncthreads();
     if (threadIdx.x < CNN_CH) {
         double t = 0.0;
-        for (int i = 0; i < 8; ++i) t += part[i][c];
-        pool[b * CNN_CH + c] = t / (double)P;
+        for (int i = 0; i < 8; ++i) t += red[i][threadIdx.x];
+        part[((int64_t)b * nchunk + ch) * CNN_CH + threadIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(64) void pool_head(const double *__restrict__ part, int32_t nchunk, int64_t P,
+                                                const float *__restrict__ params, double *__restrict__ pool,
+                                                float *__restrict__ pred)
+{
+    __shared__ double pl[CNN_CH];
+    const int32_t b = blockIdx.x;
+    if (threadIdx.x < CNN_CH) {
+        double t = 0.0;
+        for (int32_t i = 0; i < nchunk; ++i) t += part[((int64_t)b * nchunk + i) * CNN_CH + threadIdx.x];
+        pl[threadIdx.x] = t / (double)P;
+        pool[b * CNN_CH + threadIdx.x] = pl[threadIdx.x];
     }
     __syncthreads();
     if (threadIdx.x < 2) {
         const int j = threadIdx.x;
         const float *wl = params + cnn_head_offset();
         double v = (double)wl[2 * CNN_CH + j];
-        for (int cc = 0; cc < CNN_CH; ++cc) v += pool[b * CNN_CH + cc] * (double)wl[j * CNN_CH + cc];
+        for (int cc = 0; cc < CNN_CH; ++cc) v += pl[cc] * (double)wl[j * CNN_CH + cc];
         pred[2 * b + j] = (float)v;
     }
 }
@@ -540,6 +557,8 @@ CnnLayout cnn_layout(int32_t B, int32_t h, int32_t w)
     }
     L.pool = off;
     off += al(sizeof(double) * (size_t)B * CNN_CH);
+    L.ppart = off;
+    off += al(sizeof(double) * (size_t)B * ceil_div((int64_t)L.hs[3] * L.ws[3], POOL_CHUNK) * CNN_CH);
     L.fwd_total = off;
     // backward: two gradient planes the size of the largest activation, partial sums
     const size_t big = sizeof(uint16_t) * (size_t)B * L.hs[0] * L.ws[0] * CNN_CH;
@@ -583,7 +602,11 @@ int cnn_forward_launch(const uint16_t *ref, int64_t ref_stride, const uint16_t *
         hh = L.hs[l];
         ww = L.ws[l];
     }
-    hipLaunchKernelGGL(pool_head, dim3(B), dim3(256), 0, s, in, (int64_t)L.hs[3] * L.ws[3], params,
+    const int64_t P4 = (int64_t)L.hs[3] * L.ws[3];
+    const int32_t nchunk = (int32_t)ceil_div(P4, POOL_CHUNK);
+    double *ppart = reinterpret_cast<double *>(base + L.ppart);
+    hipLaunchKernelGGL(pool_partial, dim3((unsigned)nchunk, (unsigned)B), dim3(256), 0, s, in, P4, nchunk, ppart);
+    hipLaunchKernelGGL(pool_head, dim3(B), dim3(64), 0, s, ppart, nchunk, P4, params,
                        reinterpret_cast<double *>(base + L.pool), pred);
     return check_launch("reduce_cnn_forward");
 }

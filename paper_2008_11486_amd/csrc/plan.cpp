@@ -114,7 +114,7 @@ bool reg_plan_from_shape(int32_t W, int32_t H, int32_t R, int32_t Rmax, const Re
 
 bool reg_plan_small(int32_t W, int32_t H, int32_t R, int32_t Rmax, RegPlan *out)
 {
-    constexpr int32_t COLS = 256, ROWS = 240;  // the device constants SMALL_COLS, SMALL_ROWS
+    constexpr int32_t COLS = 256, CH = 15, ROWS = 240;  // the device constants SMALL_COLS, SMALL_CH, SMALL_ROWS
     RegPlan p{};
     p.D = 2 * R + 1;
     if (p.D > 5) return false;
@@ -129,15 +129,18 @@ bool reg_plan_small(int32_t W, int32_t H, int32_t R, int32_t Rmax, RegPlan *out)
     p.threads = COLS;
     p.TX = COLS;
     p.NXB = 1;
-    p.TY = 15;  // rows per staged chunk
-    p.BR = ROWS;
-    p.JS = p.D;
-    p.FR = 15;
-    p.FC = COLS + 4;
-    p.lds = 2 * 15 * (COLS + 4) * sizeof(float);  // static in the kernel
-    p.th_max = th;
+    p.TY = CH;  // rows per staged chunk
+    // tile rows: the most (shorter tiles were measured slower, single-frame calls included)
     p.n_xchunks = (int32_t)ceil_div(tw, COLS);
-    p.n_bands = (int32_t)ceil_div(th, ROWS);
+    p.BR = ROWS;
+    const int32_t forced = env_int("REDUCE_SMALL_ROWS");  // for measurement: a multiple of 15, at most 240
+    if (forced >= CH && forced <= ROWS && forced % CH == 0) p.BR = forced;
+    p.JS = p.D;
+    p.FR = CH;
+    p.FC = COLS + 4;
+    p.lds = 2 * CH * (COLS + 4) * sizeof(float);  // static in the kernel
+    p.th_max = th;
+    p.n_bands = (int32_t)ceil_div(th, p.BR);
     p.n_tiles = p.n_bands * p.n_xchunks;
     p.wg_per_frame = p.n_tiles;
     *out = p;

@@ -252,7 +252,8 @@ __device__ __forceinline__ void score_tile(const ScoreArgs &a, int32_t lid, unsi
 }
 
 // ---- small windows (side D <= 5) ------------------------------------------------------------
-// A tile is SMALL_ROWS template rows x SMALL_COLS template columns for one workgroup of
+// A tile is BR template rows (the plan's, a multiple of SMALL_CH of at most SMALL_ROWS)
+// x SMALL_COLS template columns for one workgroup of
 // SMALL_COLS threads; thread t owns template column SMALL_COLS * colblock + t and walks down
 // the tile with all D x D candidate sums in registers.  The frame rows a template row needs
 // (D of them, one per window row) slide down with it in a register ring of D rows, converted
@@ -264,7 +265,7 @@ __device__ __forceinline__ void score_tile(const ScoreArgs &a, int32_t lid, unsi
 // layout of the general kernel.
 constexpr int SMALL_COLS = 256;                       // template columns per tile, one per thread
 constexpr int SMALL_CH = 15;                          // template rows per chunk (a multiple of every D)
-constexpr int SMALL_ROWS = 16 * SMALL_CH;             // template rows per tile
+constexpr int SMALL_ROWS = 16 * SMALL_CH;             // most template rows per tile
 constexpr int SMALL_FC = SMALL_COLS + 4;              // frame columns per staged row (>= SMALL_COLS + D - 1)
 constexpr int SMALL_LDS_FLOATS = 2 * SMALL_CH * SMALL_FC + SMALL_COLS;  // both chunk buffers, one spare slot per thread
 constexpr int SMALL_D_MAX = 5;
@@ -281,7 +282,7 @@ __device__ __forceinline__ void score_small_tile(const ScoreArgs &a, int32_t lid
     const int32_t strip = tile / a.n_xchunks, colb = tile - strip * a.n_xchunks;
     const int32_t x = colb * SMALL_COLS + t;
     const bool col_ok = x < a.tw;
-    const int32_t y0 = strip * SMALL_ROWS, rows = min(y0 + SMALL_ROWS, a.th) - y0;
+    const int32_t y0 = strip * a.BR, rows = min(y0 + a.BR, a.th) - y0;
     const int nch = (rows + SMALL_CH - 1) / SMALL_CH;
     const int32_t cx = a.centers ? a.centers[2 * k] : 0, cy = a.centers ? a.centers[2 * k + 1] : 0;
     const int32_t kf = k + (k >= a.skip ? 1 : 0);
@@ -323,6 +324,7 @@ __device__ __forceinline__ void score_small_tile(const ScoreArgs &a, int32_t lid
     // template value of row y0 + yl of this thread's column (rows past the tile repeat its last)
     auto tmpl_at = [&](int32_t yl) { return tcol[(uint32_t)min(a.ty0 + y0 + yl, ty_last) * W]; };
 
+    load_chunk(0);  // in flight together with the ring's first rows and the first template values
     // the ring starts with frame rows fy0 .. fy0 + D - 2 (window rows 0 .. D-2 of template row 0)
     double ring[D][D];
 #pragma unroll
@@ -341,7 +343,6 @@ __device__ __forceinline__ void score_small_tile(const ScoreArgs &a, int32_t lid
     float tv[SMALL_CH];
 #pragma unroll
     for (int p = 0; p < SMALL_CH; ++p) tv[p] = tmpl_at(p);
-    load_chunk(0);
     store_chunk(0);
     __syncthreads();
     for (int ch = 0; ch < nch; ++ch) {

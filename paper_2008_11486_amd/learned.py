@@ -279,17 +279,20 @@ class LearnedRegistrar:
         auto = register(ref, ref.reshape(1, self.H, self.W), 0, self.rmax, ws=self.ws_auto)
         o = offsets_to_numpy(refined)
         s_auto = float(offsets_to_numpy(auto)["peak"][0])
-        # a window whose maximum is on an inner border moves onto that maximum, frame by frame
+        # a window whose maximum is on an inner border moves onto that maximum; the moving
+        # frames of one step are searched back to back and read back together
         moved = 0
         for _ in range(self.moves):
             walk = np.nonzero(self._inner_border(o))[0]
             if walk.size == 0:
                 break
-            for k in walk:
-                c = torch.tensor([[int(o["dx"][k]), int(o["dy"][k])]], dtype=torch.int32, device=self.dev)
-                o[k] = offsets_to_numpy(register(ref, frames[k:k + 1], self.r, self.rmax, centers=c,
-                                                 ws=self.ws_move))[0]
-                moved += 1
+            cs = torch.from_numpy(np.stack([o["dx"][walk], o["dy"][walk]], 1).astype(np.int32)).to(self.dev)
+            outs = [register(ref, frames[k:k + 1], self.r, self.rmax, centers=cs[i:i + 1], ws=self.ws_move)
+                    for i, k in enumerate(walk)]
+            got = offsets_to_numpy(torch.cat(outs))
+            for i, k in enumerate(walk):
+                o[k] = got[i]
+            moved += int(walk.size)
         border = self._inner_border(o)
         weak = ~(o["peak"] >= self.peak_ratio * s_auto)
         fb = border | weak

@@ -257,12 +257,10 @@ def many_stacks(torch, rd, reps=2):
     g = torch.Generator(device=dev)
     g.manual_seed(20081148)
     stacks, pix = [], 0
-    # tuned shapes per frame size (they do not depend on N), timed on up to 16 frames of
-    # that size's largest stack so that the candidates see a realistically full grid
-    tune_at = {}
-    for i, sp in enumerate(specs):
-        if sp.W not in tune_at or sp.N > specs[tune_at[sp.W]].N:
-            tune_at[sp.W] = i
+    # tuned shapes per frame size (they do not depend on N), timed on up to 32 frames of
+    # that size (the batched search runs all frames of a size in one launch, so the
+    # candidates should see a full grid)
+    tune_ref, tune_frames = {}, {}
     for i, sp in enumerate(specs):
         rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([20081148, 2, 7, i])))
         x = rng.uniform(-24, sp.W + 24, sp.n_stars)
@@ -276,14 +274,23 @@ def many_stacks(torch, rd, reps=2):
         frames = rd.render_frames(torch.from_numpy(stars).to(dev),
                                   torch.arange(sp.N, dtype=torch.int64, device=dev) + 64 * i, sp.W, sp.H,
                                   sky=1000.0, fwhm=3.0, read_noise=10.0, seed=2)
-        if tune_at[sp.W] == i:
-            rd.tune_register(frames[0].contiguous(), frames[1:17].contiguous(), sp.radius)
+        have = sum(int(f.shape[0]) for f in tune_frames.get(sp.W, []))
+        if have < 32:
+            tune_ref.setdefault(sp.W, frames[0].clone())
+            tune_frames.setdefault(sp.W, []).append(frames[1:1 + 32 - have].clone())
         dark = 100.0 + 3.0 * torch.randn((sp.H, sp.W), generator=g, device=dev)
         flat = 0.95 + 0.1 * torch.rand((sp.H, sp.W), generator=g, device=dev)
         raw = frames.mul_(flat).add_(dark).round_().clamp_(0, 65535).to(torch.int32).to(torch.int16)
         del frames
         stacks.append((raw, dark, flat, sp.radius))
         pix += sp.N * sp.W * sp.H
+    plans = {}
+    for W in sorted(tune_frames):
+        fr = torch.cat(tune_frames.pop(W))
+        p = rd.tune_register(tune_ref.pop(W).contiguous(), fr, specs[0].radius)
+        plans[str(W)] = {k: p[k] for k in ("K", "G", "S", "TY", "BR", "threads", "n_tiles")}
+        del fr
+    torch.cuda.empty_cache()
     batch = rd.StackBatch(stacks)
     batch.run()
     torch.cuda.synchronize()
@@ -302,7 +309,8 @@ def many_stacks(torch, rd, reps=2):
                        f"sides 512-4096, shifts +-16 px, R=17, one batched call",
            "Mpix/s": round(pix / dt / 1e6, 1), "ms_per_call": round(dt * 1e3, 2), "input_pixels": pix,
            "search_ms": round(ms / n, 2), "search_TFLOP/s": round(flops / (ms / n / 1e3) / 1e12, 2),
-           "search_frac_fp64": round(flops / (ms / n / 1e3) / 1e12 / FP64_VALU_PEAK_TFLOPS, 4)}
+           "search_frac_fp64": round(flops / (ms / n / 1e3) / 1e12 / FP64_VALU_PEAK_TFLOPS, 4),
+           "search_plans": plans}
     del batch, stacks
     torch.cuda.empty_cache()
     return res
@@ -317,8 +325,8 @@ def learned_comparison(torch, rd, weights_path, M):
     params = learned.load_params(weights_path) if trained else learned.init_params(0)
     frames, t = learned.render_stack(0, M + 1, W, H, 64.0)
     ref, rest = frames[0], frames[1:].contiguous()
-    # both searches run with tuned launch shapes (tuned on two frames; the shape does not depend on N)
-    rd.tune_register(ref, rest[:2].contiguous(), 64, 64)
+    # both searches run with tuned launch shapes (tuned on four frames; the shape does not depend on N)
+    rd.tune_register(ref, rest[:4].contiguous(), 64, 64)
     rd.tune_register(ref, rest, 2, 64)
     ws = torch.empty(rd.register_ws_bytes(W, H, M, 64, 64), dtype=torch.uint8, device=frames.device)
     reg = learned.LearnedRegistrar(params, W, H, M, radius_max=64, refine_radius=2)
@@ -467,11 +475,14 @@ def main():
         rd.tune_load(args.tune_cache)
         tuned = "loaded"
     elif not args.no_tune:
-        st0 = stacks[0]
-        cal0 = rd.calibrate(torch.from_numpy(st0.raw.view(np.int16)).to("cuda:0"),
-                            torch.from_numpy(st0.dark).to("cuda:0"), torch.from_numpy(st0.flat).to("cuda:0"))
-        tuned = rd.tune_register(cal0[0].contiguous(), cal0[1:].contiguous(), st0.spec.radius)
-        del cal0
+        # timed on the frames one search launch covers: every stack's in the batched path
+        # (one launch for all stacks), one stack's in the stage-wise path
+        cals = [rd.calibrate(torch.from_numpy(st.raw.view(np.int16)).to("cuda:0"),
+                             torch.from_numpy(st.dark).to("cuda:0"), torch.from_numpy(st.flat).to("cuda:0"))
+                for st in (stacks if args.path == "batched" else stacks[:1])]
+        tuned = rd.tune_register(cals[0][0].contiguous(), torch.cat([c[1:] for c in cals]),
+                                 stacks[0].spec.radius)
+        del cals
         if args.tune_cache:
             rd.tune_save(args.tune_cache)
 

@@ -179,21 +179,31 @@ __device__ __forceinline__ void score_tile(const ScoreArgs &a, int32_t lid, unsi
     for (int q = 0; q < K; ++q) acc[q] = 0.0;
 
     const int pairs = a.TY * a.NXB;
+    // The frame tile is a ring of FR rows: chunk c (template rows yc = yb0 + c * TY ...) needs
+    // frame rows fy(c) + [0, FR), fy(c) = fy(0) + c * TY, and keeps them in LDS rows
+    // (c * TY + r) mod FR; from the second chunk on only the TY rows it adds are staged,
+    // into the LDS rows of the TY rows the previous chunk alone needed.
+    int32_t ring0 = 0;  // LDS row of the chunk's frame row 0
     for (int32_t yc = yb0; yc < yb1; yc += a.TY) {
         __syncthreads();
         if (in_block) {
             // template tile (zero outside T: contributes exactly nothing), then the frame
-            // tile (zero outside the frame)
+            // rows (zero outside the frame)
             stage_tile(a.TY, a.TX, a.threads, t, [&](int r, int c, bool &ok) -> int64_t {
                 ok = yc + r < yb1 && x_t + c < a.tw;
                 return (int64_t)(a.ty0 + yc + r) * a.W + a.tx0 + x_t + c;
             }, a.ref, [&](int r, int c, bool ok, float v) { rt[r * a.TX + c] = ok ? (double)v - mean : 0.0; });
             const int32_t fy0 = a.ty0 + yc + cy - a.R + j_lo;
-            stage_tile(a.FR, a.FC, a.threads, t, [&](int r, int c, bool &ok) -> int64_t {
-                const int32_t gy = fy0 + r, gx = fx0 + c;
+            const int32_t r0 = yc == yb0 ? 0 : a.FR - a.TY;  // first chunk row to stage
+            stage_tile(a.FR - r0, a.FC, a.threads, t, [&](int r, int c, bool &ok) -> int64_t {
+                const int32_t gy = fy0 + r0 + r, gx = fx0 + c;
                 ok = gy >= 0 && gy < a.H && gx >= 0 && gx < a.W;
                 return (int64_t)gy * a.W + gx;
-            }, f, [&](int r, int c, bool ok, float v) { ft[r * a.FC + c] = ok ? v : 0.0f; });
+            }, f, [&](int r, int c, bool ok, float v) {
+                int32_t lr = ring0 + r0 + r;
+                if (lr >= a.FR) lr -= a.FR;
+                ft[lr * a.FC + c] = ok ? v : 0.0f;
+            });
         }
         __syncthreads();
         if (active) {
@@ -201,8 +211,10 @@ __device__ __forceinline__ void score_tile(const ScoreArgs &a, int32_t lid, unsi
             const int dq = a.S / a.NXB, dr = a.S - dq * a.NXB;
             int yy = s / a.NXB, xb = s - (s / a.NXB) * a.NXB;
             for (int pr = s; pr < pairs; pr += a.S) {
+                int32_t lr = ring0 + yy + jr;  // < 2 FR
+                if (lr >= a.FR) lr -= a.FR;
                 const double *rrow = rt + yy * a.TX + xb * K;
-                const float *frow = ft + (yy + jr) * a.FC + (xb + bx) * K;
+                const float *frow = ft + lr * a.FC + (xb + bx) * K;
                 double r[K];
 #pragma unroll
                 for (int i = 0; i < K; ++i) r[i] = rrow[i];
@@ -223,6 +235,8 @@ __device__ __forceinline__ void score_tile(const ScoreArgs &a, int32_t lid, unsi
                 }
             }
         }
+        ring0 += a.TY % a.FR;
+        if (ring0 >= a.FR) ring0 -= a.FR;
     }
 
     // sum the sub-ranges in order s = 0, 1, ... (only needed when S > 1)

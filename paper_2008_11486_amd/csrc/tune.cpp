@@ -75,8 +75,10 @@ extern "C" size_t reduce_tune_register_ws(int32_t W, int32_t H, int32_t N, int32
     int n = 0;
     reg_shape_candidates(W, H, radius, radius_max, cand, &n, MAXC);
     for (int i = 0; i < n; ++i) {
+        RegShape one = cand[i];
+        one.CPT = 1;  // the most tiles this shape can have (the tuner also tries other tile heights)
         RegPlan p;
-        if (reg_plan_from_shape(W, H, radius, radius_max, cand[i], &p)) need = std::max(need, register_ws_bytes(p, N));
+        if (reg_plan_from_shape(W, H, radius, radius_max, one, &p)) need = std::max(need, register_ws_bytes(p, N));
     }
     return need;
 }
@@ -110,7 +112,28 @@ extern "C" int reduce_tune_register(const float *ref, const float *frames, int32
     RegShape best{};
     const int32_t tx0 = radius_max, ty0 = radius_max, tw = W - 2 * radius_max, th = H - 2 * radius_max;
     int rc = REDUCE_OK;
-    for (int i = 0; i < n; ++i) {
+    // then the winner with other tile heights (chunks per tile): taller tiles stage the frame
+    // rows that consecutive chunks share only once, shorter ones give more workgroups
+    const int n_first = n;
+    for (int i = 0;; ++i) {
+        if (i == n_first) {
+            if (best_ms >= 1e30) break;
+            for (int32_t cpt : {best.CPT * 2, best.CPT * 3, best.CPT * 4, best.CPT / 2, 1}) {
+                if (cpt < 1 || n >= MAXC) continue;
+                RegShape v = best;
+                v.CPT = cpt;
+                bool dup = false;
+                for (int j = 0; j < n; ++j)
+                    dup = dup || (cand[j].K == v.K && cand[j].G == v.G && cand[j].S == v.S && cand[j].TY == v.TY &&
+                                  cand[j].CPT == v.CPT);
+                RegPlan pv, pb;
+                if (dup || !reg_plan_from_shape(W, H, radius, radius_max, v, &pv) ||
+                    !reg_plan_from_shape(W, H, radius, radius_max, best, &pb) || pv.BR == pb.BR)
+                    continue;
+                cand[n++] = v;
+            }
+        }
+        if (i >= n) break;
         RegPlan p;
         if (!reg_plan_from_shape(W, H, radius, radius_max, cand[i], &p)) continue;
         if (register_ws_bytes(p, N) > ws_bytes) continue;

@@ -283,8 +283,9 @@ int reduce_render_frames(const float *stars, int32_t S, const int64_t *keys, int
  * cached in the process and used by every later call of that size (including the
  * batched path).  Tuning calls synchronise `stream`.
  *   reduce_tune_register: candidates of the correlation search for (W, H, radius,
- *     radius_max), each run reps times on ref/frames; only shapes whose workspace
- *     fits ws_bytes are tried; out receives the offsets (device reduce_offset_t [N]);
+ *     radius_max), each run reps times on ref/frames, then the fastest three and the
+ *     fastest with other tile heights timed again in three interleaved rounds (least
+ *     time wins); only shapes whose workspace fits ws_bytes are tried; out receives the offsets (device reduce_offset_t [N]);
  *     fields (host int32[16] or NULL) receives the chosen plan as in
  *     reduce_register_plan.
  *   reduce_tune_register_ws: workspace bytes that fit every candidate shape of

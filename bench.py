@@ -246,21 +246,16 @@ def cpu_baseline(stacks, integer_mode, min_seconds=10.0, max_reps=20):
                       f"FP64 C oracle from raw frames (calibrate, search, shift, combine), {dt:.1f} s"}
 
 
-def many_stacks(torch, rd, reps=2):
-    """64 stacks (frame counts 3-30, square sides 512-4096, sub-pixel shifts within +-16 px,
-    search radius 17) through one batched call: the stack shapes of the many-stack
-    workload, frames rendered on the GPU (star density of the 1024x1024 stacks)."""
-    import synth
-    from paper_2008_11486_amd import learned
-    specs = synth.config_specs(2)
+def many_stack_inputs(torch, rd, specs, on_frames=None):
+    """Device inputs of the many-stack workload: per stack (raw int16 [N][H][W] holding the
+    uint16 counts, dark, flat, radius), frames rendered on the GPU at the star density of
+    the 1024x1024 bands with sub-pixel shifts within +-16 px, and the true shifts
+    [N][2] (frame(x + t) = ref(x)).  on_frames(i, spec, frames) sees each stack's float
+    frames before they become raw counts."""
     dev = torch.device("cuda:0")
     g = torch.Generator(device=dev)
     g.manual_seed(20081148)
-    stacks, pix = [], 0
-    # tuned shapes per frame size (they do not depend on N), timed on up to 32 frames of
-    # that size (the batched search runs all frames of a size in one launch, so the
-    # candidates should see a full grid)
-    tune_ref, tune_frames = {}, {}
+    stacks, shifts = [], []
     for i, sp in enumerate(specs):
         rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([20081148, 2, 7, i])))
         x = rng.uniform(-24, sp.W + 24, sp.n_stars)
@@ -274,23 +269,53 @@ def many_stacks(torch, rd, reps=2):
         frames = rd.render_frames(torch.from_numpy(stars).to(dev),
                                   torch.arange(sp.N, dtype=torch.int64, device=dev) + 64 * i, sp.W, sp.H,
                                   sky=1000.0, fwhm=3.0, read_noise=10.0, seed=2)
-        have = sum(int(f.shape[0]) for f in tune_frames.get(sp.W, []))
-        if have < 32:
-            tune_ref.setdefault(sp.W, frames[0].clone())
-            tune_frames.setdefault(sp.W, []).append(frames[1:1 + 32 - have].clone())
+        if on_frames is not None:
+            on_frames(i, sp, frames)
         dark = 100.0 + 3.0 * torch.randn((sp.H, sp.W), generator=g, device=dev)
         flat = 0.95 + 0.1 * torch.rand((sp.H, sp.W), generator=g, device=dev)
         raw = frames.mul_(flat).add_(dark).round_().clamp_(0, 65535).to(torch.int32).to(torch.int16)
         del frames
         stacks.append((raw, dark, flat, sp.radius))
-        pix += sp.N * sp.W * sp.H
+        shifts.append(t)
+    return stacks, shifts
+
+
+def tune_many_stacks(torch, rd, specs, stacks_frames):
+    """Search shapes per frame size, timed on up to 32 frames of that size (the batched
+    search runs all frames of a size in one launch, so the candidates see a full grid).
+    stacks_frames: {W: (reference frame, [frame blocks])} gathered by many_stack_inputs'
+    on_frames hook; emptied here."""
     plans = {}
-    for W in sorted(tune_frames):
-        fr = torch.cat(tune_frames.pop(W))
-        p = rd.tune_register(tune_ref.pop(W).contiguous(), fr, specs[0].radius)
+    for W in sorted(stacks_frames):
+        ref, blocks = stacks_frames.pop(W)
+        fr = torch.cat(blocks)
+        p = rd.tune_register(ref.contiguous(), fr, specs[0].radius)
         plans[str(W)] = {k: p[k] for k in ("K", "G", "S", "TY", "BR", "threads", "n_tiles")}
-        del fr
+        del fr, ref, blocks
     torch.cuda.empty_cache()
+    return plans
+
+
+def tuning_hook(store, limit=32):
+    """on_frames hook that keeps up to `limit` non-reference frames per frame size."""
+    def hook(i, sp, frames):
+        ref, blocks = store.get(sp.W, (None, []))
+        have = sum(int(b.shape[0]) for b in blocks)
+        if have < limit:
+            store[sp.W] = (frames[0].clone() if ref is None else ref, blocks + [frames[1:1 + limit - have].clone()])
+    return hook
+
+
+def many_stacks(torch, rd, reps=2):
+    """64 stacks (frame counts 3-30, square sides 512-4096, sub-pixel shifts within +-16 px,
+    search radius 17) through one batched call: the stack shapes of the many-stack
+    workload, frames rendered on the GPU (star density of the 1024x1024 stacks)."""
+    import synth
+    specs = synth.config_specs(2)
+    store = {}
+    stacks, _ = many_stack_inputs(torch, rd, specs, tuning_hook(store))
+    pix = sum(sp.N * sp.W * sp.H for sp in specs)
+    plans = tune_many_stacks(torch, rd, specs, store)
     batch = rd.StackBatch(stacks)
     batch.run()
     torch.cuda.synchronize()

@@ -5,14 +5,16 @@
 //
 // Work split.  A thread owns one window row dy and K consecutive dx candidates and
 // keeps K double accumulators.  For one template row segment of K pixels it reads
-// the K template values (LDS broadcast) and 2K-1 frame values (LDS), and performs
-// K*K FMAs: the frame value at column m serves every (pixel i, candidate j) pair
-// with i + j = m.  A work item ("tile") is a band of template rows x a column chunk
+// the K template values (LDS broadcast) and 2K-1 frame values, and performs K*K FMAs:
+// the frame value at column m serves every (pixel i, candidate j) pair with
+// i + j = m.  It walks the column blocks of a template row in order, so K - 1 of the
+// frame values (already converted to FP64) carry over to the next block and only K
+// are read anew.  A work item ("tile") is a band of template rows x a column chunk
 // of the template for one group of candidate rows of one frame; the template and
 // frame tiles are staged in LDS chunk by chunk (TY template rows at a time, plus the
 // frame rows and columns the window needs).  When there are fewer candidates than
-// threads, threads also split the chunk's (row, column-block) pairs ("sub-ranges")
-// and their accumulators are summed in a fixed order.  Each tile writes one FP64
+// threads, threads also split the chunk's template rows ("sub-ranges": rows s,
+// s + S, ...) and their accumulators are summed in a fixed order.  Each tile writes one FP64
 // partial score per candidate; partials are summed over tiles in tile order, and the
 // (score, index) maximum, the runner-up, the parabola vertex and the flags follow.
 // The decomposition depends only on (W, H, R, Rmax) and the launch shape, never on
@@ -178,7 +180,6 @@ __device__ __forceinline__ void score_tile(const ScoreArgs &a, int32_t lid, unsi
 #pragma unroll
     for (int q = 0; q < K; ++q) acc[q] = 0.0;
 
-    const int pairs = a.TY * a.NXB;
     // The frame tile is a ring of FR rows: chunk c (template rows yc = yb0 + c * TY ...) needs
     // frame rows fy(c) + [0, FR), fy(c) = fy(0) + c * TY, and keeps them in LDS rows
     // (c * TY + r) mod FR; from the second chunk on only the TY rows it adds are staged,
@@ -207,31 +208,34 @@ __device__ __forceinline__ void score_tile(const ScoreArgs &a, int32_t lid, unsi
         }
         __syncthreads();
         if (active) {
-            // pairs s, s + S, ... as (template row yy, column block xb), stepped without division
-            const int dq = a.S / a.NXB, dr = a.S - dq * a.NXB;
-            int yy = s / a.NXB, xb = s - (s / a.NXB) * a.NXB;
-            for (int pr = s; pr < pairs; pr += a.S) {
+            // rows s, s + S, ...: the column blocks of a row in order; the K - 1 frame values a
+            // block shares with the next stay in registers, converted once
+            constexpr int NXB = (64 + K - 1) / K;  // column blocks per tile row (TX = K * NXB)
+            for (int yy = s; yy < a.TY; yy += a.S) {
                 int32_t lr = ring0 + yy + jr;  // < 2 FR
                 if (lr >= a.FR) lr -= a.FR;
-                const double *rrow = rt + yy * a.TX + xb * K;
-                const float *frow = ft + lr * a.FC + (xb + bx) * K;
-                double r[K];
+                const double *rrow = rt + yy * a.TX;
+                const float *frow = ft + lr * a.FC + bx * K;
+                double w[2 * K - 1];
 #pragma unroll
-                for (int i = 0; i < K; ++i) r[i] = rrow[i];
+                for (int m = 0; m < K - 1; ++m) w[m] = (double)frow[m];
 #pragma unroll
-                for (int m = 0; m < 2 * K - 1; ++m) {
-                    const double fv = (double)frow[m];
+                for (int xb = 0; xb < NXB; ++xb) {
 #pragma unroll
-                    for (int i = 0; i < K; ++i) {
-                        const int q = m - i;
-                        if (q >= 0 && q < K) acc[q] = fma(r[i], fv, acc[q]);
+                    for (int m = K - 1; m < 2 * K - 1; ++m) w[m] = (double)frow[xb * K + m];
+                    double r[K];
+#pragma unroll
+                    for (int i = 0; i < K; ++i) r[i] = rrow[xb * K + i];
+#pragma unroll
+                    for (int m = 0; m < 2 * K - 1; ++m) {
+#pragma unroll
+                        for (int i = 0; i < K; ++i) {
+                            const int q = m - i;
+                            if (q >= 0 && q < K) acc[q] = fma(r[i], w[m], acc[q]);
+                        }
                     }
-                }
-                yy += dq;
-                xb += dr;
-                if (xb >= a.NXB) {
-                    xb -= a.NXB;
-                    ++yy;
+#pragma unroll
+                    for (int m = 0; m < K - 1; ++m) w[m] = w[m + K];
                 }
             }
         }

@@ -45,7 +45,12 @@ ScoreArgs make_score_args(const RegPlan &p, const float *ref, const float *frame
                           int32_t Rmax, int32_t tx0, int32_t ty0, int32_t tw, int32_t th, int32_t skip);
 
 constexpr int BATCH_THREADS = 512;
-constexpr int COMB_PX16 = 2;    // pixel columns per thread of the up-to-16-frame combine
+constexpr int COMB_PX16 = 4;    // pixel columns per thread of the up-to-16-frame combine
+constexpr int COMB_PX32 = 2;    // ... of the up-to-32-frame combine
+
+// Plane stride (floats) of the aligned-frame workspace for an overlap of w x h: padded
+// to 4 floats so that every frame's plane starts 16-byte aligned.
+__host__ __device__ inline int64_t al_plane(int64_t w, int64_t h) { return (w * h + 3) & ~(int64_t)3; }
 
 enum ItemType : int32_t {
     IT_CAL = 0, IT_MEANPART, IT_MEANFINAL, IT_SCORE, IT_SSCORE, IT_SUM, IT_PICK, IT_RECT, IT_SHIFT, IT_COMB16,
@@ -217,12 +222,13 @@ __global__ __launch_bounds__(SH_BLOCK) void batch_shift(BatchArgs a, int32_t fir
     if (w < 1 || h < 1) return;
     const int vs = shift_vec_store(w, reinterpret_cast<uintptr_t>(s.al));
     const bool aligned = s.W % 4 == 0;
+    const int64_t pstride = al_plane(w, h);
     if (s.integer_mode)
         shift_strip<true, SH_VEC>(s.cal, s.al, s.W, s.H, k, s.soffs[2 * k], s.soffs[2 * k + 1], strip, xblk, x0, y0,
-                                  w, h, vs, aligned);
+                                  w, h, pstride, vs, aligned);
     else
         shift_strip<false, SH_VEC>(s.cal, s.al, s.W, s.H, k, s.soffs[2 * k], s.soffs[2 * k + 1], strip, xblk, x0,
-                                   y0, w, h, vs, aligned);
+                                   y0, w, h, pstride, vs, aligned);
 }
 
 // Sigma-clipped mean of block it.a of the stack's overlap; PX pixel columns per thread
@@ -233,16 +239,18 @@ __global__ __launch_bounds__(COMB_TILE) void batch_comb(BatchArgs a, int32_t fir
     const Item it = a.items[first + blockIdx.x];
     const StackDev &s = a.stacks[it.stack];
     const int64_t plane = (int64_t)s.rect[2] * s.rect[3];
-    const bool vec = PX > 1 && plane % PX == 0;
+    const int64_t pstride = al_plane(s.rect[2], s.rect[3]);
+    // the aligned planes are padded to 4 floats; the output image needs PX-float alignment
+    const bool vec = PX > 1 && (reinterpret_cast<uintptr_t>(s.out) & (uintptr_t)(4 * PX - 1)) == 0;
     const int64_t blocks = vec ? ceil_div(plane, (int64_t)COMB_TILE * PX) : ceil_div(plane, (int64_t)COMB_TILE);
     if (it.a >= blocks) return;  // uniform over the workgroup
     unsigned dropped;
     if (vec)
-        dropped = combine_cols_block<MAXV, PX>(s.al, plane, s.N, (double)s.ksigma, s.max_iters, s.out, nullptr,
-                                               it.a);
+        dropped = combine_cols_block<MAXV, PX>(s.al, plane, pstride, s.N, (double)s.ksigma, s.max_iters, s.out,
+                                               nullptr, it.a);
     else
-        dropped = combine_cols_block<MAXV, 1>(s.al, plane, s.N, (double)s.ksigma, s.max_iters, s.out, nullptr,
-                                              it.a);
+        dropped = combine_cols_block<MAXV, 1>(s.al, plane, pstride, s.N, (double)s.ksigma, s.max_iters, s.out,
+                                              nullptr, it.a);
     if (s.n_rej) {
         const unsigned total = block_sum_u32(dropped);
         if (threadIdx.x == 0 && total) atomicAdd(reinterpret_cast<unsigned long long *>(s.n_rej),
@@ -333,7 +341,7 @@ static BatchLayout layout_of(const reduce_stack_t *stacks, int32_t n)
         sl.cal = off;
         off += al(sizeof(float) * fp * s.N);
         sl.al = off;
-        off += al(sizeof(float) * fp * s.N);
+        off += al(sizeof(float) * al_plane(s.W, s.H) * s.N);
         const int32_t n_mean_parts = (int32_t)ceil_div(s.H - 2 * s.radius, MEAN_ROWS);
         sl.mean_parts = off;
         off += al(sizeof(double) * n_mean_parts);
@@ -357,7 +365,11 @@ static BatchLayout layout_of(const reduce_stack_t *stacks, int32_t n)
         sl.count[IT_RECT] = 1;
         sl.count[IT_SHIFT] =
             s.N * (int32_t)ceil_div(s.H, SH_ROWS) * (int32_t)ceil_div(s.W, (int64_t)SH_BLOCK * SH_VEC);
-        const int32_t comb_blocks = (int32_t)ceil_div(fp, (int64_t)COMB_TILE);
+        // enough clip items for the whole frame (the overlap is only known on the device),
+        // PX columns per thread when the output image allows PX-float stores
+        const int px = s.N <= 16 ? COMB_PX16 : s.N <= 32 ? COMB_PX32 : 1;
+        const bool vec = px > 1 && (reinterpret_cast<uintptr_t>(s.out) & (uintptr_t)(4 * px - 1)) == 0;
+        const int32_t comb_blocks = (int32_t)ceil_div(fp, (int64_t)COMB_TILE * (vec ? px : 1));
         sl.count[IT_COMB16] = s.N <= 16 ? comb_blocks : 0;
         sl.count[IT_COMB32] = s.N > 16 && s.N <= 32 ? comb_blocks : 0;
         sl.count[IT_COMB48] = s.N > 32 ? comb_blocks : 0;
@@ -553,7 +565,7 @@ static int launch_phases(int32_t n, void *ws, const BatchLayout &L, hipStream_t 
             hipLaunchKernelGGL((batch_comb<16, COMB_PX16>), dim3(L.count[IT_COMB16]), dim3(COMB_TILE), 0, s, a,
                                L.first[IT_COMB16]);
         if (L.count[IT_COMB32] > 0)
-            hipLaunchKernelGGL((batch_comb<32, 1>), dim3(L.count[IT_COMB32]), dim3(COMB_TILE), 0, s, a,
+            hipLaunchKernelGGL((batch_comb<32, COMB_PX32>), dim3(L.count[IT_COMB32]), dim3(COMB_TILE), 0, s, a,
                                L.first[IT_COMB32]);
         if (L.count[IT_COMB48] > 0)
             hipLaunchKernelGGL((batch_comb<48, 1>), dim3(L.count[IT_COMB48]), dim3(COMB_TILE), 0, s, a,

@@ -41,7 +41,7 @@ __global__ __launch_bounds__(COMB_TILE) void combine_cols(
     const float *__restrict__ aligned, int64_t plane, int32_t N, double ksigma, int32_t max_iters,
     float *__restrict__ out, uint8_t *__restrict__ keep, unsigned long long *__restrict__ n_rej)
 {
-    const unsigned dropped = combine_cols_block<MAXV, PX>(aligned, plane, N, ksigma, max_iters, out, keep,
+    const unsigned dropped = combine_cols_block<MAXV, PX>(aligned, plane, plane, N, ksigma, max_iters, out, keep,
                                                           (int64_t)blockIdx.x);
     if (n_rej) {
         const unsigned total = block_sum_u32(dropped);

@@ -231,12 +231,14 @@ __device__ __forceinline__ float clip_registers(const float (&x)[MAXV], int32_t 
 }
 
 // PX adjacent pixel columns per thread: each frame's PX values come in as one vector
-// load (plane and pointer aligned to PX floats), then the columns are clipped one
-// after the other.
+// load (frame k's plane starts at aligned + k * pstride; pstride >= plane, and pstride
+// and the pointers aligned to PX floats), then the columns are clipped one after the
+// other.  Columns at or past `plane` are neither written nor counted.
 template <int MAXV, int PX>
-__device__ __forceinline__ unsigned combine_cols_block(const float *__restrict__ aligned, int64_t plane, int32_t N,
-                                                       double ksigma, int32_t max_iters, float *__restrict__ out,
-                                                       uint8_t *__restrict__ keep, int64_t block)
+__device__ __forceinline__ unsigned combine_cols_block(const float *__restrict__ aligned, int64_t plane,
+                                                       int64_t pstride, int32_t N, double ksigma, int32_t max_iters,
+                                                       float *__restrict__ out, uint8_t *__restrict__ keep,
+                                                       int64_t block)
 {
     const int64_t p0 = (block * COMB_TILE + threadIdx.x) * PX;
     float xs[PX][MAXV];
@@ -244,7 +246,7 @@ __device__ __forceinline__ unsigned combine_cols_block(const float *__restrict__
 #pragma unroll
         for (int i = 0; i < MAXV; ++i) {
             if (i < N) {
-                const float *src = aligned + (int64_t)i * plane + p0;
+                const float *src = aligned + (int64_t)i * pstride + p0;
                 if (PX == 4) {
                     const float4 v = *reinterpret_cast<const float4 *>(src);
                     xs[0][i] = v.x;
@@ -268,7 +270,7 @@ __device__ __forceinline__ unsigned combine_cols_block(const float *__restrict__
         for (int i = 0; i < MAXV; ++i)
 #pragma unroll
             for (int c = 0; c < PX; ++c)
-                xs[c][i] = (i < N && p0 + c < plane) ? aligned[(int64_t)i * plane + p0 + c] : 0.0f;
+                xs[c][i] = (i < N && p0 + c < plane) ? aligned[(int64_t)i * pstride + p0 + c] : 0.0f;
     }
     unsigned dropped = 0;
     float res[PX];

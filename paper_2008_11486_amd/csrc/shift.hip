@@ -18,7 +18,7 @@ __global__ __launch_bounds__(SH_BLOCK) void shift_kernel(
 {
     const int32_t k = blockIdx.z;
     shift_strip<INTEGER, SH_VEC>(in, out, W, H, k, offs[2 * k], offs[2 * k + 1], blockIdx.y, blockIdx.x, x0, y0, w,
-                                 h, vec_store, aligned);
+                                 h, (int64_t)w * h, vec_store, aligned);
 }
 
 }  // namespace rd

@@ -90,12 +90,13 @@ struct TapRow {
 // output row is the upper tap row of the next, and the row the next output row needs
 // is requested before the current one is computed.
 // One thread's part of strip `strip` (SH_ROWS output rows) of x block `xblk` of frame k
-// (offset (sx, sy)): V consecutive outputs in each row.
+// (offset (sx, sy)): V consecutive outputs in each row.  Output frame k's plane of h
+// rows of w starts at out + k * pstride.
 template <bool INTEGER, int V>
 __device__ __forceinline__ void shift_strip(const float *__restrict__ in, float *__restrict__ out, int32_t W,
                                             int32_t H, int32_t k, float sx, float sy, int32_t strip, int32_t xblk,
-                                            int32_t x0, int32_t y0, int32_t w, int32_t h, int vec_store,
-                                            bool aligned)
+                                            int32_t x0, int32_t y0, int32_t w, int32_t h, int64_t pstride,
+                                            int vec_store, bool aligned)
 {
     const int32_t v0 = strip * SH_ROWS;
     const int32_t v1 = min(v0 + SH_ROWS, h);
@@ -142,7 +143,7 @@ __device__ __forceinline__ void shift_strip(const float *__restrict__ in, float 
                 r[e] = bilerp(ss.a, ss.b, t0[e], f10, t1[e], f11);
             }
         }
-        float *o = out + ((int64_t)k * h + v) * w;
+        float *o = out + (int64_t)k * pstride + (int64_t)v * w;
         store_outputs<V>(o, u0, w, vec_store, r);
         if (!more) break;
         if (jn == j1 && j1 != j) {

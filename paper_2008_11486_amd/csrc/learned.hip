@@ -64,66 +64,88 @@ __device__ __forceinline__ double block_sum_d(double v, double *scratch)
     return t;
 }
 
-// Block means (double) of one frame per blockIdx.y, and per-block partial sums.
+// One pass per frame: the 4x4 block means (summed in double, stored as float), and per
+// workgroup the sums of d = v - c and d^2, with c the frame's first block mean (a shift
+// that keeps the one-pass variance free of cancellation; every workgroup recomputes it,
+// the first one stores it).
+__device__ __forceinline__ double box4(const float *__restrict__ src, int32_t W)
+{
+    double s = 0.0;
+    for (int y = 0; y < 4; ++y)
+        for (int x = 0; x < 4; ++x) s += (double)src[(int64_t)y * W + x];
+    return s / 16.0;
+}
+
 __global__ __launch_bounds__(DS_BLOCK) void ds_boxmean(const float *__restrict__ frames, int32_t W, int32_t H,
-                                                       double *__restrict__ m, double *__restrict__ part)
+                                                       float *__restrict__ m, double *__restrict__ part,
+                                                       double *__restrict__ shift)
 {
     __shared__ double scratch[DS_BLOCK / 64];
     const int32_t w = W / 4, h = H / 4;
     const int64_t n = (int64_t)w * h;
     const int32_t f = blockIdx.y;
     const int64_t i = (int64_t)blockIdx.x * DS_BLOCK + threadIdx.x;
-    double v = 0.0;
+    const float *frame = frames + (int64_t)f * W * H;
+    const double c = box4(frame, W);
+    double d = 0.0;
     if (i < n) {
         const int32_t jy = (int32_t)(i / w), jx = (int32_t)(i - (int64_t)jy * w);
-        const float *src = frames + (int64_t)f * W * H + (int64_t)(4 * jy) * W + 4 * jx;
-        double s = 0.0;
-        for (int y = 0; y < 4; ++y)
-            for (int x = 0; x < 4; ++x) s += (double)src[(int64_t)y * W + x];
-        v = s / 16.0;
-        m[(int64_t)f * n + i] = v;
+        const double v = box4(frame + (int64_t)(4 * jy) * W + 4 * jx, W);
+        m[(int64_t)f * n + i] = (float)v;
+        d = v - c;
     }
-    const double t = block_sum_d(v, scratch);
-    if (threadIdx.x == 0) part[(int64_t)f * gridDim.x + blockIdx.x] = t;
+    const double t1 = block_sum_d(d, scratch);
+    const double t2 = block_sum_d(d * d, scratch);
+    if (threadIdx.x == 0) {
+        double *pp = part + 2 * ((int64_t)f * gridDim.x + blockIdx.x);
+        pp[0] = t1;
+        pp[1] = t2;
+        if (blockIdx.x == 0) shift[f] = c;
+    }
 }
 
-// Per frame: stat = sum of the partials in order / n; with `sqrt_of` the square root.
+// Per frame: mean = c + S1 / n and population sigma = sqrt(S2 / n - (S1 / n)^2), the
+// partial sums added over workgroups in a fixed order.
 __global__ __launch_bounds__(DS_BLOCK) void ds_finish(const double *__restrict__ part, int32_t nparts, double n,
-                                                      double *__restrict__ stat, int sqrt_of)
+                                                      const double *__restrict__ shift, double *__restrict__ mean,
+                                                      double *__restrict__ sd)
 {
     __shared__ double scratch[DS_BLOCK / 64];
     const int32_t f = blockIdx.x;
-    double s = 0.0;
-    for (int32_t i = threadIdx.x; i < nparts; i += DS_BLOCK) s += part[(int64_t)f * nparts + i];
-    s = block_sum_d(s, scratch);
-    if (threadIdx.x == 0) stat[f] = sqrt_of ? sqrt(s / n) : s / n;
-}
-
-__global__ __launch_bounds__(DS_BLOCK) void ds_sqdev(const double *__restrict__ m, int64_t n,
-                                                     const double *__restrict__ mean, double *__restrict__ part)
-{
-    __shared__ double scratch[DS_BLOCK / 64];
-    const int32_t f = blockIdx.y;
-    const int64_t i = (int64_t)blockIdx.x * DS_BLOCK + threadIdx.x;
-    double v = 0.0;
-    if (i < n) {
-        const double d = m[(int64_t)f * n + i] - mean[f];
-        v = d * d;
+    double s1 = 0.0, s2 = 0.0;
+    for (int32_t i = threadIdx.x; i < nparts; i += DS_BLOCK) {
+        s1 += part[2 * ((int64_t)f * nparts + i)];
+        s2 += part[2 * ((int64_t)f * nparts + i) + 1];
     }
-    const double t = block_sum_d(v, scratch);
-    if (threadIdx.x == 0) part[(int64_t)f * gridDim.x + blockIdx.x] = t;
+    s1 = block_sum_d(s1, scratch);
+    s2 = block_sum_d(s2, scratch);
+    if (threadIdx.x == 0) {
+        const double a = s1 / n;
+        mean[f] = shift[f] + a;
+        sd[f] = sqrt(fmax(s2 / n - a * a, 0.0));
+    }
 }
 
-__global__ __launch_bounds__(DS_BLOCK) void ds_normalize(const double *__restrict__ m, int64_t n,
+// Four values per thread: standardise, asinh, round to bfloat16.
+__global__ __launch_bounds__(DS_BLOCK) void ds_normalize(const float *__restrict__ m, int64_t n,
                                                          const double *__restrict__ mean,
                                                          const double *__restrict__ sd, uint16_t *__restrict__ out)
 {
     const int32_t f = blockIdx.y;
-    const int64_t i = (int64_t)blockIdx.x * DS_BLOCK + threadIdx.x;
-    if (i >= n) return;
-    const double s = sd[f];
-    const double z = asinh(s > 0.0 ? (m[(int64_t)f * n + i] - mean[f]) / s : 0.0);
-    out[(int64_t)f * n + i] = f2bf((float)z);
+    const int64_t i0 = ((int64_t)blockIdx.x * DS_BLOCK + threadIdx.x) * 4;
+    if (i0 >= n) return;
+    const double s = sd[f], mu = mean[f];
+    const float *src = m + (int64_t)f * n;
+    uint16_t *dst = out + (int64_t)f * n;
+    auto z = [&](float v) { return f2bf((float)asinh(s > 0.0 ? ((double)v - mu) / s : 0.0)); };
+    if (i0 + 4 <= n && n % 4 == 0 && (reinterpret_cast<uintptr_t>(out) & 7u) == 0) {
+        const float4 v = *reinterpret_cast<const float4 *>(src + i0);
+        const uint32_t lo = (uint32_t)z(v.x) | ((uint32_t)z(v.y) << 16);
+        const uint32_t hi = (uint32_t)z(v.z) | ((uint32_t)z(v.w) << 16);
+        *reinterpret_cast<uint2 *>(dst + i0) = make_uint2(lo, hi);
+    } else {
+        for (int64_t i = i0; i < min(i0 + 4, n); ++i) dst[i] = z(src[i]);
+    }
 }
 
 // ---- weight packing ---------------------------------------------------------------------
@@ -667,7 +689,7 @@ extern "C" size_t reduce_cnn_input_ws(int32_t W, int32_t H, int32_t N)
     if (W < 4 || H < 4 || W % 4 || H % 4 || N < 1) return 0;
     const int64_t n = (int64_t)(W / 4) * (H / 4);
     const int64_t nparts = ceil_div(n, DS_BLOCK);
-    return al(sizeof(double) * n * N) + 2 * al(sizeof(double) * nparts * N) + 2 * al(sizeof(double) * N);
+    return al(sizeof(float) * n * N) + al(2 * sizeof(double) * nparts * N) + 3 * al(sizeof(double) * N);
 }
 
 extern "C" int reduce_cnn_input(const float *frames, int32_t W, int32_t H, int32_t N, uint16_t *out, void *ws,
@@ -684,17 +706,19 @@ extern "C" int reduce_cnn_input(const float *frames, int32_t W, int32_t H, int32
     const int64_t n = (int64_t)(W / 4) * (H / 4);
     const int32_t nparts = (int32_t)ceil_div(n, DS_BLOCK);
     unsigned char *base = static_cast<unsigned char *>(ws);
-    double *m = reinterpret_cast<double *>(base);
-    double *part = reinterpret_cast<double *>(base + al(sizeof(double) * n * N));
-    double *mean = reinterpret_cast<double *>(base + al(sizeof(double) * n * N) + 2 * al(sizeof(double) * nparts * N));
-    double *sd = mean + N;
+    float *m = reinterpret_cast<float *>(base);
+    unsigned char *b1 = base + al(sizeof(float) * n * N);
+    double *part = reinterpret_cast<double *>(b1);
+    unsigned char *b2 = b1 + al(2 * sizeof(double) * nparts * N);
+    double *shift = reinterpret_cast<double *>(b2);
+    double *mean = reinterpret_cast<double *>(b2 + al(sizeof(double) * N));
+    double *sd = reinterpret_cast<double *>(b2 + 2 * al(sizeof(double) * N));
     ProfScope prof("cnn_input", s);
-    const dim3 grid((unsigned)nparts, (unsigned)N);
-    hipLaunchKernelGGL(ds_boxmean, grid, dim3(DS_BLOCK), 0, s, frames, W, H, m, part);
-    hipLaunchKernelGGL(ds_finish, dim3(N), dim3(DS_BLOCK), 0, s, part, nparts, (double)n, mean, 0);
-    hipLaunchKernelGGL(ds_sqdev, grid, dim3(DS_BLOCK), 0, s, m, n, mean, part);
-    hipLaunchKernelGGL(ds_finish, dim3(N), dim3(DS_BLOCK), 0, s, part, nparts, (double)n, sd, 1);
-    hipLaunchKernelGGL(ds_normalize, grid, dim3(DS_BLOCK), 0, s, m, n, mean, sd, out);
+    hipLaunchKernelGGL(ds_boxmean, dim3((unsigned)nparts, (unsigned)N), dim3(DS_BLOCK), 0, s, frames, W, H, m, part,
+                       shift);
+    hipLaunchKernelGGL(ds_finish, dim3(N), dim3(DS_BLOCK), 0, s, part, nparts, (double)n, shift, mean, sd);
+    hipLaunchKernelGGL(ds_normalize, dim3((unsigned)ceil_div(n, 4 * DS_BLOCK), (unsigned)N), dim3(DS_BLOCK), 0, s,
+                       m, n, mean, sd, out);
     return check_launch("reduce_cnn_input");
 }
 

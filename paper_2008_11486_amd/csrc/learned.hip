@@ -183,73 +183,101 @@ __global__ void pack_weights(const float *__restrict__ params, uint16_t *__restr
 }
 
 // ---- convolution forward ---------------------------------------------------------------------
-// One wave: 16 consecutive output pixels of a row x 32 channels.  The workgroup's four
-// waves cover 64 pixels; results go through LDS for 16-byte stores.
+// One wave: 16 consecutive output pixels of a row x 32 channels per MFMA pair; results go
+// through LDS for 16-byte stores.  Layer 1 (CIN = 2): the workgroup's four waves cover 64
+// pixels, and the three input rows of both channels they need are staged in LDS with
+// coalesced loads first.  Layers 2-4 (CIN = 32): a wave keeps the weights of all nine taps
+// in registers and covers NG groups of 64 pixels (one group per pass of the workgroup), so
+// the weights are read once per NG * 64 pixels.  The accumulation order (taps in order,
+// one MFMA per tap and 16 channels) is the same in every case.
+constexpr int CONV_NG = 4;  // 64-pixel groups per workgroup of the 32-channel layers
+
 template <int CIN>
 __global__ __launch_bounds__(256) void conv_fwd(const uint16_t *__restrict__ x, const uint16_t *__restrict__ ref,
                                                 int64_t ref_stride, const uint16_t *__restrict__ img, int32_t H,
                                                 int32_t W, const uint16_t *__restrict__ wf,
                                                 const float *__restrict__ bias, uint16_t *__restrict__ y)
 {
+    constexpr int NG = CIN == 2 ? 1 : CONV_NG;
+    constexpr int XC = 2 * 64 + 4;  // staged input columns (129 used)
     __shared__ __align__(16) uint16_t tile[4][16 * CNN_CH];
+    __shared__ uint16_t in2[CIN == 2 ? 3 * 2 * XC : 1];
     const int32_t Ho = (H + 1) / 2, Wo = (W + 1) / 2;
     const int32_t b = blockIdx.z, oy = blockIdx.y;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int32_t ox0 = blockIdx.x * 64 + wave * 16;
     const int m = lane & 15, kg = lane >> 4;
-    const int32_t ox = ox0 + m;
 
-    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-    if (CIN == 2) {
-        // K = 18 (tap, channel) pairs + zeros, gathered element by element
-        uint16_t e[8];
+    bf16x8 wb0[CIN == 2 ? 1 : 9], wb1[CIN == 2 ? 1 : 9];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int k = kg * 8 + j;
-            uint16_t v = 0;
-            if (k < 18 && ox < Wo) {
-                const int t = k >> 1, c = k & 1;
-                const int32_t iy = 2 * oy + t / 3 - 1, ix = 2 * ox + t % 3 - 1;
+    for (int t = 0; t < (CIN == 2 ? 1 : 9); ++t) {
+        wb0[t] = load8(wf + (t * 32 + m) * 32 + kg * 8);
+        wb1[t] = load8(wf + (t * 32 + 16 + m) * 32 + kg * 8);
+    }
+    const float bias0 = bias[m], bias1 = bias[16 + m];
+
+    for (int g = 0; g < NG; ++g) {
+        const int32_t gx0 = (blockIdx.x * NG + g) * 64;  // first output pixel of the group
+        if (gx0 >= Wo) break;                            // uniform over the workgroup
+        const int32_t ox0 = gx0 + wave * 16;
+        const int32_t ox = ox0 + m;
+        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (CIN == 2) {
+            // input rows 2 oy - 1 .. 2 oy + 1, columns 2 gx0 - 1 + c, both channels
+            for (int e = threadIdx.x; e < 3 * 2 * (XC - 3); e += 256) {
+                const int r = e / (2 * (XC - 3)), rem = e - r * 2 * (XC - 3);
+                const int c = rem / (XC - 3), col = rem - c * (XC - 3);
+                const int32_t iy = 2 * oy + r - 1, ix = 2 * gx0 - 1 + col;
+                uint16_t v = 0;
                 if (iy >= 0 && iy < H && ix >= 0 && ix < W) {
                     const int64_t p = (int64_t)iy * W + ix;
                     v = c == 0 ? ref[(int64_t)b * ref_stride + p] : img[(int64_t)b * H * W + p];
                 }
+                in2[(r * 2 + c) * XC + col] = v;
             }
-            e[j] = v;
-        }
-        const uint4 pk = make_uint4(e[0] | ((uint32_t)e[1] << 16), e[2] | ((uint32_t)e[3] << 16),
-                                    e[4] | ((uint32_t)e[5] << 16), e[6] | ((uint32_t)e[7] << 16));
-        const bf16x8 a = __builtin_bit_cast(bf16x8, pk);
-        const bf16x8 b0 = load8(wf + (0 * 32 + m) * 32 + kg * 8);
-        const bf16x8 b1 = load8(wf + (0 * 32 + 16 + m) * 32 + kg * 8);
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b0, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b1, acc1, 0, 0, 0);
-    } else {
+            __syncthreads();
+            // K = 18 (tap, channel) pairs + zeros
+            uint16_t e8[8];
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const int32_t iy = 2 * oy + t / 3 - 1, ix = 2 * ox + t % 3 - 1;
-            bf16x8 a = zero8();
-            if (ox < Wo && iy >= 0 && iy < H && ix >= 0 && ix < W)
-                a = load8(x + (((int64_t)b * H + iy) * W + ix) * CNN_CH + kg * 8);
-            const bf16x8 b0 = load8(wf + (t * 32 + m) * 32 + kg * 8);
-            const bf16x8 b1 = load8(wf + (t * 32 + 16 + m) * 32 + kg * 8);
-            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b0, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b1, acc1, 0, 0, 0);
-        }
-    }
-    // lane holds pixels 4 kg + j, channel m (tile 0) and 16 + m (tile 1)
+            for (int j = 0; j < 8; ++j) {
+                const int k = kg * 8 + j;
+                uint16_t v = 0;
+                if (k < 18 && ox < Wo) {
+                    const int t = k >> 1, c = k & 1;
+                    v = in2[((t / 3) * 2 + c) * XC + 2 * (ox - gx0) + t % 3];
+                }
+                e8[j] = v;
+            }
+            const uint4 pk = make_uint4(e8[0] | ((uint32_t)e8[1] << 16), e8[2] | ((uint32_t)e8[3] << 16),
+                                        e8[4] | ((uint32_t)e8[5] << 16), e8[6] | ((uint32_t)e8[7] << 16));
+            const bf16x8 a = __builtin_bit_cast(bf16x8, pk);
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wb0[0], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wb1[0], acc1, 0, 0, 0);
+        } else {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int px = 4 * kg + j;
-        tile[wave][px * CNN_CH + m] = f2bf(fmaxf(acc0[j] + bias[m], 0.0f));
-        tile[wave][px * CNN_CH + 16 + m] = f2bf(fmaxf(acc1[j] + bias[16 + m], 0.0f));
-    }
-    __syncthreads();
-    const int px = lane >> 2, c8 = (lane & 3) * 8;
-    const int32_t oxs = ox0 + px;
-    if (oxs < Wo) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(&tile[wave][px * CNN_CH + c8]);
-        *reinterpret_cast<uint4 *>(y + (((int64_t)b * Ho + oy) * Wo + oxs) * CNN_CH + c8) = v;
+            for (int t = 0; t < 9; ++t) {
+                const int32_t iy = 2 * oy + t / 3 - 1, ix = 2 * ox + t % 3 - 1;
+                bf16x8 a = zero8();
+                if (ox < Wo && iy >= 0 && iy < H && ix >= 0 && ix < W)
+                    a = load8(x + (((int64_t)b * H + iy) * W + ix) * CNN_CH + kg * 8);
+                acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wb0[t], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wb1[t], acc1, 0, 0, 0);
+            }
+        }
+        // lane holds pixels 4 kg + j, channel m (tile 0) and 16 + m (tile 1)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int px = 4 * kg + j;
+            tile[wave][px * CNN_CH + m] = f2bf(fmaxf(acc0[j] + bias0, 0.0f));
+            tile[wave][px * CNN_CH + 16 + m] = f2bf(fmaxf(acc1[j] + bias1, 0.0f));
+        }
+        __syncthreads();
+        const int px = lane >> 2, c8 = (lane & 3) * 8;
+        const int32_t oxs = ox0 + px;
+        if (oxs < Wo) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(&tile[wave][px * CNN_CH + c8]);
+            *reinterpret_cast<uint4 *>(y + (((int64_t)b * Ho + oy) * Wo + oxs) * CNN_CH + c8) = v;
+        }
+        __syncthreads();  // the tiles (and staged rows) are reused by the next group
     }
 }
 
@@ -613,7 +641,7 @@ int cnn_forward_launch(const uint16_t *ref, int64_t ref_stride, const uint16_t *
     for (int l = 0; l < 4; ++l) {
         uint16_t *out = reinterpret_cast<uint16_t *>(base + L.act[l]);
         const float *bias = params + cnn_weight_offset(l) + 9 * (l == 0 ? 2 : CNN_CH) * CNN_CH;
-        dim3 grid((unsigned)ceil_div(L.ws[l], 64), (unsigned)L.hs[l], (unsigned)B);
+        dim3 grid((unsigned)ceil_div(L.ws[l], 64 * (l == 0 ? 1 : CONV_NG)), (unsigned)L.hs[l], (unsigned)B);
         if (l == 0)
             hipLaunchKernelGGL(conv_fwd<2>, grid, dim3(256), 0, s, nullptr, ref, ref_stride, img, hh, ww, wf, bias,
                                out);

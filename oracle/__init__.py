@@ -12,6 +12,7 @@ plain definitions written out in ``oracle.c``:
 * ``register``: zero-mean-template cross-correlation, argmax, 3-point parabola;
 * ``valid_rect`` / ``shift``: common overlap and bilinear resampling (Sec. 3.1.2, 3.2.1);
 * ``combine``: iterative sigma-clipped mean (Sec. 2.1, 3.1.2);
+* ``shift_spline``: natural bicubic-spline resampling (``spline.py``, NumPy);
 * ``downsample4``: 4x4 block mean;
 * ``cnn_*``: the offset-proposal network (see ``oracle_cnn.c``).
 """
@@ -304,3 +305,6 @@ def reduce_stack(raw: np.ndarray, dark: np.ndarray, flat: np.ndarray, radius: in
     out, keep, nrej, near = combine(al, ksigma, max_iters)
     return dict(cal=cal, offsets=offs, s=s, rect=rect, aligned=al, out=out, keep=keep,
                 n_rej=nrej, near=near)
+
+
+from .spline import shift_spline  # noqa: E402  (NumPy part of the oracle)

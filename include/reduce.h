@@ -142,6 +142,24 @@ int reduce_valid_rect(const float *offs, int32_t N, int32_t W, int32_t H, int32_
 int reduce_shift(const float *in, float *out, int32_t W, int32_t H, int32_t N,
                  const float *offs, const int32_t *rect, int32_t integer_mode, void *stream);
 
+/* ---- bicubic-spline shift ---------------------------------------------------------
+ * The paper's own interpolation (Sections 2.1, 2.2; Section 3.2.1 prices its
+ * tridiagonal system per image row or column): out[k][v][u] = S_k(x0 + u + sx_k,
+ * y0 + v + sy_k), S_k the tensor-product natural cubic spline through frame k's pixels
+ * on the integer grid (second derivative zero at both ends of every row and column).
+ * Positions are clamped into the frame.  FP32 arithmetic; two passes (rows into the
+ * workspace, then columns).
+ *   in    device float [N][H][W];  out  device float dense [N][h][w]
+ *   offs  device float [N][2];     rect host int32 {x0, y0, w, h}
+ *   ws    device workspace of at least reduce_shift_spline_ws(W, H, N) bytes
+ *         (N * H * w floats are used)
+ * Errors: an empty or oversized rect -> SHAPE; N or H above 65535 -> UNSUPPORTED;
+ * small ws -> WORKSPACE. */
+size_t reduce_shift_spline_ws(int32_t W, int32_t H, int32_t N);
+int reduce_shift_spline(const float *in, float *out, int32_t W, int32_t H, int32_t N,
+                        const float *offs, const int32_t *rect, void *ws, size_t ws_bytes,
+                        void *stream);
+
 /* ---- combine --------------------------------------------------------------
  * Co-adding by sigma-clipped mean (Sections 2.1 and 3.1.2).  Per pixel, over the
  * N aligned values: up to max_iters times, take the mean m and population sigma of

@@ -46,10 +46,11 @@ def second_derivatives(f: np.ndarray) -> np.ndarray:
 
 
 def evaluate(f: np.ndarray, M: np.ndarray, x: np.ndarray) -> np.ndarray:
-    """The splines of the lines of f (last axis) at positions x in [0, L-1]."""
+    """The splines of the lines of f (last axis) at positions x, clamped into [0, L-1]
+    (positions inside the common overlap never need the clamp)."""
     f = np.asarray(f, dtype=np.float64)
     L = f.shape[-1]
-    x = np.asarray(x, dtype=np.float64)
+    x = np.clip(np.asarray(x, dtype=np.float64), 0.0, L - 1.0)
     if L == 1:
         return np.broadcast_to(f[..., :1], f.shape[:-1] + x.shape).copy()
     i = np.clip(np.floor(x).astype(np.int64), 0, L - 2)

@@ -64,6 +64,10 @@ def _declare(L):
     L.reduce_register.argtypes = [P, P, I32, I32, I32, I32, I32, P, P, P, P, P, SZ, P]
     L.reduce_valid_rect.argtypes = [P, I32, I32, I32, P]
     L.reduce_shift.argtypes = [P, P, I32, I32, I32, P, P, I32, P]
+    L.reduce_shift_spline_ws.argtypes = [I32, I32, I32]
+    L.reduce_shift_spline_ws.restype = SZ
+    L.reduce_shift_spline.argtypes = [P, P, I32, I32, I32, P, P, P, SZ, P]
+    L.reduce_shift_spline.restype = ctypes.c_int
     L.reduce_combine.argtypes = [P, I32, I32, I32, F, I32, P, P, P, P]
     L.reduce_register_plan.argtypes = [I32, I32, I32, I32, I32, P]
     L.reduce_register_plan.restype = ctypes.c_int
@@ -114,6 +118,7 @@ def exported_symbols() -> Sequence[str]:
     """Names declared in include/reduce.h that the binding knows about."""
     return ("reduce_status_str", "reduce_last_error", "reduce_version", "reduce_calibrate",
             "reduce_register_ws", "reduce_register", "reduce_valid_rect", "reduce_shift",
+            "reduce_shift_spline_ws", "reduce_shift_spline",
             "reduce_combine", "reduce_prof_enable", "reduce_prof_query", "reduce_register_plan",
             "reduce_tune_register", "reduce_tune_register_ws", "reduce_tune_combine", "reduce_tune_save",
             "reduce_tune_load",
@@ -294,6 +299,27 @@ def shift(frames: torch.Tensor, offs: torch.Tensor, rect: Sequence[int], integer
         out = torch.empty((N, int(rect[3]), int(rect[2])), dtype=torch.float32, device=frames.device)
     _check(lib().reduce_shift(_ptr(frames.contiguous()), _ptr(out), W, H, N, _ptr(offs), r,
                               1 if integer_mode else 0, _stream(stream)))
+    return out
+
+
+def shift_spline(frames: torch.Tensor, offs: torch.Tensor, rect: Sequence[int], out: Optional[torch.Tensor] = None,
+                 ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Bicubic-spline shift: frames float32 [N][H][W], offs float32 device [N][2], rect host
+    (x0, y0, w, h) -> [N][h][w]."""
+    _dev(frames, "frames")
+    _dev(offs, "offs")
+    if frames.dim() == 2:
+        frames = frames.unsqueeze(0)
+    N, H, W = frames.shape
+    if offs.dtype != torch.float32 or not offs.is_contiguous() or offs.numel() != 2 * N:
+        raise TypeError("offs must be a contiguous float32 device tensor [N][2]")
+    r = (ctypes.c_int32 * 4)(*[int(v) for v in rect])
+    if out is None:
+        out = torch.empty((N, int(rect[3]), int(rect[2])), dtype=torch.float32, device=frames.device)
+    if ws is None:
+        ws = torch.empty(max(int(lib().reduce_shift_spline_ws(W, H, N)), 1), dtype=torch.uint8, device=frames.device)
+    _check(lib().reduce_shift_spline(_ptr(frames.contiguous()), _ptr(out), W, H, N, _ptr(offs), r, _ptr(ws),
+                                     ws.numel(), _stream(stream)))
     return out
 
 

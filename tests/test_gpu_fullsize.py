@@ -114,3 +114,23 @@ def test_wide_combine_columns(wide, orc):
           f"{int(bad.sum())} near-threshold flips, {err_summary(e[~bad])}")
     assert e[~bad].max() <= TOL
     assert int(rejected.numel()) > 0  # cosmic rays were rejected
+
+
+def test_wide_spline_columns(rd, orc, wide):
+    # the bicubic-spline shift at the wide-field size, checked on sampled output columns:
+    # the oracle evaluates every row spline at those columns, then the column splines
+    spec, cal, s, rect = wide["spec"], wide["cal"], wide["s"], wide["rect"]
+    x0, y0, w, h = (int(v) for v in rect)
+    sd = torch.from_numpy(s).to(cal.device)
+    got = rd.shift_spline(cal, sd, rect)
+    rng = np.random.default_rng(6)
+    import oracle.spline as osp
+    for k in rng.choice(spec.N, 2, replace=False):
+        f = cal[k].cpu().numpy().astype(np.float64)
+        cols = np.sort(rng.choice(w, 4, replace=False))
+        xs = x0 + cols.astype(np.float64) + float(s[k, 0])
+        rows = osp.evaluate(f, osp.second_derivatives(f), xs)  # [H][4]
+        want = osp.evaluate(rows.T, osp.second_derivatives(rows.T), y0 + np.arange(h) + float(s[k, 1])).T
+        g = got[k][:, torch.from_numpy(cols).to(cal.device)].cpu().numpy()
+        e = rel_err(g, want)
+        assert e.max() <= TOL, (int(k), cols.tolist(), err_summary(e))

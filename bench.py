@@ -91,11 +91,13 @@ KERNEL_SOURCES = {
     "calibrate": ("calibrate.hip", "calibrate_core.h", "common.h"),
     "shift": ("shift.hip", "shift_core.h", "common.h"),
     "combine": ("combine.hip", "combine_core.h"),
+    "shift_spline": ("spline.hip", "common.h", "shift_core.h"),
 }
 KERNEL_SYMBOLS = {"batch_score": "batch_score", "batch_shift": "batch_shift", "batch_comb": "batch_comb",
                   "batch_cal": "batch_cal", "score_tiles": "score_tiles", "calibrate": "calibrate_",
                   "shift": "shift_kernel",
-                  "combine": "combine_"}
+                  "combine": "combine_",
+                  "shift_spline": ("spline_rows", "spline_cols")}  # one call = both passes
 
 
 def source_hash(kernel):
@@ -128,18 +130,24 @@ def traffic_from(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, workload,
     out = {"workload": WORKLOADS[workload], "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
            "copy_probe_bytes": copy_bytes, "kernels": {}}
     fr, wr = _counter_rows(fetch_dir, "FETCH_SIZE"), _counter_rows(write_dir, "WRITE_SIZE")
-    for k, sym in KERNEL_SYMBOLS.items():
+    for k, syms in KERNEL_SYMBOLS.items():
         if k not in kernels:
             continue
-        fv = [v for n, v in fr if sym in n]
-        wv = [v for n, v in wr if sym in n]
-        if not fv or not wv:
-            continue
-        fetch = sum(fv) / len(fv) * 1024 * fs
-        write = sum(wv) / len(wv) * 1024 * ws
-        out["kernels"][k] = {"fetch_bytes": round(fetch), "write_bytes": round(write),
-                             "bytes": round(fetch + write), "dispatches": len(fv),
-                             "source_sha256": source_hash(k)}
+        syms = syms if isinstance(syms, tuple) else (syms,)  # a call of several kernels: their sum
+        fetch = write = 0.0
+        dispatches = None
+        for sym in syms:
+            fv = [v for n, v in fr if sym in n]
+            wv = [v for n, v in wr if sym in n]
+            if not fv or not wv:
+                break
+            fetch += sum(fv) / len(fv) * 1024 * fs
+            write += sum(wv) / len(wv) * 1024 * ws
+            dispatches = len(fv) if dispatches is None else dispatches
+        else:
+            out["kernels"][k] = {"fetch_bytes": round(fetch), "write_bytes": round(write),
+                                 "bytes": round(fetch + write), "dispatches": dispatches,
+                                 "source_sha256": source_hash(k)}
     return out
 
 
@@ -382,7 +390,8 @@ def learned_comparison(torch, rd, weights_path, M):
 
 
 def streaming_wide(torch, rd, reps=5, traffic_path=os.path.join(ROOT, "profiles", "traffic.json")):
-    """calibrate, shift and combine over 16 frames of 6144x6160 (working sets of 1.2-2.4 GB,
+    """calibrate, shift (bilinear, and the bicubic spline timed alone) and combine over 16
+    frames of 6144x6160 (working sets of 1.2-2.4 GB,
     far beyond the 256 MB last-level cache), timed with HIP events on their stream."""
     from paper_2008_11486_amd import learned
     N, W, H, bound = 16, 6144, 6160, 64.0
@@ -414,28 +423,35 @@ def streaming_wide(torch, rd, reps=5, traffic_path=os.path.join(ROOT, "profiles"
     rect = rd.valid_rect(t.astype(np.float32), W, H)
     w, h = int(rect[2]), int(rect[3])
     al = torch.empty((N, h, w), dtype=torch.float32, device=dev)
+    al_spline = torch.empty((N, h, w), dtype=torch.float32, device=dev)
+    spline_ws = torch.empty(rd.lib().reduce_shift_spline_ws(W, H, N), dtype=torch.uint8, device=dev)
     out = torch.empty((h, w), dtype=torch.float32, device=dev)
-    for _ in range(2):
+
+    def chain():
         rd.calibrate(raw, dark, flat, out=cal)
         rd.shift(cal, s, rect, out=al)
         rd.combine(al, out=out)
+        rd.shift_spline(cal, s, rect, out=al_spline, ws=spline_ws)  # the paper's interpolation, timed alone
+
+    for _ in range(2):
+        chain()
     torch.cuda.synchronize()
     rd.prof_enable(True)
     for _ in range(reps):
-        rd.calibrate(raw, dark, flat, out=cal)
-        rd.shift(cal, s, rect, out=al)
-        rd.combine(al, out=out)
+        chain()
     torch.cuda.synchronize()
     res = {"workload": f"{N} frames {W}x{H}, 5000 stars, cosmic-ray hits on 0.01% of pixels, shifts +-64 px, "
                        f"overlap {w}x{h}"}
-    byts = {"calibrate": N * W * H * (2 + 4) + 8 * W * H, "shift": N * w * h * (4 + 4), "combine": N * w * h * 4 + w * h * 4}
-    for name in ("calibrate", "shift", "combine"):
+    byts = {"calibrate": N * W * H * (2 + 4) + 8 * W * H, "shift": N * w * h * (4 + 4), "combine": N * w * h * 4 + w * h * 4,
+            # rows: frame read, row-pass result written; columns: that result read, output written
+            "shift_spline": N * 4 * (H * W + 2 * H * w + h * w)}
+    for name in ("calibrate", "shift", "combine", "shift_spline"):
         ms, n = rd.prof_query(name)
         gbs = byts[name] / (ms / n / 1e3) / 1e9
         res[name] = {"avg_launch_ms": round(ms / n, 4), "bytes": byts[name], "GB/s": round(gbs, 1),
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(traffic_path, name, "wide")}
     rd.prof_enable(False)
-    del raw, cal, al
+    del raw, cal, al, al_spline, spline_ws
     torch.cuda.empty_cache()
     return res
 

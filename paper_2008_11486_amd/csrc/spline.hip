@@ -17,8 +17,10 @@
 //
 // Two streaming passes, FP32 arithmetic: rows (every frame row at the shifted x of every
 // output column, into a workspace [N][H][w]), then columns of that result at the shifted
-// y.  Each workgroup stages its line segment plus a 17-value halo in LDS, forms g, the
-// 33-tap stencil and the end corrections, then evaluates its outputs.
+// y.  Each workgroup stages its line segment plus a 17-value halo in LDS; every thread
+// forms g and runs the 33-tap stencil for a run of consecutive knots from a window of the
+// staged values in registers; the end corrections are formed only by workgroups near a
+// line end.
 #include <string>
 
 #include "common.h"
@@ -96,18 +98,36 @@ __device__ __forceinline__ void sp_knot(int32_t xi, float tf, int32_t L, int32_t
     }
 }
 
+// Stencil P for NK consecutive knots from a window gw[NK + 2 SP_T] of g (gw[r + SP_T] at
+// knot r), in registers.
+template <int NK>
+__device__ __forceinline__ void sp_stencil(const float (&gw)[NK + 2 * SP_T], float (&p)[NK])
+{
+    constexpr SpTaps h = sp_taps();
+#pragma unroll
+    for (int r = 0; r < NK; ++r) {
+        float a = h.v[0] * gw[r + SP_T];
+#pragma unroll
+        for (int jj = 1; jj <= SP_T; ++jj) a += h.v[jj] * (gw[r + SP_T - jj] + gw[r + SP_T + jj]);
+        p[r] = a;
+    }
+}
+
+// End corrections are needed only within a few dozen knots of a line end (z^40 < 1e-22).
+constexpr int SP_NEAR = 40;
+
 // ---- pass 1: rows -------------------------------------------------------------------------
-constexpr int SP_N = 256;                          // outputs per workgroup, one per thread
-constexpr int SP_K = SP_N + 1;                     // knots those outputs touch
+constexpr int SP_N = 256;                          // threads
+constexpr int SP_V = 4;                            // outputs (and knots) per thread
+constexpr int SP_K = SP_N * SP_V + 1;              // knots the workgroup's outputs touch
 constexpr int SP_F = SP_K + 2 * SP_T + 2;          // staged values
 
 __global__ __launch_bounds__(SP_N) void spline_rows(const float *__restrict__ in, float *__restrict__ R, int32_t W,
                                                     int32_t H, const float *__restrict__ offs, int32_t x0, int32_t w)
 {
-    constexpr SpTaps h = sp_taps();
-    __shared__ float fs[SP_F], gs[SP_F], ms[SP_K];
+    __shared__ float fs[SP_F], ms[SP_K];
     __shared__ float ends[2];
-    const int32_t k = blockIdx.z, j = blockIdx.y, u0 = blockIdx.x * SP_N;
+    const int32_t k = blockIdx.z, j = blockIdx.y, u0 = blockIdx.x * SP_N * SP_V;
     const int t = threadIdx.x;
     const float sx = offs[2 * k];
     const float fl = floorf(sx);
@@ -117,46 +137,66 @@ __global__ __launch_bounds__(SP_N) void spline_rows(const float *__restrict__ in
     float *dst = R + ((int64_t)k * H + j) * w;
     const int32_t L = W;
     if (L < 2) {
-        for (int32_t u = u0 + t; u < min(u0 + SP_N, w); u += SP_N) dst[u] = row[0];
+        for (int32_t u = u0 + t; u < min(u0 + SP_N * SP_V, w); u += SP_N) dst[u] = row[0];
         return;
     }
     const int32_t ka = clampi(x0 + u0 + fx, 0, L - 2);  // first knot of the workgroup
     const int32_t base = ka - SP_T - 1;                // line index of fs[0]
-    for (int e = t; e < SP_F; e += SP_N) fs[e] = row[clampi(base + e, 0, L - 1)];
-    if (t < 2) {
-        const float p = sp_end_p([&](int32_t i) { return row[i]; }, L, t);
-        ends[t] = p;
+    const bool near0 = ka < SP_NEAR, nearL = ka + SP_K > L - 1 - SP_NEAR;  // uniform
+    {
+        // all of a thread's loads in flight before any is stored
+        constexpr int NL = (SP_F + SP_N - 1) / SP_N;
+        float v[NL];
+#pragma unroll
+        for (int r = 0; r < NL; ++r) v[r] = row[clampi(base + t + SP_N * r, 0, L - 1)];
+#pragma unroll
+        for (int r = 0; r < NL; ++r)
+            if (t + SP_N * r < SP_F) fs[t + SP_N * r] = v[r];
     }
+    if (t < 2) ends[t] = (t == 0 ? near0 : nearL) ? sp_end_p([&](int32_t i) { return row[i]; }, L, t) : 0.0f;
     __syncthreads();
-    for (int e = t; e < SP_F; e += SP_N) {
-        const int32_t m = base + e;
-        gs[e] = (m >= 1 && m <= L - 2 && e >= 1 && e + 1 < SP_F) ? 6.0f * (fs[e + 1] - 2.0f * fs[e] + fs[e - 1]) : 0.0f;
-    }
     float A, B;
     sp_ends(ends[0], ends[1], L, A, B);
-    __syncthreads();
-    for (int q = t; q < SP_K; q += SP_N) {
-        float p = h.v[0] * gs[q + SP_T + 1];
+    {
+        // knots q0 .. q0 + SP_V (the last one is also the next thread's first); g of knots
+        // q0 - SP_T .. from the staged values in registers (zero outside the line's interior)
+        const int q0 = SP_V * t;
+        constexpr int NG = SP_V + 1 + 2 * SP_T;
+        float fw[NG + 2], gw[NG], p[SP_V + 1];
 #pragma unroll
-        for (int jj = 1; jj <= SP_T; ++jj) p += h.v[jj] * (gs[q + SP_T + 1 - jj] + gs[q + SP_T + 1 + jj]);
-        const int32_t i = ka + q;
-        ms[q] = (i <= 0 || i >= L - 1) ? 0.0f : p + A * sp_zpow(i) + B * sp_zpow(L - 1 - i);
+        for (int r = 0; r < NG + 2; ++r) fw[r] = fs[q0 + r];
+#pragma unroll
+        for (int r = 0; r < NG; ++r) {
+            const int32_t m = ka + q0 - SP_T + r;
+            gw[r] = (m >= 1 && m <= L - 2) ? 6.0f * (fw[r + 2] - 2.0f * fw[r + 1] + fw[r]) : 0.0f;
+        }
+        sp_stencil<SP_V + 1>(gw, p);
+#pragma unroll
+        for (int r = 0; r < SP_V + 1; ++r) {
+            const int32_t i = ka + q0 + r;
+            const float m = (i <= 0 || i >= L - 1) ? 0.0f : p[r] + A * sp_zpow(i) + B * sp_zpow(L - 1 - i);
+            if (r < SP_V || t == SP_N - 1) ms[q0 + r] = m;
+        }
     }
     __syncthreads();
-    const int32_t u = u0 + t;
-    if (u < w) {
-        int32_t i;
-        float tt;
-        sp_knot(x0 + u + fx, tf, L, i, tt);
-        const int q = i - ka;
-        dst[u] = sp_eval(fs[q + SP_T + 1], fs[q + SP_T + 2], ms[q], ms[q + 1], tt);
+#pragma unroll
+    for (int v = 0; v < SP_V; ++v) {
+        const int32_t u = u0 + t + SP_N * v;  // consecutive threads write consecutive columns
+        if (u < w) {
+            int32_t i;
+            float tt;
+            sp_knot(x0 + u + fx, tf, L, i, tt);
+            const int q = i - ka;
+            dst[u] = sp_eval(fs[q + SP_T + 1], fs[q + SP_T + 2], ms[q], ms[q + 1], tt);
+        }
     }
 }
 
 // ---- pass 2: columns ----------------------------------------------------------------------
 constexpr int SPC_C = 64;                          // columns per workgroup
-constexpr int SPC_V = 64;                          // output rows per workgroup
 constexpr int SPC_G = 4;                           // row groups (threads = SPC_C * SPC_G)
+constexpr int SPC_Q = 16;                          // knots (output rows) per thread
+constexpr int SPC_V = SPC_G * SPC_Q;               // output rows per workgroup
 constexpr int SPC_K = SPC_V + 1;
 constexpr int SPC_F = SPC_K + 2 * SP_T + 2;
 
@@ -164,9 +204,8 @@ __global__ __launch_bounds__(SPC_C *SPC_G) void spline_cols(const float *__restr
                                                             int32_t H, const float *__restrict__ offs, int32_t y0,
                                                             int32_t w, int32_t h)
 {
-    constexpr SpTaps hh = sp_taps();
     __shared__ float fs[SPC_F][SPC_C];
-    __shared__ float gs[SPC_F][SPC_C];  // g, then M of the knots
+    __shared__ float ms[SPC_K][SPC_C];  // M of the knots
     __shared__ float endA[SPC_C], endB[SPC_C], endP[2][SPC_C];
     const int32_t k = blockIdx.z, v0 = blockIdx.y * SPC_V, c0 = blockIdx.x * SPC_C;
     const int c = threadIdx.x % SPC_C, rg = threadIdx.x / SPC_C;
@@ -185,15 +224,19 @@ __global__ __launch_bounds__(SPC_C *SPC_G) void spline_cols(const float *__restr
     }
     const int32_t ka = clampi(y0 + v0 + fy, 0, L - 2);
     const int32_t base = ka - SP_T - 1;
-    for (int e = rg; e < SPC_F; e += SPC_G) fs[e][c] = at(clampi(base + e, 0, L - 1));
-    if (rg < 2) endP[rg][c] = sp_end_p(at, L, rg);
-    __syncthreads();
-    for (int e = rg; e < SPC_F; e += SPC_G) {
-        const int32_t m = base + e;
-        gs[e][c] = (m >= 1 && m <= L - 2 && e >= 1 && e + 1 < SPC_F)
-                       ? 6.0f * (fs[e + 1][c] - 2.0f * fs[e][c] + fs[e - 1][c])
-                       : 0.0f;
+    const bool near0 = ka < SP_NEAR, nearL = ka + SPC_K > L - 1 - SP_NEAR;  // uniform
+    {
+        // all of a thread's loads in flight before any is stored
+        constexpr int NL = (SPC_F + SPC_G - 1) / SPC_G;
+        float v[NL];
+#pragma unroll
+        for (int r = 0; r < NL; ++r) v[r] = at(clampi(base + rg + SPC_G * r, 0, L - 1));
+#pragma unroll
+        for (int r = 0; r < NL; ++r)
+            if (rg + SPC_G * r < SPC_F) fs[rg + SPC_G * r][c] = v[r];
     }
+    if (rg < 2) endP[rg][c] = (rg == 0 ? near0 : nearL) ? sp_end_p(at, L, rg) : 0.0f;
+    __syncthreads();
     if (rg == 0) {
         float A, B;
         sp_ends(endP[0][c], endP[1][c], L, A, B);
@@ -201,36 +244,41 @@ __global__ __launch_bounds__(SPC_C *SPC_G) void spline_cols(const float *__restr
         endB[c] = B;
     }
     __syncthreads();
-    constexpr int QN = (SPC_K + SPC_G - 1) / SPC_G;
-    float mv[QN];
+    // knots q0 .. q0 + SPC_Q of column c (the last one is also the next group's first)
+    const int q0 = SPC_Q * rg;
+    float p[SPC_Q + 1];
+    {
+        constexpr int NG = SPC_Q + 1 + 2 * SP_T;
+        float fw[NG + 2], gw[NG];
 #pragma unroll
-    for (int r = 0; r < QN; ++r) {
-        const int q = rg + SPC_G * r;
-        float p = 0.0f;
-        if (q < SPC_K) {
-            p = hh.v[0] * gs[q + SP_T + 1][c];
+        for (int r = 0; r < NG + 2; ++r) fw[r] = fs[q0 + r][c];
 #pragma unroll
-            for (int jj = 1; jj <= SP_T; ++jj) p += hh.v[jj] * (gs[q + SP_T + 1 - jj][c] + gs[q + SP_T + 1 + jj][c]);
-            const int32_t i = ka + q;
-            p = (i <= 0 || i >= L - 1) ? 0.0f : p + endA[c] * sp_zpow(i) + endB[c] * sp_zpow(L - 1 - i);
+        for (int r = 0; r < NG; ++r) {
+            const int32_t m = ka + q0 - SP_T + r;
+            gw[r] = (m >= 1 && m <= L - 2) ? 6.0f * (fw[r + 2] - 2.0f * fw[r + 1] + fw[r]) : 0.0f;
         }
-        mv[r] = p;
-    }
-    __syncthreads();  // every stencil has read g
+        sp_stencil<SPC_Q + 1>(gw, p);
 #pragma unroll
-    for (int r = 0; r < QN; ++r) {
-        const int q = rg + SPC_G * r;
-        if (q < SPC_K) gs[q][c] = mv[r];
+        for (int r = 0; r < SPC_Q + 1; ++r) {
+            const int32_t i = ka + q0 + r;
+            p[r] = (i <= 0 || i >= L - 1) ? 0.0f : p[r] + endA[c] * sp_zpow(i) + endB[c] * sp_zpow(L - 1 - i);
+        }
     }
+#pragma unroll
+    for (int r = 0; r < SPC_Q + 1; ++r)
+        if (r < SPC_Q || rg == SPC_G - 1) ms[q0 + r][c] = p[r];
     __syncthreads();
     if (c0 + c >= w) return;
-    for (int32_t v = v0 + rg; v < min(v0 + SPC_V, h); v += SPC_G) {
+#pragma unroll 4
+    for (int r = 0; r < SPC_Q; ++r) {
+        const int32_t v = v0 + q0 + r;
+        if (v >= h) break;
         int32_t i;
         float tt;
         sp_knot(y0 + v + fy, tf, L, i, tt);
         const int q = i - ka;
-        out[((int64_t)k * h + v) * w + c0 + c] = sp_eval(fs[q + SP_T + 1][c], fs[q + SP_T + 2][c], gs[q][c],
-                                                         gs[q + 1][c], tt);
+        out[((int64_t)k * h + v) * w + c0 + c] = sp_eval(fs[q + SP_T + 1][c], fs[q + SP_T + 2][c], ms[q][c],
+                                                         ms[q + 1][c], tt);
     }
 }
 
@@ -258,8 +306,8 @@ extern "C" int reduce_shift_spline(const float *in, float *out, int32_t W, int32
     hipStream_t s = as_stream(stream);
     float *R = static_cast<float *>(ws);
     ProfScope prof("shift_spline", s);
-    hipLaunchKernelGGL(spline_rows, dim3((unsigned)ceil_div(w, SP_N), (unsigned)H, (unsigned)N), dim3(SP_N), 0, s, in,
-                       R, W, H, offs, x0, w);
+    hipLaunchKernelGGL(spline_rows, dim3((unsigned)ceil_div(w, SP_N * SP_V), (unsigned)H, (unsigned)N), dim3(SP_N), 0,
+                       s, in, R, W, H, offs, x0, w);
     hipLaunchKernelGGL(spline_cols, dim3((unsigned)ceil_div(w, SPC_C), (unsigned)ceil_div(h, SPC_V), (unsigned)N),
                        dim3(SPC_C * SPC_G), 0, s, R, out, H, offs, y0, w, h);
     return check_launch("reduce_shift_spline");

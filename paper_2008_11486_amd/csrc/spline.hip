@@ -98,36 +98,69 @@ __device__ __forceinline__ void sp_knot(int32_t xi, float tf, int32_t L, int32_t
     }
 }
 
-// Stencil P for NK consecutive knots from a window gw[NK + 2 SP_T] of g (gw[r + SP_T] at
-// knot r), in registers.
-template <int NK>
-__device__ __forceinline__ void sp_stencil(const float (&gw)[NK + 2 * SP_T], float (&p)[NK])
+// P (up to the end corrections) of knots s .. s+K from fw[r] = f[s - SP_T - 1 + r]: the
+// inverse of (1, 4, 1) on the unbounded line factors as (-z) / ((1 - z S^-1)(1 - z S)),
+// S the shift, so P = -6 z d with c[m] = D2f[m] + z c[m-1] (causal) and
+// d[m] = c[m] + z d[m+1] (anticausal), D2f[m] = f[m+1] - 2 f[m] + f[m-1].  Both
+// recursions start SP_T knots outside the run with zero state; the state they miss is
+// below z^17 (2e-10) of the data.
+template <int K>
+__device__ __forceinline__ void sp_recur(const float (&fw)[K + 2 * SP_T + 3], float (&p)[K + 1])
 {
-    constexpr SpTaps h = sp_taps();
+    const float z = (float)SP_Z, scale = (float)(-6.0 * SP_Z);
+    float c[K + SP_T + 1];  // causal state at knots s .. s+K+SP_T
+    float st = 0.0f;
 #pragma unroll
-    for (int r = 0; r < NK; ++r) {
-        float a = h.v[0] * gw[r + SP_T];
-#pragma unroll
-        for (int jj = 1; jj <= SP_T; ++jj) a += h.v[jj] * (gw[r + SP_T - jj] + gw[r + SP_T + jj]);
-        p[r] = a;
+    for (int r = 0; r <= K + 2 * SP_T; ++r) {  // knot s - SP_T + r
+        const float g = fmaf(-2.0f, fw[r + 1], fw[r + 2] + fw[r]);
+        st = fmaf(z, st, g);
+        if (r >= SP_T) c[r - SP_T] = st;
     }
+    float d = 0.0f;
+#pragma unroll
+    for (int r = K + SP_T; r >= 0; --r) {
+        d = fmaf(z, d, c[r]);
+        if (r <= K) p[r] = scale * d;
+    }
+}
+
+// The recursion reads staged values clamped into the line, so next to an end its g holds
+// D2f[0] = f[1] - f[0] and D2f[L-1] = f[L-2] - f[L-1] instead of zero (further out the
+// clamped values give exactly zero).  Their responses, 6 h[i] e0 and 6 h[L-1-i] e1, have
+// the shape of the two end corrections, so they are taken out of (A, B): returns the
+// coefficients to add to P from P[0], P[L-1] of the true g and the four end values.
+__device__ __forceinline__ void sp_ends_raw(float P0, float PL, int32_t L, float f0, float f1, float fl2, float fl1,
+                                            float &A, float &B)
+{
+    sp_ends(P0, PL, L, A, B);
+    const float c6 = (float)(6.0 * SP_C);
+    A -= c6 * fmaf(-2.0f, f0, f1 + f0);    // the recursion's own g at knot 0
+    B -= c6 * fmaf(-2.0f, fl1, fl1 + fl2);  // and at knot L-1
 }
 
 // End corrections are needed only within a few dozen knots of a line end (z^40 < 1e-22).
 constexpr int SP_NEAR = 40;
 
-// ---- pass 1: rows -------------------------------------------------------------------------
-constexpr int SP_N = 256;                          // threads
-constexpr int SP_V = 4;                            // outputs (and knots) per thread
-constexpr int SP_K = SP_N * SP_V + 1;              // knots the workgroup's outputs touch
-constexpr int SP_F = SP_K + 2 * SP_T + 2;          // staged values
+// LDS index of staged value (or knot) e: a pad word every 16 puts the stride-16 windows
+// of the lanes on distinct banks.
+__device__ __forceinline__ int sp_pad(int e) { return e + (e >> 4); }
 
+// ---- pass 1: rows -------------------------------------------------------------------------
+constexpr int SP_N = 64;                           // lanes: one wave per workgroup
+constexpr int SP_Q = 16;                           // knots per lane
+constexpr int SP_K = SP_N * SP_Q + 1;              // knots the workgroup's outputs touch
+constexpr int SP_F = SP_K + 2 * SP_T + 2;          // staged values
+constexpr int SP_NL = (SP_F + SP_N - 1) / SP_N;    // staged values per lane
+constexpr int SP_FP = SP_F + (SP_F >> 4) + 1, SP_KP = SP_K + (SP_K >> 4) + 1;
+
+// A workgroup takes 1024 output columns of one row: it stages their knots' values plus a
+// 17-value halo, every lane runs the two recursions over its 16 knots, and the outputs
+// are evaluated from LDS with consecutive lanes on consecutive columns.
 __global__ __launch_bounds__(SP_N) void spline_rows(const float *__restrict__ in, float *__restrict__ R, int32_t W,
                                                     int32_t H, const float *__restrict__ offs, int32_t x0, int32_t w)
 {
-    __shared__ float fs[SP_F], ms[SP_K];
-    __shared__ float ends[2];
-    const int32_t k = blockIdx.z, j = blockIdx.y, u0 = blockIdx.x * SP_N * SP_V;
+    __shared__ float fs[SP_FP], ms[SP_KP];
+    const int32_t k = blockIdx.z, j = blockIdx.y, u0 = blockIdx.x * (SP_K - 1);
     const int t = threadIdx.x;
     const float sx = offs[2 * k];
     const float fl = floorf(sx);
@@ -137,57 +170,53 @@ __global__ __launch_bounds__(SP_N) void spline_rows(const float *__restrict__ in
     float *dst = R + ((int64_t)k * H + j) * w;
     const int32_t L = W;
     if (L < 2) {
-        for (int32_t u = u0 + t; u < min(u0 + SP_N * SP_V, w); u += SP_N) dst[u] = row[0];
+        for (int32_t u = u0 + t; u < min(u0 + SP_K - 1, w); u += SP_N) dst[u] = row[0];
         return;
     }
     const int32_t ka = clampi(x0 + u0 + fx, 0, L - 2);  // first knot of the workgroup
-    const int32_t base = ka - SP_T - 1;                // line index of fs[0]
+    const int32_t base = ka - SP_T - 1;                // line index of staged value 0
     const bool near0 = ka < SP_NEAR, nearL = ka + SP_K > L - 1 - SP_NEAR;  // uniform
     {
-        // all of a thread's loads in flight before any is stored
-        constexpr int NL = (SP_F + SP_N - 1) / SP_N;
-        float v[NL];
+        float v[SP_NL];
 #pragma unroll
-        for (int r = 0; r < NL; ++r) v[r] = row[clampi(base + t + SP_N * r, 0, L - 1)];
+        for (int r = 0; r < SP_NL; ++r) v[r] = row[clampi(base + t + SP_N * r, 0, L - 1)];
 #pragma unroll
-        for (int r = 0; r < NL; ++r)
-            if (t + SP_N * r < SP_F) fs[t + SP_N * r] = v[r];
+        for (int r = 0; r < SP_NL; ++r)
+            if (t + SP_N * r < SP_F) fs[sp_pad(t + SP_N * r)] = v[r];
     }
-    if (t < 2) ends[t] = (t == 0 ? near0 : nearL) ? sp_end_p([&](int32_t i) { return row[i]; }, L, t) : 0.0f;
+    float A = 0.0f, B = 0.0f;
+    if (near0 || nearL) {
+        auto get = [&](int32_t i) { return row[i]; };
+        sp_ends_raw(near0 ? sp_end_p(get, L, 0) : 0.0f, nearL ? sp_end_p(get, L, 1) : 0.0f, L, row[0],
+                    row[min(1, L - 1)], row[max(L - 2, 0)], row[L - 1], A, B);
+    }
     __syncthreads();
-    float A, B;
-    sp_ends(ends[0], ends[1], L, A, B);
     {
-        // knots q0 .. q0 + SP_V (the last one is also the next thread's first); g of knots
-        // q0 - SP_T .. from the staged values in registers (zero outside the line's interior)
-        const int q0 = SP_V * t;
-        constexpr int NG = SP_V + 1 + 2 * SP_T;
-        float fw[NG + 2], gw[NG], p[SP_V + 1];
+        const int q0 = SP_Q * t;
+        float fw[SP_Q + 2 * SP_T + 3], p[SP_Q + 1];
 #pragma unroll
-        for (int r = 0; r < NG + 2; ++r) fw[r] = fs[q0 + r];
+        for (int r = 0; r < SP_Q + 2 * SP_T + 3; ++r) fw[r] = fs[sp_pad(q0 + r)];
+        sp_recur<SP_Q>(fw, p);
 #pragma unroll
-        for (int r = 0; r < NG; ++r) {
-            const int32_t m = ka + q0 - SP_T + r;
-            gw[r] = (m >= 1 && m <= L - 2) ? 6.0f * (fw[r + 2] - 2.0f * fw[r + 1] + fw[r]) : 0.0f;
-        }
-        sp_stencil<SP_V + 1>(gw, p);
-#pragma unroll
-        for (int r = 0; r < SP_V + 1; ++r) {
-            const int32_t i = ka + q0 + r;
-            const float m = (i <= 0 || i >= L - 1) ? 0.0f : p[r] + A * sp_zpow(i) + B * sp_zpow(L - 1 - i);
-            if (r < SP_V || t == SP_N - 1) ms[q0 + r] = m;
+        for (int r = 0; r <= SP_Q; ++r) {
+            float m = p[r];
+            if (near0 || nearL) {
+                const int32_t i = ka + q0 + r;
+                m = (i <= 0 || i >= L - 1) ? 0.0f : m + A * sp_zpow(i) + B * sp_zpow(L - 1 - i);
+            }
+            if (r < SP_Q || t == SP_N - 1) ms[sp_pad(q0 + r)] = m;
         }
     }
     __syncthreads();
 #pragma unroll
-    for (int v = 0; v < SP_V; ++v) {
-        const int32_t u = u0 + t + SP_N * v;  // consecutive threads write consecutive columns
+    for (int q = 0; q < SP_Q; ++q) {
+        const int32_t u = u0 + t + SP_N * q;  // consecutive lanes write consecutive columns
         if (u < w) {
             int32_t i;
             float tt;
             sp_knot(x0 + u + fx, tf, L, i, tt);
-            const int q = i - ka;
-            dst[u] = sp_eval(fs[q + SP_T + 1], fs[q + SP_T + 2], ms[q], ms[q + 1], tt);
+            const int d = i - ka;
+            dst[u] = sp_eval(fs[sp_pad(d + SP_T + 1)], fs[sp_pad(d + SP_T + 2)], ms[sp_pad(d)], ms[sp_pad(d + 1)], tt);
         }
     }
 }
@@ -195,19 +224,31 @@ __global__ __launch_bounds__(SP_N) void spline_rows(const float *__restrict__ in
 // ---- pass 2: columns ----------------------------------------------------------------------
 constexpr int SPC_C = 64;                          // columns per workgroup
 constexpr int SPC_G = 4;                           // row groups (threads = SPC_C * SPC_G)
-constexpr int SPC_Q = 16;                          // knots (output rows) per thread
-constexpr int SPC_V = SPC_G * SPC_Q;               // output rows per workgroup
-constexpr int SPC_K = SPC_V + 1;
-constexpr int SPC_F = SPC_K + 2 * SP_T + 2;
+constexpr int SPC_Q = 16;                          // knots (output rows) per thread and tile
+constexpr int SPC_V = SPC_G * SPC_Q;               // output rows per tile
+constexpr int SPC_K = SPC_V + 1;                   // knots of a tile
+constexpr int SPC_F = SPC_K + 2 * SP_T + 2;        // line values a tile reads
+constexpr int SPC_RING = 128;                      // LDS ring of line values (>= SPC_F)
+constexpr int SPC_NT = 8;                          // tiles per workgroup
+constexpr int SPC_NL0 = (SPC_F + SPC_G - 1) / SPC_G;
+constexpr int SPC_NL = SPC_V / SPC_G;              // new lines per thread and tile
+constexpr int SP_E = SP_T + 2;                     // values at each line end that P[0], P[L-1] read
+static_assert(SPC_RING >= SPC_F && (SPC_RING & (SPC_RING - 1)) == 0, "ring");
+static_assert(2 * SP_E <= SPC_K, "end values reuse the M buffer");
 
+// A workgroup walks down SPC_NT tiles of 64 columns x 64 output rows.  Line value m of a
+// column sits in ring row m mod 128; a tile reads lines ka - 17 .. ka + 81 (ka its first
+// knot), so the next tile adds at most 64 new lines, loaded into registers while the
+// current tile is computed and stored once its reads are done.  The end corrections are
+// the same for every tile of a column: each thread forms them for its column at the start.
 __global__ __launch_bounds__(SPC_C *SPC_G) void spline_cols(const float *__restrict__ R, float *__restrict__ out,
                                                             int32_t H, const float *__restrict__ offs, int32_t y0,
                                                             int32_t w, int32_t h)
 {
-    __shared__ float fs[SPC_F][SPC_C];
-    __shared__ float ms[SPC_K][SPC_C];  // M of the knots
-    __shared__ float endA[SPC_C], endB[SPC_C], endP[2][SPC_C];
-    const int32_t k = blockIdx.z, v0 = blockIdx.y * SPC_V, c0 = blockIdx.x * SPC_C;
+    __shared__ float ring[SPC_RING][SPC_C];
+    __shared__ float ms[SPC_K][SPC_C];  // M of the knots (first the end values)
+    const int32_t k = blockIdx.z, vs = blockIdx.y * SPC_V * SPC_NT, c0 = blockIdx.x * SPC_C;
+    const int32_t ve = min(vs + SPC_V * SPC_NT, h);
     const int c = threadIdx.x % SPC_C, rg = threadIdx.x / SPC_C;
     const float sy = offs[2 * k + 1];
     const float fl = floorf(sy);
@@ -216,69 +257,87 @@ __global__ __launch_bounds__(SPC_C *SPC_G) void spline_cols(const float *__restr
     const int32_t L = H;
     const int32_t col = min(c0 + c, w - 1);
     const float *src = R + (int64_t)k * H * w + col;
-    auto at = [&](int32_t i) { return src[(int64_t)i * w]; };
+    auto at = [&](int32_t i) { return src[(int64_t)clampi(i, 0, L - 1) * w]; };
     if (L < 2) {
-        for (int32_t v = v0 + rg; v < min(v0 + SPC_V, h); v += SPC_G)
+        for (int32_t v = vs + rg; v < ve; v += SPC_G)
             if (c0 + c < w) out[((int64_t)k * h + v) * w + c0 + c] = at(0);
         return;
     }
-    const int32_t ka = clampi(y0 + v0 + fy, 0, L - 2);
-    const int32_t base = ka - SP_T - 1;
-    const bool near0 = ka < SP_NEAR, nearL = ka + SPC_K > L - 1 - SP_NEAR;  // uniform
+    auto first_knot = [&](int32_t v0) { return clampi(y0 + v0 + fy, 0, L - 2); };
+    int32_t ka = first_knot(vs);
+    const bool near0 = ka < SP_NEAR, nearL = first_knot(ve - 1) + SPC_K > L - 1 - SP_NEAR;  // uniform
     {
-        // all of a thread's loads in flight before any is stored
-        constexpr int NL = (SPC_F + SPC_G - 1) / SPC_G;
-        float v[NL];
+        float v[SPC_NL0];
 #pragma unroll
-        for (int r = 0; r < NL; ++r) v[r] = at(clampi(base + rg + SPC_G * r, 0, L - 1));
+        for (int r = 0; r < SPC_NL0; ++r) v[r] = at(ka - SP_T - 1 + rg + SPC_G * r);
+        if (near0 || nearL)
+            for (int e = rg; e < 2 * SP_E; e += SPC_G) ms[e][c] = at(e < SP_E ? e : L - 2 * SP_E + e);
 #pragma unroll
-        for (int r = 0; r < NL; ++r)
-            if (rg + SPC_G * r < SPC_F) fs[rg + SPC_G * r][c] = v[r];
-    }
-    if (rg < 2) endP[rg][c] = (rg == 0 ? near0 : nearL) ? sp_end_p(at, L, rg) : 0.0f;
-    __syncthreads();
-    if (rg == 0) {
-        float A, B;
-        sp_ends(endP[0][c], endP[1][c], L, A, B);
-        endA[c] = A;
-        endB[c] = B;
+        for (int r = 0; r < SPC_NL0; ++r)
+            if (rg + SPC_G * r < SPC_F) ring[(ka - SP_T - 1 + rg + SPC_G * r) & (SPC_RING - 1)][c] = v[r];
     }
     __syncthreads();
-    // knots q0 .. q0 + SPC_Q of column c (the last one is also the next group's first)
+    float A = 0.0f, B = 0.0f;
+    if (near0 || nearL) {
+        // ms[e] holds f[e] and ms[SP_E + e] holds f[L - SP_E + e] (indices clamped into the
+        // line); sp_end_p reads only 0 .. L-1
+        auto lo = [&](int32_t i) { return ms[min(i, SP_E - 1)][c]; };
+        auto hi = [&](int32_t i) { return ms[SP_E + max(i - (L - SP_E), 0)][c]; };
+        sp_ends_raw(near0 ? sp_end_p(lo, L, 0) : 0.0f, nearL ? sp_end_p(hi, L, 1) : 0.0f, L, lo(0), lo(1),
+                    hi(L - 2), hi(L - 1), A, B);
+    }
+    __syncthreads();  // the end values are read before ms holds M
     const int q0 = SPC_Q * rg;
-    float p[SPC_Q + 1];
-    {
-        constexpr int NG = SPC_Q + 1 + 2 * SP_T;
-        float fw[NG + 2], gw[NG];
+    for (int32_t v0 = vs; v0 < ve; v0 += SPC_V) {
+        // the next tile's new lines: hi .. hi_next - 1
+        const int32_t hi = ka + SPC_F - SP_T - 1;
+        const bool more = v0 + SPC_V < ve;
+        const int32_t ka_next = more ? first_knot(v0 + SPC_V) : ka;
+        const int32_t hi_next = ka_next + SPC_F - SP_T - 1;
+        float nv[SPC_NL];
 #pragma unroll
-        for (int r = 0; r < NG + 2; ++r) fw[r] = fs[q0 + r][c];
-#pragma unroll
-        for (int r = 0; r < NG; ++r) {
-            const int32_t m = ka + q0 - SP_T + r;
-            gw[r] = (m >= 1 && m <= L - 2) ? 6.0f * (fw[r + 2] - 2.0f * fw[r + 1] + fw[r]) : 0.0f;
+        for (int r = 0; r < SPC_NL; ++r) {
+            const int32_t m = hi + rg + SPC_G * r;
+            nv[r] = m < hi_next ? at(m) : 0.0f;
         }
-        sp_stencil<SPC_Q + 1>(gw, p);
+        {
+            float fw[SPC_Q + 2 * SP_T + 3], p[SPC_Q + 1];
+            const int32_t m0 = ka + q0 - SP_T - 1;
 #pragma unroll
-        for (int r = 0; r < SPC_Q + 1; ++r) {
-            const int32_t i = ka + q0 + r;
-            p[r] = (i <= 0 || i >= L - 1) ? 0.0f : p[r] + endA[c] * sp_zpow(i) + endB[c] * sp_zpow(L - 1 - i);
+            for (int r = 0; r < SPC_Q + 2 * SP_T + 3; ++r) fw[r] = ring[(m0 + r) & (SPC_RING - 1)][c];
+            sp_recur<SPC_Q>(fw, p);
+#pragma unroll
+            for (int r = 0; r <= SPC_Q; ++r) {
+                float m = p[r];
+                if (near0 || nearL) {
+                    const int32_t i = ka + q0 + r;
+                    m = (i <= 0 || i >= L - 1) ? 0.0f : m + A * sp_zpow(i) + B * sp_zpow(L - 1 - i);
+                }
+                if (r < SPC_Q || rg == SPC_G - 1) ms[q0 + r][c] = m;
+            }
         }
-    }
-#pragma unroll
-    for (int r = 0; r < SPC_Q + 1; ++r)
-        if (r < SPC_Q || rg == SPC_G - 1) ms[q0 + r][c] = p[r];
-    __syncthreads();
-    if (c0 + c >= w) return;
+        __syncthreads();
+        if (c0 + c < w) {
 #pragma unroll 4
-    for (int r = 0; r < SPC_Q; ++r) {
-        const int32_t v = v0 + q0 + r;
-        if (v >= h) break;
-        int32_t i;
-        float tt;
-        sp_knot(y0 + v + fy, tf, L, i, tt);
-        const int q = i - ka;
-        out[((int64_t)k * h + v) * w + c0 + c] = sp_eval(fs[q + SP_T + 1][c], fs[q + SP_T + 2][c], ms[q][c],
-                                                         ms[q + 1][c], tt);
+            for (int r = 0; r < SPC_Q; ++r) {
+                const int32_t v = v0 + q0 + r;
+                if (v >= ve) break;
+                int32_t i;
+                float tt;
+                sp_knot(y0 + v + fy, tf, L, i, tt);
+                const int d = i - ka;
+                out[((int64_t)k * h + v) * w + c0 + c] =
+                    sp_eval(ring[i & (SPC_RING - 1)][c], ring[(i + 1) & (SPC_RING - 1)][c], ms[d][c], ms[d + 1][c], tt);
+            }
+        }
+        __syncthreads();  // this tile's reads of the ring and of M are done
+#pragma unroll
+        for (int r = 0; r < SPC_NL; ++r) {
+            const int32_t m = hi + rg + SPC_G * r;
+            if (m < hi_next) ring[m & (SPC_RING - 1)][c] = nv[r];
+        }
+        __syncthreads();
+        ka = ka_next;
     }
 }
 
@@ -306,9 +365,10 @@ extern "C" int reduce_shift_spline(const float *in, float *out, int32_t W, int32
     hipStream_t s = as_stream(stream);
     float *R = static_cast<float *>(ws);
     ProfScope prof("shift_spline", s);
-    hipLaunchKernelGGL(spline_rows, dim3((unsigned)ceil_div(w, SP_N * SP_V), (unsigned)H, (unsigned)N), dim3(SP_N), 0,
-                       s, in, R, W, H, offs, x0, w);
-    hipLaunchKernelGGL(spline_cols, dim3((unsigned)ceil_div(w, SPC_C), (unsigned)ceil_div(h, SPC_V), (unsigned)N),
+    hipLaunchKernelGGL(spline_rows, dim3((unsigned)ceil_div(w, SP_K - 1), (unsigned)H, (unsigned)N), dim3(SP_N), 0, s,
+                       in, R, W, H, offs, x0, w);
+    hipLaunchKernelGGL(spline_cols,
+                       dim3((unsigned)ceil_div(w, SPC_C), (unsigned)ceil_div(h, SPC_V * SPC_NT), (unsigned)N),
                        dim3(SPC_C * SPC_G), 0, s, R, out, H, offs, y0, w, h);
     return check_launch("reduce_shift_spline");
 }

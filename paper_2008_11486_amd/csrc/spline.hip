@@ -83,6 +83,20 @@ __device__ __forceinline__ float sp_eval(float fi, float fi1, float Mi, float Mi
     return u * fi + t * fi1 + (u * u * u - u) * Mi * (1.0f / 6.0f) + (t * t * t - t) * Mi1 * (1.0f / 6.0f);
 }
 
+// The four weights of sp_eval for a fixed fraction t: S = a f[i] + b f[i+1] + c M[i] + d M[i+1].
+struct SpW {
+    float a, b, c, d;
+};
+__device__ __forceinline__ SpW sp_weights(float t)
+{
+    const float u = 1.0f - t;
+    return SpW{u, t, (u * u * u - u) * (1.0f / 6.0f), (t * t * t - t) * (1.0f / 6.0f)};
+}
+__device__ __forceinline__ float sp_apply(const SpW &wt, float fi, float fi1, float Mi, float Mi1)
+{
+    return fmaf(wt.d, Mi1, fmaf(wt.c, Mi, fmaf(wt.b, fi1, wt.a * fi)));
+}
+
 // Knot i and fraction t of position (xi + tf) clamped into [0, L-1], L >= 2.
 __device__ __forceinline__ void sp_knot(int32_t xi, float tf, int32_t L, int32_t &i, float &t)
 {
@@ -190,6 +204,9 @@ __global__ __launch_bounds__(SP_N) void spline_rows(const float *__restrict__ in
         sp_ends_raw(near0 ? sp_end_p(get, L, 0) : 0.0f, nearL ? sp_end_p(get, L, 1) : 0.0f, L, row[0],
                     row[min(1, L - 1)], row[max(L - 2, 0)], row[L - 1], A, B);
     }
+    // no output position of the workgroup is clamped: output u sits on knot ka + u - u0
+    const int32_t un = min(u0 + SP_K - 1, w) - u0;
+    const bool free = x0 + u0 + fx >= 0 && x0 + u0 + un - 1 + fx <= L - 2;  // uniform
     __syncthreads();
     {
         const int q0 = SP_Q * t;
@@ -198,19 +215,35 @@ __global__ __launch_bounds__(SP_N) void spline_rows(const float *__restrict__ in
         for (int r = 0; r < SP_Q + 2 * SP_T + 3; ++r) fw[r] = fs[sp_pad(q0 + r)];
         sp_recur<SP_Q>(fw, p);
 #pragma unroll
-        for (int r = 0; r <= SP_Q; ++r) {
-            float m = p[r];
+        for (int r = 0; r <= SP_Q; ++r)
             if (near0 || nearL) {
                 const int32_t i = ka + q0 + r;
-                m = (i <= 0 || i >= L - 1) ? 0.0f : m + A * sp_zpow(i) + B * sp_zpow(L - 1 - i);
+                p[r] = (i <= 0 || i >= L - 1) ? 0.0f : p[r] + A * sp_zpow(i) + B * sp_zpow(L - 1 - i);
             }
-            if (r < SP_Q || t == SP_N - 1) ms[sp_pad(q0 + r)] = m;
+        if (free) {
+            // the lane's 16 outputs from its own registers, through ms for coalesced stores
+            const SpW wt = sp_weights(tf);
+#pragma unroll
+            for (int r = 0; r < SP_Q; ++r)
+                ms[sp_pad(q0 + r)] = sp_apply(wt, fw[r + SP_T + 1], fw[r + SP_T + 2], p[r], p[r + 1]);
+        } else {
+#pragma unroll
+            for (int r = 0; r <= SP_Q; ++r)
+                if (r < SP_Q || t == SP_N - 1) ms[sp_pad(q0 + r)] = p[r];
         }
     }
     __syncthreads();
+    if (free) {
+#pragma unroll
+        for (int q = 0; q < SP_Q; ++q) {
+            const int d = t + SP_N * q;  // consecutive lanes write consecutive columns
+            if (d < un) dst[u0 + d] = ms[sp_pad(d)];
+        }
+        return;
+    }
 #pragma unroll
     for (int q = 0; q < SP_Q; ++q) {
-        const int32_t u = u0 + t + SP_N * q;  // consecutive lanes write consecutive columns
+        const int32_t u = u0 + t + SP_N * q;
         if (u < w) {
             int32_t i;
             float tt;
@@ -300,6 +333,9 @@ __global__ __launch_bounds__(SPC_C *SPC_G) void spline_cols(const float *__restr
             const int32_t m = hi + rg + SPC_G * r;
             nv[r] = m < hi_next ? at(m) : 0.0f;
         }
+        // no output position of the tile is clamped: output row v sits on knot ka + v - v0
+        const int32_t vn = min(v0 + SPC_V, ve) - v0;
+        const bool free = y0 + v0 + fy >= 0 && y0 + v0 + vn - 1 + fy <= L - 2;  // uniform
         {
             float fw[SPC_Q + 2 * SP_T + 3], p[SPC_Q + 1];
             const int32_t m0 = ka + q0 - SP_T - 1;
@@ -307,30 +343,44 @@ __global__ __launch_bounds__(SPC_C *SPC_G) void spline_cols(const float *__restr
             for (int r = 0; r < SPC_Q + 2 * SP_T + 3; ++r) fw[r] = ring[(m0 + r) & (SPC_RING - 1)][c];
             sp_recur<SPC_Q>(fw, p);
 #pragma unroll
-            for (int r = 0; r <= SPC_Q; ++r) {
-                float m = p[r];
+            for (int r = 0; r <= SPC_Q; ++r)
                 if (near0 || nearL) {
                     const int32_t i = ka + q0 + r;
-                    m = (i <= 0 || i >= L - 1) ? 0.0f : m + A * sp_zpow(i) + B * sp_zpow(L - 1 - i);
+                    p[r] = (i <= 0 || i >= L - 1) ? 0.0f : p[r] + A * sp_zpow(i) + B * sp_zpow(L - 1 - i);
                 }
-                if (r < SPC_Q || rg == SPC_G - 1) ms[q0 + r][c] = m;
+            if (free) {
+                // the thread's output rows are its own knots: no exchange through LDS
+                const SpW wt = sp_weights(tf);
+                if (c0 + c < w) {
+#pragma unroll
+                    for (int r = 0; r < SPC_Q; ++r)
+                        if (q0 + r < vn)
+                            out[((int64_t)k * h + v0 + q0 + r) * w + c0 + c] =
+                                sp_apply(wt, fw[r + SP_T + 1], fw[r + SP_T + 2], p[r], p[r + 1]);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r <= SPC_Q; ++r)
+                    if (r < SPC_Q || rg == SPC_G - 1) ms[q0 + r][c] = p[r];
             }
         }
-        __syncthreads();
-        if (c0 + c < w) {
+        if (!free) {
+            __syncthreads();
+            if (c0 + c < w) {
 #pragma unroll 4
-            for (int r = 0; r < SPC_Q; ++r) {
-                const int32_t v = v0 + q0 + r;
-                if (v >= ve) break;
-                int32_t i;
-                float tt;
-                sp_knot(y0 + v + fy, tf, L, i, tt);
-                const int d = i - ka;
-                out[((int64_t)k * h + v) * w + c0 + c] =
-                    sp_eval(ring[i & (SPC_RING - 1)][c], ring[(i + 1) & (SPC_RING - 1)][c], ms[d][c], ms[d + 1][c], tt);
+                for (int r = 0; r < SPC_Q; ++r) {
+                    const int32_t v = v0 + q0 + r;
+                    if (v >= ve) break;
+                    int32_t i;
+                    float tt;
+                    sp_knot(y0 + v + fy, tf, L, i, tt);
+                    const int d = i - ka;
+                    out[((int64_t)k * h + v) * w + c0 + c] = sp_eval(
+                        ring[i & (SPC_RING - 1)][c], ring[(i + 1) & (SPC_RING - 1)][c], ms[d][c], ms[d + 1][c], tt);
+                }
             }
         }
-        __syncthreads();  // this tile's reads of the ring and of M are done
+        __syncthreads();  // this tile's reads of the ring (and of M) are done
 #pragma unroll
         for (int r = 0; r < SPC_NL; ++r) {
             const int32_t m = hi + rg + SPC_G * r;

@@ -6,21 +6,22 @@
 // Along one line of L values the natural spline's second derivatives M satisfy
 //   M[i-1] + 4 M[i] + M[i+1] = g[i] := 6 (f[i+1] - 2 f[i] + f[i-1]),  0 < i < L-1,
 //   M[0] = M[L-1] = 0.
-// Instead of a sequential solve per line, every M[i] comes from a short stencil: on an
-// unbounded line the inverse of the (1, 4, 1) operator is h[j] = z^|j| / (2 sqrt 3) with
-// z = sqrt 3 - 2, so with g = 0 outside the interior, P = h * g satisfies every interior
-// equation, and M = P + A z^i + B z^(L-1-i) adds the two homogeneous solutions whose
-// coefficients make both ends zero.  |z| = 0.268, so h is cut at |j| <= 16 (the rest is
-// below 2e-10 of g).  On [i, i+1], with t = x - i,
+// On an unbounded line the inverse of the (1, 4, 1) operator is h[j] = z^|j| / (2 sqrt 3)
+// with z = sqrt 3 - 2, so with g = 0 outside the interior, P = h * g satisfies every
+// interior equation, and M = P + A z^i + B z^(L-1-i) adds the two homogeneous solutions
+// whose coefficients make both ends zero.  P is not formed as a sum over h: h factors into
+// a causal and an anticausal first-order recursion (sp_recur), which a thread runs over
+// its own run of knots, started 16 knots outside it (|z|^17 < 2e-10).  On [i, i+1], with
+// t = x - i,
 //   S(x) = (1-t) f[i] + t f[i+1] + ((1-t)^3 - (1-t)) M[i] / 6 + (t^3 - t) M[i+1] / 6.
-// Positions are clamped into [0, L-1] (inside the overlap they never need it).
+// Positions are clamped into [0, L-1] (inside the overlap they never need it); a clamped
+// position takes f[0] or f[L-1].
 //
 // Two streaming passes, FP32 arithmetic: rows (every frame row at the shifted x of every
 // output column, into a workspace [N][H][w]), then columns of that result at the shifted
-// y.  Each workgroup stages its line segment plus a 17-value halo in LDS; every thread
-// forms g and runs the 33-tap stencil for a run of consecutive knots from a window of the
-// staged values in registers; the end corrections are formed only by workgroups near a
-// line end.
+// y.  The shift is the same for the whole frame, so output u sits on knot x0 + fx + u
+// (before clamping) with the same fraction: a thread that owns a run of knots holds in
+// registers everything its run's outputs need.
 #include <string>
 
 #include "common.h"
@@ -28,7 +29,7 @@
 
 namespace rd {
 
-constexpr int SP_T = 16;                          // stencil half-width
+constexpr int SP_T = 16;                          // recursion warm-up, knots
 constexpr double SP_Z = -0.26794919243112270;     // sqrt 3 - 2
 constexpr double SP_C = 0.28867513459481287;      // 1 / (2 sqrt 3)
 
@@ -63,7 +64,8 @@ __device__ __forceinline__ void sp_ends(float P0, float PL, int32_t L, float &A,
     B = (-PL + P0 * zL) / den;
 }
 
-// P[0] (end 0) or P[L-1] (end 1) of a line read through get(i), i in [0, L).
+// P[0] (end 0) or P[L-1] (end 1) of a line read through get(i), i in [0, L): h * g with
+// g zero outside 1 .. L-2, which reaches 16 knots in.
 template <typename Get>
 __device__ __forceinline__ float sp_end_p(Get get, int32_t L, int end)
 {
@@ -71,19 +73,13 @@ __device__ __forceinline__ float sp_end_p(Get get, int32_t L, int end)
     float p = 0.0f;
 #pragma unroll
     for (int j = 1; j <= SP_T; ++j) {
-        const int32_t m = end ? L - 1 - j : j;  // g[m] is zero outside 1 .. L-2
+        const int32_t m = end ? L - 1 - j : j;
         if (m >= 1 && m <= L - 2) p += h.v[j] * (6.0f * (get(m + 1) - 2.0f * get(m) + get(m - 1)));
     }
     return p;
 }
 
-__device__ __forceinline__ float sp_eval(float fi, float fi1, float Mi, float Mi1, float t)
-{
-    const float u = 1.0f - t;
-    return u * fi + t * fi1 + (u * u * u - u) * Mi * (1.0f / 6.0f) + (t * t * t - t) * Mi1 * (1.0f / 6.0f);
-}
-
-// The four weights of sp_eval for a fixed fraction t: S = a f[i] + b f[i+1] + c M[i] + d M[i+1].
+// The four weights of S for a fixed fraction t: S = a f[i] + b f[i+1] + c M[i] + d M[i+1].
 struct SpW {
     float a, b, c, d;
 };
@@ -95,21 +91,6 @@ __device__ __forceinline__ SpW sp_weights(float t)
 __device__ __forceinline__ float sp_apply(const SpW &wt, float fi, float fi1, float Mi, float Mi1)
 {
     return fmaf(wt.d, Mi1, fmaf(wt.c, Mi, fmaf(wt.b, fi1, wt.a * fi)));
-}
-
-// Knot i and fraction t of position (xi + tf) clamped into [0, L-1], L >= 2.
-__device__ __forceinline__ void sp_knot(int32_t xi, float tf, int32_t L, int32_t &i, float &t)
-{
-    if (xi < 0) {
-        i = 0;
-        t = 0.0f;
-    } else if (xi >= L - 1) {
-        i = L - 2;
-        t = 1.0f;
-    } else {
-        i = xi;
-        t = tf;
-    }
 }
 
 // P (up to the end corrections) of knots s .. s+K from fw[r] = f[s - SP_T - 1 + r]: the
@@ -155,41 +136,66 @@ __device__ __forceinline__ void sp_ends_raw(float P0, float PL, int32_t L, float
 // End corrections are needed only within a few dozen knots of a line end (z^40 < 1e-22).
 constexpr int SP_NEAR = 40;
 
-// LDS index of staged value (or knot) e: a pad word every 16 puts the stride-16 windows
-// of the lanes on distinct banks.
+// The outputs of a run of K knots s .. s+K-1 (M of knot s+K is p[K]): fw and p as in
+// sp_recur.  Knots at or beyond an end first get their M (zero at both ends, plus the
+// end corrections near them); a knot outside 0 .. L-2 is a clamped position, whose value
+// is the staged (clamped) line value.
+template <int K>
+__device__ __forceinline__ void sp_outputs(const float (&fw)[K + 2 * SP_T + 3], float (&p)[K + 1], int32_t s,
+                                           int32_t L, bool near, float A, float B, const SpW &wt, float (&o)[K])
+{
+    if (near) {
+#pragma unroll
+        for (int r = 0; r <= K; ++r) {
+            const int32_t i = s + r;
+            p[r] = (i <= 0 || i >= L - 1) ? 0.0f : p[r] + A * sp_zpow(i) + B * sp_zpow(L - 1 - i);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        o[r] = sp_apply(wt, fw[r + SP_T + 1], fw[r + SP_T + 2], p[r], p[r + 1]);
+        if (near) {
+            const int32_t i = s + r;
+            if (i < 0 || i > L - 2) o[r] = fw[r + SP_T + 1];
+        }
+    }
+}
+
+// LDS index of staged value (or output) e: a pad word every 16 puts the stride-16
+// windows of the lanes on distinct banks.
 __device__ __forceinline__ int sp_pad(int e) { return e + (e >> 4); }
 
 // ---- pass 1: rows -------------------------------------------------------------------------
 constexpr int SP_N = 64;                           // lanes: one wave per workgroup
-constexpr int SP_Q = 16;                           // knots per lane
-constexpr int SP_K = SP_N * SP_Q + 1;              // knots the workgroup's outputs touch
-constexpr int SP_F = SP_K + 2 * SP_T + 2;          // staged values
+constexpr int SP_Q = 16;                           // knots (outputs) per lane
+constexpr int SP_U = SP_N * SP_Q;                  // outputs per workgroup
+constexpr int SP_F = SP_U + 1 + 2 * SP_T + 2;      // staged values
 constexpr int SP_NL = (SP_F + SP_N - 1) / SP_N;    // staged values per lane
-constexpr int SP_FP = SP_F + (SP_F >> 4) + 1, SP_KP = SP_K + (SP_K >> 4) + 1;
+constexpr int SP_FP = SP_F + (SP_F >> 4) + 1;
 
 // A workgroup takes 1024 output columns of one row: it stages their knots' values plus a
-// 17-value halo, every lane runs the two recursions over its 16 knots, and the outputs
-// are evaluated from LDS with consecutive lanes on consecutive columns.
+// 17-value halo, every lane runs the two recursions over its 16 knots and forms their
+// outputs, which go back through LDS so that consecutive lanes store consecutive columns.
 __global__ __launch_bounds__(SP_N) void spline_rows(const float *__restrict__ in, float *__restrict__ R, int32_t W,
                                                     int32_t H, const float *__restrict__ offs, int32_t x0, int32_t w)
 {
-    __shared__ float fs[SP_FP], ms[SP_KP];
-    const int32_t k = blockIdx.z, j = blockIdx.y, u0 = blockIdx.x * (SP_K - 1);
+    __shared__ float fs[SP_FP];
+    const int32_t k = blockIdx.z, j = blockIdx.y, u0 = blockIdx.x * SP_U;
     const int t = threadIdx.x;
     const float sx = offs[2 * k];
     const float fl = floorf(sx);
-    const float tf = sx - fl;
     const int32_t fx = (int32_t)fl;
     const float *row = in + ((int64_t)k * H + j) * W;
     float *dst = R + ((int64_t)k * H + j) * w;
     const int32_t L = W;
+    const int32_t un = min(u0 + SP_U, w) - u0;
     if (L < 2) {
-        for (int32_t u = u0 + t; u < min(u0 + SP_K - 1, w); u += SP_N) dst[u] = row[0];
+        for (int32_t d = t; d < un; d += SP_N) dst[u0 + d] = row[0];
         return;
     }
-    const int32_t ka = clampi(x0 + u0 + fx, 0, L - 2);  // first knot of the workgroup
-    const int32_t base = ka - SP_T - 1;                // line index of staged value 0
-    const bool near0 = ka < SP_NEAR, nearL = ka + SP_K > L - 1 - SP_NEAR;  // uniform
+    const int32_t ka = x0 + u0 + fx;     // knot of output u0 (before clamping)
+    const int32_t base = ka - SP_T - 1;  // line index of staged value 0
+    const bool near0 = ka < SP_NEAR, nearL = ka + SP_U + 1 > L - 1 - SP_NEAR;  // uniform
     {
         float v[SP_NL];
 #pragma unroll
@@ -204,53 +210,24 @@ __global__ __launch_bounds__(SP_N) void spline_rows(const float *__restrict__ in
         sp_ends_raw(near0 ? sp_end_p(get, L, 0) : 0.0f, nearL ? sp_end_p(get, L, 1) : 0.0f, L, row[0],
                     row[min(1, L - 1)], row[max(L - 2, 0)], row[L - 1], A, B);
     }
-    // no output position of the workgroup is clamped: output u sits on knot ka + u - u0
-    const int32_t un = min(u0 + SP_K - 1, w) - u0;
-    const bool free = x0 + u0 + fx >= 0 && x0 + u0 + un - 1 + fx <= L - 2;  // uniform
     __syncthreads();
+    float o[SP_Q];
     {
         const int q0 = SP_Q * t;
         float fw[SP_Q + 2 * SP_T + 3], p[SP_Q + 1];
 #pragma unroll
         for (int r = 0; r < SP_Q + 2 * SP_T + 3; ++r) fw[r] = fs[sp_pad(q0 + r)];
         sp_recur<SP_Q>(fw, p);
-#pragma unroll
-        for (int r = 0; r <= SP_Q; ++r)
-            if (near0 || nearL) {
-                const int32_t i = ka + q0 + r;
-                p[r] = (i <= 0 || i >= L - 1) ? 0.0f : p[r] + A * sp_zpow(i) + B * sp_zpow(L - 1 - i);
-            }
-        if (free) {
-            // the lane's 16 outputs from its own registers, through ms for coalesced stores
-            const SpW wt = sp_weights(tf);
-#pragma unroll
-            for (int r = 0; r < SP_Q; ++r)
-                ms[sp_pad(q0 + r)] = sp_apply(wt, fw[r + SP_T + 1], fw[r + SP_T + 2], p[r], p[r + 1]);
-        } else {
-#pragma unroll
-            for (int r = 0; r <= SP_Q; ++r)
-                if (r < SP_Q || t == SP_N - 1) ms[sp_pad(q0 + r)] = p[r];
-        }
+        sp_outputs<SP_Q>(fw, p, ka + q0, L, near0 || nearL, A, B, sp_weights(sx - fl), o);
     }
+    __syncthreads();  // every lane has read its window
+#pragma unroll
+    for (int r = 0; r < SP_Q; ++r) fs[sp_pad(SP_Q * t + r)] = o[r];
     __syncthreads();
-    if (free) {
-#pragma unroll
-        for (int q = 0; q < SP_Q; ++q) {
-            const int d = t + SP_N * q;  // consecutive lanes write consecutive columns
-            if (d < un) dst[u0 + d] = ms[sp_pad(d)];
-        }
-        return;
-    }
 #pragma unroll
     for (int q = 0; q < SP_Q; ++q) {
-        const int32_t u = u0 + t + SP_N * q;
-        if (u < w) {
-            int32_t i;
-            float tt;
-            sp_knot(x0 + u + fx, tf, L, i, tt);
-            const int d = i - ka;
-            dst[u] = sp_eval(fs[sp_pad(d + SP_T + 1)], fs[sp_pad(d + SP_T + 2)], ms[sp_pad(d)], ms[sp_pad(d + 1)], tt);
-        }
+        const int d = t + SP_N * q;  // consecutive lanes store consecutive columns
+        if (d < un) dst[u0 + d] = fs[sp_pad(d)];
     }
 }
 
@@ -259,135 +236,95 @@ constexpr int SPC_C = 64;                          // columns per workgroup
 constexpr int SPC_G = 4;                           // row groups (threads = SPC_C * SPC_G)
 constexpr int SPC_Q = 16;                          // knots (output rows) per thread and tile
 constexpr int SPC_V = SPC_G * SPC_Q;               // output rows per tile
-constexpr int SPC_K = SPC_V + 1;                   // knots of a tile
-constexpr int SPC_F = SPC_K + 2 * SP_T + 2;        // line values a tile reads
+constexpr int SPC_F = SPC_V + 1 + 2 * SP_T + 2;    // line values a tile reads
 constexpr int SPC_RING = 128;                      // LDS ring of line values (>= SPC_F)
 constexpr int SPC_NT = 8;                          // tiles per workgroup
 constexpr int SPC_NL0 = (SPC_F + SPC_G - 1) / SPC_G;
 constexpr int SPC_NL = SPC_V / SPC_G;              // new lines per thread and tile
 constexpr int SP_E = SP_T + 2;                     // values at each line end that P[0], P[L-1] read
 static_assert(SPC_RING >= SPC_F && (SPC_RING & (SPC_RING - 1)) == 0, "ring");
-static_assert(2 * SP_E <= SPC_K, "end values reuse the M buffer");
+static_assert(2 * SP_E <= SPC_RING, "the end values pass through the ring");
 
 // A workgroup walks down SPC_NT tiles of 64 columns x 64 output rows.  Line value m of a
-// column sits in ring row m mod 128; a tile reads lines ka - 17 .. ka + 81 (ka its first
-// knot), so the next tile adds at most 64 new lines, loaded into registers while the
-// current tile is computed and stored once its reads are done.  The end corrections are
-// the same for every tile of a column: each thread forms them for its column at the start.
+// column sits in ring row m mod 128; a tile whose first output row sits on knot kb reads
+// lines kb - 17 .. kb + 81, so the next tile adds 64 new lines, loaded into registers
+// while the current tile is computed and stored once its reads are done.  A thread's 16
+// output rows are its own knots.  The end corrections are the same for every tile of a
+// column: each thread forms them for its column at the start.
 __global__ __launch_bounds__(SPC_C *SPC_G) void spline_cols(const float *__restrict__ R, float *__restrict__ out,
                                                             int32_t H, const float *__restrict__ offs, int32_t y0,
                                                             int32_t w, int32_t h)
 {
     __shared__ float ring[SPC_RING][SPC_C];
-    __shared__ float ms[SPC_K][SPC_C];  // M of the knots (first the end values)
     const int32_t k = blockIdx.z, vs = blockIdx.y * SPC_V * SPC_NT, c0 = blockIdx.x * SPC_C;
     const int32_t ve = min(vs + SPC_V * SPC_NT, h);
     const int c = threadIdx.x % SPC_C, rg = threadIdx.x / SPC_C;
     const float sy = offs[2 * k + 1];
     const float fl = floorf(sy);
-    const float tf = sy - fl;
     const int32_t fy = (int32_t)fl;
     const int32_t L = H;
     const int32_t col = min(c0 + c, w - 1);
+    const bool live = c0 + c < w;
     const float *src = R + (int64_t)k * H * w + col;
     auto at = [&](int32_t i) { return src[(int64_t)clampi(i, 0, L - 1) * w]; };
     if (L < 2) {
         for (int32_t v = vs + rg; v < ve; v += SPC_G)
-            if (c0 + c < w) out[((int64_t)k * h + v) * w + c0 + c] = at(0);
+            if (live) out[((int64_t)k * h + v) * w + c0 + c] = at(0);
         return;
     }
-    auto first_knot = [&](int32_t v0) { return clampi(y0 + v0 + fy, 0, L - 2); };
-    int32_t ka = first_knot(vs);
-    const bool near0 = ka < SP_NEAR, nearL = first_knot(ve - 1) + SPC_K > L - 1 - SP_NEAR;  // uniform
+    int32_t kb = y0 + vs + fy;  // knot of the tile's first output row (before clamping)
+    const bool near0 = kb < SP_NEAR, nearL = y0 + ve - 1 + fy + 1 > L - 1 - SP_NEAR;  // uniform
+    float A = 0.0f, B = 0.0f;
+    if (near0 || nearL) {
+        // ring row e holds f[e] and ring row SP_E + e holds f[L - SP_E + e] (indices clamped
+        // into the line) until the first tile is staged; sp_end_p reads only 0 .. L-1
+        for (int e = rg; e < 2 * SP_E; e += SPC_G) ring[e][c] = at(e < SP_E ? e : L - 2 * SP_E + e);
+        __syncthreads();
+        auto lo = [&](int32_t i) { return ring[min(i, SP_E - 1)][c]; };
+        auto hi = [&](int32_t i) { return ring[SP_E + max(i - (L - SP_E), 0)][c]; };
+        sp_ends_raw(near0 ? sp_end_p(lo, L, 0) : 0.0f, nearL ? sp_end_p(hi, L, 1) : 0.0f, L, lo(0), lo(1),
+                    hi(L - 2), hi(L - 1), A, B);
+        __syncthreads();
+    }
     {
         float v[SPC_NL0];
 #pragma unroll
-        for (int r = 0; r < SPC_NL0; ++r) v[r] = at(ka - SP_T - 1 + rg + SPC_G * r);
-        if (near0 || nearL)
-            for (int e = rg; e < 2 * SP_E; e += SPC_G) ms[e][c] = at(e < SP_E ? e : L - 2 * SP_E + e);
+        for (int r = 0; r < SPC_NL0; ++r) v[r] = at(kb - SP_T - 1 + rg + SPC_G * r);
 #pragma unroll
         for (int r = 0; r < SPC_NL0; ++r)
-            if (rg + SPC_G * r < SPC_F) ring[(ka - SP_T - 1 + rg + SPC_G * r) & (SPC_RING - 1)][c] = v[r];
+            if (rg + SPC_G * r < SPC_F) ring[(kb - SP_T - 1 + rg + SPC_G * r) & (SPC_RING - 1)][c] = v[r];
     }
-    __syncthreads();
-    float A = 0.0f, B = 0.0f;
-    if (near0 || nearL) {
-        // ms[e] holds f[e] and ms[SP_E + e] holds f[L - SP_E + e] (indices clamped into the
-        // line); sp_end_p reads only 0 .. L-1
-        auto lo = [&](int32_t i) { return ms[min(i, SP_E - 1)][c]; };
-        auto hi = [&](int32_t i) { return ms[SP_E + max(i - (L - SP_E), 0)][c]; };
-        sp_ends_raw(near0 ? sp_end_p(lo, L, 0) : 0.0f, nearL ? sp_end_p(hi, L, 1) : 0.0f, L, lo(0), lo(1),
-                    hi(L - 2), hi(L - 1), A, B);
-    }
-    __syncthreads();  // the end values are read before ms holds M
+    const SpW wt = sp_weights(sy - fl);
     const int q0 = SPC_Q * rg;
-    for (int32_t v0 = vs; v0 < ve; v0 += SPC_V) {
-        // the next tile's new lines: hi .. hi_next - 1
-        const int32_t hi = ka + SPC_F - SP_T - 1;
+    for (int32_t v0 = vs; v0 < ve; v0 += SPC_V, kb += SPC_V) {
+        __syncthreads();  // the ring holds this tile's lines
+        // the next tile's new lines: hi .. hi + 63
+        const int32_t hi = kb + SPC_F - SP_T - 1;
         const bool more = v0 + SPC_V < ve;
-        const int32_t ka_next = more ? first_knot(v0 + SPC_V) : ka;
-        const int32_t hi_next = ka_next + SPC_F - SP_T - 1;
         float nv[SPC_NL];
+        if (more) {
 #pragma unroll
-        for (int r = 0; r < SPC_NL; ++r) {
-            const int32_t m = hi + rg + SPC_G * r;
-            nv[r] = m < hi_next ? at(m) : 0.0f;
+            for (int r = 0; r < SPC_NL; ++r) nv[r] = at(hi + rg + SPC_G * r);
         }
-        // no output position of the tile is clamped: output row v sits on knot ka + v - v0
-        const int32_t vn = min(v0 + SPC_V, ve) - v0;
-        const bool free = y0 + v0 + fy >= 0 && y0 + v0 + vn - 1 + fy <= L - 2;  // uniform
+        float o[SPC_Q];
         {
             float fw[SPC_Q + 2 * SP_T + 3], p[SPC_Q + 1];
-            const int32_t m0 = ka + q0 - SP_T - 1;
+            const int32_t m0 = kb + q0 - SP_T - 1;
 #pragma unroll
             for (int r = 0; r < SPC_Q + 2 * SP_T + 3; ++r) fw[r] = ring[(m0 + r) & (SPC_RING - 1)][c];
             sp_recur<SPC_Q>(fw, p);
-#pragma unroll
-            for (int r = 0; r <= SPC_Q; ++r)
-                if (near0 || nearL) {
-                    const int32_t i = ka + q0 + r;
-                    p[r] = (i <= 0 || i >= L - 1) ? 0.0f : p[r] + A * sp_zpow(i) + B * sp_zpow(L - 1 - i);
-                }
-            if (free) {
-                // the thread's output rows are its own knots: no exchange through LDS
-                const SpW wt = sp_weights(tf);
-                if (c0 + c < w) {
-#pragma unroll
-                    for (int r = 0; r < SPC_Q; ++r)
-                        if (q0 + r < vn)
-                            out[((int64_t)k * h + v0 + q0 + r) * w + c0 + c] =
-                                sp_apply(wt, fw[r + SP_T + 1], fw[r + SP_T + 2], p[r], p[r + 1]);
-                }
-            } else {
-#pragma unroll
-                for (int r = 0; r <= SPC_Q; ++r)
-                    if (r < SPC_Q || rg == SPC_G - 1) ms[q0 + r][c] = p[r];
-            }
+            sp_outputs<SPC_Q>(fw, p, kb + q0, L, near0 || nearL, A, B, wt, o);
         }
-        if (!free) {
-            __syncthreads();
-            if (c0 + c < w) {
-#pragma unroll 4
-                for (int r = 0; r < SPC_Q; ++r) {
-                    const int32_t v = v0 + q0 + r;
-                    if (v >= ve) break;
-                    int32_t i;
-                    float tt;
-                    sp_knot(y0 + v + fy, tf, L, i, tt);
-                    const int d = i - ka;
-                    out[((int64_t)k * h + v) * w + c0 + c] = sp_eval(
-                        ring[i & (SPC_RING - 1)][c], ring[(i + 1) & (SPC_RING - 1)][c], ms[d][c], ms[d + 1][c], tt);
-                }
-            }
-        }
-        __syncthreads();  // this tile's reads of the ring (and of M) are done
+        if (live) {
 #pragma unroll
-        for (int r = 0; r < SPC_NL; ++r) {
-            const int32_t m = hi + rg + SPC_G * r;
-            if (m < hi_next) ring[m & (SPC_RING - 1)][c] = nv[r];
+            for (int r = 0; r < SPC_Q; ++r)
+                if (v0 + q0 + r < ve) out[((int64_t)k * h + v0 + q0 + r) * w + c0 + c] = o[r];
         }
-        __syncthreads();
-        ka = ka_next;
+        if (more) {
+            __syncthreads();  // this tile's reads of the ring are done
+#pragma unroll
+            for (int r = 0; r < SPC_NL; ++r) ring[(hi + rg + SPC_G * r) & (SPC_RING - 1)][c] = nv[r];
+        }
     }
 }
 
@@ -415,8 +352,8 @@ extern "C" int reduce_shift_spline(const float *in, float *out, int32_t W, int32
     hipStream_t s = as_stream(stream);
     float *R = static_cast<float *>(ws);
     ProfScope prof("shift_spline", s);
-    hipLaunchKernelGGL(spline_rows, dim3((unsigned)ceil_div(w, SP_K - 1), (unsigned)H, (unsigned)N), dim3(SP_N), 0, s,
-                       in, R, W, H, offs, x0, w);
+    hipLaunchKernelGGL(spline_rows, dim3((unsigned)ceil_div(w, SP_U), (unsigned)H, (unsigned)N), dim3(SP_N), 0, s, in,
+                       R, W, H, offs, x0, w);
     hipLaunchKernelGGL(spline_cols,
                        dim3((unsigned)ceil_div(w, SPC_C), (unsigned)ceil_div(h, SPC_V * SPC_NT), (unsigned)N),
                        dim3(SPC_C * SPC_G), 0, s, R, out, H, offs, y0, w, h);

@@ -152,7 +152,8 @@ int reduce_shift(const float *in, float *out, int32_t W, int32_t H, int32_t N,
  *   in    device float [N][H][W];  out  device float dense [N][h][w]
  *   offs  device float [N][2];     rect host int32 {x0, y0, w, h}
  *   ws    device workspace of at least reduce_shift_spline_ws(W, H, N) bytes
- *         (N * H * w floats are used)
+ *         (the row pass's result, N * H rows of w floats at a pitch of w rounded up
+ *         to 64 floats, so that the column pass reads whole 256-byte segments)
  * Errors: an empty or oversized rect -> SHAPE; N or H above 65535 -> UNSUPPORTED;
  * small ws -> WORKSPACE. */
 size_t reduce_shift_spline_ws(int32_t W, int32_t H, int32_t N);

@@ -177,7 +177,8 @@ constexpr int SP_FP = SP_F + (SP_F >> 4) + 1;
 // 17-value halo, every lane runs the two recursions over its 16 knots and forms their
 // outputs, which go back through LDS so that consecutive lanes store consecutive columns.
 __global__ __launch_bounds__(SP_N) void spline_rows(const float *__restrict__ in, float *__restrict__ R, int32_t W,
-                                                    int32_t H, const float *__restrict__ offs, int32_t x0, int32_t w)
+                                                    int32_t H, const float *__restrict__ offs, int32_t x0, int32_t w,
+                                                    int32_t wp)
 {
     __shared__ float fs[SP_FP];
     const int32_t k = blockIdx.z, j = blockIdx.y, u0 = blockIdx.x * SP_U;
@@ -186,7 +187,7 @@ __global__ __launch_bounds__(SP_N) void spline_rows(const float *__restrict__ in
     const float fl = floorf(sx);
     const int32_t fx = (int32_t)fl;
     const float *row = in + ((int64_t)k * H + j) * W;
-    float *dst = R + ((int64_t)k * H + j) * w;
+    float *dst = R + ((int64_t)k * H + j) * wp;
     const int32_t L = W;
     const int32_t un = min(u0 + SP_U, w) - u0;
     if (L < 2) {
@@ -253,7 +254,7 @@ static_assert(2 * SP_E <= SPC_RING, "the end values pass through the ring");
 // column: each thread forms them for its column at the start.
 __global__ __launch_bounds__(SPC_C *SPC_G) void spline_cols(const float *__restrict__ R, float *__restrict__ out,
                                                             int32_t H, const float *__restrict__ offs, int32_t y0,
-                                                            int32_t w, int32_t h)
+                                                            int32_t w, int32_t wp, int32_t h)
 {
     __shared__ float ring[SPC_RING][SPC_C];
     const int32_t k = blockIdx.z, vs = blockIdx.y * SPC_V * SPC_NT, c0 = blockIdx.x * SPC_C;
@@ -265,8 +266,8 @@ __global__ __launch_bounds__(SPC_C *SPC_G) void spline_cols(const float *__restr
     const int32_t L = H;
     const int32_t col = min(c0 + c, w - 1);
     const bool live = c0 + c < w;
-    const float *src = R + (int64_t)k * H * w + col;
-    auto at = [&](int32_t i) { return src[(int64_t)clampi(i, 0, L - 1) * w]; };
+    const float *src = R + (int64_t)k * H * wp + col;
+    auto at = [&](int32_t i) { return src[(int64_t)clampi(i, 0, L - 1) * wp]; };
     if (L < 2) {
         for (int32_t v = vs + rg; v < ve; v += SPC_G)
             if (live) out[((int64_t)k * h + v) * w + c0 + c] = at(0);
@@ -332,10 +333,13 @@ __global__ __launch_bounds__(SPC_C *SPC_G) void spline_cols(const float *__restr
 
 using namespace rd;
 
+// row pitch of the workspace: whole 256-byte segments for the column pass's loads
+static int32_t spline_pitch(int32_t w) { return (w + 63) & ~63; }
+
 extern "C" size_t reduce_shift_spline_ws(int32_t W, int32_t H, int32_t N)
 {
     if (W < 1 || H < 1 || N < 1) return 0;
-    return (sizeof(float) * (size_t)N * H * W + 255) & ~(size_t)255;
+    return sizeof(float) * (size_t)N * H * (size_t)spline_pitch(W);
 }
 
 extern "C" int reduce_shift_spline(const float *in, float *out, int32_t W, int32_t H, int32_t N, const float *offs,
@@ -346,16 +350,17 @@ extern "C" int reduce_shift_spline(const float *in, float *out, int32_t W, int32
     const int32_t x0 = rect[0], y0 = rect[1], w = rect[2], h = rect[3];
     if (w < 1 || h < 1 || w > W || h > H) return fail(REDUCE_ERR_SHAPE, "reduce_shift_spline: empty or oversized rect");
     if (N > 65535 || H > 65535) return fail(REDUCE_ERR_UNSUPPORTED, "reduce_shift_spline: N or H above 65535");
-    const size_t need = sizeof(float) * (size_t)N * H * w;
+    const int32_t wp = spline_pitch(w);
+    const size_t need = sizeof(float) * (size_t)N * H * (size_t)wp;
     if (ws_bytes < need)
         return fail(REDUCE_ERR_WORKSPACE, "reduce_shift_spline: workspace needs " + std::to_string(need) + " bytes");
     hipStream_t s = as_stream(stream);
     float *R = static_cast<float *>(ws);
     ProfScope prof("shift_spline", s);
     hipLaunchKernelGGL(spline_rows, dim3((unsigned)ceil_div(w, SP_U), (unsigned)H, (unsigned)N), dim3(SP_N), 0, s, in,
-                       R, W, H, offs, x0, w);
+                       R, W, H, offs, x0, w, wp);
     hipLaunchKernelGGL(spline_cols,
                        dim3((unsigned)ceil_div(w, SPC_C), (unsigned)ceil_div(h, SPC_V * SPC_NT), (unsigned)N),
-                       dim3(SPC_C * SPC_G), 0, s, R, out, H, offs, y0, w, h);
+                       dim3(SPC_C * SPC_G), 0, s, R, out, H, offs, y0, w, wp, h);
     return check_launch("reduce_shift_spline");
 }

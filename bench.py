@@ -91,12 +91,13 @@ KERNEL_SOURCES = {
     "calibrate": ("calibrate.hip", "calibrate_core.h", "common.h"),
     "shift": ("shift.hip", "shift_core.h", "common.h"),
     "combine": ("combine.hip", "combine_core.h"),
+    "combine_deep": ("combine.hip", "combine_core.h"),
     "shift_spline": ("spline.hip", "common.h", "shift_core.h"),
 }
 KERNEL_SYMBOLS = {"batch_score": "batch_score", "batch_shift": "batch_shift", "batch_comb": "batch_comb",
                   "batch_cal": "batch_cal", "score_tiles": "score_tiles", "calibrate": "calibrate_",
                   "shift": "shift_kernel",
-                  "combine": "combine_",
+                  "combine": "combine_cols", "combine_deep": "combine_deep",
                   "shift_spline": ("spline_rows", "spline_cols")}  # one call = both passes
 
 
@@ -391,8 +392,9 @@ def learned_comparison(torch, rd, weights_path, M):
 
 def streaming_wide(torch, rd, reps=5, traffic_path=os.path.join(ROOT, "profiles", "traffic.json")):
     """calibrate, shift (bilinear, and the bicubic spline timed alone) and combine over 16
-    frames of 6144x6160 (working sets of 1.2-2.4 GB,
-    far beyond the 256 MB last-level cache), timed with HIP events on their stream."""
+    frames of 6144x6160 (working sets of 1.2-2.4 GB, far beyond the 256 MB last-level
+    cache), and the combine of a 97-frame stack (the deepest co-adding set of the paper)
+    of 2048x2048, timed with HIP events on their stream."""
     from paper_2008_11486_amd import learned
     N, W, H, bound = 16, 6144, 6160, 64.0
     dev = torch.device("cuda:0")
@@ -426,12 +428,20 @@ def streaming_wide(torch, rd, reps=5, traffic_path=os.path.join(ROOT, "profiles"
     al_spline = torch.empty((N, h, w), dtype=torch.float32, device=dev)
     spline_ws = torch.empty(rd.lib().reduce_shift_spline_ws(W, H, N), dtype=torch.uint8, device=dev)
     out = torch.empty((h, w), dtype=torch.float32, device=dev)
+    # deep stack: aligned values N(1000, 30) with outliers on 0.01% of them
+    ND, SD = 97, 2040
+    deep = 1000.0 + 30.0 * torch.randn((ND, SD, SD), generator=g, device=dev)
+    dh = torch.rand((ND, SD, SD), generator=g, device=dev) < 1e-4
+    deep.add_(dh * (5e3 + 5.5e4 * torch.rand((ND, SD, SD), generator=g, device=dev)))
+    del dh
+    deep_out = torch.empty((SD, SD), dtype=torch.float32, device=dev)
 
     def chain():
         rd.calibrate(raw, dark, flat, out=cal)
         rd.shift(cal, s, rect, out=al)
         rd.combine(al, out=out)
         rd.shift_spline(cal, s, rect, out=al_spline, ws=spline_ws)  # the paper's interpolation, timed alone
+        rd.combine(deep, out=deep_out)
 
     for _ in range(2):
         chain()
@@ -441,17 +451,17 @@ def streaming_wide(torch, rd, reps=5, traffic_path=os.path.join(ROOT, "profiles"
         chain()
     torch.cuda.synchronize()
     res = {"workload": f"{N} frames {W}x{H}, 5000 stars, cosmic-ray hits on 0.01% of pixels, shifts +-64 px, "
-                       f"overlap {w}x{h}"}
+                       f"overlap {w}x{h}; deep combine: {ND} frames {SD}x{SD}"}
     byts = {"calibrate": N * W * H * (2 + 4) + 8 * W * H, "shift": N * w * h * (4 + 4), "combine": N * w * h * 4 + w * h * 4,
             # rows: frame read, row-pass result written; columns: that result read, output written
-            "shift_spline": N * 4 * (H * W + 2 * H * w + h * w)}
-    for name in ("calibrate", "shift", "combine", "shift_spline"):
+            "shift_spline": N * 4 * (H * W + 2 * H * w + h * w), "combine_deep": (ND + 1) * SD * SD * 4}
+    for name in ("calibrate", "shift", "combine", "shift_spline", "combine_deep"):
         ms, n = rd.prof_query(name)
         gbs = byts[name] / (ms / n / 1e3) / 1e9
         res[name] = {"avg_launch_ms": round(ms / n, 4), "bytes": byts[name], "GB/s": round(gbs, 1),
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(traffic_path, name, "wide")}
     rd.prof_enable(False)
-    del raw, cal, al, al_spline, spline_ws
+    del raw, cal, al, al_spline, spline_ws, deep, deep_out
     torch.cuda.empty_cache()
     return res
 

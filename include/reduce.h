@@ -169,7 +169,10 @@ int reduce_shift_spline(const float *in, float *out, int32_t W, int32_t H, int32
  *   aligned  device float [N][h][w];  out device float [h][w]
  *   keep     device uint8 [N][h][w] (1 = kept) or NULL
  *   n_rej    device int64 [1], set to the number of dropped values, or NULL
- * Errors: ksigma <= 0, max_iters < 0 -> RANGE; N > 48 -> UNSUPPORTED. */
+ * Stacks of up to 48 frames hold a pixel's values in registers (or, with the tuned
+ * lanes per column, in an LDS tile); 49 - 128 frames (the paper's co-adding sets
+ * reach 97, Section 3.1.2) in the thread's own slice of LDS.
+ * Errors: ksigma <= 0, max_iters < 0 -> RANGE; N > 128 -> UNSUPPORTED. */
 int reduce_combine(const float *aligned, int32_t w, int32_t h, int32_t N, float ksigma,
                    int32_t max_iters, float *out, uint8_t *keep, int64_t *n_rej, void *stream);
 
@@ -195,7 +198,7 @@ int reduce_combine(const float *aligned, int32_t w, int32_t h, int32_t N, float 
  * descriptors are copied into the workspace at every call (the host image is kept
  * per workspace and rebuilt, after synchronising `stream`, when the descriptors
  * change).  Calls sharing one workspace must not overlap.  Errors: as the stage-wise
- * calls, per stack; N > 48 -> UNSUPPORTED. */
+ * calls, per stack; N > 128 -> UNSUPPORTED. */
 typedef struct {
     const uint16_t *raw;
     int64_t raw_row_pitch, raw_frame_pitch;

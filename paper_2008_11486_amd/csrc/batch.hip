@@ -12,7 +12,7 @@
 //   RECT       common overlap of the stack from its offsets
 //   SHIFT      a 16-row strip of one frame's bilinear shift onto the overlap
 //   COMB*      sigma-clipped mean of a block of pixel columns (one launch per frame-count
-//              class: up to 16, 32 or 48 frames)
+//              class: up to 16, 32, 48, 64 or 128 frames)
 //
 // Each phase is one kernel launch with one workgroup per item over all stacks; the
 // stream orders the phases, so every dependency is met at a kernel boundary and no
@@ -54,9 +54,9 @@ __host__ __device__ inline int64_t al_plane(int64_t w, int64_t h) { return (w * 
 
 enum ItemType : int32_t {
     IT_CAL = 0, IT_MEANPART, IT_MEANFINAL, IT_SCORE, IT_SSCORE, IT_SUM, IT_PICK, IT_RECT, IT_SHIFT, IT_COMB16,
-    IT_COMB32, IT_COMB48
+    IT_COMB32, IT_COMB48, IT_COMBDEEP
 };
-constexpr int N_PHASES = IT_COMB48 + 1;
+constexpr int N_PHASES = IT_COMBDEEP + 1;
 
 struct Item {
     int32_t type, stack, a, pad;
@@ -258,6 +258,25 @@ __global__ __launch_bounds__(COMB_TILE) void batch_comb(BatchArgs a, int32_t fir
     }
 }
 
+// Stacks of 49 - 128 frames: block it.a of 64 pixel columns, values in LDS [N][64]
+// (the launch sizes the tile for the deepest stack).
+__global__ __launch_bounds__(COMB_DEEP_PX) void batch_comb_deep(BatchArgs a, int32_t first)
+{
+    extern __shared__ float tile[];
+    const Item it = a.items[first + blockIdx.x];
+    const StackDev &s = a.stacks[it.stack];
+    const int64_t plane = (int64_t)s.rect[2] * s.rect[3];
+    if (it.a >= ceil_div(plane, (int64_t)COMB_DEEP_PX)) return;  // uniform over the workgroup
+    unsigned dropped = combine_deep_block(s.al, plane, al_plane(s.rect[2], s.rect[3]), s.N, (double)s.ksigma,
+                                                s.max_iters, s.out, nullptr, it.a, tile);
+    if (s.n_rej) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) dropped += __shfl_xor(dropped, off, 64);
+        if (threadIdx.x == 0 && dropped)
+            atomicAdd(reinterpret_cast<unsigned long long *>(s.n_rej), (unsigned long long)dropped);
+    }
+}
+
 __global__ void batch_reset(int64_t *const *n_rej, int32_t n_stacks)
 {
     for (int32_t i = threadIdx.x; i < n_stacks; i += blockDim.x)
@@ -286,6 +305,7 @@ struct BatchLayout {
     int32_t n_items;
     int32_t first[N_PHASES], count[N_PHASES];
     size_t score_lds;
+    int32_t deep_n = 0;  // deepest stack of the deep combine phase
     std::vector<ScoreGroup> groups;
 };
 
@@ -306,7 +326,7 @@ static int validate(const reduce_stack_t *stacks, int32_t n)
         if (s.raw_row_pitch < s.W || s.raw_frame_pitch < s.raw_row_pitch * (int64_t)(s.H - 1) + s.W ||
             s.cal_row_pitch < s.W)
             return fail(REDUCE_ERR_SHAPE, who + ": pitch smaller than the frame");
-        if (s.N > COMB_MAX_N) return fail(REDUCE_ERR_UNSUPPORTED, who + ": N above 48");
+        if (s.N > COMB_MAX_N_COLS) return fail(REDUCE_ERR_UNSUPPORTED, who + ": N above 128");
         if (s.ref_index < 0 || s.ref_index >= s.N) return fail(REDUCE_ERR_RANGE, who + ": ref_index out of range");
         if (s.radius < 0 || s.W - 2 * s.radius < 1 || s.H - 2 * s.radius < 1)
             return fail(REDUCE_ERR_RANGE, who + ": radius leaves no template");
@@ -372,7 +392,10 @@ static BatchLayout layout_of(const reduce_stack_t *stacks, int32_t n)
         const int32_t comb_blocks = (int32_t)ceil_div(fp, (int64_t)COMB_TILE * (vec ? px : 1));
         sl.count[IT_COMB16] = s.N <= 16 ? comb_blocks : 0;
         sl.count[IT_COMB32] = s.N > 16 && s.N <= 32 ? comb_blocks : 0;
-        sl.count[IT_COMB48] = s.N > 32 ? comb_blocks : 0;
+        sl.count[IT_COMB48] = s.N > 32 && s.N <= 48 ? comb_blocks : 0;
+        const int32_t deep_blocks = (int32_t)ceil_div(fp, (int64_t)COMB_DEEP_PX);
+        sl.count[IT_COMBDEEP] = s.N > 48 ? deep_blocks : 0;
+        if (s.N > 48) L.deep_n = std::max(L.deep_n, s.N);
         for (int q = 0; q < N_PHASES; ++q) L.count[q] += sl.count[q];
         if (nreg > 0 && p.K != 0) L.score_lds = std::max(L.score_lds, p.lds);
         L.st.push_back(sl);
@@ -570,6 +593,9 @@ static int launch_phases(int32_t n, void *ws, const BatchLayout &L, hipStream_t 
         if (L.count[IT_COMB48] > 0)
             hipLaunchKernelGGL((batch_comb<48, 1>), dim3(L.count[IT_COMB48]), dim3(COMB_TILE), 0, s, a,
                                L.first[IT_COMB48]);
+        if (L.count[IT_COMBDEEP] > 0)
+            hipLaunchKernelGGL(batch_comb_deep, dim3(L.count[IT_COMBDEEP]), dim3(COMB_DEEP_PX),
+                               sizeof(float) * L.deep_n * COMB_DEEP_PX, s, a, L.first[IT_COMBDEEP]);
     }
     return check_launch("reduce_stack_batch");
 }

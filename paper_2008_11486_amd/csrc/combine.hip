@@ -49,6 +49,21 @@ __global__ __launch_bounds__(COMB_TILE) void combine_cols(
     }
 }
 
+// Stacks of 49 - 128 frames: 64 pixel columns per workgroup, values in LDS [N][64].
+__global__ __launch_bounds__(COMB_DEEP_PX) void combine_deep(
+    const float *__restrict__ aligned, int64_t plane, int32_t N, double ksigma, int32_t max_iters,
+    float *__restrict__ out, uint8_t *__restrict__ keep, unsigned long long *__restrict__ n_rej)
+{
+    extern __shared__ float tile[];
+    unsigned dropped = combine_deep_block(aligned, plane, plane, N, ksigma, max_iters, out, keep,
+                                          (int64_t)blockIdx.x, tile);
+    if (n_rej) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) dropped += __shfl_xor(dropped, off, 64);
+        if (threadIdx.x == 0 && dropped) atomicAdd(n_rej, (unsigned long long)dropped);
+    }
+}
+
 __global__ void zero_u64(unsigned long long *p) { *p = 0ull; }
 
 // Pixel columns per thread of the one-lane kernel (at most 4); REDUCE_COMBINE_PX overrides.
@@ -67,7 +82,7 @@ void combine_dispatch(int lanes, const float *aligned, int64_t plane, int32_t N,
 {
     const unsigned blocks = (unsigned)ceil_div(plane, COMB_TILE);
     const size_t lds = sizeof(float) * (size_t)N * COMB_TILE;
-    ProfScope prof("combine", s);
+    ProfScope prof(N > COMB_MAX_N ? "combine_deep" : "combine", s);
     auto launch = [&](auto Lc, auto Vc) {
         constexpr int L = decltype(Lc)::value, V = decltype(Vc)::value;
         hipLaunchKernelGGL((combine_kernel<L, V>), dim3(blocks), dim3(COMB_TILE), lds, s, aligned, plane, N, ksigma,
@@ -93,8 +108,12 @@ void combine_dispatch(int lanes, const float *aligned, int64_t plane, int32_t N,
         } else if (N <= 32) {
             if (v2 && px >= 2) launch_cols(std::integral_constant<int, 32>{}, std::integral_constant<int, 2>{});
             else launch_cols(std::integral_constant<int, 32>{}, std::integral_constant<int, 1>{});
-        } else {
+        } else if (N <= 48) {
             launch_cols(std::integral_constant<int, 48>{}, std::integral_constant<int, 1>{});
+        } else {
+            hipLaunchKernelGGL(combine_deep, dim3((unsigned)ceil_div(plane, (int64_t)COMB_DEEP_PX)),
+                               dim3(COMB_DEEP_PX), sizeof(float) * N * COMB_DEEP_PX, s, aligned, plane, N, ksigma,
+                               max_iters, out, keep, n_rej);
         }
         break;
     case 2: launch(std::integral_constant<int, 2>{}, std::integral_constant<int, 24>{}); break;
@@ -119,10 +138,12 @@ extern "C" int reduce_combine(const float *aligned, int32_t w, int32_t h, int32_
     if (w < 1 || h < 1 || N < 1) return fail(REDUCE_ERR_SHAPE, "reduce_combine: w, h, N must be >= 1");
     if (!(ksigma > 0.0f) || !std::isfinite(ksigma) || max_iters < 0)
         return fail(REDUCE_ERR_RANGE, "reduce_combine: ksigma must be > 0 and max_iters >= 0");
-    if (N > COMB_MAX_N) return fail(REDUCE_ERR_UNSUPPORTED, "reduce_combine: N above 48");
+    if (N > COMB_MAX_N_COLS) return fail(REDUCE_ERR_UNSUPPORTED, "reduce_combine: N above 128");
     hipStream_t s = as_stream(stream);
     unsigned long long *nr = reinterpret_cast<unsigned long long *>(n_rej);
     if (nr) hipLaunchKernelGGL(zero_u64, dim3(1), dim3(1), 0, s, nr);
-    combine_dispatch(combine_lanes_for(N), aligned, (int64_t)w * h, N, (double)ksigma, max_iters, out, keep, nr, s);
+    // past the LDS tile's depth only the one-lane kernel (column in registers) applies
+    const int lanes = N > COMB_MAX_N ? 1 : combine_lanes_for(N);
+    combine_dispatch(lanes, aligned, (int64_t)w * h, N, (double)ksigma, max_iters, out, keep, nr, s);
     return check_launch("reduce_combine");
 }

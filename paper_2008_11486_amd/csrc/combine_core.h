@@ -10,7 +10,8 @@
 namespace rd {
 
 constexpr int COMB_TILE = 256;
-constexpr int COMB_MAX_N = 48;  // LDS tile [N][256] floats stays within 48 KB
+constexpr int COMB_MAX_N = 48;        // LDS tile [N][256] floats stays within 48 KB
+constexpr int COMB_MAX_N_COLS = 128;  // one lane per column: the column in registers
 
 template <int MAXV>
 struct ClipResult {
@@ -159,63 +160,91 @@ __device__ __forceinline__ unsigned block_sum_u32(unsigned v)
     return t;
 }
 
-// One thread per pixel column, the column's N values in registers straight from
-// HBM (coalesced across the workgroup's 256 adjacent pixels).  The arithmetic is
-// that of clip_column with one lane: sums in frame order in double, m = s / n,
-// q = sum of (x - m)^2, threshold ksigma * sqrt(q / n), drop |x - m| > threshold.
-// Two shortcuts leave every result unchanged: the largest |x - m| of the q pass
-// decides whether the drop pass is needed at all, and when an iteration drops
-// nothing its own sum is the final sum.
-template <int MAXV, bool ALL>
-__device__ __forceinline__ bool kept_at(uint64_t kept, int i, int32_t N)
-{
-    return ALL ? i < N : ((kept >> i) & 1ull) != 0;
-}
+// Kept flags of up to MAXV values, one bit each (i is a compile-time index after
+// unrolling, so the word and the bit are fixed).
+template <int MAXV>
+struct KeptBits {
+    static constexpr int W = (MAXV + 63) / 64;
+    uint64_t w[W];
+    __device__ __forceinline__ bool get(int i) const { return ((w[i >> 6] >> (i & 63)) & 1ull) != 0; }
+    __device__ __forceinline__ void clear(int i) { w[i >> 6] &= ~(1ull << (i & 63)); }
+    __device__ __forceinline__ void first(int32_t N)  // values 0 .. N-1 kept
+    {
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            const int32_t r = N - 64 * j;
+            w[j] = r >= 64 ? ~0ull : r <= 0 ? 0ull : ((1ull << r) - 1ull);
+        }
+    }
+};
 
 template <int MAXV, bool ALL>
-__device__ __forceinline__ void clip_pass(const float (&x)[MAXV], uint64_t kept, int32_t N, int n, double &s,
-                                          double &m, double &q, double &dmax)
+__device__ __forceinline__ bool kept_at(const KeptBits<MAXV> &kept, int i, int32_t N)
 {
+    return ALL ? i < N : kept.get(i);
+}
+
+// One thread per pixel column, the column's values read through x(i) (registers, or
+// the thread's own slice of LDS).  The arithmetic is that of clip_column with one
+// lane: sums in frame order in double, m = s / n, q = sum of (x - m)^2, threshold
+// ksigma * sqrt(q / n), drop |x - m| > threshold.  Two shortcuts leave every result
+// unchanged: the largest |x - m| of the q pass decides whether the drop pass is
+// needed at all, and when an iteration drops nothing its own sum is the final sum.
+// With FENCE a compiler barrier at each pass keeps values read from LDS from being
+// held in registers across passes.
+template <bool FENCE>
+__device__ __forceinline__ void clip_fence()
+{
+    if (FENCE) asm volatile("" ::: "memory");
+}
+
+template <int MAXV, bool ALL, bool FENCE, typename X>
+__device__ __forceinline__ void clip_pass(X x, const KeptBits<MAXV> &kept, int32_t N, int n, double &s, double &m,
+                                          double &q, double &dmax)
+{
+    clip_fence<FENCE>();
     s = 0.0;
 #pragma unroll
     for (int i = 0; i < MAXV; ++i)
-        if (kept_at<MAXV, ALL>(kept, i, N)) s = __dadd_rn(s, (double)x[i]);
+        if (kept_at<MAXV, ALL>(kept, i, N)) s = __dadd_rn(s, (double)x(i));
     m = s / (double)n;
     q = 0.0;
     dmax = 0.0;
+    clip_fence<FENCE>();
 #pragma unroll
     for (int i = 0; i < MAXV; ++i)
         if (kept_at<MAXV, ALL>(kept, i, N)) {
-            const double d = __dsub_rn((double)x[i], m);
+            const double d = __dsub_rn((double)x(i), m);
             q = __dadd_rn(q, __dmul_rn(d, d));
             dmax = fmax(dmax, fabs(d));
         }
 }
 
-// Clip one column held in registers; returns the mean and updates kept / dropped.
-template <int MAXV>
-__device__ __forceinline__ float clip_registers(const float (&x)[MAXV], int32_t N, double ksigma, int32_t max_iters,
-                                                uint64_t &kept, unsigned &dropped)
+// Clip one column; returns the mean and updates kept / dropped.
+template <int MAXV, bool FENCE, typename X>
+__device__ __forceinline__ float clip_values(X x, int32_t N, double ksigma, int32_t max_iters, KeptBits<MAXV> &kept,
+                                             unsigned &dropped)
 {
-    kept = N >= 64 ? ~0ull : ((1ull << N) - 1ull);
+    kept.first(N);
     int n = N;
     double s = 0.0, m = 0.0, q = 0.0, dmax = 0.0;
     bool final_known = false;
     for (int32_t it = 0; it < max_iters; ++it) {
         if (it == 0)
-            clip_pass<MAXV, true>(x, kept, N, n, s, m, q, dmax);
+            clip_pass<MAXV, true, FENCE>(x, kept, N, n, s, m, q, dmax);
         else
-            clip_pass<MAXV, false>(x, kept, N, n, s, m, q, dmax);
+            clip_pass<MAXV, false, FENCE>(x, kept, N, n, s, m, q, dmax);
         const double thr = __dmul_rn(ksigma, sqrt(q / (double)n));
         if (!(dmax > thr)) {
             final_known = true;  // nothing drops: s is the sum over the final set
             break;
         }
         int drop = 0;
+        clip_fence<FENCE>();
 #pragma unroll
         for (int i = 0; i < MAXV; ++i)
-            if (((kept >> i) & 1ull) && fabs(__dsub_rn((double)x[i], m)) > thr) {
-                kept &= ~(1ull << i);
+            if (kept.get(i) && fabs(__dsub_rn((double)x(i), m)) > thr) {
+                kept.clear(i);
                 ++drop;
             }
         n -= drop;
@@ -223,11 +252,19 @@ __device__ __forceinline__ float clip_registers(const float (&x)[MAXV], int32_t 
     }
     if (!final_known) {
         s = 0.0;
+        clip_fence<FENCE>();
 #pragma unroll
         for (int i = 0; i < MAXV; ++i)
-            if ((kept >> i) & 1ull) s = __dadd_rn(s, (double)x[i]);
+            if (kept.get(i)) s = __dadd_rn(s, (double)x(i));
     }
     return (float)(s / (double)n);
+}
+
+template <int MAXV>
+__device__ __forceinline__ float clip_registers(const float (&x)[MAXV], int32_t N, double ksigma, int32_t max_iters,
+                                                KeptBits<MAXV> &kept, unsigned &dropped)
+{
+    return clip_values<MAXV, false>([&](int i) { return x[i]; }, N, ksigma, max_iters, kept, dropped);
 }
 
 // PX adjacent pixel columns per thread: each frame's PX values come in as one vector
@@ -274,7 +311,7 @@ __device__ __forceinline__ unsigned combine_cols_block(const float *__restrict__
     }
     unsigned dropped = 0;
     float res[PX];
-    uint64_t kept[PX];
+    KeptBits<MAXV> kept[PX];
 #pragma unroll
     for (int c = 0; c < PX; ++c) {
         unsigned d = 0;
@@ -297,8 +334,92 @@ __device__ __forceinline__ unsigned combine_cols_block(const float *__restrict__
             if (i < N)
 #pragma unroll
                 for (int c = 0; c < PX; ++c)
-                    if (p0 + c < plane) keep[(int64_t)i * plane + p0 + c] = (uint8_t)((kept[c] >> i) & 1ull);
+                    if (p0 + c < plane) keep[(int64_t)i * plane + p0 + c] = (uint8_t)kept[c].get(i);
     }
+    return dropped;
+}
+
+// Stacks deeper than a register column: a 64-thread workgroup, one thread per pixel
+// column, whose N values wait in the thread's own slice of an LDS tile [N][64] (each
+// thread writes and reads only its own column, so no barrier is needed).  The frames
+// come in batches of 32 loads in flight; the passes loop over the frames at run time
+// with the kept flags in two 64-bit words.  Same arithmetic, in the same order, as
+// clip_values (sums over the kept values in frame order, m = s / n, the squared
+// deviations and the largest one, the threshold, the drops).
+constexpr int COMB_DEEP_PX = 64;
+constexpr int COMB_DEEP_BATCH = 64;  // the most loads a wave keeps in flight
+
+// f(i, x_i, kept_i) for the values of a column in frame order (f selects rather than
+// branches on kept_i); the kept flags are bit i of k0 (i < 64) and bit i - 64 of k1.
+template <typename F>
+__device__ __forceinline__ void deep_each(const float *col, uint64_t k0, uint64_t k1, int32_t N, F f)
+{
+    uint64_t w = k0;
+    const int32_t n0 = min(N, 64);
+#pragma unroll 4
+    for (int i = 0; i < n0; ++i, w >>= 1) f(i, (double)col[i * COMB_DEEP_PX], (w & 1ull) != 0);
+    w = k1;
+#pragma unroll 4
+    for (int i = 64; i < N; ++i, w >>= 1) f(i, (double)col[i * COMB_DEEP_PX], (w & 1ull) != 0);
+}
+
+__device__ __forceinline__ unsigned combine_deep_block(const float *__restrict__ aligned, int64_t plane,
+                                                       int64_t pstride, int32_t N, double ksigma, int32_t max_iters,
+                                                       float *__restrict__ out, uint8_t *__restrict__ keep,
+                                                       int64_t block, float *tile)
+{
+    const int t = threadIdx.x;
+    const int64_t p = block * COMB_DEEP_PX + t;
+    const float *src = aligned + (p < plane ? p : plane - 1);
+    float *col = tile + t;
+    for (int32_t i0 = 0; i0 < N; i0 += COMB_DEEP_BATCH) {
+        float v[COMB_DEEP_BATCH];
+#pragma unroll
+        for (int j = 0; j < COMB_DEEP_BATCH; ++j) v[j] = src[(int64_t)min(i0 + j, N - 1) * pstride];
+#pragma unroll
+        for (int j = 0; j < COMB_DEEP_BATCH; ++j)
+            if (i0 + j < N) col[(i0 + j) * COMB_DEEP_PX] = v[j];
+    }
+    uint64_t k0 = N >= 64 ? ~0ull : ((1ull << N) - 1ull);
+    uint64_t k1 = N >= 128 ? ~0ull : N <= 64 ? 0ull : ((1ull << (N - 64)) - 1ull);
+    int n = N;
+    unsigned dropped = 0;
+    // the drop pass of one iteration also forms the next sum (the same values in the
+    // same order as a separate pass over the kept set)
+    double s = 0.0;
+    deep_each(col, k0, k1, N, [&](int, double x, bool k) { s = k ? __dadd_rn(s, x) : s; });
+    for (int32_t it = 0; it < max_iters; ++it) {
+        const double m = s / (double)n;
+        double q = 0.0, dmax = 0.0;
+        deep_each(col, k0, k1, N, [&](int, double x, bool k) {
+            const double d = __dsub_rn(x, m);
+            q = k ? __dadd_rn(q, __dmul_rn(d, d)) : q;
+            dmax = k ? fmax(dmax, fabs(d)) : dmax;
+        });
+        const double thr = __dmul_rn(ksigma, sqrt(q / (double)n));
+        if (!(dmax > thr)) break;  // nothing drops: s is the sum over the final set
+        int drop = 0;
+        s = 0.0;
+        uint64_t n0 = 0, n1 = 0;  // the flags after this iteration
+        deep_each(col, k0, k1, N, [&](int i, double x, bool k) {
+            const bool out = k && fabs(__dsub_rn(x, m)) > thr;
+            const bool stay = k && !out;
+            drop += out ? 1 : 0;
+            s = stay ? __dadd_rn(s, x) : s;
+            const uint64_t bit = stay ? 1ull : 0ull;
+            if (i < 64) n0 |= bit << i;
+            else n1 |= bit << (i - 64);
+        });
+        k0 = n0;
+        k1 = n1;
+        n -= drop;
+        dropped += (unsigned)drop;
+    }
+    if (p >= plane) return 0u;
+    out[p] = (float)(s / (double)n);
+    if (keep)
+        for (int i = 0; i < N; ++i)
+            keep[(int64_t)i * plane + p] = (uint8_t)((((i < 64 ? k0 : k1) >> (i & 63)) & 1ull) != 0);
     return dropped;
 }
 

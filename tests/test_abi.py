@@ -46,7 +46,7 @@ def test_null_and_shape_errors_before_launch(rd):
     assert L.reduce_calibrate(b, 4, 64, b, b, 8, b, 8, 8, 1, None) == rd.ERR_SHAPE
     assert b"pitch" in L.reduce_last_error()
     assert L.reduce_combine(b, 4, 4, 3, ctypes.c_float(0.0), 3, b, None, None, None) == rd.ERR_RANGE
-    assert L.reduce_combine(b, 4, 4, 49, ctypes.c_float(3.0), 3, b, None, None, None) == rd.ERR_UNSUPPORTED
+    assert L.reduce_combine(b, 4, 4, 129, ctypes.c_float(3.0), 3, b, None, None, None) == rd.ERR_UNSUPPORTED
     assert L.reduce_register(b, b, 32, 32, 1, -1, 2, None, None, b, None, b, 1 << 20, None) == rd.ERR_RANGE
     assert L.reduce_register(b, b, 32, 32, 1, 2, 2, None, None, b, None, b, 8, None) == rd.ERR_WORKSPACE
     r = (ctypes.c_int32 * 4)(0, 0, 0, 5)

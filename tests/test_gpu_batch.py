@@ -124,6 +124,33 @@ def test_batch_workload1_three_bands(rd):
         assert err.max() < 0.1
 
 
+def test_batch_deep_stacks(rd, orc):
+    """Stacks of 60 and 97 frames (the paper's co-adding sets reach 97) beside a short
+    one in one call: bit-identical to the stage-wise chain, and the 97-frame stack
+    against the oracle end to end."""
+    specs = [(97, 96, 80, 3, True), (60, 112, 72, 4, True), (10, 64, 64, 2, False)]
+    stacks = [_make(20 + i, N, W, H, R, cos, seed=4) for i, (N, W, H, R, cos) in enumerate(specs)]
+    dev = [(to_dev(st.raw), to_dev(st.dark), to_dev(st.flat), sp[3]) for st, sp in zip(stacks, specs)]
+    batch = rd.StackBatch(dev)
+    batch.run()
+    for i, (raw, dark, flat, R) in enumerate(dev):
+        img, rect, offs, nrej = batch.result(i)
+        ref_img, ref_rect, ref_offs, ref_nrej = stagewise(rd, raw, dark, flat, R)
+        assert np.array_equal(rect, ref_rect) and np.array_equal(img.cpu().numpy(), ref_img), i
+        assert offs.tobytes() == ref_offs.tobytes() and nrej == ref_nrej, i
+    assert batch.result(0)[3] > 0 and batch.result(1)[3] > 0
+    img, rect, offs, _ = batch.result(0)
+    st = stacks[0]
+    o = orc.reduce_stack(st.raw, st.dark, st.flat, specs[0][3])
+    assert np.array_equal(offs["dx"][1:], o["offsets"]["dx"][1:]) and np.array_equal(offs["dy"][1:], o["offsets"]["dy"][1:])
+    s = np.stack([offs["sx"], offs["sy"]], 1).astype(np.float32)
+    assert np.array_equal(rect, o["rect"])
+    if np.array_equal(s, o["s"]):
+        e = rel_err(img.cpu().numpy(), o["out"])[~o["near"].any(axis=0)]  # A11's band aside
+        print("97-frame batch vs oracle:", err_summary(e))
+        assert e.max() <= TOL
+
+
 def test_batch_rejects_bad_stacks(rd):
     st = _make(4, 5, 128, 96, 4, False, seed=6)
     raw = to_dev(st.raw)

@@ -218,6 +218,27 @@ def test_combine_parity_with_outliers(rd, orc, N, lanes):
         assert nrej == 0
 
 
+@pytest.mark.parametrize("N", [49, 64, 65, 97, 128])
+def test_combine_parity_deep_stacks(rd, orc, N):
+    """Stacks past the LDS tile's depth (the paper's sets reach 97 frames): the one-lane
+    path with the column in LDS, across a ragged last block of 64 pixels."""
+    rng = np.random.default_rng(7000 + N)
+    h, w = 23, 171
+    vals = rng.normal(1000, 30, size=(N, h, w)).astype(np.float32)
+    hits = rng.random(size=vals.shape) < 0.02
+    vals[hits] += rng.uniform(5e3, 6e4, size=hits.sum()).astype(np.float32)
+    flips, nrej, e = _combine_check(rd, orc, vals)
+    print(f"combine N={N}: rejected {nrej}, mask flips {flips}, {err_summary(e)}")
+    assert nrej > 0
+    for iters in (0, 1, 2, 5):
+        _combine_check(rd, orc, vals[:, :4, :70].copy(), iters=iters)
+    one = np.full((N, 1, 5), 1234.5, np.float32)
+    one[N - 1, 0, 2] = 1.0e5  # the last frame's value sits in the second kept word
+    out, keep, nr = rd.combine(to_dev(one), want_keep=True, want_nrej=True)
+    assert np.array_equal(out.cpu().numpy(), np.full((1, 5), 1234.5, np.float32))
+    assert int(nr.cpu()[0]) == 1 and keep.cpu().numpy()[N - 1, 0, 2] == 0 and keep.cpu().numpy().sum() == 5 * N - 1
+
+
 def test_combine_closed_forms(rd, orc):
     col = np.full((16, 1, 3), 1234.5, np.float32)
     col[7, 0, 1] = 1.0e5

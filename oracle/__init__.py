@@ -76,11 +76,11 @@ def lib() -> ctypes.CDLL:
 def _declare(L: ctypes.CDLL) -> None:
     P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     L.oracle_num_threads.restype = ctypes.c_int
-    L.oracle_calibrate.argtypes = [P, I64, I64, P, P, I64, P, I32, I32, I32]
+    L.oracle_calibrate.argtypes = [P, I64, I64, P, P, P, I64, P, I32, I32, I32]
     L.oracle_register.argtypes = [P, P, I32, I32, I32, I32, I32, P, P, P, P]
     L.oracle_valid_rect.argtypes = [P, I32, I32, I32, P]
-    L.oracle_shift.argtypes = [P, P, I32, I32, I32, P, P]
-    L.oracle_combine.argtypes = [P, I32, I32, I32, D, I32, P, P, P, P, D]
+    L.oracle_shift.argtypes = [P, P, I32, I32, I32, P, P, P]
+    L.oracle_combine.argtypes = [P, I32, I32, I32, D, I32, P, P, P, P, D, I32]
     L.oracle_downsample4.argtypes = [P, I32, I32, P]
     L.oracle_cnn_input.argtypes = [P, I32, I32, P]
     for name in ("oracle_calibrate", "oracle_register", "oracle_valid_rect", "oracle_shift",
@@ -121,8 +121,8 @@ def num_threads() -> int:
     return int(lib().oracle_num_threads())
 
 
-def calibrate(raw: np.ndarray, dark: np.ndarray, flat: np.ndarray) -> np.ndarray:
-    """raw uint16 [N][H][W] (any row/frame pitch via a view), dark/flat [H][W]."""
+def calibrate(raw: np.ndarray, dark: np.ndarray, flat: np.ndarray, bias: Optional[np.ndarray] = None) -> np.ndarray:
+    """raw uint16 [N][H][W] (any row/frame pitch via a view), bias (or None)/dark/flat [H][W]."""
     raw = np.asarray(raw)
     if raw.ndim == 2:
         raw = raw[None]
@@ -130,13 +130,15 @@ def calibrate(raw: np.ndarray, dark: np.ndarray, flat: np.ndarray) -> np.ndarray
     N, H, W = raw.shape
     if raw.strides[2] != 2 or raw.strides[1] < 0 or raw.strides[0] < raw.strides[1] * H:
         raw = np.ascontiguousarray(raw)  # the C side takes nested row and frame pitches
-    dark = np.asarray(dark, dtype=np.float64)
-    flat = np.asarray(flat, dtype=np.float64)
-    if dark.strides[1] != 8 or flat.strides != dark.strides:
-        dark, flat = np.ascontiguousarray(dark), np.ascontiguousarray(flat)
+    dark = np.ascontiguousarray(dark, dtype=np.float64)
+    flat = np.ascontiguousarray(flat, dtype=np.float64)
+    b = None if bias is None else np.ascontiguousarray(bias, dtype=np.float64)
+    if b is not None:
+        assert b.shape == dark.shape
     out = np.empty((N, H, W), dtype=np.float64)
     _check(lib().oracle_calibrate(_p(raw), raw.strides[1] // 2, raw.strides[0] // 2,
-                                  _p(dark), _p(flat), dark.strides[0] // 8, _p(out), W, H, N),
+                                  None if b is None else _p(b), _p(dark), _p(flat), dark.strides[0] // 8,
+                                  _p(out), W, H, N),
            "oracle_calibrate")
     return out
 
@@ -168,7 +170,8 @@ def valid_rect(offs: np.ndarray, W: int, H: int) -> np.ndarray:
     return rect
 
 
-def shift(frames: np.ndarray, offs: np.ndarray, rect) -> np.ndarray:
+def shift(frames: np.ndarray, offs: np.ndarray, rect, mask: Optional[np.ndarray] = None) -> np.ndarray:
+    """Bilinear shift; mask: bad-pixel map uint8 [H][W] (nonzero = bad) or None."""
     frames = _f64(frames)
     if frames.ndim == 2:
         frames = frames[None]
@@ -176,13 +179,18 @@ def shift(frames: np.ndarray, offs: np.ndarray, rect) -> np.ndarray:
     o = np.ascontiguousarray(offs, dtype=np.float32).reshape(N, 2)
     r = np.ascontiguousarray(rect, dtype=np.int32).reshape(4)
     out = np.empty((N, int(r[3]), int(r[2])), dtype=np.float64)
-    _check(lib().oracle_shift(_p(frames), _p(out), W, H, N, _p(o), _p(r)), "oracle_shift")
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    if m is not None:
+        assert m.shape == (H, W)
+    _check(lib().oracle_shift(_p(frames), _p(out), W, H, N, _p(o), _p(r), None if m is None else _p(m)),
+           "oracle_shift")
     return out
 
 
 def combine(aligned: np.ndarray, ksigma: float = 3.0, max_iters: int = 3,
-            rel_band: float = 1e-6):
-    """Returns (out [h][w], keep uint8 [N][h][w], n_rejected, near uint8 [N][h][w])."""
+            rel_band: float = 1e-6, missing: bool = False):
+    """Returns (out [h][w], keep uint8 [N][h][w], n_rejected, near uint8 [N][h][w]); with
+    missing, NaN values are left out (never kept, not counted as rejected)."""
     a = _f64(aligned)
     if a.ndim == 1:
         a = a.reshape(-1, 1, 1)
@@ -192,7 +200,7 @@ def combine(aligned: np.ndarray, ksigma: float = 3.0, max_iters: int = 3,
     near = np.empty((N, h, w), dtype=np.uint8)
     nrej = np.zeros(1, dtype=np.int64)
     _check(lib().oracle_combine(_p(a), w, h, N, float(ksigma), int(max_iters), _p(out), _p(keep),
-                                _p(nrej), _p(near), float(rel_band)), "oracle_combine")
+                                _p(nrej), _p(near), float(rel_band), 1 if missing else 0), "oracle_combine")
     return out, keep, int(nrej[0]), near
 
 
@@ -292,17 +300,19 @@ def cnn_loss_backward(x: np.ndarray, params: np.ndarray, target: np.ndarray, hub
 
 def reduce_stack(raw: np.ndarray, dark: np.ndarray, flat: np.ndarray, radius: int,
                  ref_index: int = 0, ksigma: float = 3.0, max_iters: int = 3,
-                 integer_mode: bool = False):
-    """End-to-end chain from raw: calibrate, register to frame ref_index, shift, combine."""
-    cal = calibrate(raw, dark, flat)
+                 integer_mode: bool = False, bias: Optional[np.ndarray] = None,
+                 mask: Optional[np.ndarray] = None):
+    """End-to-end chain from raw: calibrate, register to frame ref_index, shift, combine
+    (with a bad-pixel mask, the outputs that read a bad pixel are missing in combine)."""
+    cal = calibrate(raw, dark, flat, bias)
     offs = register(cal[ref_index], cal, radius)
     s = np.stack([offs["sx"], offs["sy"]], axis=1).astype(np.float32)
     if integer_mode:
         s = np.stack([offs["dx"], offs["dy"]], axis=1).astype(np.float32)
     s[ref_index] = 0.0
     rect = valid_rect(s, raw.shape[2], raw.shape[1])
-    al = shift(cal, s, rect)
-    out, keep, nrej, near = combine(al, ksigma, max_iters)
+    al = shift(cal, s, rect, mask)
+    out, keep, nrej, near = combine(al, ksigma, max_iters, missing=mask is not None)
     return dict(cal=cal, offsets=offs, s=s, rect=rect, aligned=al, out=out, keep=keep,
                 n_rej=nrej, near=near)
 

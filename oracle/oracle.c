@@ -30,12 +30,12 @@ int oracle_num_threads(void)
 }
 
 /* ------------------------------------------------------------------------------
- * Calibration (Section 2.1 and 2.2: dark subtraction and flat fielding after the
- * 16-bit to floating-point cast).  The master dark is taken to contain the bias
- * and the flat to be normalised already.
+ * Calibration (Section 2.1 and 2.2: the 16-bit to floating-point cast at the bias
+ * subtraction, then dark subtraction and flat fielding).  Without a bias frame the
+ * master dark is taken to contain the bias; the flat is normalised already.
  * ---------------------------------------------------------------------------- */
 int oracle_calibrate(const uint16_t *raw, int64_t raw_row_pitch, int64_t raw_frame_pitch,
-                     const double *dark, const double *flat, int64_t cal_row_pitch,
+                     const double *bias, const double *dark, const double *flat, int64_t cal_row_pitch,
                      double *out, int32_t W, int32_t H, int32_t N)
 {
     if (!raw || !dark || !flat || !out) return O_NULL;
@@ -47,6 +47,7 @@ int oracle_calibrate(const uint16_t *raw, int64_t raw_row_pitch, int64_t raw_fra
         for (int32_t y = 0; y < H; ++y)
             for (int32_t x = 0; x < W; ++x) {
                 double r = (double)raw[(int64_t)k * raw_frame_pitch + (int64_t)y * raw_row_pitch + x];
+                if (bias) r = r - bias[(int64_t)y * cal_row_pitch + x];
                 double d = dark[(int64_t)y * cal_row_pitch + x];
                 double f = flat[(int64_t)y * cal_row_pitch + x];
                 out[((int64_t)k * H + y) * W + x] = (r - d) / f;
@@ -216,7 +217,7 @@ int oracle_valid_rect(const float *offs, int32_t N, int32_t W, int32_t H, int32_
  * weight is zero has its index clamped so that it never leaves the frame.
  * ---------------------------------------------------------------------------- */
 int oracle_shift(const double *in, double *out, int32_t W, int32_t H, int32_t N,
-                 const float *offs, const int32_t *rect)
+                 const float *offs, const int32_t *rect, const uint8_t *mask)
 {
     if (!in || !out || !offs || !rect) return O_NULL;
     if (W < 1 || H < 1 || N < 1) return O_SHAPE;
@@ -245,9 +246,13 @@ int oracle_shift(const double *in, double *out, int32_t W, int32_t H, int32_t N,
                 const int32_t i1 = (a > 0.0) ? i + 1 : i;
                 const double f00 = f[(int64_t)j * W + i], f10 = f[(int64_t)j * W + i1];
                 const double f01 = f[(int64_t)j1 * W + i], f11 = f[(int64_t)j1 * W + i1];
-                out[((int64_t)k * h + v) * w + u] =
-                    (1.0 - a) * (1.0 - b) * f00 + a * (1.0 - b) * f10 +
-                    (1.0 - a) * b * f01 + a * b * f11;
+                double val = (1.0 - a) * (1.0 - b) * f00 + a * (1.0 - b) * f10 +
+                             (1.0 - a) * b * f01 + a * b * f11;
+                /* bad-pixel masking: an output that reads a bad pixel is missing */
+                if (mask && (mask[(int64_t)j * W + i] || mask[(int64_t)j * W + i1] ||
+                             mask[(int64_t)j1 * W + i] || mask[(int64_t)j1 * W + i1]))
+                    val = NAN;
+                out[((int64_t)k * h + v) * w + u] = val;
             }
         }
     return O_OK;
@@ -262,7 +267,7 @@ int oracle_shift(const double *in, double *out, int32_t W, int32_t H, int32_t N,
  * ---------------------------------------------------------------------------- */
 int oracle_combine(const double *aligned, int32_t w, int32_t h, int32_t N, double ksigma,
                    int32_t max_iters, double *out, uint8_t *keep, int64_t *n_rej,
-                   uint8_t *near, double rel_band)
+                   uint8_t *near, double rel_band, int32_t missing)
 {
     if (!aligned || !out) return O_NULL;
     if (w < 1 || h < 1 || N < 1 || N > 4096) return O_SHAPE;
@@ -273,8 +278,12 @@ int oracle_combine(const double *aligned, int32_t w, int32_t h, int32_t N, doubl
     for (int64_t p = 0; p < plane; ++p) {
         uint8_t kept[4096];
         uint8_t close[4096];
-        int32_t nk = N;
-        for (int32_t k = 0; k < N; ++k) { kept[k] = 1; close[k] = 0; }
+        int32_t nk = 0;
+        for (int32_t k = 0; k < N; ++k) {
+            kept[k] = !(missing && isnan(aligned[k * plane + p]));
+            nk += kept[k];
+            close[k] = 0;
+        }
         for (int32_t it = 0; it < max_iters; ++it) {
             double s = 0.0;
             for (int32_t k = 0; k < N; ++k)

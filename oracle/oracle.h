@@ -38,11 +38,12 @@ typedef struct {
 
 int oracle_num_threads(void);
 
-/* out[k][y][x] = (raw[k][y][x] - dark[y][x]) / flat[y][x] in double.  raw has row
- * pitch raw_row_pitch and frame pitch raw_frame_pitch (elements); dark and flat
- * have row pitch cal_row_pitch; out is dense [N][H][W]. */
+/* out[k][y][x] = ((raw[k][y][x] - bias[y][x]) - dark[y][x]) / flat[y][x] in double
+ * (bias may be NULL: no bias term).  raw has row pitch raw_row_pitch and frame pitch
+ * raw_frame_pitch (elements); bias, dark and flat have row pitch cal_row_pitch; out is
+ * dense [N][H][W]. */
 int oracle_calibrate(const uint16_t *raw, int64_t raw_row_pitch, int64_t raw_frame_pitch,
-                     const double *dark, const double *flat, int64_t cal_row_pitch,
+                     const double *bias, const double *dark, const double *flat, int64_t cal_row_pitch,
                      double *out, int32_t W, int32_t H, int32_t N);
 
 /* Register every frame against ref over the window [c-R, c+R]^2 clipped to
@@ -57,16 +58,20 @@ int oracle_register(const double *ref, const double *frames, int32_t W, int32_t 
  * for y.  rect = {x0, y0, w, h}.  Returns 3 if the overlap is empty. */
 int oracle_valid_rect(const float *offs, int32_t N, int32_t W, int32_t H, int32_t *rect);
 
-/* Bilinear resample: out[k][v][u] = f_k(x0+u+sx_k, y0+v+sy_k) over rect. */
+/* Bilinear resample: out[k][v][u] = f_k(x0+u+sx_k, y0+v+sy_k) over rect.  mask (may
+ * be NULL) is a bad-pixel map [H][W] shared by the frames: an output one of whose taps
+ * is a bad pixel is NaN (missing). */
 int oracle_shift(const double *in, double *out, int32_t W, int32_t H, int32_t N,
-                 const float *offs, const int32_t *rect);
+                 const float *offs, const int32_t *rect, const uint8_t *mask);
 
 /* Sigma-clipped mean along the frame axis.  keep and near may be NULL: near marks
  * values whose distance from the mean lay within rel_band * k*sigma of the
- * threshold at some iteration in which they were tested. */
+ * threshold at some iteration in which they were tested.  With missing != 0 NaN
+ * values are missing: never kept, not counted as rejected, and n is the number of
+ * the pixel's other values (a pixel without any gives NaN). */
 int oracle_combine(const double *aligned, int32_t w, int32_t h, int32_t N, double ksigma,
                    int32_t max_iters, double *out, uint8_t *keep, int64_t *n_rej,
-                   uint8_t *near, double rel_band);
+                   uint8_t *near, double rel_band, int32_t missing);
 
 /* 4x4 block mean: out[j][i] = mean of in[4j..4j+3][4i..4i+3]. */
 int oracle_downsample4(const double *in, int32_t W, int32_t H, double *out);

@@ -430,3 +430,82 @@ def test_combine_golden_closed_forms(orc):
         assert nrej == mask.count("0")
         n += 1
     assert n == 5
+
+
+# ----------------------------------------------------------------------------- bias, bad pixels
+def test_calibrate_bias_then_dark_then_flat(orc):
+    """Section 2.1's order: the cast at the bias subtraction, then dark, then flat.  With
+    integer bias, dark and signal and a power-of-two flat every step is exact."""
+    rng = np.random.default_rng(81)
+    N, H, W = 3, 9, 13
+    bias = rng.integers(200, 400, size=(H, W)).astype(np.float32)
+    dark = rng.integers(10, 90, size=(H, W)).astype(np.float32)
+    flat = rng.choice([0.5, 1.0, 2.0], size=(H, W)).astype(np.float32)
+    S = 2 * rng.integers(0, 10000, size=(N, H, W))  # flat * S is an integer
+    raw = (bias + dark + flat * S).astype(np.uint16)
+    assert np.array_equal(orc.calibrate(raw, dark, flat, bias=bias), S.astype(np.float64))
+    # without a bias frame, a dark that carries the bias gives the same frames
+    assert np.array_equal(orc.calibrate(raw, dark + bias, flat), S.astype(np.float64))
+
+
+@pytest.mark.parametrize("s", [(0.0, 0.0), (3.0, -2.0), (0.25, 0.0), (0.0, -0.75), (1.5, 2.25)])
+def test_shift_bad_pixel_reaches_exactly_its_taps(orc, s):
+    """A bad pixel at (px, py) makes missing exactly the outputs whose bilinear taps
+    include it: columns i with px in {i, i + 1 if the x fraction is non-zero}, rows
+    likewise; every other output equals the unmasked shift."""
+    rng = np.random.default_rng(82)
+    H, W = 24, 30
+    f = rng.normal(1000, 20, size=(1, H, W))
+    mask = np.zeros((H, W), np.uint8)
+    px, py = 14, 11
+    mask[py, px] = 1
+    offs = np.array([s], np.float32)
+    rect = orc.valid_rect(offs, W, H)
+    x0, y0, w, h = (int(v) for v in rect)
+    got = orc.shift(f, offs, rect, mask)[0]
+    plain = orc.shift(f, offs, rect)[0]
+    fx, fy = np.floor(s[0]), np.floor(s[1])
+    cols = {px - (x0 + int(fx))} | ({px - 1 - (x0 + int(fx))} if s[0] != fx else set())
+    rows = {py - (y0 + int(fy))} | ({py - 1 - (y0 + int(fy))} if s[1] != fy else set())
+    want = np.zeros((h, w), bool)
+    for v in rows:
+        for u in cols:
+            if 0 <= v < h and 0 <= u < w:
+                want[v, u] = True
+    assert np.array_equal(np.isnan(got), want)
+    assert want.sum() == len(rows) * len(cols)
+    assert np.array_equal(got[~want], plain[~want])
+
+
+def test_combine_missing_values_are_left_out(orc):
+    """NaN values are missing: the clip runs over the other values of the pixel.  Pinned
+    against numpy's nanmean where no clip can reject (n <= 10, A10), against
+    scipy.stats.sigmaclip of the remaining values, and all-missing pixels give NaN."""
+    rng = np.random.default_rng(83)
+    N, h, w = 24, 6, 50
+    vals = rng.normal(1000, 10, size=(N, h, w))
+    hits = rng.random(size=vals.shape) < 0.05
+    vals[hits] += rng.uniform(500, 5e4, size=hits.sum())
+    miss = rng.random(size=vals.shape) < 0.3
+    miss[:, 0, 0] = True                      # a pixel without any value
+    miss[:, 0, 1] = True
+    miss[:7, 0, 1] = False                    # a pixel with 7 values: a plain mean
+    vals[miss] = np.nan
+    out, keep, nrej, _ = orc.combine(vals, max_iters=1000, missing=True)
+    assert np.isnan(out[0, 0]) and not keep[:, 0, 0].any()
+    assert out[0, 1] == pytest.approx(np.nanmean(vals[:, 0, 1]), rel=1e-15)
+    assert not keep[miss].any()
+    total = 0
+    for y in range(h):
+        for x in range(w):
+            if (y, x) in ((0, 0), (0, 1)):
+                continue
+            col = vals[:, y, x]
+            c, _, _ = scipy.stats.sigmaclip(col[~np.isnan(col)], 3, 3)
+            assert keep[:, y, x].sum() == c.size
+            assert out[y, x] == pytest.approx(c.mean(), rel=1e-13)
+            total += int((~np.isnan(col)).sum()) - c.size
+    assert nrej == total > 0
+    # without the missing rule a NaN poisons its pixel, as IEEE arithmetic does
+    out2, _, _, _ = orc.combine(vals[:, :2, :3], missing=False)
+    assert np.isnan(out2).all()

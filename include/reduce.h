@@ -74,19 +74,19 @@ int reduce_prof_enable(int on);
 int reduce_prof_query(const char *kernel, double *total_ms, int64_t *launches);
 
 /* ---- calibrate ------------------------------------------------------------
- * Dark subtraction and flat fielding after the 16-bit to float cast (Section 2.1,
- * "bias subtraction, dark subtraction, flat fielding"; Section 2.2).  For every
- * frame k:  out[k][y][x] = (float(raw[k][y][x]) - dark[y][x]) / flat[y][x]  in
- * IEEE single precision with a correctly rounded division.  The master dark is
- * taken to include the bias.
+ * Bias subtraction (where the 16-bit to float cast happens), dark subtraction and
+ * flat fielding (Section 2.1; Section 2.2).  For every frame k:
+ *   out[k][y][x] = ((float(raw[k][y][x]) - bias[y][x]) - dark[y][x]) / flat[y][x]
+ * in IEEE single precision, each step correctly rounded.  bias may be NULL: then
+ * out = (float(raw) - dark) / flat, the master dark carrying the bias.
  *   raw    device uint16, frame k row y at raw + k*raw_frame_pitch + y*raw_row_pitch
  *          (a pitch larger than W expresses the overscan cut of Section 2.1 as a
  *          zero-copy region of interest)
- *   dark, flat  device float [H] rows of pitch cal_row_pitch
+ *   bias, dark, flat  device float [H] rows of pitch cal_row_pitch (bias may be NULL)
  *   out    device float, dense [N][H][W]
  * Errors: NULL -> REDUCE_ERR_NULL; W, H, N < 1 or pitches too small -> SHAPE. */
 int reduce_calibrate(const uint16_t *raw, int64_t raw_row_pitch, int64_t raw_frame_pitch,
-                     const float *dark, const float *flat, int64_t cal_row_pitch,
+                     const float *bias, const float *dark, const float *flat, int64_t cal_row_pitch,
                      float *out, int32_t W, int32_t H, int32_t N, void *stream);
 
 /* ---- register -------------------------------------------------------------
@@ -142,6 +142,21 @@ int reduce_valid_rect(const float *offs, int32_t N, int32_t W, int32_t H, int32_
 int reduce_shift(const float *in, float *out, int32_t W, int32_t H, int32_t N,
                  const float *offs, const int32_t *rect, int32_t integer_mode, void *stream);
 
+/* ---- bad-pixel masking ------------------------------------------------------------
+ * Bad-pixel masking (Section 2.1 lists it between flat fielding and alignment; the
+ * method is not given): mask [H][W] uint8 is the detector's bad-pixel map shared by
+ * the N frames (nonzero = bad).  After reduce_shift with the same offs, rect and
+ * integer_mode, every aligned value whose bilinear taps (rows j and j+1 when the y
+ * fraction is non-zero, columns i and i+1 when the x fraction is non-zero; the one
+ * copied pixel in integer mode) include a bad pixel is set to NaN in out, for the
+ * missing-value combine (reduce_combine with missing = 1).
+ *   mask  device uint8 [H][W];  out  device float dense [N][h][w] (reduce_shift's output)
+ *   offs  device float [N][2];  rect host int32 {x0, y0, w, h}
+ * Errors: NULL -> NULL; empty or oversized rect -> SHAPE; N or h above 65535 ->
+ * UNSUPPORTED. */
+int reduce_mask_shifted(const uint8_t *mask, float *out, int32_t W, int32_t H, int32_t N,
+                        const float *offs, const int32_t *rect, int32_t integer_mode, void *stream);
+
 /* ---- bicubic-spline shift ---------------------------------------------------------
  * The paper's own interpolation (Sections 2.1, 2.2; Section 3.2.1 prices its
  * tridiagonal system per image row or column): out[k][v][u] = S_k(x0 + u + sx_k,
@@ -172,9 +187,13 @@ int reduce_shift_spline(const float *in, float *out, int32_t W, int32_t H, int32
  * Stacks of up to 48 frames hold a pixel's values in registers (or, with the tuned
  * lanes per column, in an LDS tile); 49 - 128 frames (the paper's co-adding sets
  * reach 97, Section 3.1.2) in the thread's own slice of LDS.
+ * missing != 0: NaN values (bad pixels, see reduce_mask_shifted) are missing: never
+ * kept (keep 0), not counted in n_rej, and the clip runs over the pixel's other
+ * values; a pixel without any gives NaN.  missing == 0: a NaN poisons its pixel.
  * Errors: ksigma <= 0, max_iters < 0 -> RANGE; N > 128 -> UNSUPPORTED. */
 int reduce_combine(const float *aligned, int32_t w, int32_t h, int32_t N, float ksigma,
-                   int32_t max_iters, float *out, uint8_t *keep, int64_t *n_rej, void *stream);
+                   int32_t max_iters, float *out, uint8_t *keep, int64_t *n_rej, int32_t missing,
+                   void *stream);
 
 /* ---- batched stacks -----------------------------------------------------------
  * The whole chain for many independent stacks (for instance the three bands of the
@@ -195,6 +214,9 @@ int reduce_combine(const float *aligned, int32_t w, int32_t h, int32_t N, float 
  *   n_rej     device int64[1] (values dropped by the clip) or NULL
  * ws: device workspace of reduce_stack_batch_ws(stacks, n) bytes (calibrated frames,
  * partial scores, the work-item table); query again after tuning.  The stack
+ * A stack with a bias frame calibrates as reduce_calibrate with it; a stack with a
+ * bad-pixel map masks its aligned values as reduce_mask_shifted and combines with
+ * missing = 1.
  * descriptors are copied into the workspace at every call (the host image is kept
  * per workspace and rebuilt, after synchronising `stream`, when the descriptors
  * change).  Calls sharing one workspace must not overlap.  Errors: as the stage-wise
@@ -211,6 +233,8 @@ typedef struct {
     int32_t *out_rect;
     reduce_offset_t *offsets;
     int64_t *n_rej;
+    const float *bias;      /* [H][W] at cal_row_pitch, or NULL (the dark carries the bias) */
+    const uint8_t *mask;    /* bad-pixel map [H][W] (row pitch W, nonzero = bad) or NULL */
 } reduce_stack_t;
 
 size_t reduce_stack_batch_ws(const reduce_stack_t *stacks, int32_t n);

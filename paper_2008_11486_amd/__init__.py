@@ -58,7 +58,7 @@ def _declare(L):
     L.reduce_status_str.argtypes = [ctypes.c_int]
     L.reduce_last_error.restype = ctypes.c_char_p
     L.reduce_version.restype = ctypes.c_int
-    L.reduce_calibrate.argtypes = [P, I64, I64, P, P, I64, P, I32, I32, I32, P]
+    L.reduce_calibrate.argtypes = [P, I64, I64, P, P, P, I64, P, I32, I32, I32, P]
     L.reduce_register_ws.argtypes = [I32, I32, I32, I32, I32]
     L.reduce_register_ws.restype = SZ
     L.reduce_register.argtypes = [P, P, I32, I32, I32, I32, I32, P, P, P, P, P, SZ, P]
@@ -68,7 +68,8 @@ def _declare(L):
     L.reduce_shift_spline_ws.restype = SZ
     L.reduce_shift_spline.argtypes = [P, P, I32, I32, I32, P, P, P, SZ, P]
     L.reduce_shift_spline.restype = ctypes.c_int
-    L.reduce_combine.argtypes = [P, I32, I32, I32, F, I32, P, P, P, P]
+    L.reduce_combine.argtypes = [P, I32, I32, I32, F, I32, P, P, P, I32, P]
+    L.reduce_mask_shifted.argtypes = [P, P, I32, I32, I32, P, P, I32, P]
     L.reduce_register_plan.argtypes = [I32, I32, I32, I32, I32, P]
     L.reduce_register_plan.restype = ctypes.c_int
     L.reduce_tune_register.argtypes = [P, P, I32, I32, I32, I32, I32, P, P, SZ, I32, P, P]
@@ -103,7 +104,7 @@ def _declare(L):
     L.reduce_prof_enable.argtypes = [ctypes.c_int]
     L.reduce_prof_query.argtypes = [ctypes.c_char_p, P, P]
     for n in ("reduce_calibrate", "reduce_register", "reduce_valid_rect", "reduce_shift", "reduce_combine",
-              "reduce_prof_enable", "reduce_prof_query"):
+              "reduce_mask_shifted", "reduce_prof_enable", "reduce_prof_query"):
         getattr(L, n).restype = ctypes.c_int
     for n, args in _EXTRA_DECLS.items():
         if hasattr(L, n):
@@ -118,7 +119,7 @@ def exported_symbols() -> Sequence[str]:
     """Names declared in include/reduce.h that the binding knows about."""
     return ("reduce_status_str", "reduce_last_error", "reduce_version", "reduce_calibrate",
             "reduce_register_ws", "reduce_register", "reduce_valid_rect", "reduce_shift",
-            "reduce_shift_spline_ws", "reduce_shift_spline",
+            "reduce_shift_spline_ws", "reduce_shift_spline", "reduce_mask_shifted",
             "reduce_combine", "reduce_prof_enable", "reduce_prof_query", "reduce_register_plan",
             "reduce_tune_register", "reduce_tune_register_ws", "reduce_tune_combine", "reduce_tune_save",
             "reduce_tune_load",
@@ -168,8 +169,8 @@ def _raw_view(raw: torch.Tensor) -> torch.Tensor:
 
 # ---------------------------------------------------------------------------- calibrate
 def calibrate(raw: torch.Tensor, dark: torch.Tensor, flat: torch.Tensor,
-              out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
-    """raw [N][H][W] uint16 (row/frame strides honoured), dark/flat [H][W] float32."""
+              out: Optional[torch.Tensor] = None, stream=None, bias: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """raw [N][H][W] uint16 (row/frame strides honoured), bias (or None)/dark/flat [H][W] float32."""
     raw = _raw_view(_dev(raw, "raw"))
     if raw.dim() == 2:
         raw = raw.unsqueeze(0)
@@ -178,9 +179,11 @@ def calibrate(raw: torch.Tensor, dark: torch.Tensor, flat: torch.Tensor,
         raise ValueError("x must be contiguous and dark/flat must share strides")
     if dark.dtype != torch.float32 or flat.dtype != torch.float32:
         raise TypeError("dark and flat must be float32")
+    if bias is not None and (bias.dtype != torch.float32 or bias.stride() != dark.stride()):
+        raise ValueError("bias must be float32 with the strides of dark")
     if out is None:
         out = torch.empty((N, H, W), dtype=torch.float32, device=raw.device)
-    _check(lib().reduce_calibrate(_ptr(raw), raw.stride(1), raw.stride(0), _ptr(dark), _ptr(flat),
+    _check(lib().reduce_calibrate(_ptr(raw), raw.stride(1), raw.stride(0), _ptr(bias), _ptr(dark), _ptr(flat),
                                   dark.stride(0), _ptr(out), W, H, N, _stream(stream)))
     return out
 
@@ -325,8 +328,9 @@ def shift_spline(frames: torch.Tensor, offs: torch.Tensor, rect: Sequence[int], 
 
 # ---------------------------------------------------------------------------- combine
 def combine(aligned: torch.Tensor, ksigma: float = 3.0, max_iters: int = 3, want_keep: bool = False,
-            want_nrej: bool = False, out: Optional[torch.Tensor] = None, stream=None):
-    """Returns (out [h][w] float32, keep uint8 [N][h][w] or None, n_rej int64 [1] or None)."""
+            want_nrej: bool = False, out: Optional[torch.Tensor] = None, stream=None, missing: bool = False):
+    """Returns (out [h][w] float32, keep uint8 [N][h][w] or None, n_rej int64 [1] or None);
+    with missing, NaN values are left out."""
     _dev(aligned, "aligned")
     N, h, w = aligned.shape
     if not aligned.is_contiguous():
@@ -338,8 +342,27 @@ def combine(aligned: torch.Tensor, ksigma: float = 3.0, max_iters: int = 3, want
     keep = torch.empty((N, h, w), dtype=torch.uint8, device=aligned.device) if want_keep else None
     nrej = torch.empty(1, dtype=torch.int64, device=aligned.device) if want_nrej else None
     _check(lib().reduce_combine(_ptr(aligned), w, h, N, float(ksigma), int(max_iters), _ptr(out),
-                                _ptr(keep), _ptr(nrej), _stream(stream)))
+                                _ptr(keep), _ptr(nrej), 1 if missing else 0, _stream(stream)))
     return out, keep, nrej
+
+
+def mask_shifted(mask: torch.Tensor, out: torch.Tensor, offs: torch.Tensor, rect: Sequence[int], W: int, H: int,
+                 integer_mode: bool = False, stream=None) -> torch.Tensor:
+    """Sets to NaN the values of shift()'s output out [N][h][w] that read a bad pixel of
+    mask uint8 [H][W] (nonzero = bad)."""
+    _dev(mask, "mask")
+    _dev(out, "out")
+    if mask.dtype != torch.uint8 or not mask.is_contiguous() or tuple(mask.shape) != (H, W):
+        raise ValueError("mask must be a contiguous uint8 device tensor [H][W]")
+    if out.dim() == 2:
+        out = out.unsqueeze(0)
+    N = out.shape[0]
+    if not out.is_contiguous() or offs.numel() != 2 * N:
+        raise ValueError("out must be contiguous [N][h][w] with offs [N][2]")
+    r = (ctypes.c_int32 * 4)(*[int(v) for v in rect])
+    _check(lib().reduce_mask_shifted(_ptr(mask), _ptr(out), W, H, N, _ptr(offs), r, 1 if integer_mode else 0,
+                                     _stream(stream)))
+    return out
 
 
 # ---------------------------------------------------------------------------- batched stacks
@@ -350,13 +373,15 @@ class StackDesc(ctypes.Structure):
                 ("W", ctypes.c_int32), ("H", ctypes.c_int32), ("N", ctypes.c_int32), ("ref_index", ctypes.c_int32),
                 ("radius", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("ksigma", ctypes.c_float),
                 ("integer_mode", ctypes.c_int32), ("out", ctypes.c_void_p), ("out_rect", ctypes.c_void_p),
-                ("offsets", ctypes.c_void_p), ("n_rej", ctypes.c_void_p)]
+                ("offsets", ctypes.c_void_p), ("n_rej", ctypes.c_void_p), ("bias", ctypes.c_void_p),
+                ("mask", ctypes.c_void_p)]
 
 
 class StackBatch:
     """Device buffers and descriptors of a batch of stacks (caller-owned torch tensors).
 
-    Each stack is (raw uint16 [N][H][W], dark [H][W], flat [H][W], radius); outputs
+    Each stack is (raw uint16 [N][H][W], dark [H][W], flat [H][W], radius) or that tuple
+    followed by bias [H][W] (or None) and a bad-pixel map uint8 [H][W] (or None); outputs
     are allocated here once: out [H*W] float32 (the image is out[:h*w] as [h][w]),
     rect int32 [4], offsets [N][48] bytes, n_rej int64 [1].
     """
@@ -364,7 +389,12 @@ class StackBatch:
     def __init__(self, stacks, ksigma: float = 3.0, max_iters: int = 3, ref_index=0, integer_mode=False):
         self.items = []
         descs = []
-        for i, (raw, dark, flat, radius) in enumerate(stacks):
+        for i, st in enumerate(stacks):
+            raw, dark, flat, radius = st[:4]
+            bias = st[4] if len(st) > 4 else None
+            mask = st[5] if len(st) > 5 else None
+            if mask is not None and (mask.dtype != torch.uint8 or not mask.is_contiguous()):
+                raise ValueError("mask must be a contiguous uint8 tensor [H][W]")
             raw = _raw_view(_dev(raw, "raw"))
             N, H, W = raw.shape
             dev = raw.device
@@ -376,9 +406,11 @@ class StackBatch:
             nrej = torch.zeros(1, dtype=torch.int64, device=dev)
             d = StackDesc(raw.data_ptr(), raw.stride(1), raw.stride(0), dark.data_ptr(), flat.data_ptr(),
                           dark.stride(0), W, H, N, int(ref), int(radius), int(max_iters), float(ksigma),
-                          1 if imode else 0, out.data_ptr(), rect.data_ptr(), offs.data_ptr(), nrej.data_ptr())
+                          1 if imode else 0, out.data_ptr(), rect.data_ptr(), offs.data_ptr(), nrej.data_ptr(),
+                          0 if bias is None else bias.data_ptr(), 0 if mask is None else mask.data_ptr())
             descs.append(d)
-            self.items.append(dict(raw=raw, dark=dark, flat=flat, out=out, rect=rect, offsets=offs, n_rej=nrej,
+            self.items.append(dict(raw=raw, dark=dark, flat=flat, bias=bias, mask=mask, out=out, rect=rect,
+                                   offsets=offs, n_rej=nrej,
                                    W=W, H=H, N=N))
         self.descs = (StackDesc * len(descs))(*descs)
         self.n = len(descs)

@@ -53,10 +53,10 @@ constexpr int COMB_PX32 = 2;    // ... of the up-to-32-frame combine
 __host__ __device__ inline int64_t al_plane(int64_t w, int64_t h) { return (w * h + 3) & ~(int64_t)3; }
 
 enum ItemType : int32_t {
-    IT_CAL = 0, IT_MEANPART, IT_MEANFINAL, IT_SCORE, IT_SSCORE, IT_SUM, IT_PICK, IT_RECT, IT_SHIFT, IT_COMB16,
-    IT_COMB32, IT_COMB48, IT_COMBDEEP
+    IT_CAL = 0, IT_MEANPART, IT_MEANFINAL, IT_SCORE, IT_SSCORE, IT_SUM, IT_PICK, IT_RECT, IT_SHIFT, IT_MASK,
+    IT_COMB16, IT_COMB32, IT_COMB48, IT_COMBDEEP, IT_COMBMISS
 };
-constexpr int N_PHASES = IT_COMBDEEP + 1;
+constexpr int N_PHASES = IT_COMBMISS + 1;
 
 struct Item {
     int32_t type, stack, a, pad;
@@ -68,6 +68,8 @@ struct StackDev {
     int64_t rrp, rfp;
     const float *dark, *flat;
     int64_t crp;
+    const float *bias;     // or NULL
+    const uint8_t *mask;   // bad-pixel map [H][W] or NULL
     float *out;
     int32_t *out_rect;
     reduce_offset_t *offsets;
@@ -100,9 +102,9 @@ __global__ __launch_bounds__(CAL_BLOCK) void batch_cal(BatchArgs a, int32_t firs
     const StackDev &s = a.stacks[it.stack];
     const int64_t i = (int64_t)it.a * CAL_BLOCK + threadIdx.x;
     if (s.cal_vec)
-        calibrate_group8(s.raw, s.rrp, s.rfp, s.dark, s.flat, s.crp, s.cal, s.W, s.H, s.N, i);
+        calibrate_group8(s.raw, s.rrp, s.rfp, s.bias, s.dark, s.flat, s.crp, s.cal, s.W, s.H, s.N, i);
     else
-        calibrate_pixel(s.raw, s.rrp, s.rfp, s.dark, s.flat, s.crp, s.cal, s.W, s.H, s.N, i);
+        calibrate_pixel(s.raw, s.rrp, s.rfp, s.bias, s.dark, s.flat, s.crp, s.cal, s.W, s.H, s.N, i);
 }
 
 __global__ __launch_bounds__(MEAN_THREADS) void batch_meanpart(BatchArgs a, int32_t first)
@@ -258,8 +260,25 @@ __global__ __launch_bounds__(COMB_TILE) void batch_comb(BatchArgs a, int32_t fir
     }
 }
 
-// Stacks of 49 - 128 frames: block it.a of 64 pixel columns, values in LDS [N][64]
-// (the launch sizes the tile for the deepest stack).
+// Row v = it.a % H of frame k = it.a / H of a stack with a bad-pixel map: aligned values
+// that read a bad pixel become NaN (missing in the combine).
+__global__ __launch_bounds__(256) void batch_mask(BatchArgs a, int32_t first)
+{
+    const Item it = a.items[first + blockIdx.x];
+    const StackDev &s = a.stacks[it.stack];
+    const int32_t k = it.a / s.H, v = it.a - k * s.H;
+    const int32_t x0 = s.rect[0], y0 = s.rect[1], w = s.rect[2], h = s.rect[3];
+    if (v >= h) return;  // uniform over the workgroup
+    const ShiftSetup ss = shift_setup(s.soffs[2 * k], s.soffs[2 * k + 1]);
+    float *row = s.al + (int64_t)k * al_plane(w, h) + (int64_t)v * w;
+    for (int32_t u = threadIdx.x; u < w; u += blockDim.x)
+        if (reads_bad_pixel(s.mask, s.W, s.H, ss, s.integer_mode != 0, x0 + u, y0 + v)) row[u] = __builtin_nanf("");
+}
+
+// Stacks of 49 - 128 frames (MISS: stacks with a bad-pixel map, any depth): block it.a
+// of 64 pixel columns, values in LDS [N][64] (the launch sizes the tile for the deepest
+// stack of the phase).
+template <bool MISS>
 __global__ __launch_bounds__(COMB_DEEP_PX) void batch_comb_deep(BatchArgs a, int32_t first)
 {
     extern __shared__ float tile[];
@@ -267,7 +286,7 @@ __global__ __launch_bounds__(COMB_DEEP_PX) void batch_comb_deep(BatchArgs a, int
     const StackDev &s = a.stacks[it.stack];
     const int64_t plane = (int64_t)s.rect[2] * s.rect[3];
     if (it.a >= ceil_div(plane, (int64_t)COMB_DEEP_PX)) return;  // uniform over the workgroup
-    unsigned dropped = combine_deep_block(s.al, plane, al_plane(s.rect[2], s.rect[3]), s.N, (double)s.ksigma,
+    unsigned dropped = combine_deep_block<MISS>(s.al, plane, al_plane(s.rect[2], s.rect[3]), s.N, (double)s.ksigma,
                                                 s.max_iters, s.out, nullptr, it.a, tile);
     if (s.n_rej) {
 #pragma unroll
@@ -306,6 +325,7 @@ struct BatchLayout {
     int32_t first[N_PHASES], count[N_PHASES];
     size_t score_lds;
     int32_t deep_n = 0;  // deepest stack of the deep combine phase
+    int32_t miss_n = 0;  // deepest stack of the combine with missing values
     std::vector<ScoreGroup> groups;
 };
 
@@ -342,7 +362,7 @@ static bool cal_vec_ok(const reduce_stack_t &s)
 {
     const auto a16 = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
     return s.W % CAL_VEC == 0 && s.raw_row_pitch % CAL_VEC == 0 && s.raw_frame_pitch % CAL_VEC == 0 &&
-           s.cal_row_pitch % 4 == 0 && a16(s.raw) && a16(s.dark) && a16(s.flat);
+           s.cal_row_pitch % 4 == 0 && a16(s.raw) && a16(s.dark) && a16(s.flat) && (!s.bias || a16(s.bias));
 }
 
 static BatchLayout layout_of(const reduce_stack_t *stacks, int32_t n)
@@ -390,12 +410,18 @@ static BatchLayout layout_of(const reduce_stack_t *stacks, int32_t n)
         const int px = s.N <= 16 ? COMB_PX16 : s.N <= 32 ? COMB_PX32 : 1;
         const bool vec = px > 1 && (reinterpret_cast<uintptr_t>(s.out) & (uintptr_t)(4 * px - 1)) == 0;
         const int32_t comb_blocks = (int32_t)ceil_div(fp, (int64_t)COMB_TILE * (vec ? px : 1));
-        sl.count[IT_COMB16] = s.N <= 16 ? comb_blocks : 0;
-        sl.count[IT_COMB32] = s.N > 16 && s.N <= 32 ? comb_blocks : 0;
-        sl.count[IT_COMB48] = s.N > 32 && s.N <= 48 ? comb_blocks : 0;
+        // a stack with a bad-pixel map has its aligned values masked and takes the combine
+        // that leaves missing values out
+        const bool miss = s.mask != nullptr;
+        sl.count[IT_MASK] = miss ? s.N * s.H : 0;
+        sl.count[IT_COMB16] = !miss && s.N <= 16 ? comb_blocks : 0;
+        sl.count[IT_COMB32] = !miss && s.N > 16 && s.N <= 32 ? comb_blocks : 0;
+        sl.count[IT_COMB48] = !miss && s.N > 32 && s.N <= 48 ? comb_blocks : 0;
         const int32_t deep_blocks = (int32_t)ceil_div(fp, (int64_t)COMB_DEEP_PX);
-        sl.count[IT_COMBDEEP] = s.N > 48 ? deep_blocks : 0;
-        if (s.N > 48) L.deep_n = std::max(L.deep_n, s.N);
+        sl.count[IT_COMBDEEP] = !miss && s.N > 48 ? deep_blocks : 0;
+        sl.count[IT_COMBMISS] = miss ? deep_blocks : 0;
+        if (!miss && s.N > 48) L.deep_n = std::max(L.deep_n, s.N);
+        if (miss) L.miss_n = std::max(L.miss_n, s.N);
         for (int q = 0; q < N_PHASES; ++q) L.count[q] += sl.count[q];
         if (nreg > 0 && p.K != 0) L.score_lds = std::max(L.score_lds, p.lds);
         L.st.push_back(sl);
@@ -473,6 +499,8 @@ static int build_descriptors(const reduce_stack_t *stacks, int32_t n, void *ws, 
         d.rfp = st.raw_frame_pitch;
         d.dark = st.dark;
         d.flat = st.flat;
+        d.bias = st.bias;
+        d.mask = st.mask;
         d.crp = st.cal_row_pitch;
         d.out = st.out;
         d.out_rect = st.out_rect;
@@ -582,6 +610,8 @@ static int launch_phases(int32_t n, void *ws, const BatchLayout &L, hipStream_t 
         ProfScope prof("batch_shift", s);
         hipLaunchKernelGGL(batch_shift, dim3(L.count[IT_SHIFT]), dim3(SH_BLOCK), 0, s, a, L.first[IT_SHIFT]);
     }
+    if (L.count[IT_MASK] > 0)
+        hipLaunchKernelGGL(batch_mask, dim3(L.count[IT_MASK]), dim3(256), 0, s, a, L.first[IT_MASK]);
     {
         ProfScope prof("batch_comb", s);
         if (L.count[IT_COMB16] > 0)
@@ -594,8 +624,11 @@ static int launch_phases(int32_t n, void *ws, const BatchLayout &L, hipStream_t 
             hipLaunchKernelGGL((batch_comb<48, 1>), dim3(L.count[IT_COMB48]), dim3(COMB_TILE), 0, s, a,
                                L.first[IT_COMB48]);
         if (L.count[IT_COMBDEEP] > 0)
-            hipLaunchKernelGGL(batch_comb_deep, dim3(L.count[IT_COMBDEEP]), dim3(COMB_DEEP_PX),
+            hipLaunchKernelGGL(batch_comb_deep<false>, dim3(L.count[IT_COMBDEEP]), dim3(COMB_DEEP_PX),
                                sizeof(float) * L.deep_n * COMB_DEEP_PX, s, a, L.first[IT_COMBDEEP]);
+        if (L.count[IT_COMBMISS] > 0)
+            hipLaunchKernelGGL(batch_comb_deep<true>, dim3(L.count[IT_COMBMISS]), dim3(COMB_DEEP_PX),
+                               sizeof(float) * L.miss_n * COMB_DEEP_PX, s, a, L.first[IT_COMBMISS]);
     }
     return check_launch("reduce_stack_batch");
 }

@@ -49,14 +49,16 @@ __global__ __launch_bounds__(COMB_TILE) void combine_cols(
     }
 }
 
-// Stacks of 49 - 128 frames: 64 pixel columns per workgroup, values in LDS [N][64].
+// Stacks of 49 - 128 frames, and stacks with missing values: 64 pixel columns per
+// workgroup, values in LDS [N][64].
+template <bool MISS>
 __global__ __launch_bounds__(COMB_DEEP_PX) void combine_deep(
     const float *__restrict__ aligned, int64_t plane, int32_t N, double ksigma, int32_t max_iters,
     float *__restrict__ out, uint8_t *__restrict__ keep, unsigned long long *__restrict__ n_rej)
 {
     extern __shared__ float tile[];
-    unsigned dropped = combine_deep_block(aligned, plane, plane, N, ksigma, max_iters, out, keep,
-                                          (int64_t)blockIdx.x, tile);
+    unsigned dropped = combine_deep_block<MISS>(aligned, plane, plane, N, ksigma, max_iters, out, keep,
+                                                (int64_t)blockIdx.x, tile);
     if (n_rej) {
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) dropped += __shfl_xor(dropped, off, 64);
@@ -75,6 +77,19 @@ static int combine_px()
         if (v == 1 || v == 2 || v == 4) return v;
     }
     return 4;
+}
+
+static void launch_deep(bool missing, const float *aligned, int64_t plane, int32_t N, double ksigma,
+                        int32_t max_iters, float *out, uint8_t *keep, unsigned long long *n_rej, hipStream_t s)
+{
+    const dim3 grid((unsigned)ceil_div(plane, (int64_t)COMB_DEEP_PX));
+    const size_t lds = sizeof(float) * N * COMB_DEEP_PX;
+    if (missing)
+        hipLaunchKernelGGL(combine_deep<true>, grid, dim3(COMB_DEEP_PX), lds, s, aligned, plane, N, ksigma, max_iters,
+                           out, keep, n_rej);
+    else
+        hipLaunchKernelGGL(combine_deep<false>, grid, dim3(COMB_DEEP_PX), lds, s, aligned, plane, N, ksigma,
+                           max_iters, out, keep, n_rej);
 }
 
 void combine_dispatch(int lanes, const float *aligned, int64_t plane, int32_t N, double ksigma, int32_t max_iters,
@@ -111,9 +126,7 @@ void combine_dispatch(int lanes, const float *aligned, int64_t plane, int32_t N,
         } else if (N <= 48) {
             launch_cols(std::integral_constant<int, 48>{}, std::integral_constant<int, 1>{});
         } else {
-            hipLaunchKernelGGL(combine_deep, dim3((unsigned)ceil_div(plane, (int64_t)COMB_DEEP_PX)),
-                               dim3(COMB_DEEP_PX), sizeof(float) * N * COMB_DEEP_PX, s, aligned, plane, N, ksigma,
-                               max_iters, out, keep, n_rej);
+            launch_deep(false, aligned, plane, N, ksigma, max_iters, out, keep, n_rej, s);
         }
         break;
     case 2: launch(std::integral_constant<int, 2>{}, std::integral_constant<int, 24>{}); break;
@@ -132,7 +145,8 @@ int combine_lanes_for(int32_t N);
 using namespace rd;
 
 extern "C" int reduce_combine(const float *aligned, int32_t w, int32_t h, int32_t N, float ksigma,
-                              int32_t max_iters, float *out, uint8_t *keep, int64_t *n_rej, void *stream)
+                              int32_t max_iters, float *out, uint8_t *keep, int64_t *n_rej, int32_t missing,
+                              void *stream)
 {
     if (!aligned || !out) return fail(REDUCE_ERR_NULL, "reduce_combine: NULL buffer");
     if (w < 1 || h < 1 || N < 1) return fail(REDUCE_ERR_SHAPE, "reduce_combine: w, h, N must be >= 1");
@@ -142,6 +156,12 @@ extern "C" int reduce_combine(const float *aligned, int32_t w, int32_t h, int32_
     hipStream_t s = as_stream(stream);
     unsigned long long *nr = reinterpret_cast<unsigned long long *>(n_rej);
     if (nr) hipLaunchKernelGGL(zero_u64, dim3(1), dim3(1), 0, s, nr);
+    if (missing) {
+        // values that are NaN (bad pixels) are left out: the LDS-column kernel at any depth
+        ProfScope prof("combine_missing", s);
+        launch_deep(true, aligned, (int64_t)w * h, N, (double)ksigma, max_iters, out, keep, nr, s);
+        return check_launch("reduce_combine");
+    }
     // past the LDS tile's depth only the one-lane kernel (column in registers) applies
     const int lanes = N > COMB_MAX_N ? 1 : combine_lanes_for(N);
     combine_dispatch(lanes, aligned, (int64_t)w * h, N, (double)ksigma, max_iters, out, keep, nr, s);

@@ -345,7 +345,9 @@ __device__ __forceinline__ unsigned combine_cols_block(const float *__restrict__
 // come in batches of 32 loads in flight; the passes loop over the frames at run time
 // with the kept flags in two 64-bit words.  Same arithmetic, in the same order, as
 // clip_values (sums over the kept values in frame order, m = s / n, the squared
-// deviations and the largest one, the threshold, the drops).
+// deviations and the largest one, the threshold, the drops).  With MISS, NaN values are
+// missing: never kept, not counted as dropped, and n counts the others (a pixel with
+// none gives NaN).
 constexpr int COMB_DEEP_PX = 64;
 constexpr int COMB_DEEP_BATCH = 64;  // the most loads a wave keeps in flight
 
@@ -363,6 +365,7 @@ __device__ __forceinline__ void deep_each(const float *col, uint64_t k0, uint64_
     for (int i = 64; i < N; ++i, w >>= 1) f(i, (double)col[i * COMB_DEEP_PX], (w & 1ull) != 0);
 }
 
+template <bool MISS>
 __device__ __forceinline__ unsigned combine_deep_block(const float *__restrict__ aligned, int64_t plane,
                                                        int64_t pstride, int32_t N, double ksigma, int32_t max_iters,
                                                        float *__restrict__ out, uint8_t *__restrict__ keep,
@@ -383,6 +386,17 @@ __device__ __forceinline__ unsigned combine_deep_block(const float *__restrict__
     uint64_t k0 = N >= 64 ? ~0ull : ((1ull << N) - 1ull);
     uint64_t k1 = N >= 128 ? ~0ull : N <= 64 ? 0ull : ((1ull << (N - 64)) - 1ull);
     int n = N;
+    if (MISS) {
+        uint64_t m0 = 0, m1 = 0;
+        deep_each(col, k0, k1, N, [&](int i, double x, bool k) {
+            const uint64_t bit = (k && x == x) ? 1ull : 0ull;
+            if (i < 64) m0 |= bit << i;
+            else m1 |= bit << (i - 64);
+        });
+        k0 = m0;
+        k1 = m1;
+        n = __popcll(k0) + __popcll(k1);
+    }
     unsigned dropped = 0;
     // the drop pass of one iteration also forms the next sum (the same values in the
     // same order as a separate pass over the kept set)

@@ -51,6 +51,12 @@ __device__ __forceinline__ float calib_px(uint16_t raw, float dark, float flat)
     return __fdiv_rn(__fsub_rn((float)raw, dark), flat);
 }
 
+// ((raw - bias) - dark) / flat: the cast happens at the bias subtraction (Section 2.1).
+__device__ __forceinline__ float calib_px(uint16_t raw, float bias, float dark, float flat)
+{
+    return __fdiv_rn(__fsub_rn(__fsub_rn((float)raw, bias), dark), flat);
+}
+
 // Per-frame bilinear setup: integer part and exact fraction of the offset.
 struct ShiftSetup {
     int32_t ix, iy;     // floor(s)

@@ -21,6 +21,19 @@ __global__ __launch_bounds__(SH_BLOCK) void shift_kernel(
                                  h, (int64_t)w * h, vec_store, aligned);
 }
 
+// Grid (ceil(w / 256), h, N): one thread per output pixel.
+__global__ __launch_bounds__(256) void mask_shifted_kernel(const uint8_t *__restrict__ mask, float *__restrict__ out,
+                                                           int32_t W, int32_t H, const float *__restrict__ offs,
+                                                           int32_t x0, int32_t y0, int32_t w, int32_t h,
+                                                           int integer)
+{
+    const int32_t u = blockIdx.x * 256 + threadIdx.x, v = blockIdx.y, k = blockIdx.z;
+    if (u >= w) return;
+    const ShiftSetup ss = shift_setup(offs[2 * k], offs[2 * k + 1]);
+    if (reads_bad_pixel(mask, W, H, ss, integer != 0, x0 + u, y0 + v))
+        out[((int64_t)k * h + v) * w + u] = __builtin_nanf("");
+}
+
 }  // namespace rd
 
 using namespace rd;
@@ -45,4 +58,20 @@ extern "C" int reduce_shift(const float *in, float *out, int32_t W, int32_t H, i
         hipLaunchKernelGGL(shift_kernel<false>, grid, dim3(SH_BLOCK), 0, s, in, out, W, H, offs, x0, y0, w,
                            h, vec_store, aligned);
     return check_launch("reduce_shift");
+}
+
+extern "C" int reduce_mask_shifted(const uint8_t *mask, float *out, int32_t W, int32_t H, int32_t N,
+                                   const float *offs, const int32_t *rect, int32_t integer_mode, void *stream)
+{
+    if (!mask || !out || !offs || !rect) return fail(REDUCE_ERR_NULL, "reduce_mask_shifted: NULL argument");
+    if (W < 1 || H < 1 || N < 1) return fail(REDUCE_ERR_SHAPE, "reduce_mask_shifted: W, H, N must be >= 1");
+    const int32_t x0 = rect[0], y0 = rect[1], w = rect[2], h = rect[3];
+    if (w < 1 || h < 1 || w > W || h > H)
+        return fail(REDUCE_ERR_SHAPE, "reduce_mask_shifted: empty or oversized rect");
+    if (N > 65535 || h > 65535) return fail(REDUCE_ERR_UNSUPPORTED, "reduce_mask_shifted: N or h above 65535");
+    hipStream_t s = as_stream(stream);
+    ProfScope prof("mask_shifted", s);
+    hipLaunchKernelGGL(mask_shifted_kernel, dim3((unsigned)ceil_div(w, 256), (unsigned)h, (unsigned)N), dim3(256), 0,
+                       s, mask, out, W, H, offs, x0, y0, w, h, integer_mode ? 1 : 0);
+    return check_launch("reduce_mask_shifted");
 }

@@ -164,4 +164,21 @@ __host__ __device__ inline int shift_vec_store(int32_t w, uintptr_t out_addr)
     return (w % 4 == 0 && (out_addr & 15u) == 0) ? 4 : (w % 2 == 0 && (out_addr & 7u) == 0) ? 2 : 1;
 }
 
+// Bad-pixel masking after the shift (the paper masks bad pixels before alignment,
+// Section 2.1): output u of row v of frame k becomes NaN (missing) when one of the taps
+// the bilinear shift read for it is a bad pixel of mask [H][W], the bad-pixel map
+// shared by the frames (integer mode: the one pixel it copied).  The taps are those of
+// shift_strip: rows j and j + 1 (when the y fraction is non-zero), columns i and i + 1
+// (when the x fraction is non-zero), clamped into the frame as there.
+__device__ __forceinline__ bool reads_bad_pixel(const uint8_t *__restrict__ mask, int32_t W, int32_t H,
+                                                const ShiftSetup &ss, bool integer, int32_t x, int32_t y)
+{
+    const int32_t c = x + ss.ix;
+    const int32_t i = clampi(c, 0, W - 1), j = clampi(y + ss.iy, 0, H - 1);
+    const int32_t i1 = (!integer && ss.a > 0.0) ? clampi(c + 1, 0, W - 1) : i;
+    const int32_t j1 = (!integer && ss.b > 0.0) ? clampi(j + 1, 0, H - 1) : j;
+    const uint8_t *r0 = mask + (int64_t)j * W, *r1 = mask + (int64_t)j1 * W;
+    return (r0[i] | r0[i1] | r1[i] | r1[i1]) != 0;
+}
+
 }  // namespace rd

@@ -41,12 +41,16 @@ def test_status_strings(rd):
 
 def test_null_and_shape_errors_before_launch(rd):
     L = rd.lib()
-    assert L.reduce_calibrate(None, 8, 64, None, None, 8, None, 8, 8, 1, None) == rd.ERR_NULL
+    assert L.reduce_calibrate(None, 8, 64, None, None, None, 8, None, 8, 8, 1, None) == rd.ERR_NULL
     b = ctypes.c_void_p(16)  # never dereferenced: validation fails first
-    assert L.reduce_calibrate(b, 4, 64, b, b, 8, b, 8, 8, 1, None) == rd.ERR_SHAPE
+    assert L.reduce_calibrate(b, 4, 64, None, b, b, 8, b, 8, 8, 1, None) == rd.ERR_SHAPE
     assert b"pitch" in L.reduce_last_error()
-    assert L.reduce_combine(b, 4, 4, 3, ctypes.c_float(0.0), 3, b, None, None, None) == rd.ERR_RANGE
-    assert L.reduce_combine(b, 4, 4, 129, ctypes.c_float(3.0), 3, b, None, None, None) == rd.ERR_UNSUPPORTED
+    assert L.reduce_combine(b, 4, 4, 3, ctypes.c_float(0.0), 3, b, None, None, 0, None) == rd.ERR_RANGE
+    assert L.reduce_combine(b, 4, 4, 129, ctypes.c_float(3.0), 3, b, None, None, 1, None) == rd.ERR_UNSUPPORTED
+    r4 = (ctypes.c_int32 * 4)(0, 0, 4, 4)
+    assert L.reduce_mask_shifted(None, b, 8, 8, 1, b, r4, 0, None) == rd.ERR_NULL
+    r9 = (ctypes.c_int32 * 4)(0, 0, 9, 4)
+    assert L.reduce_mask_shifted(b, b, 8, 8, 1, b, r9, 0, None) == rd.ERR_SHAPE
     assert L.reduce_register(b, b, 32, 32, 1, -1, 2, None, None, b, None, b, 1 << 20, None) == rd.ERR_RANGE
     assert L.reduce_register(b, b, 32, 32, 1, 2, 2, None, None, b, None, b, 8, None) == rd.ERR_WORKSPACE
     r = (ctypes.c_int32 * 4)(0, 0, 0, 5)

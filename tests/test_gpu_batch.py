@@ -20,10 +20,10 @@ def rd():
     return rd
 
 
-def stagewise(rd, raw, dark, flat, R, ref=0, integer_mode=False):
+def stagewise(rd, raw, dark, flat, R, ref=0, integer_mode=False, bias=None, mask=None):
     """The same chain through the stage-wise entry points."""
     N, H, W = raw.shape
-    cal = rd.calibrate(raw, dark, flat)
+    cal = rd.calibrate(raw, dark, flat, bias=bias)
     offs = np.zeros(N, dtype=rd.OFFSET_DTYPE)
     offs["second"] = -np.inf
     offs["margin"] = np.inf
@@ -37,7 +37,9 @@ def stagewise(rd, raw, dark, flat, R, ref=0, integer_mode=False):
             s[k] = (o["dx"][i], o["dy"][i]) if integer_mode else (o["sx"][i], o["sy"][i])
     rect = rd.valid_rect(s, W, H)
     al = rd.shift(cal, to_dev(s), rect, integer_mode=integer_mode)
-    out, _, nrej = rd.combine(al, want_nrej=True)
+    if mask is not None:
+        rd.mask_shifted(mask, al, to_dev(s), rect, W, H, integer_mode=integer_mode)
+    out, _, nrej = rd.combine(al, want_nrej=True, missing=mask is not None)
     return out.cpu().numpy(), rect, offs, int(nrej.cpu()[0])
 
 
@@ -149,6 +151,47 @@ def test_batch_deep_stacks(rd, orc):
         e = rel_err(img.cpu().numpy(), o["out"])[~o["near"].any(axis=0)]  # A11's band aside
         print("97-frame batch vs oracle:", err_summary(e))
         assert e.max() <= TOL
+
+
+def test_batch_bias_and_bad_pixels(rd, orc):
+    """Stacks with a bias frame and a bad-pixel map beside plain ones: bit-identical to
+    the stage-wise chain (bias calibrate, shift, masking, missing-value combine), and
+    against the oracle end to end."""
+    rng = np.random.default_rng(95)
+    specs = [(12, 120, 100, 4, True), (6, 96, 80, 3, False), (60, 64, 72, 3, True), (9, 80, 64, 3, False)]
+    dev, stacks, extras = [], [], []
+    for i, (N, W, H, R, cos) in enumerate(specs):
+        st = _make(30 + i, N, W, H, R, cos, seed=5)
+        bias = (250 + rng.normal(0, 2, size=(H, W))).astype(np.float32) if i != 3 else None
+        raw = st.raw.astype(np.int64) + (0 if bias is None else np.round(bias).astype(np.int64))
+        raw = np.clip(raw, 0, 65535).astype(np.uint16)
+        mask = (rng.random(size=(H, W)) < 0.004).astype(np.uint8) if i in (0, 2, 3) else None
+        stacks.append((raw, st.dark, st.flat, R, bias, mask))
+        extras.append(i % 2 == 1)
+        dev.append((to_dev(raw), to_dev(st.dark), to_dev(st.flat), R, None if bias is None else to_dev(bias),
+                    None if mask is None else to_dev(mask)))
+    batch = rd.StackBatch(dev, integer_mode=extras)
+    batch.run()
+    for i, (raw, dark, flat, R, bias, mask) in enumerate(dev):
+        img, rect, offs, nrej = batch.result(i)
+        ref_img, ref_rect, ref_offs, ref_nrej = stagewise(rd, raw, dark, flat, R, integer_mode=extras[i], bias=bias,
+                                                          mask=mask)
+        assert np.array_equal(rect, ref_rect), i
+        assert np.array_equal(img.cpu().numpy(), ref_img, equal_nan=True), i
+        assert offs.tobytes() == ref_offs.tobytes() and nrej == ref_nrej, i
+    for i in (0, 2):
+        raw, dark, flat, R, bias, mask = stacks[i]
+        img, rect, offs, _ = batch.result(i)
+        o = orc.reduce_stack(raw, dark, flat, R, bias=bias, mask=mask, integer_mode=extras[i])
+        assert np.array_equal(offs["dx"][1:], o["offsets"]["dx"][1:]) and np.array_equal(offs["dy"][1:], o["offsets"]["dy"][1:])
+        s = np.stack([offs["sx"], offs["sy"]], 1).astype(np.float32)
+        if np.array_equal(rect, o["rect"]) and np.array_equal(s, o["s"]):
+            g = img.cpu().numpy()
+            assert np.array_equal(np.isnan(g), np.isnan(o["out"]))
+            ok = ~np.isnan(o["out"]) & ~o["near"].any(axis=0)
+            e = rel_err(g[ok], o["out"][ok])
+            print(f"stack {i} with bias and bad pixels vs oracle:", err_summary(e))
+            assert e.max() <= TOL
 
 
 def test_batch_rejects_bad_stacks(rd):

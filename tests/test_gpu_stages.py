@@ -69,6 +69,26 @@ def test_calibrate_identity_and_pitched_roi(rd, orc):
     assert rel_err(got2, ref2).max() <= TOL
 
 
+@pytest.mark.parametrize("shape", [(4, 96, 128), (3, 37, 53)])
+def test_calibrate_with_bias_parity(rd, orc, shape):
+    """Bias, then dark, then flat (Section 2.1), on the vector and the scalar paths."""
+    N, H, W = shape
+    rng = np.random.default_rng(W + 7)
+    raw = rng.integers(0, 65536, size=shape, dtype=np.uint16)
+    bias = (300 + rng.normal(0, 2, size=(H, W))).astype(np.float32)
+    dark = (20 + rng.normal(0, 3, size=(H, W))).astype(np.float32)
+    flat = rng.uniform(0.95, 1.05, size=(H, W)).astype(np.float32)
+    cal = rd.calibrate(to_dev(raw), to_dev(dark), to_dev(flat), bias=to_dev(bias)).cpu().numpy()
+    e = rel_err(cal, orc.calibrate(raw, dark, flat, bias=bias))
+    print(f"calibrate+bias {shape}: {err_summary(e)}")
+    assert e.max() <= TOL
+    # an overscan cut (50 columns and a 2-pixel border, as Section 2.1) through the pitches
+    full = rng.integers(0, 65536, size=(2, H + 4, W + 54), dtype=np.uint16)
+    roi = to_dev(full)[:, 2:H + 2, 2:W + 2]
+    got = rd.calibrate(roi, to_dev(dark), to_dev(flat), bias=to_dev(bias)).cpu().numpy()
+    assert rel_err(got, orc.calibrate(full[:, 2:H + 2, 2:W + 2], dark, flat, bias=bias)).max() <= TOL
+
+
 # ----------------------------------------------------------------------------- register
 def _check_offsets(g, o, label):
     tie = (o["flags"] & 4) != 0
@@ -182,6 +202,57 @@ def test_shift_integer_mode_is_exact_copy(rd, orc):
         for k in range(3):
             sx, sy = int(offs[k, 0]), int(offs[k, 1])
             assert np.array_equal(got[k], frames[k, y0 + sy:y0 + sy + h, x0 + sx:x0 + sx + w])
+
+
+@pytest.mark.parametrize("integer_mode", [False, True])
+def test_mask_shifted_marks_exactly_the_oracle_outputs(rd, orc, integer_mode):
+    """Bad pixels (0.3% of a 97x131 map) reach exactly the outputs whose taps read them;
+    every other value equals the unmasked shift."""
+    rng = np.random.default_rng(91 + integer_mode)
+    N, H, W = 5, 97, 131
+    frames = rng.normal(1000, 30, size=(N, H, W)).astype(np.float32)
+    mask = (rng.random(size=(H, W)) < 0.003).astype(np.uint8)
+    s = rng.uniform(-6, 6, size=(N, 2)).astype(np.float32)
+    s[0] = 0.0
+    s[1] = (2.0, -3.0)        # an integer offset: one tap
+    s[2] = (0.5, 0.0)         # a fraction on one axis only
+    if integer_mode:
+        s = np.round(s).astype(np.float32)
+    rect = rd.valid_rect(s, W, H)
+    dev = to_dev(frames)
+    offs = to_dev(s)
+    al = rd.shift(dev, offs, rect, integer_mode=integer_mode)
+    rd.mask_shifted(to_dev(mask), al, offs, rect, W, H, integer_mode=integer_mode)
+    got = al.cpu().numpy()
+    want = orc.shift(frames.astype(np.float64), s, rect, mask)
+    assert np.array_equal(np.isnan(got), np.isnan(want))
+    ok = ~np.isnan(want)
+    assert rel_err(got[ok], want[ok]).max() <= TOL
+    assert np.isnan(want).sum() > 20
+
+
+@pytest.mark.parametrize("N", [5, 16, 40, 97])
+def test_combine_missing_values_parity(rd, orc, N):
+    rng = np.random.default_rng(4000 + N)
+    h, w = 19, 157
+    vals = rng.normal(1000, 30, size=(N, h, w)).astype(np.float32)
+    hits = rng.random(size=vals.shape) < 0.02
+    vals[hits] += rng.uniform(5e3, 6e4, size=hits.sum()).astype(np.float32)
+    vals[rng.random(size=vals.shape) < 0.2] = np.nan
+    vals[:, 0, :3] = np.nan                       # pixels without any value
+    out, keep, nrej = rd.combine(to_dev(vals), want_keep=True, want_nrej=True, missing=True)
+    out, keep, nrej = out.cpu().numpy(), keep.cpu().numpy(), int(nrej.cpu().numpy()[0])
+    o_out, o_keep, o_nrej, near = orc.combine(vals.astype(np.float64), 3.0, 3, missing=True)
+    assert np.array_equal(np.isnan(out), np.isnan(o_out)) and np.isnan(out[0, :3]).all()
+    flips = keep != o_keep
+    assert np.all(~flips | (near == 1))
+    good = ~flips.any(axis=0) & ~np.isnan(o_out)
+    e = rel_err(out[good], o_out[good])
+    print(f"combine missing N={N}: rejected {o_nrej}, flips {int(flips.sum())}, {err_summary(e)}")
+    assert e.max() <= TOL
+    if not flips.any():
+        assert nrej == o_nrej
+    assert not keep[np.isnan(vals)].any()
 
 
 # ----------------------------------------------------------------------------- combine

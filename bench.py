@@ -73,6 +73,8 @@ def parse():
                     help="skip the streaming kernels at the wide-field size (16 frames of 6144x6160)")
     ap.add_argument("--no-many", action="store_true",
                     help="skip the batched leg over 64 stacks of 3-30 frames, sides 512-4096")
+    ap.add_argument("--sweep", action="store_true",
+                    help="only the sweeps over image size and frame count (one JSON line)")
     ap.add_argument("--wide-only", action="store_true",
                     help="run only the wide-field streaming kernels (for counter runs) and print their figures")
     ap.add_argument("--traffic-key", default="kernels",
@@ -92,12 +94,15 @@ KERNEL_SOURCES = {
     "shift": ("shift.hip", "shift_core.h", "common.h"),
     "combine": ("combine.hip", "combine_core.h"),
     "combine_deep": ("combine.hip", "combine_core.h"),
+    "combine_missing": ("combine.hip", "combine_core.h"),
+    "mask_shifted": ("shift.hip", "shift_core.h", "common.h"),
     "shift_spline": ("spline.hip", "common.h", "shift_core.h"),
 }
 KERNEL_SYMBOLS = {"batch_score": "batch_score", "batch_shift": "batch_shift", "batch_comb": "batch_comb",
                   "batch_cal": "batch_cal", "score_tiles": "score_tiles", "calibrate": "calibrate_",
                   "shift": "shift_kernel",
-                  "combine": "combine_cols", "combine_deep": "combine_deep",
+                  "combine": "combine_cols", "combine_deep": "combine_deep<false>",
+                  "combine_missing": "combine_deep<true>", "mask_shifted": "mask_shifted",
                   "shift_spline": ("spline_rows", "spline_cols")}  # one call = both passes
 
 
@@ -350,6 +355,43 @@ def many_stacks(torch, rd, reps=2):
     return res
 
 
+def sweep(torch, rd, reps=3):
+    """Time of the batched path while the image side N grows at n = 300 frames (three
+    stacks of 100), and while the frame count n grows at N = 1020 (stacks of at most 100
+    frames), as the two sweeps of the paper's Section 3.2.2; frames rendered on the GPU
+    at the star density of the 1024x1024 stacks, shifts within +-16 px, search radius 17,
+    the search shapes the library picks without tuning."""
+    from collections import namedtuple
+    Spec = namedtuple("Spec", "N W H n_stars radius")
+
+    def run(side, counts):
+        specs = [Spec(c, side, side, max(8, round(200 * side * side / 1024 ** 2)), 17) for c in counts]
+        stacks, _ = many_stack_inputs(torch, rd, specs)
+        batch = rd.StackBatch(stacks)
+        batch.run()
+        torch.cuda.synchronize()
+        rd.prof_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            batch.run()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        ms, n = rd.prof_query("batch_score")
+        rd.prof_enable(False)
+        pix = sum(c * side * side for c in counts)
+        res = {"N": side, "n": sum(counts), "stacks": len(counts), "ms_per_call": round(dt * 1e3, 3),
+               "Mpix/s": round(pix / dt / 1e6, 1), "search_share": round(ms / n / 1e3 / dt, 3)}
+        del batch, stacks
+        torch.cuda.empty_cache()
+        return res
+
+    out = {"sizes": [run(side, [100, 100, 100]) for side in (256, 512, 1020, 2048, 4096)], "counts": []}
+    for n in (30, 90, 300, 600, 900, 1500):
+        per = min(100, n // 3)
+        out["counts"].append(run(1020, [per] * (n // per)))
+    return out
+
+
 def learned_comparison(torch, rd, weights_path, M):
     """Full +-64 px search vs network proposal + +-2 px search + fallbacks on one stack of
     4096x4096 frames (a reference and M shifted frames, shifts uniform in +-64 px)."""
@@ -393,8 +435,9 @@ def learned_comparison(torch, rd, weights_path, M):
 def streaming_wide(torch, rd, reps=5, traffic_path=os.path.join(ROOT, "profiles", "traffic.json")):
     """calibrate, shift (bilinear, and the bicubic spline timed alone) and combine over 16
     frames of 6144x6160 (working sets of 1.2-2.4 GB, far beyond the 256 MB last-level
-    cache), and the combine of a 97-frame stack (the deepest co-adding set of the paper)
-    of 2048x2048, timed with HIP events on their stream."""
+    cache), bad-pixel masking with the missing-value combine, and the combine of a
+    97-frame stack (the deepest co-adding set of the paper) of 2040x2040, timed with
+    HIP events on their stream."""
     from paper_2008_11486_amd import learned
     N, W, H, bound = 16, 6144, 6160, 64.0
     dev = torch.device("cuda:0")
@@ -435,11 +478,16 @@ def streaming_wide(torch, rd, reps=5, traffic_path=os.path.join(ROOT, "profiles"
     deep.add_(dh * (5e3 + 5.5e4 * torch.rand((ND, SD, SD), generator=g, device=dev)))
     del dh
     deep_out = torch.empty((SD, SD), dtype=torch.float32, device=dev)
+    # bad-pixel map: 0.1% of the detector's pixels
+    bad = (torch.rand((H, W), generator=g, device=dev) < 1e-3).to(torch.uint8)
+    out_miss = torch.empty((h, w), dtype=torch.float32, device=dev)
 
     def chain():
         rd.calibrate(raw, dark, flat, out=cal)
         rd.shift(cal, s, rect, out=al)
         rd.combine(al, out=out)
+        rd.mask_shifted(bad, al, s, rect, W, H)  # bad-pixel masking, then the missing-value combine
+        rd.combine(al, out=out_miss, missing=True)
         rd.shift_spline(cal, s, rect, out=al_spline, ws=spline_ws)  # the paper's interpolation, timed alone
         rd.combine(deep, out=deep_out)
 
@@ -451,17 +499,19 @@ def streaming_wide(torch, rd, reps=5, traffic_path=os.path.join(ROOT, "profiles"
         chain()
     torch.cuda.synchronize()
     res = {"workload": f"{N} frames {W}x{H}, 5000 stars, cosmic-ray hits on 0.01% of pixels, shifts +-64 px, "
-                       f"overlap {w}x{h}; deep combine: {ND} frames {SD}x{SD}"}
+                       f"overlap {w}x{h}, bad pixels 0.1%; deep combine: {ND} frames {SD}x{SD}"}
     byts = {"calibrate": N * W * H * (2 + 4) + 8 * W * H, "shift": N * w * h * (4 + 4), "combine": N * w * h * 4 + w * h * 4,
             # rows: frame read, row-pass result written; columns: that result read, output written
-            "shift_spline": N * 4 * (H * W + 2 * H * w + h * w), "combine_deep": (ND + 1) * SD * SD * 4}
-    for name in ("calibrate", "shift", "combine", "shift_spline", "combine_deep"):
+            "shift_spline": N * 4 * (H * W + 2 * H * w + h * w), "combine_deep": (ND + 1) * SD * SD * 4,
+            # the map (from L2 after the first frame) and the marked values
+            "mask_shifted": H * W + int(torch.isnan(al).sum()) * 4, "combine_missing": N * w * h * 4 + w * h * 4}
+    for name in ("calibrate", "shift", "combine", "shift_spline", "combine_deep", "mask_shifted", "combine_missing"):
         ms, n = rd.prof_query(name)
         gbs = byts[name] / (ms / n / 1e3) / 1e9
         res[name] = {"avg_launch_ms": round(ms / n, 4), "bytes": byts[name], "GB/s": round(gbs, 1),
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(traffic_path, name, "wide")}
     rd.prof_enable(False)
-    del raw, cal, al, al_spline, spline_ws, deep, deep_out
+    del raw, cal, al, al_spline, spline_ws, deep, deep_out, bad, out_miss
     torch.cuda.empty_cache()
     return res
 
@@ -516,6 +566,10 @@ def main():
     if args.wide_only:
         rd.lib()
         print(json.dumps({"streaming_wide": streaming_wide(torch, rd)}))
+        return 0
+    if args.sweep:
+        rd.lib()
+        print(json.dumps({"sweep": sweep(torch, rd)}))
         return 0
     rd.lib()
     stacks = synth.make_config(args.workload)

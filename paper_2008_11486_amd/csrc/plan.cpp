@@ -207,6 +207,16 @@ RegPlan reg_plan(int32_t W, int32_t H, int32_t R, int32_t Rmax, int32_t K_force,
     if (!K_force && !TY_force && env_int("REDUCE_REG_GENERAL") != 1 && reg_plan_small(W, H, R, Rmax, &p)) return p;
     if (!K_force && !TY_force && tuned_reg_shape(W, H, R, Rmax, &sh) && reg_plan_from_shape(W, H, R, Rmax, sh, &p))
         return p;
+    // the model's choice depends only on the arguments: searched once per key (the
+    // search scores every candidate shape, milliseconds of host time)
+    static std::mutex mu;
+    static std::map<std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t, int32_t>, RegPlan> chosen;
+    const auto key = std::make_tuple(W, H, R, Rmax, K_force, TY_force);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        const auto it = chosen.find(key);
+        if (it != chosen.end()) return it->second;
+    }
     std::vector<std::pair<double, RegShape>> shapes;
     all_shapes(W, H, R, Rmax, K_force, TY_force, &shapes);
     if (shapes.empty()) all_shapes(W, H, R, Rmax, 0, 0, &shapes);
@@ -220,6 +230,8 @@ RegPlan reg_plan(int32_t W, int32_t H, int32_t R, int32_t Rmax, int32_t K_force,
         // a window too large for any shape: leave D = 0 so the caller reports it
         p = RegPlan{};
     }
+    std::lock_guard<std::mutex> lk(mu);
+    chosen[key] = p;
     return p;
 }
 

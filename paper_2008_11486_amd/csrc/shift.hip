@@ -21,17 +21,39 @@ __global__ __launch_bounds__(SH_BLOCK) void shift_kernel(
                                  h, (int64_t)w * h, vec_store, aligned);
 }
 
-// Grid (ceil(w / 256), h, N): one thread per output pixel.
+// Grid (ceil(w / 2048), h, N): a thread checks 8 consecutive outputs of a row against
+// the bad-pixel map (the bytes of one mask row serve all 8), and writes only the outputs
+// that read a bad pixel.
+constexpr int MASK_PX = 8;
+
 __global__ __launch_bounds__(256) void mask_shifted_kernel(const uint8_t *__restrict__ mask, float *__restrict__ out,
                                                            int32_t W, int32_t H, const float *__restrict__ offs,
                                                            int32_t x0, int32_t y0, int32_t w, int32_t h,
                                                            int integer)
 {
-    const int32_t u = blockIdx.x * 256 + threadIdx.x, v = blockIdx.y, k = blockIdx.z;
-    if (u >= w) return;
+    const int32_t u0 = (blockIdx.x * 256 + threadIdx.x) * MASK_PX, v = blockIdx.y, k = blockIdx.z;
+    if (u0 >= w) return;
     const ShiftSetup ss = shift_setup(offs[2 * k], offs[2 * k + 1]);
-    if (reads_bad_pixel(mask, W, H, ss, integer != 0, x0 + u, y0 + v))
-        out[((int64_t)k * h + v) * w + u] = __builtin_nanf("");
+    const bool sx = !integer && ss.a > 0.0, sy = !integer && ss.b > 0.0;
+    const int32_t j = clampi(y0 + v + ss.iy, 0, H - 1);
+    const int32_t j1 = sy ? clampi(j + 1, 0, H - 1) : j;
+    const uint8_t *r0 = mask + (int64_t)j * W, *r1 = mask + (int64_t)j1 * W;
+    // column c = x0 + u0 + ix + e, e = 0 .. MASK_PX: bad if either tap row has it
+    uint32_t bad = 0;
+#pragma unroll
+    for (int e = 0; e <= MASK_PX; ++e) {
+        const int32_t c = clampi(x0 + u0 + ss.ix + e, 0, W - 1);
+        bad |= (uint32_t)((r0[c] | r1[c]) != 0) << e;
+    }
+    if (!bad) return;
+    float *row = out + ((int64_t)k * h + v) * w;
+#pragma unroll
+    for (int e = 0; e < MASK_PX; ++e) {
+        // output u0 + e reads the clamped columns of bits e and, when the x fraction is
+        // non-zero, e + 1
+        const bool hit = ((bad >> e) & 1u) || (sx && ((bad >> (e + 1)) & 1u));
+        if (u0 + e < w && hit) row[u0 + e] = __builtin_nanf("");
+    }
 }
 
 }  // namespace rd
@@ -71,7 +93,7 @@ extern "C" int reduce_mask_shifted(const uint8_t *mask, float *out, int32_t W, i
     if (N > 65535 || h > 65535) return fail(REDUCE_ERR_UNSUPPORTED, "reduce_mask_shifted: N or h above 65535");
     hipStream_t s = as_stream(stream);
     ProfScope prof("mask_shifted", s);
-    hipLaunchKernelGGL(mask_shifted_kernel, dim3((unsigned)ceil_div(w, 256), (unsigned)h, (unsigned)N), dim3(256), 0,
-                       s, mask, out, W, H, offs, x0, y0, w, h, integer_mode ? 1 : 0);
+    hipLaunchKernelGGL(mask_shifted_kernel, dim3((unsigned)ceil_div(w, 256 * MASK_PX), (unsigned)h, (unsigned)N),
+                       dim3(256), 0, s, mask, out, W, H, offs, x0, y0, w, h, integer_mode ? 1 : 0);
     return check_launch("reduce_mask_shifted");
 }

@@ -105,3 +105,12 @@ def test_stack_batch_workspace_query_is_host_only(rd):
     assert rd.lib().reduce_stack_batch_ws((rd.StackDesc * 1)(bad), 1) == 0
     assert rd.lib().reduce_stack_batch(None, 1, None, 0, None) == rd.ERR_NULL
     assert rd.lib().reduce_stack_batch((rd.StackDesc * 1)(bad), 1, C.c_void_p(b), 1 << 40, None) == rd.ERR_RANGE
+
+
+def test_spline_workspace_holds_padded_rows(rd):
+    """The row pass's result sits at a pitch of w rounded up to 64 floats, for any w <= W."""
+    L = rd.lib()
+    for W, H, N in ((1, 1, 1), (63, 5, 2), (64, 7, 3), (6144, 6160, 16), (1000, 3, 4)):
+        need = 4 * N * H * ((W + 63) // 64 * 64)
+        assert L.reduce_shift_spline_ws(W, H, N) >= need
+    assert L.reduce_shift_spline_ws(0, 4, 4) == 0

@@ -101,8 +101,9 @@ KERNEL_SOURCES = {
 KERNEL_SYMBOLS = {"batch_score": "batch_score", "batch_shift": "batch_shift", "batch_comb": "batch_comb",
                   "batch_cal": "batch_cal", "score_tiles": "score_tiles", "calibrate": "calibrate_",
                   "shift": "shift_kernel",
-                  "combine": "combine_cols", "combine_deep": "combine_deep<false>",
-                  "combine_missing": "combine_deep<true>", "mask_shifted": "mask_shifted",
+                  # a list: every part must appear in the kernel name
+                  "combine": ["combine_cols<", "false>"], "combine_deep": "combine_deep<false>",
+                  "combine_missing": ["combine_cols<", "true>"], "mask_shifted": "mask_shifted",
                   "shift_spline": ("spline_rows", "spline_cols")}  # one call = both passes
 
 
@@ -143,8 +144,9 @@ def traffic_from(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, workload,
         fetch = write = 0.0
         dispatches = None
         for sym in syms:
-            fv = [v for n, v in fr if sym in n]
-            wv = [v for n, v in wr if sym in n]
+            parts = sym if isinstance(sym, list) else [sym]
+            fv = [v for n, v in fr if all(q in n for q in parts)]
+            wv = [v for n, v in wr if all(q in n for q in parts)]
             if not fv or not wv:
                 break
             fetch += sum(fv) / len(fv) * 1024 * fs

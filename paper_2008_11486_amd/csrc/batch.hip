@@ -54,7 +54,7 @@ __host__ __device__ inline int64_t al_plane(int64_t w, int64_t h) { return (w * 
 
 enum ItemType : int32_t {
     IT_CAL = 0, IT_MEANPART, IT_MEANFINAL, IT_SCORE, IT_SSCORE, IT_SUM, IT_PICK, IT_RECT, IT_SHIFT, IT_MASK,
-    IT_COMB16, IT_COMB32, IT_COMB48, IT_COMBDEEP, IT_COMBMISS
+    IT_COMB16, IT_COMB32, IT_COMB48, IT_COMBDEEP, IT_COMB16M, IT_COMB32M, IT_COMB48M, IT_COMBMISS
 };
 constexpr int N_PHASES = IT_COMBMISS + 1;
 
@@ -235,7 +235,7 @@ __global__ __launch_bounds__(SH_BLOCK) void batch_shift(BatchArgs a, int32_t fir
 
 // Sigma-clipped mean of block it.a of the stack's overlap; PX pixel columns per thread
 // when the overlap plane allows vector loads, else one.
-template <int MAXV, int PX>
+template <int MAXV, int PX, bool MISS>
 __global__ __launch_bounds__(COMB_TILE) void batch_comb(BatchArgs a, int32_t first)
 {
     const Item it = a.items[first + blockIdx.x];
@@ -248,11 +248,11 @@ __global__ __launch_bounds__(COMB_TILE) void batch_comb(BatchArgs a, int32_t fir
     if (it.a >= blocks) return;  // uniform over the workgroup
     unsigned dropped;
     if (vec)
-        dropped = combine_cols_block<MAXV, PX>(s.al, plane, pstride, s.N, (double)s.ksigma, s.max_iters, s.out,
-                                               nullptr, it.a);
+        dropped = combine_cols_block<MAXV, PX, MISS>(s.al, plane, pstride, s.N, (double)s.ksigma, s.max_iters,
+                                                     s.out, nullptr, it.a);
     else
-        dropped = combine_cols_block<MAXV, 1>(s.al, plane, pstride, s.N, (double)s.ksigma, s.max_iters, s.out,
-                                              nullptr, it.a);
+        dropped = combine_cols_block<MAXV, 1, MISS>(s.al, plane, pstride, s.N, (double)s.ksigma, s.max_iters, s.out,
+                                                    nullptr, it.a);
     if (s.n_rej) {
         const unsigned total = block_sum_u32(dropped);
         if (threadIdx.x == 0 && total) atomicAdd(reinterpret_cast<unsigned long long *>(s.n_rej),
@@ -373,7 +373,7 @@ static BatchLayout layout_of(const reduce_stack_t *stacks, int32_t n)
     for (int p = 0; p < N_PHASES; ++p) L.count[p] = 0;
     for (int32_t i = 0; i < n; ++i) {
         const reduce_stack_t &s = stacks[i];
-        StackLayout sl;
+        StackLayout sl{};  // every phase count starts at zero
         sl.plan = reg_plan(s.W, s.H, s.radius, s.radius);
         const RegPlan &p = sl.plan;
         const int64_t fp = (int64_t)s.W * s.H;
@@ -414,14 +414,15 @@ static BatchLayout layout_of(const reduce_stack_t *stacks, int32_t n)
         // that leaves missing values out
         const bool miss = s.mask != nullptr;
         sl.count[IT_MASK] = miss ? s.N * s.H : 0;
-        sl.count[IT_COMB16] = !miss && s.N <= 16 ? comb_blocks : 0;
-        sl.count[IT_COMB32] = !miss && s.N > 16 && s.N <= 32 ? comb_blocks : 0;
-        sl.count[IT_COMB48] = !miss && s.N > 32 && s.N <= 48 ? comb_blocks : 0;
-        const int32_t deep_blocks = (int32_t)ceil_div(fp, (int64_t)COMB_DEEP_PX);
-        sl.count[IT_COMBDEEP] = !miss && s.N > 48 ? deep_blocks : 0;
-        sl.count[IT_COMBMISS] = miss ? deep_blocks : 0;
-        if (!miss && s.N > 48) L.deep_n = std::max(L.deep_n, s.N);
-        if (miss) L.miss_n = std::max(L.miss_n, s.N);
+        const int32_t c16 = s.N <= 16 ? comb_blocks : 0;
+        const int32_t c32 = s.N > 16 && s.N <= 32 ? comb_blocks : 0;
+        const int32_t c48 = s.N > 32 && s.N <= 48 ? comb_blocks : 0;
+        const int32_t deep_blocks = s.N > 48 ? (int32_t)ceil_div(fp, (int64_t)COMB_DEEP_PX) : 0;
+        sl.count[miss ? IT_COMB16M : IT_COMB16] = c16;
+        sl.count[miss ? IT_COMB32M : IT_COMB32] = c32;
+        sl.count[miss ? IT_COMB48M : IT_COMB48] = c48;
+        sl.count[miss ? IT_COMBMISS : IT_COMBDEEP] = deep_blocks;
+        if (s.N > 48) (miss ? L.miss_n : L.deep_n) = std::max(miss ? L.miss_n : L.deep_n, s.N);
         for (int q = 0; q < N_PHASES; ++q) L.count[q] += sl.count[q];
         if (nreg > 0 && p.K != 0) L.score_lds = std::max(L.score_lds, p.lds);
         L.st.push_back(sl);
@@ -615,14 +616,23 @@ static int launch_phases(int32_t n, void *ws, const BatchLayout &L, hipStream_t 
     {
         ProfScope prof("batch_comb", s);
         if (L.count[IT_COMB16] > 0)
-            hipLaunchKernelGGL((batch_comb<16, COMB_PX16>), dim3(L.count[IT_COMB16]), dim3(COMB_TILE), 0, s, a,
-                               L.first[IT_COMB16]);
+            hipLaunchKernelGGL((batch_comb<16, COMB_PX16, false>), dim3(L.count[IT_COMB16]), dim3(COMB_TILE), 0, s,
+                               a, L.first[IT_COMB16]);
         if (L.count[IT_COMB32] > 0)
-            hipLaunchKernelGGL((batch_comb<32, COMB_PX32>), dim3(L.count[IT_COMB32]), dim3(COMB_TILE), 0, s, a,
-                               L.first[IT_COMB32]);
+            hipLaunchKernelGGL((batch_comb<32, COMB_PX32, false>), dim3(L.count[IT_COMB32]), dim3(COMB_TILE), 0, s,
+                               a, L.first[IT_COMB32]);
         if (L.count[IT_COMB48] > 0)
-            hipLaunchKernelGGL((batch_comb<48, 1>), dim3(L.count[IT_COMB48]), dim3(COMB_TILE), 0, s, a,
+            hipLaunchKernelGGL((batch_comb<48, 1, false>), dim3(L.count[IT_COMB48]), dim3(COMB_TILE), 0, s, a,
                                L.first[IT_COMB48]);
+        if (L.count[IT_COMB16M] > 0)
+            hipLaunchKernelGGL((batch_comb<16, COMB_PX16, true>), dim3(L.count[IT_COMB16M]), dim3(COMB_TILE), 0, s,
+                               a, L.first[IT_COMB16M]);
+        if (L.count[IT_COMB32M] > 0)
+            hipLaunchKernelGGL((batch_comb<32, COMB_PX32, true>), dim3(L.count[IT_COMB32M]), dim3(COMB_TILE), 0, s,
+                               a, L.first[IT_COMB32M]);
+        if (L.count[IT_COMB48M] > 0)
+            hipLaunchKernelGGL((batch_comb<48, 1, true>), dim3(L.count[IT_COMB48M]), dim3(COMB_TILE), 0, s, a,
+                               L.first[IT_COMB48M]);
         if (L.count[IT_COMBDEEP] > 0)
             hipLaunchKernelGGL(batch_comb_deep<false>, dim3(L.count[IT_COMBDEEP]), dim3(COMB_DEEP_PX),
                                sizeof(float) * L.deep_n * COMB_DEEP_PX, s, a, L.first[IT_COMBDEEP]);

@@ -35,14 +35,14 @@ __global__ __launch_bounds__(COMB_TILE) void combine_kernel(
 }
 
 // PX adjacent pixel columns per thread (combine_cols_block); one atomic per workgroup
-// for the rejection count.
-template <int MAXV, int PX>
+// for the rejection count.  MISS: NaN values are missing.
+template <int MAXV, int PX, bool MISS>
 __global__ __launch_bounds__(COMB_TILE) void combine_cols(
     const float *__restrict__ aligned, int64_t plane, int32_t N, double ksigma, int32_t max_iters,
     float *__restrict__ out, uint8_t *__restrict__ keep, unsigned long long *__restrict__ n_rej)
 {
-    const unsigned dropped = combine_cols_block<MAXV, PX>(aligned, plane, plane, N, ksigma, max_iters, out, keep,
-                                                          (int64_t)blockIdx.x);
+    const unsigned dropped = combine_cols_block<MAXV, PX, MISS>(aligned, plane, plane, N, ksigma, max_iters, out,
+                                                                keep, (int64_t)blockIdx.x);
     if (n_rej) {
         const unsigned total = block_sum_u32(dropped);
         if (threadIdx.x == 0 && total) atomicAdd(n_rej, (unsigned long long)total);
@@ -92,6 +92,37 @@ static void launch_deep(bool missing, const float *aligned, int64_t plane, int32
                            max_iters, out, keep, n_rej);
 }
 
+// One lane per column (missing = 1 takes only this path): registers up to 48 frames,
+// the LDS-column kernel past that.
+template <bool MISS>
+static void dispatch_cols(const float *aligned, int64_t plane, int32_t N, double ksigma, int32_t max_iters,
+                          float *out, uint8_t *keep, unsigned long long *n_rej, hipStream_t s)
+{
+    // vector loads need the frame planes and the pointer aligned to the pixel group
+    const bool v4 = plane % 4 == 0 && (reinterpret_cast<uintptr_t>(aligned) & 15u) == 0 &&
+                    (reinterpret_cast<uintptr_t>(out) & 15u) == 0;
+    const bool v2 = plane % 2 == 0 && (reinterpret_cast<uintptr_t>(aligned) & 7u) == 0 &&
+                    (reinterpret_cast<uintptr_t>(out) & 7u) == 0;
+    auto launch_cols = [&](auto Vc, auto Pc) {
+        constexpr int V = decltype(Vc)::value, P = decltype(Pc)::value;
+        hipLaunchKernelGGL((combine_cols<V, P, MISS>), dim3((unsigned)ceil_div(plane, (int64_t)COMB_TILE * P)),
+                           dim3(COMB_TILE), 0, s, aligned, plane, N, ksigma, max_iters, out, keep, n_rej);
+    };
+    const int px = combine_px();
+    if (N <= 16) {
+        if (v4 && px >= 4) launch_cols(std::integral_constant<int, 16>{}, std::integral_constant<int, 4>{});
+        else if (v2 && px >= 2) launch_cols(std::integral_constant<int, 16>{}, std::integral_constant<int, 2>{});
+        else launch_cols(std::integral_constant<int, 16>{}, std::integral_constant<int, 1>{});
+    } else if (N <= 32) {
+        if (v2 && px >= 2) launch_cols(std::integral_constant<int, 32>{}, std::integral_constant<int, 2>{});
+        else launch_cols(std::integral_constant<int, 32>{}, std::integral_constant<int, 1>{});
+    } else if (N <= 48) {
+        launch_cols(std::integral_constant<int, 48>{}, std::integral_constant<int, 1>{});
+    } else {
+        launch_deep(MISS, aligned, plane, N, ksigma, max_iters, out, keep, n_rej, s);
+    }
+}
+
 void combine_dispatch(int lanes, const float *aligned, int64_t plane, int32_t N, double ksigma, int32_t max_iters,
                       float *out, uint8_t *keep, unsigned long long *n_rej, hipStream_t s)
 {
@@ -103,32 +134,8 @@ void combine_dispatch(int lanes, const float *aligned, int64_t plane, int32_t N,
         hipLaunchKernelGGL((combine_kernel<L, V>), dim3(blocks), dim3(COMB_TILE), lds, s, aligned, plane, N, ksigma,
                            max_iters, out, keep, n_rej);
     };
-    // vector loads need the frame planes and the pointer aligned to the pixel group
-    const bool v4 = plane % 4 == 0 && (reinterpret_cast<uintptr_t>(aligned) & 15u) == 0 &&
-                    (reinterpret_cast<uintptr_t>(out) & 15u) == 0;
-    const bool v2 = plane % 2 == 0 && (reinterpret_cast<uintptr_t>(aligned) & 7u) == 0 &&
-                    (reinterpret_cast<uintptr_t>(out) & 7u) == 0;
-    auto launch_cols = [&](auto Vc, auto Pc) {
-        constexpr int V = decltype(Vc)::value, P = decltype(Pc)::value;
-        hipLaunchKernelGGL((combine_cols<V, P>), dim3((unsigned)ceil_div(plane, (int64_t)COMB_TILE * P)),
-                           dim3(COMB_TILE), 0, s, aligned, plane, N, ksigma, max_iters, out, keep, n_rej);
-    };
-    const int px = combine_px();
     switch (lanes) {
-    case 1:
-        if (N <= 16) {
-            if (v4 && px >= 4) launch_cols(std::integral_constant<int, 16>{}, std::integral_constant<int, 4>{});
-            else if (v2 && px >= 2) launch_cols(std::integral_constant<int, 16>{}, std::integral_constant<int, 2>{});
-            else launch_cols(std::integral_constant<int, 16>{}, std::integral_constant<int, 1>{});
-        } else if (N <= 32) {
-            if (v2 && px >= 2) launch_cols(std::integral_constant<int, 32>{}, std::integral_constant<int, 2>{});
-            else launch_cols(std::integral_constant<int, 32>{}, std::integral_constant<int, 1>{});
-        } else if (N <= 48) {
-            launch_cols(std::integral_constant<int, 48>{}, std::integral_constant<int, 1>{});
-        } else {
-            launch_deep(false, aligned, plane, N, ksigma, max_iters, out, keep, n_rej, s);
-        }
-        break;
+    case 1: dispatch_cols<false>(aligned, plane, N, ksigma, max_iters, out, keep, n_rej, s); break;
     case 2: launch(std::integral_constant<int, 2>{}, std::integral_constant<int, 24>{}); break;
     case 4: launch(std::integral_constant<int, 4>{}, std::integral_constant<int, 12>{}); break;
     case 8: launch(std::integral_constant<int, 8>{}, std::integral_constant<int, 6>{}); break;
@@ -157,9 +164,9 @@ extern "C" int reduce_combine(const float *aligned, int32_t w, int32_t h, int32_
     unsigned long long *nr = reinterpret_cast<unsigned long long *>(n_rej);
     if (nr) hipLaunchKernelGGL(zero_u64, dim3(1), dim3(1), 0, s, nr);
     if (missing) {
-        // values that are NaN (bad pixels) are left out: the LDS-column kernel at any depth
+        // values that are NaN (bad pixels) are left out: one lane per column
         ProfScope prof("combine_missing", s);
-        launch_deep(true, aligned, (int64_t)w * h, N, (double)ksigma, max_iters, out, keep, nr, s);
+        dispatch_cols<true>(aligned, (int64_t)w * h, N, (double)ksigma, max_iters, out, keep, nr, s);
         return check_launch("reduce_combine");
     }
     // past the LDS tile's depth only the one-lane kernel (column in registers) applies

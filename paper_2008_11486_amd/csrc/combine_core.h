@@ -221,16 +221,26 @@ __device__ __forceinline__ void clip_pass(X x, const KeptBits<MAXV> &kept, int32
 }
 
 // Clip one column; returns the mean and updates kept / dropped.
-template <int MAXV, bool FENCE, typename X>
+// With MISS, NaN values are missing: never kept, not counted as dropped, and n counts
+// the others (a pixel with none gives NaN).
+template <int MAXV, bool FENCE, bool MISS, typename X>
 __device__ __forceinline__ float clip_values(X x, int32_t N, double ksigma, int32_t max_iters, KeptBits<MAXV> &kept,
                                              unsigned &dropped)
 {
     kept.first(N);
     int n = N;
+    if (MISS) {
+#pragma unroll
+        for (int i = 0; i < MAXV; ++i)
+            if (i < N && !(x(i) == x(i))) kept.clear(i);
+        n = 0;
+#pragma unroll
+        for (int j = 0; j < KeptBits<MAXV>::W; ++j) n += __popcll(kept.w[j]);
+    }
     double s = 0.0, m = 0.0, q = 0.0, dmax = 0.0;
     bool final_known = false;
     for (int32_t it = 0; it < max_iters; ++it) {
-        if (it == 0)
+        if (it == 0 && !MISS)
             clip_pass<MAXV, true, FENCE>(x, kept, N, n, s, m, q, dmax);
         else
             clip_pass<MAXV, false, FENCE>(x, kept, N, n, s, m, q, dmax);
@@ -260,18 +270,18 @@ __device__ __forceinline__ float clip_values(X x, int32_t N, double ksigma, int3
     return (float)(s / (double)n);
 }
 
-template <int MAXV>
+template <int MAXV, bool MISS = false>
 __device__ __forceinline__ float clip_registers(const float (&x)[MAXV], int32_t N, double ksigma, int32_t max_iters,
                                                 KeptBits<MAXV> &kept, unsigned &dropped)
 {
-    return clip_values<MAXV, false>([&](int i) { return x[i]; }, N, ksigma, max_iters, kept, dropped);
+    return clip_values<MAXV, false, MISS>([&](int i) { return x[i]; }, N, ksigma, max_iters, kept, dropped);
 }
 
 // PX adjacent pixel columns per thread: each frame's PX values come in as one vector
 // load (frame k's plane starts at aligned + k * pstride; pstride >= plane, and pstride
 // and the pointers aligned to PX floats), then the columns are clipped one after the
 // other.  Columns at or past `plane` are neither written nor counted.
-template <int MAXV, int PX>
+template <int MAXV, int PX, bool MISS = false>
 __device__ __forceinline__ unsigned combine_cols_block(const float *__restrict__ aligned, int64_t plane,
                                                        int64_t pstride, int32_t N, double ksigma, int32_t max_iters,
                                                        float *__restrict__ out, uint8_t *__restrict__ keep,
@@ -315,7 +325,7 @@ __device__ __forceinline__ unsigned combine_cols_block(const float *__restrict__
 #pragma unroll
     for (int c = 0; c < PX; ++c) {
         unsigned d = 0;
-        res[c] = clip_registers<MAXV>(xs[c], N, ksigma, max_iters, kept[c], d);
+        res[c] = clip_registers<MAXV, MISS>(xs[c], N, ksigma, max_iters, kept[c], d);
         if (p0 + c < plane) dropped += d;
     }
     if (PX > 1 && p0 + PX <= plane) {

@@ -260,13 +260,14 @@ __global__ __launch_bounds__(COMB_TILE) void batch_comb(BatchArgs a, int32_t fir
     }
 }
 
-// Row v = it.a % H of frame k = it.a / H of a stack with a bad-pixel map: aligned values
-// that read a bad pixel become NaN (missing in the combine).
+// Row v = it.a / N of frame k = it.a % N of a stack with a bad-pixel map (the frames
+// of a row consecutive, so that they share the map rows in L2): aligned values that
+// read a bad pixel become NaN (missing in the combine).
 __global__ __launch_bounds__(256) void batch_mask(BatchArgs a, int32_t first)
 {
     const Item it = a.items[first + blockIdx.x];
     const StackDev &s = a.stacks[it.stack];
-    const int32_t k = it.a / s.H, v = it.a - k * s.H;
+    const int32_t v = it.a / s.N, k = it.a - v * s.N;
     const int32_t x0 = s.rect[0], y0 = s.rect[1], w = s.rect[2], h = s.rect[3];
     if (v >= h) return;  // uniform over the workgroup
     const ShiftSetup ss = shift_setup(s.soffs[2 * k], s.soffs[2 * k + 1]);

@@ -21,39 +21,61 @@ __global__ __launch_bounds__(SH_BLOCK) void shift_kernel(
                                  h, (int64_t)w * h, vec_store, aligned);
 }
 
-// Grid (ceil(w / 2048), h, N): a thread checks 8 consecutive outputs of a row against
-// the bad-pixel map (the bytes of one mask row serve all 8), and writes only the outputs
-// that read a bad pixel.
-constexpr int MASK_PX = 8;
+// Grid (N * ceil(w / 8192), h), the frame index fastest: the workgroups of one output
+// row of all frames run together and read the same few map rows (one frame's offset
+// apart) from L2.  A thread checks 32 consecutive outputs of a row: the map bytes of the
+// 33 columns they read in each tap row come in as ten 4-byte words (when the span lies
+// inside the row and the rows are 4-byte aligned; byte by byte, clamped, otherwise), a
+// word's four bytes become four "bad" bits, and the thread writes only the outputs
+// whose taps hold a bad pixel.
+constexpr int MASK_PX = 32;
+
+// bit i (i < 4) set when byte i of v is non-zero
+__device__ __forceinline__ uint32_t nonzero_bytes(uint32_t v)
+{
+    const uint32_t t = (v | ((v & 0x7f7f7f7fu) + 0x7f7f7f7fu)) & 0x80808080u;
+    return ((t >> 7) & 1u) | ((t >> 14) & 2u) | ((t >> 21) & 4u) | ((t >> 28) & 8u);
+}
+
+// bit e (e <= MASK_PX) set when map row r is bad at column clamp(c0 + e)
+__device__ __forceinline__ uint64_t bad_columns(const uint8_t *__restrict__ r, int32_t c0, int32_t W, bool words)
+{
+    uint64_t m = 0;
+    if (words && c0 >= 0 && c0 + 40 <= W) {
+        const int32_t base = c0 & ~3, off = c0 - base;
+        const uint32_t *p = reinterpret_cast<const uint32_t *>(r + base);
+#pragma unroll
+        for (int i = 0; i < 10; ++i) m |= (uint64_t)nonzero_bytes(p[i]) << (4 * i);
+        return m >> off;
+    }
+#pragma unroll
+    for (int e = 0; e <= MASK_PX; ++e) m |= (uint64_t)(r[clampi(c0 + e, 0, W - 1)] != 0) << e;
+    return m;
+}
 
 __global__ __launch_bounds__(256) void mask_shifted_kernel(const uint8_t *__restrict__ mask, float *__restrict__ out,
                                                            int32_t W, int32_t H, const float *__restrict__ offs,
                                                            int32_t x0, int32_t y0, int32_t w, int32_t h,
-                                                           int integer)
+                                                           int32_t N, int integer)
 {
-    const int32_t u0 = (blockIdx.x * 256 + threadIdx.x) * MASK_PX, v = blockIdx.y, k = blockIdx.z;
+    const int32_t k = blockIdx.x % N, xb = blockIdx.x / N, v = blockIdx.y;
+    const int32_t u0 = (xb * 256 + threadIdx.x) * MASK_PX;
     if (u0 >= w) return;
     const ShiftSetup ss = shift_setup(offs[2 * k], offs[2 * k + 1]);
     const bool sx = !integer && ss.a > 0.0, sy = !integer && ss.b > 0.0;
     const int32_t j = clampi(y0 + v + ss.iy, 0, H - 1);
     const int32_t j1 = sy ? clampi(j + 1, 0, H - 1) : j;
-    const uint8_t *r0 = mask + (int64_t)j * W, *r1 = mask + (int64_t)j1 * W;
-    // column c = x0 + u0 + ix + e, e = 0 .. MASK_PX: bad if either tap row has it
-    uint32_t bad = 0;
-#pragma unroll
-    for (int e = 0; e <= MASK_PX; ++e) {
-        const int32_t c = clampi(x0 + u0 + ss.ix + e, 0, W - 1);
-        bad |= (uint32_t)((r0[c] | r1[c]) != 0) << e;
-    }
-    if (!bad) return;
+    const bool words = (W & 3) == 0 && (reinterpret_cast<uintptr_t>(mask) & 3u) == 0;
+    const int32_t c0 = x0 + u0 + ss.ix;
+    uint64_t bad = bad_columns(mask + (int64_t)j * W, c0, W, words);
+    if (j1 != j) bad |= bad_columns(mask + (int64_t)j1 * W, c0, W, words);
+    // output e reads the clamped columns of bits e and, when the x fraction is non-zero, e + 1
+    const uint32_t hit = (uint32_t)(bad | (sx ? bad >> 1 : 0ull));
+    if (!hit) return;
     float *row = out + ((int64_t)k * h + v) * w;
-#pragma unroll
-    for (int e = 0; e < MASK_PX; ++e) {
-        // output u0 + e reads the clamped columns of bits e and, when the x fraction is
-        // non-zero, e + 1
-        const bool hit = ((bad >> e) & 1u) || (sx && ((bad >> (e + 1)) & 1u));
-        if (u0 + e < w && hit) row[u0 + e] = __builtin_nanf("");
-    }
+#pragma unroll 4
+    for (int e = 0; e < MASK_PX; ++e)
+        if (((hit >> e) & 1u) && u0 + e < w) row[u0 + e] = __builtin_nanf("");
 }
 
 }  // namespace rd
@@ -93,7 +115,7 @@ extern "C" int reduce_mask_shifted(const uint8_t *mask, float *out, int32_t W, i
     if (N > 65535 || h > 65535) return fail(REDUCE_ERR_UNSUPPORTED, "reduce_mask_shifted: N or h above 65535");
     hipStream_t s = as_stream(stream);
     ProfScope prof("mask_shifted", s);
-    hipLaunchKernelGGL(mask_shifted_kernel, dim3((unsigned)ceil_div(w, 256 * MASK_PX), (unsigned)h, (unsigned)N),
-                       dim3(256), 0, s, mask, out, W, H, offs, x0, y0, w, h, integer_mode ? 1 : 0);
+    hipLaunchKernelGGL(mask_shifted_kernel, dim3((unsigned)(N * ceil_div(w, 256 * MASK_PX)), (unsigned)h), dim3(256),
+                       0, s, mask, out, W, H, offs, x0, y0, w, h, N, integer_mode ? 1 : 0);
     return check_launch("reduce_mask_shifted");
 }

@@ -280,7 +280,7 @@ __global__ __launch_bounds__(256) void batch_mask(BatchArgs a, int32_t first)
 // of 64 pixel columns, values in LDS [N][64] (the launch sizes the tile for the deepest
 // stack of the phase).
 template <bool MISS>
-__global__ __launch_bounds__(COMB_DEEP_PX) void batch_comb_deep(BatchArgs a, int32_t first)
+__global__ __launch_bounds__(COMB_DEEP_PX) __attribute__((amdgpu_waves_per_eu(3))) void batch_comb_deep(BatchArgs a, int32_t first)
 {
     extern __shared__ float tile[];
     const Item it = a.items[first + blockIdx.x];
@@ -636,10 +636,10 @@ static int launch_phases(int32_t n, void *ws, const BatchLayout &L, hipStream_t 
                                L.first[IT_COMB48M]);
         if (L.count[IT_COMBDEEP] > 0)
             hipLaunchKernelGGL(batch_comb_deep<false>, dim3(L.count[IT_COMBDEEP]), dim3(COMB_DEEP_PX),
-                               sizeof(float) * L.deep_n * COMB_DEEP_PX, s, a, L.first[IT_COMBDEEP]);
+                               sizeof(float) * (L.deep_n - COMB_DEEP_REG) * COMB_DEEP_PX, s, a, L.first[IT_COMBDEEP]);
         if (L.count[IT_COMBMISS] > 0)
             hipLaunchKernelGGL(batch_comb_deep<true>, dim3(L.count[IT_COMBMISS]), dim3(COMB_DEEP_PX),
-                               sizeof(float) * L.miss_n * COMB_DEEP_PX, s, a, L.first[IT_COMBMISS]);
+                               sizeof(float) * (L.miss_n - COMB_DEEP_REG) * COMB_DEEP_PX, s, a, L.first[IT_COMBMISS]);
     }
     return check_launch("reduce_stack_batch");
 }

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(COMB_TILE) void combine_cols(
 // Stacks of 49 - 128 frames, and stacks with missing values: 64 pixel columns per
 // workgroup, values in LDS [N][64].
 template <bool MISS>
-__global__ __launch_bounds__(COMB_DEEP_PX) void combine_deep(
+__global__ __launch_bounds__(COMB_DEEP_PX) __attribute__((amdgpu_waves_per_eu(3))) void combine_deep(
     const float *__restrict__ aligned, int64_t plane, int32_t N, double ksigma, int32_t max_iters,
     float *__restrict__ out, uint8_t *__restrict__ keep, unsigned long long *__restrict__ n_rej)
 {
@@ -83,7 +83,7 @@ static void launch_deep(bool missing, const float *aligned, int64_t plane, int32
                         int32_t max_iters, float *out, uint8_t *keep, unsigned long long *n_rej, hipStream_t s)
 {
     const dim3 grid((unsigned)ceil_div(plane, (int64_t)COMB_DEEP_PX));
-    const size_t lds = sizeof(float) * N * COMB_DEEP_PX;
+    const size_t lds = sizeof(float) * (N - COMB_DEEP_REG) * COMB_DEEP_PX;
     if (missing)
         hipLaunchKernelGGL(combine_deep<true>, grid, dim3(COMB_DEEP_PX), lds, s, aligned, plane, N, ksigma, max_iters,
                            out, keep, n_rej);

@@ -350,8 +350,9 @@ __device__ __forceinline__ unsigned combine_cols_block(const float *__restrict__
 }
 
 // Stacks deeper than a register column: a 64-thread workgroup, one thread per pixel
-// column, whose N values wait in the thread's own slice of an LDS tile [N][64] (each
-// thread writes and reads only its own column, so no barrier is needed).  The frames
+// column; the first 32 values of a column stay in registers, the others wait in the
+// thread's own slice of an LDS tile [N - 32][64] (each thread writes and reads only its
+// own column, so no barrier is needed).  The frames
 // come in batches of 32 loads in flight; the passes loop over the frames at run time
 // with the kept flags in two 64-bit words.  Same arithmetic, in the same order, as
 // clip_values (sums over the kept values in frame order, m = s / n, the squared
@@ -360,19 +361,27 @@ __device__ __forceinline__ unsigned combine_cols_block(const float *__restrict__
 // none gives NaN).
 constexpr int COMB_DEEP_PX = 64;
 constexpr int COMB_DEEP_BATCH = 64;  // the most loads a wave keeps in flight
+constexpr int COMB_DEEP_REG = 32;    // the first values of a column stay in registers
+static_assert(COMB_DEEP_REG < COMB_MAX_N + 1, "the LDS-column kernels serve stacks deeper than COMB_MAX_N");
 
 // f(i, x_i, kept_i) for the values of a column in frame order (f selects rather than
-// branches on kept_i); the kept flags are bit i of k0 (i < 64) and bit i - 64 of k1.
+// branches on kept_i): values 0 .. COMB_DEEP_REG-1 from xr, the others from the LDS
+// slice col (value i at col[(i - COMB_DEEP_REG) * COMB_DEEP_PX]); the kept flags are
+// bit i of k0 (i < 64) and bit i - 64 of k1.  N > COMB_DEEP_REG.
 template <typename F>
-__device__ __forceinline__ void deep_each(const float *col, uint64_t k0, uint64_t k1, int32_t N, F f)
+__device__ __forceinline__ void deep_each(const float (&xr)[COMB_DEEP_REG], const float *col, uint64_t k0,
+                                          uint64_t k1, int32_t N, F f)
 {
-    uint64_t w = k0;
+#pragma unroll
+    for (int i = 0; i < COMB_DEEP_REG; ++i) f(i, (double)xr[i], ((k0 >> i) & 1ull) != 0);
+    uint64_t w = k0 >> COMB_DEEP_REG;
     const int32_t n0 = min(N, 64);
 #pragma unroll 4
-    for (int i = 0; i < n0; ++i, w >>= 1) f(i, (double)col[i * COMB_DEEP_PX], (w & 1ull) != 0);
+    for (int i = COMB_DEEP_REG; i < n0; ++i, w >>= 1)
+        f(i, (double)col[(i - COMB_DEEP_REG) * COMB_DEEP_PX], (w & 1ull) != 0);
     w = k1;
 #pragma unroll 4
-    for (int i = 64; i < N; ++i, w >>= 1) f(i, (double)col[i * COMB_DEEP_PX], (w & 1ull) != 0);
+    for (int i = 64; i < N; ++i, w >>= 1) f(i, (double)col[(i - COMB_DEEP_REG) * COMB_DEEP_PX], (w & 1ull) != 0);
 }
 
 template <bool MISS>
@@ -384,21 +393,26 @@ __device__ __forceinline__ unsigned combine_deep_block(const float *__restrict__
     const int t = threadIdx.x;
     const int64_t p = block * COMB_DEEP_PX + t;
     const float *src = aligned + (p < plane ? p : plane - 1);
-    float *col = tile + t;
+    float *col = tile + t;  // values COMB_DEEP_REG .. N-1 (the tile is [N - COMB_DEEP_REG][64])
+    float xr[COMB_DEEP_REG];
     for (int32_t i0 = 0; i0 < N; i0 += COMB_DEEP_BATCH) {
         float v[COMB_DEEP_BATCH];
 #pragma unroll
         for (int j = 0; j < COMB_DEEP_BATCH; ++j) v[j] = src[(int64_t)min(i0 + j, N - 1) * pstride];
+        if (i0 == 0) {
+#pragma unroll
+            for (int j = 0; j < COMB_DEEP_REG; ++j) xr[j] = v[j];
+        }
 #pragma unroll
         for (int j = 0; j < COMB_DEEP_BATCH; ++j)
-            if (i0 + j < N) col[(i0 + j) * COMB_DEEP_PX] = v[j];
+            if (i0 + j >= COMB_DEEP_REG && i0 + j < N) col[(i0 + j - COMB_DEEP_REG) * COMB_DEEP_PX] = v[j];
     }
     uint64_t k0 = N >= 64 ? ~0ull : ((1ull << N) - 1ull);
     uint64_t k1 = N >= 128 ? ~0ull : N <= 64 ? 0ull : ((1ull << (N - 64)) - 1ull);
     int n = N;
     if (MISS) {
         uint64_t m0 = 0, m1 = 0;
-        deep_each(col, k0, k1, N, [&](int i, double x, bool k) {
+        deep_each(xr, col, k0, k1, N, [&](int i, double x, bool k) {
             const uint64_t bit = (k && x == x) ? 1ull : 0ull;
             if (i < 64) m0 |= bit << i;
             else m1 |= bit << (i - 64);
@@ -411,11 +425,11 @@ __device__ __forceinline__ unsigned combine_deep_block(const float *__restrict__
     // the drop pass of one iteration also forms the next sum (the same values in the
     // same order as a separate pass over the kept set)
     double s = 0.0;
-    deep_each(col, k0, k1, N, [&](int, double x, bool k) { s = k ? __dadd_rn(s, x) : s; });
+    deep_each(xr, col, k0, k1, N, [&](int, double x, bool k) { s = k ? __dadd_rn(s, x) : s; });
     for (int32_t it = 0; it < max_iters; ++it) {
         const double m = s / (double)n;
         double q = 0.0, dmax = 0.0;
-        deep_each(col, k0, k1, N, [&](int, double x, bool k) {
+        deep_each(xr, col, k0, k1, N, [&](int, double x, bool k) {
             const double d = __dsub_rn(x, m);
             q = k ? __dadd_rn(q, __dmul_rn(d, d)) : q;
             dmax = k ? fmax(dmax, fabs(d)) : dmax;
@@ -425,7 +439,7 @@ __device__ __forceinline__ unsigned combine_deep_block(const float *__restrict__
         int drop = 0;
         s = 0.0;
         uint64_t n0 = 0, n1 = 0;  // the flags after this iteration
-        deep_each(col, k0, k1, N, [&](int i, double x, bool k) {
+        deep_each(xr, col, k0, k1, N, [&](int i, double x, bool k) {
             const bool out = k && fabs(__dsub_rn(x, m)) > thr;
             const bool stay = k && !out;
             drop += out ? 1 : 0;

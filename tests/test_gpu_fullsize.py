@@ -134,3 +134,72 @@ def test_wide_spline_columns(rd, orc, wide):
         g = got[k][:, torch.from_numpy(cols).to(cal.device)].cpu().numpy()
         e = rel_err(g, want)
         assert e.max() <= TOL, (int(k), cols.tolist(), err_summary(e))
+
+
+def test_wide_bad_pixels_and_missing_combine(rd, orc, wide):
+    # a bad-pixel map on 0.1% of the detector (the wide leg's): the values the masking
+    # marks on sampled shifted rows equal the oracle's masked shift of the same rows, and
+    # the missing-value combine of sampled columns equals the oracle's
+    spec, cal, s, rect = wide["spec"], wide["cal"], wide["s"], wide["rect"]
+    x0, y0, w, h = (int(v) for v in rect)
+    rng = np.random.default_rng(7)
+    mask = (rng.random((spec.H, spec.W)) < 1e-3).astype(np.uint8)
+    sd = torch.from_numpy(s).to(cal.device)
+    al = wide["al"].clone()
+    rd.mask_shifted(to_dev(mask), al, sd, rect, spec.W, spec.H)
+    out, keep, _ = rd.combine(al, want_keep=True, missing=True)
+    for k in rng.choice(spec.N, 4, replace=False):
+        for v in rng.choice(h, 3, replace=False):
+            iy = int(np.floor(s[k, 1]))
+            lo = max(y0 + v + iy - 1, 0)
+            hi = min(y0 + v + iy + 3, spec.H)
+            crop = cal[k, lo:hi].cpu().numpy().astype(np.float64)
+            want = orc.shift(crop[None], s[k:k + 1], (x0, y0 + v - lo, w, 1), mask[lo:hi])[0, 0]
+            got = al[k, v].cpu().numpy().astype(np.float64)
+            assert np.array_equal(np.isnan(got), np.isnan(want)), (int(k), int(v))
+            ok = ~np.isnan(want)
+            assert rel_err(got[ok], want[ok]).max() <= TOL, (int(k), int(v))
+    N = al.shape[0]
+    flat = al.reshape(N, -1)
+    holes = torch.nonzero(torch.isnan(flat).any(dim=0)).flatten()
+    pick = np.unique(np.concatenate([rng.choice(h * w, 30000, replace=False), holes[:20000].cpu().numpy()]))
+    idx = torch.from_numpy(pick).to(al.device)
+    cols = flat[:, idx].cpu().numpy().astype(np.float64)
+    oo, okeep, _, near = orc.combine(cols.reshape(N, 1, -1), missing=True)
+    gk = keep.reshape(N, -1)[:, idx].cpu().numpy().reshape(N, 1, -1)
+    flips = gk != okeep
+    assert np.all(~flips | (near == 1))
+    bad = flips.any(axis=0)[0]
+    g = out.reshape(-1)[idx].cpu().numpy()
+    assert np.array_equal(np.isnan(g), np.isnan(oo[0]))
+    e = rel_err(g, oo[0])[~bad & ~np.isnan(oo[0])]
+    print(f"wide missing-value combine: {len(pick)} columns, {int(holes.numel())} with missing values, "
+          f"{err_summary(e)}")
+    assert e.max() <= TOL and int(holes.numel()) > 0
+
+
+def test_deep_combine_columns_at_full_size(rd, orc):
+    # 97 frames of 2040x2040 (the paper's deepest co-adding set, the benchmark's deep
+    # leg), sampled pixel columns against the oracle
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(97)
+    ND, SD = 97, 2040
+    deep = 1000.0 + 30.0 * torch.randn((ND, SD, SD), generator=g, device="cuda:0")
+    hit = torch.rand((ND, SD, SD), generator=g, device="cuda:0") < 1e-4
+    deep.add_(hit * (5e3 + 5.5e4 * torch.rand((ND, SD, SD), generator=g, device="cuda:0")))
+    del hit
+    out, keep, nrej = rd.combine(deep, want_keep=True, want_nrej=True)
+    rng = np.random.default_rng(8)
+    pick = np.unique(rng.choice(SD * SD, 30000, replace=False))
+    idx = torch.from_numpy(pick).to(deep.device)
+    cols = deep.reshape(ND, -1)[:, idx].cpu().numpy().astype(np.float64)
+    oo, okeep, _, near = orc.combine(cols.reshape(ND, 1, -1))
+    gk = keep.reshape(ND, -1)[:, idx].cpu().numpy().reshape(ND, 1, -1)
+    flips = gk != okeep
+    assert np.all(~flips | (near == 1))
+    bad = flips.any(axis=0)[0]
+    e = rel_err(out.reshape(-1)[idx].cpu().numpy(), oo[0])[~bad]
+    print(f"deep combine 97 x 2040^2: {len(pick)} columns, {int(nrej.cpu()[0])} rejected, {err_summary(e)}")
+    assert e.max() <= TOL and int(nrej.cpu()[0]) > 0
+    del deep, keep, out
+    torch.cuda.empty_cache()

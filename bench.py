@@ -537,7 +537,7 @@ def main():
         return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only; the multi-GPU sharding is a design "
+        print("bench.py: the library runs on one GPU; sharding stacks over several GPUs is a design "
               "note, not a measured path. Run with --gpus 1.", file=sys.stderr)
         return 2
 

@@ -41,7 +41,7 @@ extern "C" {
 #define REDUCE_ERR_RANGE        3  /* a parameter is outside its valid range */
 #define REDUCE_ERR_WORKSPACE    4  /* workspace missing or smaller than *_ws() */
 #define REDUCE_ERR_HIP          5  /* the HIP runtime reported an error */
-#define REDUCE_ERR_UNSUPPORTED  6  /* valid request this build cannot serve */
+#define REDUCE_ERR_UNSUPPORTED  6  /* valid request the library does not serve */
 
 /* ---- registration result ------------------------------------------------- */
 #define REDUCE_EDGE_X    1   /* x argmax on the window border: no sub-pixel step */

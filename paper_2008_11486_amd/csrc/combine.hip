@@ -98,8 +98,9 @@ template <bool MISS>
 static void dispatch_cols(const float *aligned, int64_t plane, int32_t N, double ksigma, int32_t max_iters,
                           float *out, uint8_t *keep, unsigned long long *n_rej, hipStream_t s)
 {
-    // vector loads need the frame planes and the pointer aligned to the pixel group
-    const bool v4 = plane % 4 == 0 && (reinterpret_cast<uintptr_t>(aligned) & 15u) == 0 &&
+    // vector loads need the frame planes and the pointer aligned to the pixel group (four
+    // pixels: frames of even length, 8-byte loads where a frame starts off 16 bytes)
+    const bool v4 = plane % 2 == 0 && (reinterpret_cast<uintptr_t>(aligned) & 15u) == 0 &&
                     (reinterpret_cast<uintptr_t>(out) & 15u) == 0;
     const bool v2 = plane % 2 == 0 && (reinterpret_cast<uintptr_t>(aligned) & 7u) == 0 &&
                     (reinterpret_cast<uintptr_t>(out) & 7u) == 0;

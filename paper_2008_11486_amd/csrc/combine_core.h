@@ -279,7 +279,8 @@ __device__ __forceinline__ float clip_registers(const float (&x)[MAXV], int32_t 
 
 // PX adjacent pixel columns per thread: each frame's PX values come in as one vector
 // load (frame k's plane starts at aligned + k * pstride; pstride >= plane, and pstride
-// and the pointers aligned to PX floats), then the columns are clipped one after the
+// and the pointers aligned to PX floats; with PX = 4 an even pstride is enough, a frame
+// that starts 8-byte aligned taking two 8-byte loads), then the columns are clipped one after the
 // other.  Columns at or past `plane` are neither written nor counted.
 template <int MAXV, int PX, bool MISS = false>
 __device__ __forceinline__ unsigned combine_cols_block(const float *__restrict__ aligned, int64_t plane,
@@ -294,12 +295,19 @@ __device__ __forceinline__ unsigned combine_cols_block(const float *__restrict__
         for (int i = 0; i < MAXV; ++i) {
             if (i < N) {
                 const float *src = aligned + (int64_t)i * pstride + p0;
-                if (PX == 4) {
+                if (PX == 4 && (((int64_t)i * pstride) & 3) == 0) {
                     const float4 v = *reinterpret_cast<const float4 *>(src);
                     xs[0][i] = v.x;
                     xs[1][i] = v.y;
                     xs[2][i] = v.z;
                     xs[3][i] = v.w;
+                } else if (PX == 4) {  // a plane of even length: this frame starts 8-byte aligned
+                    const float2 u = *reinterpret_cast<const float2 *>(src);
+                    const float2 v = *reinterpret_cast<const float2 *>(src + 2);
+                    xs[0][i] = u.x;
+                    xs[1][i] = u.y;
+                    xs[2][i] = v.x;
+                    xs[3][i] = v.y;
                 } else if (PX == 2) {
                     const float2 v = *reinterpret_cast<const float2 *>(src);
                     xs[0][i] = v.x;

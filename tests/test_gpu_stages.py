@@ -289,6 +289,27 @@ def test_combine_parity_with_outliers(rd, orc, N, lanes):
         assert nrej == 0
 
 
+@pytest.mark.parametrize("shape", [(16, 10, 64), (16, 10, 61), (16, 9, 63), (5, 11, 62), (12, 7, 66)])
+@pytest.mark.parametrize("missing", [False, True])
+def test_combine_pixel_groups_every_plane_alignment(rd, orc, shape, missing):
+    """Planes of length 0, 1, 2, 3 mod 4: four pixels per thread with 16- or 8-byte loads
+    per frame, two, or one, and the ragged last group."""
+    N, h, w = shape
+    rng = np.random.default_rng(h * w + N)
+    vals = rng.normal(1000, 30, size=shape).astype(np.float32)
+    vals[rng.random(size=shape) < 0.03] += 2e4
+    if missing:
+        vals[rng.random(size=shape) < 0.1] = np.nan
+    out, keep, nrej = rd.combine(to_dev(vals), want_keep=True, want_nrej=True, missing=missing)
+    out, keep = out.cpu().numpy(), keep.cpu().numpy()
+    o_out, o_keep, o_nrej, near = orc.combine(vals.astype(np.float64), 3.0, 3, missing=missing)
+    flips = keep != o_keep
+    assert np.all(~flips | (near == 1))
+    good = ~flips.any(axis=0) & ~np.isnan(o_out)
+    assert np.array_equal(np.isnan(out), np.isnan(o_out))
+    assert rel_err(out[good], o_out[good]).max() <= TOL
+
+
 @pytest.mark.parametrize("N", [49, 64, 65, 97, 128])
 def test_combine_parity_deep_stacks(rd, orc, N):
     """Stacks past the LDS tile's depth (the paper's sets reach 97 frames): the one-lane

@@ -307,6 +307,38 @@ int reduce_cnn_centres(const float *pred, int32_t B, float scale, int32_t radius
  *   int32 [N][2] (updated in place). */
 int reduce_recentre(const reduce_offset_t *offs, int32_t N, int32_t radius_max, int32_t *centres, void *stream);
 
+/* reduce_propose: learned registration of N frames against one reference, entirely on
+ *   `stream` (no host round trip).  The network proposes each frame's offset from the
+ *   4x-downsampled pair (reduce_cnn_input + reduce_cnn_forward with params; window centre
+ *   c_k = clamp(rint(4 * pred_k), +-radius_max) as reduce_cnn_centres); the correlation
+ *   search of reduce_register then runs in the window [c_k - refine_radius, c_k +
+ *   refine_radius]^2 with the full search's template (the interior shrunk by radius_max),
+ *   so its scores S_k(d) are those of the full search.  A frame whose maximum lies on a
+ *   window border strictly inside +-radius_max moves its centre onto that maximum and is
+ *   searched again (at most max_moves times; only those frames are searched).  The
+ *   full-window search (radius radius_max) then replaces the result of every frame whose
+ *   maximum is still on such a border or whose peak is below peak_ratio times the
+ *   reference's own zero-offset score S_ref(0) = sum_T r' ref; those frames get
+ *   REDUCE_FALLBACK in their flags.  The network only moves the window: the score,
+ *   argmax and sub-pixel vertex are reduce_register's.
+ *   ref     device float [H][W];  frames device float [N][H][W] (W, H multiples of 4, >= 64)
+ *   params  device float, the network's reduce_cnn_num_params() values
+ *   out     device reduce_offset_t [N]
+ *   centres device int32 [N][2] (the network's window centres) or NULL
+ *   info    device int32 [N] or NULL: number of window moves | 256 if the fallback was
+ *           taken for a border maximum | 512 if it was taken for a weak peak
+ *   ws      device workspace of at least reduce_propose_ws(W, H, N, refine_radius,
+ *           radius_max) bytes (network input and activations, the narrowed and the
+ *           fallback searches' partial scores; the fallback scores as many frames at a
+ *           time as fit 256 MiB of partials)
+ * Errors: NULL -> NULL; bad sizes -> SHAPE; refine_radius > radius_max, a radius that
+ * leaves no template, max_moves outside [0, 64] or a non-finite peak_ratio -> RANGE;
+ * small ws -> WORKSPACE. */
+size_t reduce_propose_ws(int32_t W, int32_t H, int32_t N, int32_t refine_radius, int32_t radius_max);
+int reduce_propose(const float *ref, const float *frames, int32_t W, int32_t H, int32_t N, const float *params,
+                   int32_t refine_radius, int32_t radius_max, float peak_ratio, int32_t max_moves,
+                   reduce_offset_t *out, int32_t *centres, int32_t *info, void *ws, size_t ws_bytes, void *stream);
+
 /* ---- training and evaluation frames --------------------------------------------
  * reduce_render_frames: F synthetic sky frames [F][H][W] (device float out) for the
  *   network's training and evaluation pairs: sky + sum over the frame's S catalogue

@@ -98,6 +98,10 @@ def _declare(L):
     L.reduce_cnn_centres.argtypes = [P, I32, F, I32, P, P]
     L.reduce_recentre.argtypes = [P, I32, I32, P, P]
     L.reduce_render_frames.argtypes = [P, I32, P, I32, I32, I32, F, F, F, I32, ctypes.c_uint64, P, P]
+    L.reduce_propose_ws.argtypes = [I32, I32, I32, I32, I32]
+    L.reduce_propose_ws.restype = SZ
+    L.reduce_propose.argtypes = [P, P, I32, I32, I32, P, I32, I32, F, I32, P, P, P, P, SZ, P]
+    L.reduce_propose.restype = ctypes.c_int
     for n in ("reduce_cnn_input", "reduce_cnn_ws_offsets", "reduce_cnn_forward", "reduce_cnn_backward",
               "reduce_cnn_adamw", "reduce_cnn_centres", "reduce_render_frames", "reduce_recentre"):
         getattr(L, n).restype = ctypes.c_int
@@ -126,7 +130,8 @@ def exported_symbols() -> Sequence[str]:
             "reduce_tune_clear", "reduce_stack_batch_ws", "reduce_stack_batch",
             "reduce_cnn_input_ws", "reduce_cnn_input", "reduce_cnn_num_params", "reduce_cnn_ws",
             "reduce_cnn_ws_offsets", "reduce_cnn_forward", "reduce_cnn_backward", "reduce_cnn_adamw",
-            "reduce_cnn_centres", "reduce_render_frames", "reduce_recentre")
+            "reduce_cnn_centres", "reduce_render_frames", "reduce_recentre", "reduce_propose_ws",
+            "reduce_propose")
 
 
 def _check(rc: int) -> None:
@@ -565,3 +570,38 @@ def recentre(offsets: torch.Tensor, centres: torch.Tensor, radius_max: int, stre
         raise ValueError("offsets [N][48] bytes and contiguous int32 centres [N][2] needed")
     _check(lib().reduce_recentre(_ptr(offsets), N, int(radius_max), _ptr(centres), _stream(stream)))
     return centres
+
+
+def propose_ws_bytes(W: int, H: int, N: int, refine_radius: int = 2, radius_max: int = 64) -> int:
+    return int(lib().reduce_propose_ws(W, H, N, refine_radius, radius_max))
+
+
+def propose(ref: torch.Tensor, frames: torch.Tensor, params: torch.Tensor, radius_max: int = 64,
+            refine_radius: int = 2, peak_ratio: float = 0.5, max_moves: int = 4, ws: Optional[torch.Tensor] = None,
+            out: Optional[torch.Tensor] = None, centres: Optional[torch.Tensor] = None,
+            info: Optional[torch.Tensor] = None, stream=None):
+    """Network proposal, narrowed search, window moves and full-search fallback in one call:
+    ref [H][W], frames [N][H][W] float32, params float32 -> (offsets [N][48] bytes, centres
+    int32 [N][2], info int32 [N]), all on the device."""
+    _dev(ref, "ref")
+    _dev(frames, "frames")
+    N, H, W = frames.shape
+    if not (ref.is_contiguous() and frames.is_contiguous() and params.is_contiguous()):
+        raise ValueError("ref, frames and params must be contiguous")
+    if params.dtype != torch.float32 or params.numel() != cnn_num_params():
+        raise ValueError("params must be the network's float32 parameter vector")
+    need = propose_ws_bytes(W, H, N, refine_radius, radius_max)
+    if need == 0:
+        raise ReduceError(ERR_SHAPE, "reduce_propose: unsupported sizes")
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=frames.device)
+    if out is None:
+        out = torch.empty((N, OFFSET_BYTES), dtype=torch.uint8, device=frames.device)
+    if centres is None:
+        centres = torch.empty((N, 2), dtype=torch.int32, device=frames.device)
+    if info is None:
+        info = torch.empty(N, dtype=torch.int32, device=frames.device)
+    _check(lib().reduce_propose(_ptr(ref), _ptr(frames), W, H, N, _ptr(params), int(refine_radius), int(radius_max),
+                                float(peak_ratio), int(max_moves), _ptr(out), _ptr(centres), _ptr(info), _ptr(ws),
+                                ws.numel(), _stream(stream)))
+    return out, centres, info

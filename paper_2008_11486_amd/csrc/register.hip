@@ -37,26 +37,34 @@ __global__ __launch_bounds__(512) void score_tiles(ScoreArgs a)
 }
 
 // Scores of each frame from its tile partials (64 candidates per workgroup).
+// Slot k works on frame map[k] (nothing when negative), or on frame k without a map;
+// centres and offsets are indexed by frame, partials and scores by slot.
 __global__ __launch_bounds__(64 * SUM_WAVES) void sum_tiles(const double *__restrict__ partial, int32_t n_tiles,
                                                             int32_t D, int32_t R, int32_t Rmax,
                                                             const int32_t *__restrict__ centers,
+                                                            const int32_t *__restrict__ map,
                                                             double *__restrict__ scores)
 {
     __shared__ double part[SUM_WAVES][64];
     const int32_t k = blockIdx.y;
-    const int32_t cx = centers ? centers[2 * k] : 0, cy = centers ? centers[2 * k + 1] : 0;
+    const int32_t kf = map ? map[k] : k;
+    if (kf < 0) return;
+    const int32_t cx = centers ? centers[2 * kf] : 0, cy = centers ? centers[2 * kf + 1] : 0;
     sum_candidate_block(partial + (int64_t)k * n_tiles * D * D, n_tiles, D, R, Rmax, cx, cy, blockIdx.x,
                         scores + (int64_t)k * D * D, part);
 }
 
 __global__ __launch_bounds__(256) void pick_offsets(const double *__restrict__ scores, int32_t D, int32_t R,
                                                     int32_t Rmax, const int32_t *__restrict__ centers,
+                                                    const int32_t *__restrict__ map,
                                                     reduce_offset_t *__restrict__ out)
 {
     __shared__ Best scratch[4];
     const int32_t k = blockIdx.x;
-    const int32_t cx = centers ? centers[2 * k] : 0, cy = centers ? centers[2 * k + 1] : 0;
-    pick_frame(scores + (int64_t)k * D * D, D, R, Rmax, cx, cy, out + k, scratch);
+    const int32_t kf = map ? map[k] : k;
+    if (kf < 0) return;
+    const int32_t cx = centers ? centers[2 * kf] : 0, cy = centers ? centers[2 * kf + 1] : 0;
+    pick_frame(scores + (int64_t)k * D * D, D, R, Rmax, cx, cy, out + kf, scratch);
 }
 
 // ---- host side ---------------------------------------------------------------------
@@ -98,6 +106,7 @@ ScoreArgs make_score_args(const RegPlan &p, const float *ref, const float *frame
     a.G = p.G;
     a.threads = p.threads;
     a.skip = skip;
+    a.map = nullptr;
     return a;
 }
 
@@ -116,24 +125,27 @@ static void launch_score(const ScoreArgs &a, const RegPlan &p, hipStream_t s)
                        a);
 }
 
-int register_launch(const float *ref, const float *frames, int32_t W, int32_t H, int32_t N, int32_t R,
-                    int32_t Rmax, const int32_t *centers, int32_t tx0, int32_t ty0, int32_t tw, int32_t th,
-                    reduce_offset_t *out, double *scores, void *ws, const RegPlan &p, hipStream_t s)
+// Template mean of the reference (two launches): parts [ceil(th / MEAN_ROWS)], mean [1].
+void register_mean(const float *ref, int32_t W, int32_t tx0, int32_t ty0, int32_t tw, int32_t th,
+                   double *mean_parts, double *mean, hipStream_t s)
 {
-    ProfScope prof_all("register", s);
-    const RegWs L = reg_ws_layout(p, N);
-    unsigned char *base = static_cast<unsigned char *>(ws);
-    double *mean_parts = reinterpret_cast<double *>(base + L.mean_parts);
-    double *mean = reinterpret_cast<double *>(base + L.mean);
-    double *partial = reinterpret_cast<double *>(base + L.partial);
-    double *sc = scores ? scores : reinterpret_cast<double *>(base + L.scores);
-
     const int32_t nparts = (int32_t)ceil_div(th, MEAN_ROWS);
     hipLaunchKernelGGL(tmpl_sum_rows, dim3(nparts), dim3(MEAN_THREADS), 0, s, ref, W, tx0, ty0, tw, th, mean_parts);
     hipLaunchKernelGGL(tmpl_mean_final, dim3(1), dim3(MEAN_THREADS), 0, s, mean_parts, nparts,
                        (double)tw * (double)th, mean);
-    const ScoreArgs a =
+}
+
+// Score tiles, tile sums and argmax for N work slots with a known template mean.
+// map: slot -> frame (negative: idle slot) or NULL (slot k is frame k); partial holds
+// [N][n_tiles][D*D] and scores [N][D*D] doubles.
+void register_scores(const RegPlan &p, const float *ref, const float *frames, int32_t W, int32_t H, int32_t N,
+                     int32_t R, int32_t Rmax, const int32_t *centers, const int32_t *map, int32_t tx0, int32_t ty0,
+                     int32_t tw, int32_t th, const double *mean, double *partial, double *sc, reduce_offset_t *out,
+                     hipStream_t s)
+{
+    ScoreArgs a =
         make_score_args(p, ref, frames, centers, mean, partial, W, H, N, R, Rmax, tx0, ty0, tw, th, 0x7fffffff);
+    a.map = map;
     if (p.K == 0) {
         ProfScope prof("score_tiles", s);
         // workgroups for this call's template (at most the plan's, which is sized for the largest)
@@ -154,8 +166,23 @@ int register_launch(const float *ref, const float *frames, int32_t W, int32_t H,
     }
     }
     hipLaunchKernelGGL(sum_tiles, dim3((unsigned)ceil_div((int64_t)p.D * p.D, 64), N), dim3(64 * SUM_WAVES), 0, s,
-                       partial, a.n_tiles, p.D, R, Rmax, centers, sc);
-    hipLaunchKernelGGL(pick_offsets, dim3(N), dim3(256), 0, s, sc, p.D, R, Rmax, centers, out);
+                       partial, a.n_tiles, p.D, R, Rmax, centers, map, sc);
+    hipLaunchKernelGGL(pick_offsets, dim3(N), dim3(256), 0, s, sc, p.D, R, Rmax, centers, map, out);
+}
+
+int register_launch(const float *ref, const float *frames, int32_t W, int32_t H, int32_t N, int32_t R,
+                    int32_t Rmax, const int32_t *centers, int32_t tx0, int32_t ty0, int32_t tw, int32_t th,
+                    reduce_offset_t *out, double *scores, void *ws, const RegPlan &p, hipStream_t s)
+{
+    ProfScope prof_all("register", s);
+    const RegWs L = reg_ws_layout(p, N);
+    unsigned char *base = static_cast<unsigned char *>(ws);
+    double *mean_parts = reinterpret_cast<double *>(base + L.mean_parts);
+    double *mean = reinterpret_cast<double *>(base + L.mean);
+    double *partial = reinterpret_cast<double *>(base + L.partial);
+    double *sc = scores ? scores : reinterpret_cast<double *>(base + L.scores);
+    register_mean(ref, W, tx0, ty0, tw, th, mean_parts, mean, s);
+    register_scores(p, ref, frames, W, H, N, R, Rmax, centers, nullptr, tx0, ty0, tw, th, mean, partial, sc, out, s);
     return check_launch("reduce_register");
 }
 

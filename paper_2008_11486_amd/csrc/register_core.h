@@ -35,7 +35,8 @@ constexpr int MEAN_U = 4;          // columns per thread loaded together
 struct ScoreArgs {
     const float *ref;
     const float *frames;     // frame k at frames + (k + (k >= skip)) * W * H
-    const int32_t *centers;  // [N][2] or NULL
+    const int32_t *centers;  // [N][2] or NULL (indexed by frame when map is set, else by k)
+    const int32_t *map;      // [N] frame of work slot k (negative: nothing to do), or NULL
     const double *mean;
     double *partial;         // [N][n_tiles][D*D]
     int32_t W, H, R, Rmax, D;
@@ -150,14 +151,17 @@ __device__ __forceinline__ void score_tile(const ScoreArgs &a, int32_t lid, unsi
     const int32_t gk = lid / a.n_tiles;
     const int32_t g = gk % a.G;
     const int32_t k = gk / a.G;
+    const int32_t kf = a.map ? a.map[k] : k + (k >= a.skip ? 1 : 0);
+    if (kf < 0) return;  // an idle slot: the whole workgroup leaves before any barrier
+    const int32_t ci = a.map ? kf : k;
     const int32_t band = tile / a.n_xchunks;
     const int32_t xc = tile - band * a.n_xchunks;
     const int32_t c0 = g * a.CW;
     const int32_t x_t = xc * a.TX;                 // first template column of the tile
     const int32_t yb0 = band * a.BR;               // first template row of the band
     const int32_t yb1 = min(yb0 + a.BR, a.th);
-    const int32_t cx = a.centers ? a.centers[2 * k] : 0;
-    const int32_t cy = a.centers ? a.centers[2 * k + 1] : 0;
+    const int32_t cx = a.centers ? a.centers[2 * ci] : 0;
+    const int32_t cy = a.centers ? a.centers[2 * ci + 1] : 0;
     const int32_t j_lo = c0 / a.NBX;
 
     const int t = threadIdx.x;
@@ -171,7 +175,6 @@ __device__ __forceinline__ void score_tile(const ScoreArgs &a, int32_t lid, unsi
     const int jr = j - j_lo;                       // frame-tile row offset of this thread
 
     const double mean = *a.mean;
-    const int32_t kf = k + (k >= a.skip ? 1 : 0);
     const float *f = a.frames + (int64_t)kf * a.W * a.H;
     // frame tile origin: template row yc + (cy - R + j_lo), column x_t + (cx - R)
     const int32_t fx0 = a.tx0 + x_t + cx - a.R;
@@ -297,13 +300,15 @@ __device__ __forceinline__ void score_small_tile(const ScoreArgs &a, int32_t lid
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
     const int32_t tile = lid % a.n_tiles, k = lid / a.n_tiles;
+    const int32_t kf = a.map ? a.map[k] : k + (k >= a.skip ? 1 : 0);
+    if (kf < 0) return;  // an idle slot: the whole workgroup leaves before any barrier
+    const int32_t ci = a.map ? kf : k;
     const int32_t strip = tile / a.n_xchunks, colb = tile - strip * a.n_xchunks;
     const int32_t x = colb * SMALL_COLS + t;
     const bool col_ok = x < a.tw;
     const int32_t y0 = strip * a.BR, rows = min(y0 + a.BR, a.th) - y0;
     const int nch = (rows + SMALL_CH - 1) / SMALL_CH;
-    const int32_t cx = a.centers ? a.centers[2 * k] : 0, cy = a.centers ? a.centers[2 * k + 1] : 0;
-    const int32_t kf = k + (k >= a.skip ? 1 : 0);
+    const int32_t cx = a.centers ? a.centers[2 * ci] : 0, cy = a.centers ? a.centers[2 * ci + 1] : 0;
     const float *f = a.frames + (int64_t)kf * a.W * a.H;
     const double mean = *a.mean;
     // staged column c is frame column fx0 + c, clamped into the frame (an offset beyond

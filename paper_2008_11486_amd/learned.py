@@ -6,12 +6,12 @@
   the network learns from what the pipeline produces.
 * ``ProposalTrainer`` runs forward, Huber-loss backward and AdamW, all in the
   library's kernels, on freshly rendered pairs.
-* ``LearnedRegistrar`` proposes an offset per frame, searches only a small window
-  around it with the same template as the full search (a window whose maximum lies
-  on its border moves onto that maximum, a few times at most), and falls back to the
-  full window when the narrowed result cannot be trusted (its maximum still on a
-  window border inside the search limit, or a peak far below the reference's own
-  zero-offset score).
+* ``LearnedRegistrar`` marshals ``reduce_propose``: the network proposes an offset per
+  frame, the search runs only in a small window around it with the same template as
+  the full search (a window whose maximum lies on its border moves onto that maximum,
+  a few times at most), and the full window replaces the result when the narrowed one
+  cannot be trusted (its maximum still on a window border inside the search limit, or
+  a peak far below the reference's own zero-offset score); all of it on the device.
 
 The registration problem itself (score, argmax, sub-pixel vertex) is the one of
 ``reduce_register``; the network only moves the window.
@@ -26,9 +26,9 @@ from typing import Optional, Sequence
 import numpy as np
 import torch
 
-from . import (CLIPPED, EDGE_X, EDGE_Y, FALLBACK, CnnWorkspace, cnn_adamw, cnn_backward, cnn_centres,
-               cnn_forward, cnn_input, cnn_input_ws_bytes, cnn_num_params, offsets_to_numpy, recentre, register,
-               register_ws_bytes, render_frames)
+from . import (CLIPPED, FALLBACK, OFFSET_BYTES, CnnWorkspace, cnn_adamw, cnn_backward, cnn_forward, cnn_input,
+               cnn_input_ws_bytes, cnn_num_params, offsets_to_numpy, propose, propose_ws_bytes, register,
+               render_frames)
 
 SEED_ROOT = 20081148
 STAR_DENSITY = 200.0 / (1024 * 1024)     # stars per pixel, as in the 1024x1024 stacks
@@ -228,8 +228,9 @@ class LearnedResult:
 
 
 class LearnedRegistrar:
-    """Network proposal -> narrowed search -> full-window fallback, for frames [M][H][W]
-    against one reference [H][W] (all device float32)."""
+    """Network proposal -> narrowed search -> window moves -> full-window fallback, for
+    frames [M][H][W] against one reference [H][W] (all device float32): one
+    ``reduce_propose`` call, every decision taken on the device."""
 
     def __init__(self, params, W: int, H: int, M: int, radius_max: int = 64, refine_radius: int = 2,
                  peak_ratio: float = 0.5, moves: int = 4, device="cuda:0"):
@@ -240,69 +241,29 @@ class LearnedRegistrar:
         self.dev = torch.device(device)
         p = params if isinstance(params, torch.Tensor) else torch.from_numpy(np.asarray(params, np.float32))
         self.params = p.to(self.dev).contiguous()
-        self.h, self.w = H // DOWNSAMPLE, W // DOWNSAMPLE
-        self.inp_ref = torch.empty((1, self.h, self.w), dtype=torch.int16, device=self.dev)
-        self.inp = torch.empty((M, self.h, self.w), dtype=torch.int16, device=self.dev)
-        self.in_ws = torch.empty(max(cnn_input_ws_bytes(W, H, M), 1), dtype=torch.uint8, device=self.dev)
-        self.cws = CnnWorkspace(M, self.h, self.w, device=self.dev)
-        self.pred = torch.empty((M, 2), dtype=torch.float32, device=self.dev)
+        self.ws = torch.empty(max(propose_ws_bytes(W, H, M, refine_radius, radius_max), 1), dtype=torch.uint8,
+                              device=self.dev)
+        self.out = torch.empty((M, OFFSET_BYTES), dtype=torch.uint8, device=self.dev)
         self.centres = torch.empty((M, 2), dtype=torch.int32, device=self.dev)
-        self.ws_refine = torch.empty(max(register_ws_bytes(W, H, M, refine_radius, radius_max), 1),
-                                     dtype=torch.uint8, device=self.dev)
-        self.ws_auto = torch.empty(max(register_ws_bytes(W, H, 1, 0, radius_max), 1), dtype=torch.uint8,
-                                   device=self.dev)
-        self.ws_full = torch.empty(max(register_ws_bytes(W, H, 1, radius_max, radius_max), 1), dtype=torch.uint8,
-                                   device=self.dev)
-        self.ws_move = torch.empty(max(register_ws_bytes(W, H, 1, refine_radius, radius_max), 1),
-                                   dtype=torch.uint8, device=self.dev)
+        self.info = torch.empty(M, dtype=torch.int32, device=self.dev)
 
-    def propose(self, ref: torch.Tensor, frames: torch.Tensor) -> torch.Tensor:
-        """Enqueue network input, forward and centres; returns the device centres."""
-        cnn_input(ref.reshape(1, self.H, self.W), out=self.inp_ref, ws=self.in_ws)
-        cnn_input(frames, out=self.inp, ws=self.in_ws)
-        cnn_forward(self.inp_ref[0], self.inp, self.params, self.cws, ref_shared=True, pred=self.pred)
-        return cnn_centres(self.pred, float(DOWNSAMPLE), self.rmax, out=self.centres)
-
-    def _inner_border(self, o: np.ndarray) -> np.ndarray:
-        """Frames whose maximum lies on a window border inside +-R_max (a border at
-        +-R_max is the full search's border too)."""
-        inner_x = (o["dx"] > -self.rmax) & (o["dx"] < self.rmax)
-        inner_y = (o["dy"] > -self.rmax) & (o["dy"] < self.rmax)
-        return (((o["flags"] & EDGE_X) != 0) & inner_x) | (((o["flags"] & EDGE_Y) != 0) & inner_y)
-
-    def register(self, ref: torch.Tensor, frames: torch.Tensor) -> LearnedResult:
+    def enqueue(self, ref: torch.Tensor, frames: torch.Tensor) -> torch.Tensor:
+        """Enqueue the whole learned registration; returns the device offsets."""
         if frames.shape != (self.M, self.H, self.W):
             raise ValueError(f"frames must be [{self.M}][{self.H}][{self.W}]")
-        centres = self.propose(ref, frames)
-        proposed = centres.clone()
-        refined = register(ref, frames, self.r, self.rmax, centers=centres, ws=self.ws_refine)
-        auto = register(ref, ref.reshape(1, self.H, self.W), 0, self.rmax, ws=self.ws_auto)
-        o = offsets_to_numpy(refined)
-        s_auto = float(offsets_to_numpy(auto)["peak"][0])
-        # a window whose maximum is on an inner border moves onto that maximum; the moving
-        # frames of one step are searched back to back and read back together
-        moved = 0
-        for _ in range(self.moves):
-            walk = np.nonzero(self._inner_border(o))[0]
-            if walk.size == 0:
-                break
-            cs = torch.from_numpy(np.stack([o["dx"][walk], o["dy"][walk]], 1).astype(np.int32)).to(self.dev)
-            outs = [register(ref, frames[k:k + 1], self.r, self.rmax, centers=cs[i:i + 1], ws=self.ws_move)
-                    for i, k in enumerate(walk)]
-            got = offsets_to_numpy(torch.cat(outs))
-            for i, k in enumerate(walk):
-                o[k] = got[i]
-            moved += int(walk.size)
-        border = self._inner_border(o)
-        weak = ~(o["peak"] >= self.peak_ratio * s_auto)
-        fb = border | weak
-        for k in np.nonzero(fb)[0]:
-            full = offsets_to_numpy(register(ref, frames[k:k + 1], self.rmax, self.rmax, ws=self.ws_full))
-            o[k] = full[0]
-            o["flags"][k] |= FALLBACK
-        return LearnedResult(offsets=o, centres=proposed.cpu().numpy(), fallback=fb,
-                             reason=dict(border=int(border.sum()), weak=int(weak.sum()), moves=moved,
-                                         clipped=int(((o["flags"] & CLIPPED) != 0).sum()), s_auto=s_auto))
+        propose(ref, frames, self.params, radius_max=self.rmax, refine_radius=self.r, peak_ratio=self.peak_ratio,
+                max_moves=self.moves, ws=self.ws, out=self.out, centres=self.centres, info=self.info)
+        return self.out
+
+    def register(self, ref: torch.Tensor, frames: torch.Tensor) -> LearnedResult:
+        self.enqueue(ref, frames)
+        o = offsets_to_numpy(self.out)
+        info = self.info.cpu().numpy()
+        fb = (o["flags"] & FALLBACK) != 0
+        return LearnedResult(offsets=o, centres=self.centres.cpu().numpy(), fallback=fb,
+                             reason=dict(border=int(((info >> 8) & 1).sum()), weak=int(((info >> 9) & 1).sum()),
+                                         moves=int((info & 255).sum()),
+                                         clipped=int(((o["flags"] & CLIPPED) != 0).sum())))
 
 
 def full_search(ref: torch.Tensor, frames: torch.Tensor, radius_max: int = 64, ws=None) -> torch.Tensor:

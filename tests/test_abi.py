@@ -114,3 +114,20 @@ def test_spline_workspace_holds_padded_rows(rd):
         need = 4 * N * H * ((W + 63) // 64 * 64)
         assert L.reduce_shift_spline_ws(W, H, N) >= need
     assert L.reduce_shift_spline_ws(0, 4, 4) == 0
+
+
+def test_propose_validation_before_launch(rd):
+    L = rd.lib()
+    b = ctypes.c_void_p(16)  # never dereferenced: validation fails first
+    f = ctypes.c_float(0.5)
+    assert L.reduce_propose(None, b, 256, 256, 4, b, 2, 16, f, 4, b, None, None, b, 1 << 30, None) == rd.ERR_NULL
+    assert L.reduce_propose(b, b, 250, 256, 4, b, 2, 16, f, 4, b, None, None, b, 1 << 30, None) == rd.ERR_SHAPE
+    assert L.reduce_propose(b, b, 256, 256, 4, b, 17, 16, f, 4, b, None, None, b, 1 << 30, None) == rd.ERR_RANGE
+    assert L.reduce_propose(b, b, 256, 256, 4, b, 2, 16, f, 65, b, None, None, b, 1 << 30, None) == rd.ERR_RANGE
+    assert L.reduce_propose(b, b, 256, 256, 4, b, 2, 16, ctypes.c_float(float("nan")), 4, b, None, None, b,
+                            1 << 30, None) == rd.ERR_RANGE
+    need = rd.propose_ws_bytes(256, 256, 4, 2, 16)
+    assert need > rd.register_ws_bytes(256, 256, 4, 2, 16)
+    assert L.reduce_propose(b, b, 256, 256, 4, b, 2, 16, f, 4, b, None, None, b, need - 1, None) == rd.ERR_WORKSPACE
+    assert b"workspace needs" in L.reduce_last_error()
+    assert rd.propose_ws_bytes(256, 256, 4, 3, 2) == 0 and rd.propose_ws_bytes(254, 256, 4, 2, 16) == 0

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import synth
-from helpers import TOL, err_summary, rel_err, to_dev
+from helpers import assert_end_to_end, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -105,11 +105,8 @@ def test_batch_matches_oracle_end_to_end(rd, orc):
     o = orc.reduce_stack(st.raw, st.dark, st.flat, 6)
     assert np.array_equal(offs["dx"][1:], o["offsets"]["dx"][1:]) and np.array_equal(offs["dy"][1:], o["offsets"]["dy"][1:])
     assert np.array_equal(rect, o["rect"])
-    e = rel_err(img.cpu().numpy(), o["out"])
-    print("batch vs oracle:", err_summary(e))
     s = np.stack([offs["sx"], offs["sy"]], 1).astype(np.float32)
-    if np.array_equal(s, o["s"]):
-        assert e.max() <= TOL
+    assert_end_to_end(orc, o["cal"], s, o["s"], rect, img.cpu().numpy(), "batch vs oracle")
 
 
 def test_batch_workload1_three_bands(rd):
@@ -147,10 +144,7 @@ def test_batch_deep_stacks(rd, orc):
     assert np.array_equal(offs["dx"][1:], o["offsets"]["dx"][1:]) and np.array_equal(offs["dy"][1:], o["offsets"]["dy"][1:])
     s = np.stack([offs["sx"], offs["sy"]], 1).astype(np.float32)
     assert np.array_equal(rect, o["rect"])
-    if np.array_equal(s, o["s"]):
-        e = rel_err(img.cpu().numpy(), o["out"])[~o["near"].any(axis=0)]  # A11's band aside
-        print("97-frame batch vs oracle:", err_summary(e))
-        assert e.max() <= TOL
+    assert_end_to_end(orc, o["cal"], s, o["s"], rect, img.cpu().numpy(), "97-frame batch vs oracle")
 
 
 def test_batch_bias_and_bad_pixels(rd, orc):
@@ -184,14 +178,11 @@ def test_batch_bias_and_bad_pixels(rd, orc):
         img, rect, offs, _ = batch.result(i)
         o = orc.reduce_stack(raw, dark, flat, R, bias=bias, mask=mask, integer_mode=extras[i])
         assert np.array_equal(offs["dx"][1:], o["offsets"]["dx"][1:]) and np.array_equal(offs["dy"][1:], o["offsets"]["dy"][1:])
-        s = np.stack([offs["sx"], offs["sy"]], 1).astype(np.float32)
-        if np.array_equal(rect, o["rect"]) and np.array_equal(s, o["s"]):
-            g = img.cpu().numpy()
-            assert np.array_equal(np.isnan(g), np.isnan(o["out"]))
-            ok = ~np.isnan(o["out"]) & ~o["near"].any(axis=0)
-            e = rel_err(g[ok], o["out"][ok])
-            print(f"stack {i} with bias and bad pixels vs oracle:", err_summary(e))
-            assert e.max() <= TOL
+        s = (np.stack([offs["dx"], offs["dy"]], 1) if extras[i] else np.stack([offs["sx"], offs["sy"]], 1))
+        s = s.astype(np.float32)
+        assert np.array_equal(rect, o["rect"]), (i, rect, o["rect"])
+        assert_end_to_end(orc, o["cal"], s, o["s"], rect, img.cpu().numpy(),
+                          f"stack {i} with bias and bad pixels vs oracle", mask=mask, missing=True)
 
 
 def test_batch_rejects_bad_stacks(rd):

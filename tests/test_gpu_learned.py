@@ -5,11 +5,13 @@ stage.  The GPU accumulates in FP32 where the oracle uses FP64, so a stored bflo
 value may differ by one bfloat16 unit when the exact value lies near a rounding
 boundary; such values are counted and must be rare.
 """
+import os
+
 import numpy as np
 import pytest
 
 import synth
-from helpers import to_dev
+from helpers import to_dev, ulp32
 
 pytestmark = pytest.mark.gpu
 
@@ -284,3 +286,93 @@ def test_recentre_moves_border_windows_only(rd):
     rd.recentre(raw, c, 64)
     # the last window's maximum is on the +64 border, which the full search shares: it stays
     np.testing.assert_array_equal(c.cpu().numpy(), [[5, -2], [-62, 1], [1, 1], [9, 63], [63, 10]])
+
+
+def _host_flow(rd, learned, params, ref, frames, rmax, r=2, ratio=0.5, moves=4):
+    """The proposal -> narrowed search -> window moves -> fallback decisions taken on the
+    host, one stage-wise call at a time (the reference for the device-side call)."""
+    M, H, W = frames.shape
+    inp_ref = rd.cnn_input(ref.reshape(1, H, W))
+    inp = rd.cnn_input(frames)
+    cws = rd.CnnWorkspace(M, H // 4, W // 4)
+    pred = rd.cnn_forward(inp_ref[0], inp, torch.from_numpy(np.asarray(params, np.float32)).to("cuda:0"), cws)
+    cen = rd.cnn_centres(pred, 4.0, rmax)
+    o = rd.offsets_to_numpy(rd.register(ref, frames, r, rmax, centers=cen))
+    s_auto = float(rd.offsets_to_numpy(rd.register(ref, ref.reshape(1, H, W), 0, rmax))["peak"][0])
+
+    def inner(o):
+        ix = (o["dx"] > -rmax) & (o["dx"] < rmax)
+        iy = (o["dy"] > -rmax) & (o["dy"] < rmax)
+        return (((o["flags"] & rd.EDGE_X) != 0) & ix) | (((o["flags"] & rd.EDGE_Y) != 0) & iy)
+
+    n_moves = np.zeros(M, np.int32)
+    c = cen.cpu().numpy().copy()
+    for _ in range(moves):
+        walk = np.nonzero(inner(o))[0]
+        for k in walk:
+            c[k] = (o["dx"][k], o["dy"][k])
+            o[k] = rd.offsets_to_numpy(rd.register(ref, frames[k:k + 1], r, rmax,
+                                                   centers=torch.from_numpy(c[k:k + 1].copy()).to("cuda:0")))[0]
+            n_moves[k] += 1
+    fb = inner(o) | ~(o["peak"] >= ratio * s_auto)
+    for k in np.nonzero(fb)[0]:
+        o[k] = rd.offsets_to_numpy(rd.register(ref, frames[k:k + 1], rmax, rmax))[0]
+        o["flags"][k] |= rd.FALLBACK
+    return o, cen.cpu().numpy(), fb, n_moves
+
+
+def test_propose_matches_the_host_flow(rd, trained):
+    """reduce_propose takes every decision on the device; the same decisions taken on the
+    host with the stage-wise calls give the same bytes, for trained and untrained weights."""
+    learned, p0, p1, _ = trained
+    M = 24
+    frames, _ = learned.render_stack(3, M + 1, TRAIN_W, TRAIN_W, TRAIN_BOUND)
+    ref, rest = frames[0], frames[1:].contiguous()
+    for name, p in (("untrained", p0), ("trained", p1)):
+        o_dev, c_dev, info = rd.propose(ref, rest, p, radius_max=TRAIN_RMAX)
+        got = rd.offsets_to_numpy(o_dev)
+        want, c_host, fb, n_moves = _host_flow(rd, learned, p.cpu().numpy(), ref, rest, TRAIN_RMAX)
+        info = info.cpu().numpy()
+        print(f"{name}: {int(fb.sum())} fallbacks, {int(n_moves.sum())} moves")
+        np.testing.assert_array_equal(c_dev.cpu().numpy(), c_host)
+        np.testing.assert_array_equal(info & 255, n_moves)
+        np.testing.assert_array_equal((info >> 8) & 3 != 0, fb)
+        assert got.tobytes() == want.tobytes(), name
+
+
+@pytest.mark.slow
+def test_trained_weights_at_4096_match_the_full_search(rd, orc):
+    """The shipped network (trained on the GPU by these kernels on 4096x4096 pairs with
+    shifts within +-64 px) on two evaluation stacks of 16 frames each: the learned call's
+    integer offsets equal the full +-64 px search on every frame, with no fallback; the
+    untrained network needs the fallback far more often; the full search itself matches
+    the oracle's whole window on one frame."""
+    from paper_2008_11486_amd import learned
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    trained_p = learned.load_params(os.path.join(root, "paper_2008_11486_amd", "weights", "proposal_4096.npy"))
+    M, S = 16, 4096
+    stats = {"trained": [0, 0, []], "untrained": [0, 0, []]}
+    for index in (0, 1):
+        frames, t = learned.render_stack(index, M + 1, S, S, 64.0)
+        ref, rest = frames[0], frames[1:].contiguous()
+        full = rd.offsets_to_numpy(learned.full_search(ref, rest, 64))
+        for name, p in (("trained", trained_p), ("untrained", learned.init_params(0))):
+            res = learned.LearnedRegistrar(p, S, S, M, radius_max=64).register(ref, rest)
+            np.testing.assert_array_equal(res.offsets["dx"], full["dx"])
+            np.testing.assert_array_equal(res.offsets["dy"], full["dy"])
+            err = np.abs(res.centres - np.stack([full["dx"], full["dy"]], 1)).max(axis=1)
+            stats[name][0] += int(res.fallback.sum())
+            stats[name][1] += M
+            stats[name][2] += list(err)
+        if index == 0:
+            o = orc.register(ref.cpu().numpy().astype(np.float64), rest[0].cpu().numpy().astype(np.float64), 64)
+            assert (o["dx"][0], o["dy"][0]) == (full["dx"][0], full["dy"][0])
+            for ax in ("sx", "sy"):
+                assert abs(float(o[ax][0]) - float(full[ax][0])) <= 2 * ulp32(o[ax][0])
+            np.testing.assert_allclose(full["peak"][0], o["peak"][0], rtol=1e-10)
+        del frames, ref, rest
+    for name, (nfb, n, err) in stats.items():
+        print(f"{name}: fallback rate {nfb / n:.3f} ({nfb} of {n}), centre error median {np.median(err):.1f} px, "
+              f"max {np.max(err):.0f} px")
+    assert stats["trained"][0] == 0
+    assert stats["untrained"][0] > stats["trained"][0]

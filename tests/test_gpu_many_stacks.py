@@ -5,8 +5,10 @@ same way, all stacks in one batched call.  The oracle checks, on stacks of every
 (the largest stack of each size and the smallest stack): the overlap rectangle, the
 integer and sub-pixel offsets of sampled frames (the oracle's 3x3 window around the
 GPU's maximum on the same calibrated frames must peak at the same offset with the same
-parabola), and whole rows of the combined image (the oracle's shift and clipped mean of
-the GPU's calibrated frames with the GPU's offsets).
+parabola; for one frame of every stack the oracle searches the whole +-17 px window and
+must find the same maximum, flags and parabola), and whole rows of the combined image
+(the oracle's shift and clipped mean of the GPU's calibrated frames with the GPU's
+offsets).
 """
 import numpy as np
 import pytest
@@ -53,7 +55,7 @@ def _calibrated(rd, stack):
 
 def test_many_stack_offsets_and_rectangles(rd, orc, many):
     specs, picks = many["specs"], many["picks"]
-    checked = 0
+    checked = full = 0
     for i in picks:
         sp = specs[i]
         img, rect, offs, nrej = many["results"][i]
@@ -74,8 +76,19 @@ def test_many_stack_offsets_and_rectangles(rd, orc, many):
                 assert diff <= 2 * ulp32(o[ax][0]), (i, k, ax, o[ax][0], offs[ax][k])
             np.testing.assert_allclose(offs["peak"][k], o["peak"][0], rtol=1e-10)
             checked += 1
+        # the whole window on the first frame of the stack
+        frame = cal[1].cpu().numpy().astype(np.float64)
+        o = orc.register(ref, frame, sp.radius)
+        assert (o["dx"][0], o["dy"][0]) == (offs["dx"][1], offs["dy"][1]), (i, o, offs[1])
+        assert o["flags"][0] == offs["flags"][1], (i, o["flags"][0], offs["flags"][1])
+        for ax in ("sx", "sy"):
+            assert abs(float(o[ax][0]) - float(offs[ax][1])) <= 2 * ulp32(o[ax][0]), (i, ax, o[ax][0], offs[ax][1])
+        np.testing.assert_allclose(offs["peak"][1], o["peak"][0], rtol=1e-10)
+        np.testing.assert_allclose(offs["second"][1], o["second"][0], rtol=1e-10)
+        full += 1
         del cal
-    print(f"{len(picks)} stacks, {checked} frames checked; plans {many['plans']}")
+    print(f"{len(picks)} stacks, {checked} frames checked locally, {full} over the whole window; "
+          f"plans {many['plans']}")
 
 
 def test_many_stack_combined_rows(rd, orc, many):

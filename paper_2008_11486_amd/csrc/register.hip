@@ -201,30 +201,43 @@ extern "C" size_t reduce_register_ws(int32_t W, int32_t H, int32_t N, int32_t ra
     return register_ws_bytes(p, N);
 }
 
+// Argument checks shared by the search entry points; fills the template rectangle and the plan.
+static int register_checks(const char *who, const float *ref, const float *frames, int32_t W, int32_t H, int32_t N,
+                           int32_t radius, int32_t radius_max, const int32_t *tmpl, const reduce_offset_t *out,
+                           int32_t t[4], RegPlan *plan)
+{
+    const std::string w(who);
+    if (!ref || !frames || !out) return fail(REDUCE_ERR_NULL, w + ": NULL buffer");
+    if (W < 1 || H < 1 || N < 1) return fail(REDUCE_ERR_SHAPE, w + ": W, H, N must be >= 1");
+    if (radius < 0 || radius_max < 0) return fail(REDUCE_ERR_RANGE, w + ": negative radius");
+    if (radius > 1024) return fail(REDUCE_ERR_UNSUPPORTED, w + ": radius above 1024");
+    if (W - 2 * radius_max < 1 || H - 2 * radius_max < 1)
+        return fail(REDUCE_ERR_RANGE, w + ": radius_max leaves no template");
+    t[0] = radius_max; t[1] = radius_max; t[2] = W - 2 * radius_max; t[3] = H - 2 * radius_max;
+    if (tmpl) {
+        t[0] = tmpl[0]; t[1] = tmpl[1]; t[2] = tmpl[2]; t[3] = tmpl[3];
+        if (t[2] < 1 || t[3] < 1) return fail(REDUCE_ERR_SHAPE, w + ": empty template");
+        if (t[0] - radius_max < 0 || t[1] - radius_max < 0 || (int64_t)t[0] + t[2] + radius_max > W ||
+            (int64_t)t[1] + t[3] + radius_max > H)
+            return fail(REDUCE_ERR_RANGE, w + ": template dilated by radius_max leaves the frame");
+    }
+    if (N > 65535) return fail(REDUCE_ERR_UNSUPPORTED, w + ": N above 65535");
+    *plan = reg_plan(W, H, radius, radius_max);
+    if (plan->D == 0) return fail(REDUCE_ERR_UNSUPPORTED, w + ": window too large for any launch shape");
+    return REDUCE_OK;
+}
+
 extern "C" int reduce_register(const float *ref, const float *frames, int32_t W, int32_t H, int32_t N,
                                int32_t radius, int32_t radius_max, const int32_t *centers, const int32_t *tmpl,
                                reduce_offset_t *out, double *scores, void *ws, size_t ws_bytes, void *stream)
 {
-    if (!ref || !frames || !out) return fail(REDUCE_ERR_NULL, "reduce_register: NULL buffer");
-    if (W < 1 || H < 1 || N < 1) return fail(REDUCE_ERR_SHAPE, "reduce_register: W, H, N must be >= 1");
-    if (radius < 0 || radius_max < 0) return fail(REDUCE_ERR_RANGE, "reduce_register: negative radius");
-    if (radius > 1024) return fail(REDUCE_ERR_UNSUPPORTED, "reduce_register: radius above 1024");
-    if (W - 2 * radius_max < 1 || H - 2 * radius_max < 1)
-        return fail(REDUCE_ERR_RANGE, "reduce_register: radius_max leaves no template");
-    int32_t tx0 = radius_max, ty0 = radius_max, tw = W - 2 * radius_max, th = H - 2 * radius_max;
-    if (tmpl) {
-        tx0 = tmpl[0]; ty0 = tmpl[1]; tw = tmpl[2]; th = tmpl[3];
-        if (tw < 1 || th < 1) return fail(REDUCE_ERR_SHAPE, "reduce_register: empty template");
-        if (tx0 - radius_max < 0 || ty0 - radius_max < 0 || (int64_t)tx0 + tw + radius_max > W ||
-            (int64_t)ty0 + th + radius_max > H)
-            return fail(REDUCE_ERR_RANGE, "reduce_register: template dilated by radius_max leaves the frame");
-    }
-    if (N > 65535) return fail(REDUCE_ERR_UNSUPPORTED, "reduce_register: N above 65535");
-    const RegPlan p = reg_plan(W, H, radius, radius_max);
-    if (p.D == 0) return fail(REDUCE_ERR_UNSUPPORTED, "reduce_register: window too large for any launch shape");
+    int32_t t[4];
+    RegPlan p;
+    const int c = register_checks("reduce_register", ref, frames, W, H, N, radius, radius_max, tmpl, out, t, &p);
+    if (c != REDUCE_OK) return c;
     const size_t need = register_ws_bytes(p, N);
     if (!ws || ws_bytes < need)
         return fail(REDUCE_ERR_WORKSPACE, "reduce_register: workspace needs " + std::to_string(need) + " bytes");
-    return register_launch(ref, frames, W, H, N, radius, radius_max, centers, tx0, ty0, tw, th, out, scores, ws, p,
-                           as_stream(stream));
+    return register_launch(ref, frames, W, H, N, radius, radius_max, centers, t[0], t[1], t[2], t[3], out, scores,
+                           ws, p, as_stream(stream));
 }

@@ -76,6 +76,8 @@ def lib() -> ctypes.CDLL:
 def _declare(L: ctypes.CDLL) -> None:
     P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     L.oracle_num_threads.restype = ctypes.c_int
+    L.oracle_set_num_threads.argtypes = [ctypes.c_int]
+    L.oracle_set_num_threads.restype = None
     L.oracle_calibrate.argtypes = [P, I64, I64, P, P, P, I64, P, I32, I32, I32]
     L.oracle_register.argtypes = [P, P, I32, I32, I32, I32, I32, P, P, P, P]
     L.oracle_valid_rect.argtypes = [P, I32, I32, I32, P]
@@ -119,6 +121,11 @@ def _f64(a) -> np.ndarray:
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (results do not depend on it)."""
+    lib().oracle_set_num_threads(int(n))
 
 
 def calibrate(raw: np.ndarray, dark: np.ndarray, flat: np.ndarray, bias: Optional[np.ndarray] = None) -> np.ndarray:

@@ -29,6 +29,17 @@ int oracle_num_threads(void)
 #endif
 }
 
+/* Threads of the following parallel loops (the CPU baseline times 1 and all); the
+ * result does not depend on it: every parallel loop writes disjoint outputs. */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------------
  * Calibration (Section 2.1 and 2.2: the 16-bit to floating-point cast at the bias
  * subtraction, then dark subtraction and flat fielding).  Without a bias frame the

@@ -37,6 +37,7 @@ typedef struct {
 } oracle_offset_t;
 
 int oracle_num_threads(void);
+void oracle_set_num_threads(int n);
 
 /* out[k][y][x] = ((raw[k][y][x] - bias[y][x]) - dark[y][x]) / flat[y][x] in double
  * (bias may be NULL: no bias term).  raw has row pitch raw_row_pitch and frame pitch

@@ -154,19 +154,32 @@ def render_sky(W: int, H: int, stars: np.ndarray, t: Sequence[float]) -> np.ndar
     return img
 
 
-def _cosmic_rays(raw_f: np.ndarray, rng: np.random.Generator) -> None:
-    H, W = raw_f.shape
+def cosmic_ray_hits(W: int, H: int, rng: np.random.Generator):
+    """Pixels of one frame hit by cosmic-ray tracks and the ADU each hit adds:
+    round(1e-4 W H / 2.5) tracks, each of length U{1..4} from a uniform start pixel in one
+    of 8 directions, every hit pixel inside the frame adding U(5e3, 6e4).  Returns
+    (ys, xs, adu) in draw order (a pixel may appear more than once)."""
     n_tracks = int(round(1e-4 * W * H / 2.5))
     lengths = rng.integers(1, 5, size=n_tracks)
     dirs = rng.integers(0, 8, size=n_tracks)
     xs = rng.integers(0, W, size=n_tracks)
     ys = rng.integers(0, H, size=n_tracks)
+    hy, hx, adu = [], [], []
     for L, d, x, y in zip(lengths, dirs, xs, ys):
         ddx, ddy = _DIRECTIONS[d]
         for step in range(int(L)):
             px, py = int(x) + ddx * step, int(y) + ddy * step
             if 0 <= px < W and 0 <= py < H:
-                raw_f[py, px] += rng.uniform(5.0e3, 6.0e4)
+                hy.append(py)
+                hx.append(px)
+                adu.append(rng.uniform(5.0e3, 6.0e4))
+    return np.array(hy, dtype=np.int64), np.array(hx, dtype=np.int64), np.array(adu, dtype=np.float64)
+
+
+def _cosmic_rays(raw_f: np.ndarray, rng: np.random.Generator) -> None:
+    H, W = raw_f.shape
+    ys, xs, adu = cosmic_ray_hits(W, H, rng)
+    np.add.at(raw_f, (ys, xs), adu)
 
 
 def _stack_setup(spec: StackSpec):

@@ -106,7 +106,8 @@ def test_batch_matches_oracle_end_to_end(rd, orc):
     assert np.array_equal(offs["dx"][1:], o["offsets"]["dx"][1:]) and np.array_equal(offs["dy"][1:], o["offsets"]["dy"][1:])
     assert np.array_equal(rect, o["rect"])
     s = np.stack([offs["sx"], offs["sy"]], 1).astype(np.float32)
-    assert_end_to_end(orc, o["cal"], s, o["s"], rect, img.cpu().numpy(), "batch vs oracle")
+    cal_gpu = rd.calibrate(to_dev(st.raw), to_dev(st.dark), to_dev(st.flat)).cpu().numpy()
+    assert_end_to_end(orc, o["cal"], cal_gpu, offs, s, o["s"], rect, img.cpu().numpy(), 6, "batch vs oracle")
 
 
 def test_batch_workload1_three_bands(rd):
@@ -144,7 +145,9 @@ def test_batch_deep_stacks(rd, orc):
     assert np.array_equal(offs["dx"][1:], o["offsets"]["dx"][1:]) and np.array_equal(offs["dy"][1:], o["offsets"]["dy"][1:])
     s = np.stack([offs["sx"], offs["sy"]], 1).astype(np.float32)
     assert np.array_equal(rect, o["rect"])
-    assert_end_to_end(orc, o["cal"], s, o["s"], rect, img.cpu().numpy(), "97-frame batch vs oracle")
+    cal_gpu = rd.calibrate(dev[0][0], dev[0][1], dev[0][2]).cpu().numpy()
+    assert_end_to_end(orc, o["cal"], cal_gpu, offs, s, o["s"], rect, img.cpu().numpy(), specs[0][3],
+                      "97-frame batch vs oracle")
 
 
 def test_batch_bias_and_bad_pixels(rd, orc):
@@ -181,8 +184,10 @@ def test_batch_bias_and_bad_pixels(rd, orc):
         s = (np.stack([offs["dx"], offs["dy"]], 1) if extras[i] else np.stack([offs["sx"], offs["sy"]], 1))
         s = s.astype(np.float32)
         assert np.array_equal(rect, o["rect"]), (i, rect, o["rect"])
-        assert_end_to_end(orc, o["cal"], s, o["s"], rect, img.cpu().numpy(),
-                          f"stack {i} with bias and bad pixels vs oracle", mask=mask, missing=True)
+        cal_gpu = rd.calibrate(dev[i][0], dev[i][1], dev[i][2], bias=dev[i][4]).cpu().numpy()
+        assert_end_to_end(orc, o["cal"], cal_gpu, offs, s, o["s"], rect, img.cpu().numpy(), R,
+                          f"stack {i} with bias and bad pixels vs oracle", integer_mode=extras[i], mask=mask,
+                          missing=True)
 
 
 def test_batch_rejects_bad_stacks(rd):

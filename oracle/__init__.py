@@ -97,8 +97,9 @@ def _declare(L: ctypes.CDLL) -> None:
         L.oracle_cnn_num_params.restype = ctypes.c_int64
         L.oracle_cnn_act_size.argtypes = [I32, I32, I32]
         L.oracle_cnn_act_size.restype = ctypes.c_int64
+        L.oracle_adamw.argtypes = [P, P, P, P, I64, D, D, D, D, D, I32]
         for name in ("oracle_bf16_round", "oracle_conv3x3s2_forward", "oracle_conv3x3s2_backward",
-                     "oracle_cnn_forward", "oracle_cnn_loss_backward"):
+                     "oracle_cnn_forward", "oracle_cnn_loss_backward", "oracle_adamw"):
             getattr(L, name).restype = ctypes.c_int
 
 
@@ -303,6 +304,17 @@ def cnn_loss_backward(x: np.ndarray, params: np.ndarray, target: np.ndarray, hub
     _check(lib().oracle_cnn_loss_backward(_p(x), B, H, W, _p(params), 1 if bf16 else 0, _p(target),
                                           float(huber_delta), _p(loss), _p(grad)), "oracle_cnn_loss_backward")
     return float(loss[0]), grad
+
+
+def adamw(params, m, v, grad, lr: float, step: int, beta1: float = 0.9, beta2: float = 0.999,
+          eps: float = 1e-8, weight_decay: float = 0.0):
+    """One AdamW step (FP64); returns the new (params, m, v), the inputs untouched."""
+    p2, m2, v2 = (np.array(a, dtype=np.float64, copy=True).ravel() for a in (params, m, v))
+    g = _f64(grad).ravel()
+    assert p2.shape == m2.shape == v2.shape == g.shape
+    _check(lib().oracle_adamw(_p(p2), _p(m2), _p(v2), _p(g), p2.size, float(lr), float(beta1), float(beta2),
+                              float(eps), float(weight_decay), int(step)), "oracle_adamw")
+    return p2, m2, v2
 
 
 def reduce_stack(raw: np.ndarray, dark: np.ndarray, flat: np.ndarray, radius: int,

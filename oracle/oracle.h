@@ -96,6 +96,9 @@ int oracle_cnn_forward(const double *x, int32_t B, int32_t H, int32_t W, const d
 int oracle_cnn_loss_backward(const double *x, int32_t B, int32_t H, int32_t W, const double *params,
                              int32_t bf16, const double *target, double huber_delta, double *loss,
                              double *grad);
+/* One AdamW step in place on p, m, v [n] (decoupled weight decay, bias-corrected moments). */
+int oracle_adamw(double *p, double *m, double *v, const double *g, int64_t n, double lr, double beta1,
+                 double beta2, double eps, double wd, int32_t step);
 
 #ifdef __cplusplus
 }

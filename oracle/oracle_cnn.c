@@ -25,7 +25,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { O_OK = 0, O_NULL = 1, O_SHAPE = 2 };
+enum { O_OK = 0, O_NULL = 1, O_SHAPE = 2, O_RANGE = 3 };
 
 #define NCH 32
 static const int32_t CIN[4] = {2, NCH, NCH, NCH};
@@ -334,4 +334,32 @@ done:
     free(pool);
     free(pred);
     return rc;
+}
+
+/* ------------------------------------------------------------------------------
+ * One AdamW step (Loshchilov and Hutter, "Decoupled weight decay regularization",
+ * ICLR 2019, Adam with decoupled weight decay; moments bias-corrected as in Kingma and
+ * Ba, "Adam", ICLR 2015), in FP64:
+ *   m <- beta1 m + (1 - beta1) g          first moment
+ *   v <- beta2 v + (1 - beta2) g^2        second moment
+ *   mhat = m / (1 - beta1^t), vhat = v / (1 - beta2^t)
+ *   p <- p - lr (mhat / (sqrt(vhat) + eps) + wd p)
+ * The weight decay acts on the parameter itself (not through the gradient), at the
+ * parameter's value before the step.  t = step >= 1.
+ * ---------------------------------------------------------------------------- */
+int oracle_adamw(double *p, double *m, double *v, const double *g, int64_t n, double lr, double beta1,
+                 double beta2, double eps, double wd, int32_t step)
+{
+    if (!p || !m || !v || !g) return O_NULL;
+    if (n < 0 || step < 1 || !(eps > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0))
+        return O_RANGE;
+    const double c1 = 1.0 - pow(beta1, (double)step);
+    const double c2 = 1.0 - pow(beta2, (double)step);
+    for (int64_t i = 0; i < n; ++i) {
+        m[i] = beta1 * m[i] + (1.0 - beta1) * g[i];
+        v[i] = beta2 * v[i] + (1.0 - beta2) * g[i] * g[i];
+        const double mhat = m[i] / c1, vhat = v[i] / c2;
+        p[i] = p[i] - lr * (mhat / (sqrt(vhat) + eps) + wd * p[i]);
+    }
+    return O_OK;
 }

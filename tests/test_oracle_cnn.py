@@ -145,3 +145,49 @@ def test_network_input_normalisation(orc):
     np.testing.assert_allclose(z, ref, rtol=2 ** -8, atol=2 ** -8)  # bfloat16 has 8 significant bits
     np.testing.assert_array_equal(z, orc.bf16_round(z))
     assert np.array_equal(orc.cnn_input(np.full((32, 32), 7.0)), np.zeros((8, 8)))
+
+
+def test_adamw_constant_gradient_closed_form(orc):
+    """With the same gradient g at every step the bias-corrected moments are exactly g and
+    g^2, so every step is p <- (1 - lr wd) p - lr g / (|g| + eps): after T steps
+    p_T = q^T p_0 - c (1 - q^T) / (1 - q) with q = 1 - lr wd, c = lr g / (|g| + eps).
+    A coupled (L2-in-the-gradient) decay, a missing bias correction or eps inside the
+    square root all break it."""
+    rng = np.random.default_rng(12)
+    n, lr, wd, eps, T = 64, 1e-2, 0.1, 1e-3, 7
+    p0 = rng.normal(size=n)
+    g = rng.normal(size=n) * np.exp(rng.uniform(-3, 3, size=n))
+    p, m, v = p0.copy(), np.zeros(n), np.zeros(n)
+    for t in range(1, T + 1):
+        p, m, v = orc.adamw(p, m, v, g, lr, t, beta1=0.9, beta2=0.99, eps=eps, weight_decay=wd)
+    q = 1.0 - lr * wd
+    c = lr * g / (np.abs(g) + eps)
+    want = q ** T * p0 - c * (1.0 - q ** T) / (1.0 - q)
+    np.testing.assert_allclose(p, want, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(m, (1 - 0.9 ** T) * g, rtol=1e-13)
+    np.testing.assert_allclose(v, (1 - 0.99 ** T) * g * g, rtol=1e-13)
+
+
+def test_adamw_first_step_by_hand(orc):
+    """Step 1 from zero moments, worked by hand: m = 0.1 g, v = 0.001 g^2, mhat = g,
+    vhat = g^2; for g = 2, p = 3, lr = 0.5, wd = 0.25, eps = 1:
+    p <- 3 - 0.5 (2 / (2 + 1) + 0.25 * 3) = 3 - 0.5 * (17 / 12) = 2.291666..."""
+    p, m, v = orc.adamw([3.0], [0.0], [0.0], [2.0], 0.5, 1, beta1=0.9, beta2=0.999, eps=1.0, weight_decay=0.25)
+    assert p[0] == pytest.approx(3.0 - 0.5 * 17.0 / 12.0, rel=1e-15)
+    assert m[0] == pytest.approx(0.2, rel=1e-15) and v[0] == pytest.approx(0.004, rel=1e-13)
+
+
+def test_adamw_matches_torch_float64(orc):
+    """Independent implementation of the same rule: torch.optim.AdamW in float64 on the CPU."""
+    rng = np.random.default_rng(13)
+    n = 200
+    p0 = rng.normal(size=n)
+    tp = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.AdamW([tp], lr=3e-3, betas=(0.8, 0.95), eps=1e-6, weight_decay=0.02)
+    p, m, v = p0.copy(), np.zeros(n), np.zeros(n)
+    for t in range(1, 6):
+        g = rng.normal(size=n)
+        tp.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+        p, m, v = orc.adamw(p, m, v, g, 3e-3, t, beta1=0.8, beta2=0.95, eps=1e-6, weight_decay=0.02)
+    np.testing.assert_allclose(p, tp.detach().numpy(), rtol=1e-13, atol=1e-15)

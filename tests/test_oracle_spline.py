@@ -1,6 +1,6 @@
 """Pins of the oracle's bicubic-spline shift (natural cubic spline per row and column).
 
-* The paper's own check (Sec. 3.1.2): an image of cubic B-spline basis functions is
+* The paper's own check (Sec. 3.1.1): an image of cubic B-spline basis functions is
   reproduced exactly by cubic-spline interpolation, so its shifted image is known in
   closed form without interpolating.
 * Linear images are reproduced exactly; integer shifts are exact copies.

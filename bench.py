@@ -4,13 +4,16 @@
 One step = one pass of the whole path (dark subtraction + flat division, registration
 against frame 0 of each stack, bilinear shift onto the common overlap, sigma-clipped
 mean) over one batch of synthetic frames already resident in HBM.  The default
-workload is three bands x 10 frames of 1024x1024 uint16 with sub-pixel shifts within
-+-20 px (search radius 21) and a 3-sigma, 3-iteration clip.
+workload is the largest one that runs as one call on one GPU: 64 independent stacks of
+3-30 frames with square sides from 512 to 4096 (6.56 Gpix of uint16 frames), sub-pixel
+shifts within +-16 px (search radius 17), all stacks in one batched call.
 
 Prints one JSON line: stacked Mpix/s (input pixels of all frames per second), the
-roofline position of the dominant kernel (timed with HIP events on its own stream
-over the timed steps), the streaming kernels' HBM fractions, and the FP64 CPU oracle
-timed on this host as a baseline.
+roofline position of the dominant kernel (timed with HIP events on its own stream over
+the timed steps), the FP64 CPU oracle timed on this host on a stated sample of the same
+workload (and the parity of the GPU's results on that sample), and extra legs: the three
+1024x1024 bands, the wide-field chain of 16 frames of 6144x6160 with the +-65 px search,
+the streaming kernels at that size, and the learned proposal against the full search.
 """
 from __future__ import annotations
 
@@ -34,11 +37,20 @@ FP64_VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 METRIC = "stacked Mpix/s & % HBM peak; learned vs full-search registration speedup"
 
 WORKLOADS = {
+    2: "64 stacks, N uniform in 3-30, square sides from {512, 1024, 2048, 4096} (6.56 Gpix of uint16 frames), "
+       "200 stars per 1024x1024, sub-pixel shifts +-16 px, search radius 17, bilinear shift, 3-sigma clipped "
+       "mean (3 iterations), all stacks in one batched call",
     1: "3 bands x 10 frames 1024x1024 uint16, 200 stars, sub-pixel shifts +-20 px, search radius 21, "
        "bilinear shift, 3-sigma clipped mean (3 iterations)",
     0: "5 frames 512x512 uint16, 20 stars, integer shifts +-8 px, search radius 8, integer shift, "
        "3-sigma clipped mean (3 iterations)",
 }
+REDUCE_NEAR_TIE = 4
+
+
+def log(msg):
+    """A progress line on stderr as each leg of the run ends (the JSON line goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def parse():
@@ -46,7 +58,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", type=int, default=1, choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", type=int, default=2, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the cost-model launch shapes")
     ap.add_argument("--path", choices=("stagewise", "batched"), default="batched",
@@ -71,14 +83,17 @@ def parse():
     ap.add_argument("--learned-frames", type=int, default=16)
     ap.add_argument("--no-wide", action="store_true",
                     help="skip the streaming kernels at the wide-field size (16 frames of 6144x6160)")
-    ap.add_argument("--no-many", action="store_true",
-                    help="skip the batched leg over 64 stacks of 3-30 frames, sides 512-4096")
+    ap.add_argument("--no-bands", action="store_true",
+                    help="skip the leg over three bands of 10 frames of 1024x1024 (with --workload 2)")
+    ap.add_argument("--no-wide-chain", action="store_true",
+                    help="skip the end-to-end wide-field chain with the +-65 px search")
     ap.add_argument("--sweep", action="store_true",
                     help="only the sweeps over image size and frame count (one JSON line)")
     ap.add_argument("--wide-only", action="store_true",
                     help="run only the wide-field streaming kernels (for counter runs) and print their figures")
-    ap.add_argument("--traffic-key", default="kernels",
-                    help="with --traffic-from: the section of the traffic file to write (kernels, wide)")
+    ap.add_argument("--traffic-key", default=None,
+                    help="with --traffic-from: the section of the traffic file to write (many, kernels, wide); "
+                         "default: many for workload 2, kernels otherwise")
     return ap.parse_args()
 
 
@@ -116,12 +131,24 @@ def source_hash(kernel):
 
 
 def _counter_rows(folder, counter):
+    """(kernel name, value) of every dispatch's counter in a rocprofv3 --pmc output folder:
+    CSV output (*counter_collection.csv) or the SQLite database rocprofv3 writes by default
+    (*_results.db, its counters_collection view)."""
+    import sqlite3
     rows = []
     for f in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
         with open(f, newline="") as fh:
             for r in csv.DictReader(fh):
                 if r["Counter_Name"] == counter:
                     rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    for f in glob.glob(os.path.join(folder, "**", "*_results.db"), recursive=True):
+        db = sqlite3.connect(f"file:{f}?mode=ro", uri=True)
+        try:
+            rows += [(n, float(v)) for n, v in db.execute(
+                "select kernel_name, value from counters_collection where counter_name = ? order by dispatch_id",
+                (counter,))]
+        finally:
+            db.close()
     if not rows:
         raise SystemExit(f"no {counter} rows under {folder}")
     return rows
@@ -322,37 +349,215 @@ def tuning_hook(store, limit=32):
     return hook
 
 
-def many_stacks(torch, rd, reps=2):
-    """64 stacks (frame counts 3-30, square sides 512-4096, sub-pixel shifts within +-16 px,
-    search radius 17) through one batched call: the stack shapes of the many-stack
-    workload, frames rendered on the GPU (star density of the 1024x1024 stacks)."""
+def search_flops(specs):
+    """Algorithmic flops of the full-window search of every non-reference frame: one FMA
+    (2 flop) per template pixel (the interior shrunk by the radius) per candidate offset."""
+    return sum(2.0 * (sp.N - 1) * (sp.W - 2 * sp.radius) * (sp.H - 2 * sp.radius) * (2 * sp.radius + 1) ** 2
+               for sp in specs)
+
+
+class ManyStackPipeline:
+    """The 64-stack workload (frame counts 3-30, square sides 512-4096, sub-pixel shifts
+    within +-16 px, search radius 17): frames rendered on the GPU at the star density of the
+    1024x1024 stacks, search shapes tuned per frame size, all stacks in one batched call
+    per step."""
+
+    def __init__(self, rd, torch, tune=True, tune_cache=None):
+        import synth
+        self.specs = synth.config_specs(2)
+        store = {}
+        cached = tune_cache is not None and os.path.exists(tune_cache)
+        if cached:
+            rd.tune_load(tune_cache)
+        tune = tune and not cached
+        self.stacks, self.shifts = many_stack_inputs(torch, rd, self.specs, tuning_hook(store) if tune else None)
+        log("64-stack inputs rendered")
+        self.plans = tune_many_stacks(torch, rd, self.specs, store) if tune else ("loaded" if cached else None)
+        if tune and tune_cache:
+            rd.tune_save(tune_cache)
+        self.batch = rd.StackBatch(self.stacks)
+        self.pixels = sum(sp.N * sp.W * sp.H for sp in self.specs)
+
+    def step(self):
+        self.batch.run()
+
+
+def many_sample(pipe, min_frames=5):
+    """Host copies for the CPU leg: per frame size, the stack with the fewest frames (at
+    least min_frames), its raw counts, dark, flat and the GPU's results; the GPU's offsets
+    of every stack (for the near-tie count)."""
+    specs = pipe.specs
+    picks = []
+    for W in sorted({sp.W for sp in specs}):
+        cand = [i for i, sp in enumerate(specs) if sp.W == W and sp.N >= min_frames]
+        picks.append(min(cand, key=lambda i: (specs[i].N, i)))
+    sample = []
+    for i in picks:
+        raw, dark, flat, R = pipe.stacks[i]
+        img, rect, offs, nrej = pipe.batch.result(i)
+        sample.append(dict(index=i, spec=specs[i], raw=raw.cpu().numpy().view(np.uint16), dark=dark.cpu().numpy(),
+                           flat=flat.cpu().numpy(), img=img.cpu().numpy(), rect=np.asarray(rect), offs=offs,
+                           n_rej=nrej))
+    all_offs = [pipe.batch.result(i)[2] for i in range(len(specs))]
+    return sample, all_offs
+
+
+def err_stats(e):
+    e = np.asarray(e, np.float64).ravel()
+    if e.size == 0:
+        return {"max": None, "p99.9": None, "p95": None, "p90": None}
+    return {"max": float(e.max()), "p99.9": float(np.quantile(e, 0.999)), "p95": float(np.quantile(e, 0.95)),
+            "p90": float(np.quantile(e, 0.90))}
+
+
+def _oracle_chain_timed(oracle, raw, dark, flat, R):
+    """The oracle's chain from raw, stage by stage, with the time of each stage."""
+    t = {}
+    t0 = time.perf_counter()
+    cal = oracle.calibrate(raw, dark, flat)
+    t["calibrate"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    offs = oracle.register(cal[0], cal, R)
+    t["register"] = time.perf_counter() - t0
+    s = np.stack([offs["sx"], offs["sy"]], axis=1).astype(np.float32)
+    s[0] = 0.0
+    rect = oracle.valid_rect(s, raw.shape[2], raw.shape[1])
+    t0 = time.perf_counter()
+    al = oracle.shift(cal, s, rect)
+    t["shift"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    out, keep, nrej, near = oracle.combine(al)
+    t["combine"] = time.perf_counter() - t0
+    return dict(cal=cal, offsets=offs, s=s, rect=rect, out=out, near=near, n_rej=nrej), t
+
+
+def cpu_baseline_many(sample, all_offs, specs, one_thread_sides=(512, 1024)):
+    """The FP64 C oracle on this host's cores, from raw frames, on the sampled stacks (one
+    per frame size), stage by stage; the whole workload's time extrapolated from it (the
+    search by its FMA count per frame size, calibrate + shift + combine by pixel count),
+    at all threads and at one thread (one thread: the stacks of the sides named, larger
+    sides at the per-FMA rate of the largest of them).  The same oracle outputs give the
+    parity of the GPU's results on the sample: offsets from raw (integer offsets must be
+    identical), and the combined images against the oracle's shift and clip at the GPU's
+    offsets (pixels inside the clip's threshold band are counted, not value-checked)."""
+    import oracle
+    all_threads = oracle.num_threads()
+
+    def fma(sp):
+        return (sp.N - 1) * (sp.W - 2 * sp.radius) * (sp.H - 2 * sp.radius) * (2 * sp.radius + 1) ** 2
+
+    def extrapolate(times):
+        """times: {side: (t_register, t_stream, sample fma, sample pixels)} -> workload seconds."""
+        stream_rate = sum(v[1] for v in times.values()) / sum(v[3] for v in times.values())
+        top = max(times)
+        total = 0.0
+        for sp in specs:
+            key = sp.W if sp.W in times else top
+            total += fma(sp) * times[key][0] / times[key][2] + sp.N * sp.W * sp.H * stream_rate
+        return total
+
+    pix_all = sum(sp.N * sp.W * sp.H for sp in specs)
+    t_all, parity_rows = {}, []
+    wall0 = time.perf_counter()
+    for smp in sample:
+        sp = smp["spec"]
+        o, t = _oracle_chain_timed(oracle, smp["raw"], smp["dark"], smp["flat"], sp.radius)
+        t_all[sp.W] = (t["register"], t["calibrate"] + t["shift"] + t["combine"], fma(sp), sp.N * sp.W * sp.H)
+        parity_rows.append(_parity_row(oracle, smp, o))
+        del o
+    wall_all = time.perf_counter() - wall0
+    t_one = {}
+    oracle.set_num_threads(1)
+    wall0 = time.perf_counter()
+    try:
+        for smp in sample:
+            sp = smp["spec"]
+            if sp.W in one_thread_sides:
+                _, t = _oracle_chain_timed(oracle, smp["raw"], smp["dark"], smp["flat"], sp.radius)
+                t_one[sp.W] = (t["register"], t["calibrate"] + t["shift"] + t["combine"], fma(sp),
+                               sp.N * sp.W * sp.H)
+    finally:
+        oracle.set_num_threads(all_threads)
+    wall_one = time.perf_counter() - wall0
+    T_all, T_one = extrapolate(t_all), extrapolate(t_one)
+    desc = ", ".join(f"{smp['spec'].N} x {smp['spec'].W}x{smp['spec'].H} (stack {smp['index']})" for smp in sample)
+    baseline = {"value": round(pix_all / T_all / 1e6, 3), "unit": "Mpix/s", "cores": all_threads, "kind": "oracle",
+                "sample": f"FP64 C oracle from raw frames (calibrate, full-window search, shift, combine) on one "
+                          f"stack per frame size: {desc}; {wall_all:.1f} s at {all_threads} threads; the workload's "
+                          f"{pix_all / 1e6:.0f} Mpix extrapolated per frame size (search by FMA count, the other "
+                          f"stages by pixel count): {T_all:.0f} s",
+                "value_1_thread": round(pix_all / T_one / 1e6, 4),
+                "sample_1_thread": f"the {', '.join(str(w) for w in sorted(t_one))} stacks of the sample at 1 "
+                                   f"thread ({wall_one:.1f} s); larger sides at the per-FMA search rate of the "
+                                   f"{max(t_one)} stack: {T_one:.0f} s for the workload"}
+    return baseline, _parity_summary(parity_rows, all_offs, specs)
+
+
+def _parity_row(oracle, smp, o):
+    """One sampled stack: GPU results against the oracle's chain from raw."""
+    sp, offs = smp["spec"], smp["offs"]
+    s_gpu = np.stack([offs["sx"], offs["sy"]], 1).astype(np.float32)
+    same_int = (offs["dx"][1:] == o["offsets"]["dx"][1:]) & (offs["dy"][1:] == o["offsets"]["dy"][1:])
+    ds = np.abs(s_gpu.astype(np.float64) - o["s"].astype(np.float64))[1:]
+    rect_same = bool(np.array_equal(smp["rect"], o["rect"]))
+    if np.array_equal(s_gpu[1:], o["s"][1:]) and rect_same:
+        ref, near = o["out"], o["near"].any(axis=0)
+    else:  # the oracle's shift and clip of its own calibration at the GPU's offsets
+        al = oracle.shift(o["cal"], s_gpu, smp["rect"])
+        ref, _, _, nb = oracle.combine(al)
+        near = nb.any(axis=0)
+        del al
+    g = smp["img"].astype(np.float64)
+    ok = ~near
+    e = np.abs(g[ok] - ref[ok]) / np.maximum(np.abs(ref[ok]), 1.0)
+    return dict(index=smp["index"], N=sp.N, W=sp.W, frames=int(sp.N - 1), same_int=int(same_int.sum()),
+                s_diff_frames=int(np.any(ds > 0, axis=1).sum()), s_diff_max=float(ds.max()) if ds.size else 0.0,
+                rect_same=rect_same, pixels=int(g.size), band=int(near.sum()), err=e, n_rej=smp["n_rej"])
+
+
+def _parity_summary(rows, all_offs, specs, tol=2e-6):
+    e = np.concatenate([r["err"] for r in rows])
+    frames = sum(r["frames"] for r in rows)
+    near_ties = sum(int(np.sum((o["flags"][1:] & REDUCE_NEAR_TIE) != 0)) for o in all_offs)
+    st = err_stats(e)
+    ok = all(r["same_int"] == r["frames"] and r["rect_same"] for r in rows) and (st["max"] or 0.0) <= tol
+    return {"stacks": [r["index"] for r in rows], "frames_searched": frames,
+            "identical_integer_offsets": round(sum(r["same_int"] for r in rows) / max(frames, 1), 6),
+            "frames_with_subpixel_offset_difference": sum(r["s_diff_frames"] for r in rows),
+            "max_subpixel_offset_difference_px": max(r["s_diff_max"] for r in rows),
+            "rects_identical": all(r["rect_same"] for r in rows),
+            "pixels_checked": int(e.size), "threshold_band_pixels": sum(r["band"] for r in rows),
+            "rel_err": st, "tolerance": tol,
+            "near_tie_frames_all_stacks": near_ties,
+            "frames_all_stacks": sum(sp.N - 1 for sp in specs), "within_tolerance": bool(ok)}
+
+
+def bands_leg(torch, rd, steps=20, warmup=3):
+    """The three 1024x1024 bands of 10 frames (search radius 21) through one batched call."""
     import synth
-    specs = synth.config_specs(2)
-    store = {}
-    stacks, _ = many_stack_inputs(torch, rd, specs, tuning_hook(store))
-    pix = sum(sp.N * sp.W * sp.H for sp in specs)
-    plans = tune_many_stacks(torch, rd, specs, store)
-    batch = rd.StackBatch(stacks)
-    batch.run()
+    stacks = synth.make_config(1)
+    pipe = BatchedPipeline(rd, torch, stacks, False)
+    cals = [rd.calibrate(torch.from_numpy(st.raw.view(np.int16)).to("cuda:0"),
+                         torch.from_numpy(st.dark).to("cuda:0"), torch.from_numpy(st.flat).to("cuda:0"))
+            for st in stacks]
+    rd.tune_register(cals[0][0].contiguous(), torch.cat([c[1:] for c in cals]), stacks[0].spec.radius)
+    del cals
+    for _ in range(warmup):
+        pipe.step()
     torch.cuda.synchronize()
     rd.prof_enable(True)
     t0 = time.perf_counter()
-    for _ in range(reps):
-        batch.run()
+    for _ in range(steps):
+        pipe.step()
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / reps
+    dt = (time.perf_counter() - t0) / steps
     ms, n = rd.prof_query("batch_score")
     rd.prof_enable(False)
-    flops = sum(2.0 * (sp.N - 1) * (sp.W - 2 * sp.radius) * (sp.H - 2 * sp.radius) * (2 * sp.radius + 1) ** 2
-                for sp in specs)
-    frames_n = [sp.N for sp in specs]
-    res = {"workload": f"{len(specs)} stacks, N in {min(frames_n)}-{max(frames_n)} ({sum(frames_n)} frames), "
-                       f"sides 512-4096, shifts +-16 px, R=17, one batched call",
-           "Mpix/s": round(pix / dt / 1e6, 1), "ms_per_call": round(dt * 1e3, 2), "input_pixels": pix,
-           "search_ms": round(ms / n, 2), "search_TFLOP/s": round(flops / (ms / n / 1e3) / 1e12, 2),
-           "search_frac_fp64": round(flops / (ms / n / 1e3) / 1e12 / FP64_VALU_PEAK_TFLOPS, 4),
-           "search_plans": plans}
-    del batch, stacks
+    flops = search_flops([st.spec for st in stacks]) / (n / steps)
+    res = {"workload": WORKLOADS[1], "Mpix/s": round(pipe.pixels / dt / 1e6, 1), "ms_per_step": round(dt * 1e3, 4),
+           "search_avg_launch_ms": round(ms / n, 4),
+           "search_frac_fp64": round(flops / (ms / n / 1e3) / 1e12 / FP64_VALU_PEAK_TFLOPS, 4)}
+    del pipe
     torch.cuda.empty_cache()
     return res
 
@@ -434,19 +639,16 @@ def learned_comparison(torch, rd, weights_path, M):
             "true_offset_max_abs_px": float(np.abs(t).max()), "learned_breakdown": parts}
 
 
-def streaming_wide(torch, rd, reps=5, traffic_path=os.path.join(ROOT, "profiles", "traffic.json")):
-    """calibrate, shift (bilinear, and the bicubic spline timed alone) and combine over 16
-    frames of 6144x6160 (working sets of 1.2-2.4 GB, far beyond the 256 MB last-level
-    cache), bad-pixel masking with the missing-value combine, and the combine of a
-    97-frame stack (the deepest co-adding set of the paper) of 2040x2040, timed with
-    HIP events on their stream."""
-    from paper_2008_11486_amd import learned
+def wide_inputs(torch, rd):
+    """The wide-field stack: 16 frames of 6144x6160 rendered on the GPU (5000 stars, sky
+    1000 ADU, read noise 10 ADU), shifts uniform in +-64 px, dark 100 +- 3 ADU, flat
+    1 +- 0.05, cosmic-ray tracks of 1-4 px on 0.01% of the pixels of every frame (5e3-6e4
+    ADU per hit pixel), rounded to uint16."""
+    import synth
     N, W, H, bound = 16, 6144, 6160, 64.0
     dev = torch.device("cuda:0")
     g = torch.Generator(device=dev)
     g.manual_seed(20081148)
-    # input preparation: rendered sky (5000 stars per frame), then dark, flat, single-pixel
-    # cosmic-ray hits on 0.01% of pixels, rounding to uint16
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([20081148, 3])))
     S = 5000
     x = rng.uniform(-bound - 8, W + bound + 8, S)
@@ -462,10 +664,67 @@ def streaming_wide(torch, rd, reps=5, traffic_path=os.path.join(ROOT, "profiles"
                      sky=1000.0, fwhm=3.0, read_noise=10.0, seed=3, out=cal)
     dark = 100.0 + 3.0 * torch.randn((H, W), generator=g, device=dev)
     flat = 0.95 + 0.1 * torch.rand((H, W), generator=g, device=dev)
-    hits = torch.rand((N, H, W), generator=g, device=dev) < 1e-4
-    cal.mul_(flat).add_(dark).add_(hits * (5e3 + 5.5e4 * torch.rand((N, H, W), generator=g, device=dev)))
+    cal.mul_(flat).add_(dark)
+    hit_pixels = 0
+    for k in range(N):
+        ys, xs, adu = synth.cosmic_ray_hits(W, H, np.random.Generator(np.random.PCG64(
+            np.random.SeedSequence([20081148, 3, 1, k]))))
+        idx = (torch.full((len(ys),), k, dtype=torch.int64, device=dev), torch.from_numpy(ys).to(dev),
+               torch.from_numpy(xs).to(dev))
+        cal.index_put_(idx, torch.from_numpy(adu.astype(np.float32)).to(dev), accumulate=True)
+        hit_pixels += len(ys)
     raw = cal.round_().clamp_(0, 65535).to(torch.int32).to(torch.int16)  # two's-complement bits of uint16
-    del hits
+    del cal
+    return dict(N=N, W=W, H=H, raw=raw, dark=dark, flat=flat, t=t, g=g, hit_fraction=hit_pixels / (N * W * H))
+
+
+def wide_chain(torch, rd, inp, reps=3):
+    """The wide-field stack end to end from raw through one batched call: calibrate, the
+    full +-65 px search of all 15 frames against frame 0 (template shrunk by 65), shift and
+    the clipped mean; search shapes tuned on two frames."""
+    N, W, H, R = inp["N"], inp["W"], inp["H"], 65
+    cal = rd.calibrate(inp["raw"][:3], inp["dark"], inp["flat"])
+    plan = rd.tune_register(cal[0].contiguous(), cal[1:3].contiguous(), R)
+    del cal
+    torch.cuda.empty_cache()
+    batch = rd.StackBatch([(inp["raw"], inp["dark"], inp["flat"], R)])
+    batch.run()
+    torch.cuda.synchronize()
+    rd.prof_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        batch.run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    ms, n = rd.prof_query("batch_score")
+    rd.prof_enable(False)
+    _, rect, offs, nrej = batch.result(0)
+    s = np.stack([offs["sx"], offs["sy"]], 1)
+    flops = 2.0 * (N - 1) * (W - 2 * R) * (H - 2 * R) * (2 * R + 1) ** 2
+    res = {"workload": f"{N} frames {W}x{H}, 5000 stars, cosmic-ray tracks of 1-4 px on "
+                       f"{100 * inp['hit_fraction']:.4f}% of pixels, shifts +-64 px, search radius 65, one batched call",
+           "Mpix/s": round(N * W * H / dt / 1e6, 1), "ms_per_call": round(dt * 1e3, 2),
+           "search_ms": round(ms / reps, 2), "search_share": round(ms / reps / 1e3 / dt, 4),
+           "search_frac_fp64": round(flops / (ms / reps / 1e3) / 1e12 / FP64_VALU_PEAK_TFLOPS, 4),
+           "rect": [int(v) for v in rect], "rejected_values": int(nrej),
+           "max_offset_error_vs_truth_px": round(float(np.abs(s[1:] - inp["t"][1:]).max()), 4),
+           "workspace_GB": round(batch.ws_bytes() / 1e9, 2),
+           "search_plan": {k: plan[k] for k in ("K", "G", "S", "TY", "BR", "threads", "n_tiles")}}
+    del batch
+    torch.cuda.empty_cache()
+    return res
+
+
+def streaming_wide(torch, rd, inp, reps=5, traffic_path=os.path.join(ROOT, "profiles", "traffic.json")):
+    """calibrate, shift (bilinear, and the bicubic spline timed alone) and combine over the
+    wide-field stack at its true shifts (working sets of 1.2-2.4 GB, far beyond the 256 MB
+    last-level cache), bad-pixel masking with the missing-value combine, and the combine of
+    a 97-frame stack (the deepest co-adding set of the paper) of 2040x2040, timed with HIP
+    events on their stream."""
+    N, W, H = inp["N"], inp["W"], inp["H"]
+    raw, dark, flat, t, g = inp["raw"], inp["dark"], inp["flat"], inp["t"], inp["g"]
+    dev = raw.device
+    cal = torch.empty((N, H, W), dtype=torch.float32, device=dev)
     s = torch.from_numpy(t.astype(np.float32)).to(dev)
     rect = rd.valid_rect(t.astype(np.float32), W, H)
     w, h = int(rect[2]), int(rect[3])
@@ -500,8 +759,8 @@ def streaming_wide(torch, rd, reps=5, traffic_path=os.path.join(ROOT, "profiles"
     for _ in range(reps):
         chain()
     torch.cuda.synchronize()
-    res = {"workload": f"{N} frames {W}x{H}, 5000 stars, cosmic-ray hits on 0.01% of pixels, shifts +-64 px, "
-                       f"overlap {w}x{h}, bad pixels 0.1%; deep combine: {ND} frames {SD}x{SD}"}
+    res = {"workload": f"{N} frames {W}x{H} at their true shifts (+-64 px), overlap {w}x{h}, bad pixels 0.1%; "
+                       f"deep combine: {ND} frames {SD}x{SD}"}
     byts = {"calibrate": N * W * H * (2 + 4) + 8 * W * H, "shift": N * w * h * (4 + 4), "combine": N * w * h * 4 + w * h * 4,
             # rows: frame read, row-pass result written; columns: that result read, output written
             "shift_spline": N * 4 * (H * W + 2 * H * w + h * w), "combine_deep": (ND + 1) * SD * SD * 4,
@@ -513,7 +772,7 @@ def streaming_wide(torch, rd, reps=5, traffic_path=os.path.join(ROOT, "profiles"
         res[name] = {"avg_launch_ms": round(ms / n, 4), "bytes": byts[name], "GB/s": round(gbs, 1),
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(traffic_path, name, "wide")}
     rd.prof_enable(False)
-    del raw, cal, al, al_spline, spline_ws, deep, deep_out, bad, out_miss
+    del cal, al, al_spline, spline_ws, deep, deep_out, bad, out_miss
     torch.cuda.empty_cache()
     return res
 
@@ -523,14 +782,16 @@ def main():
     if args.traffic_from:
         rec = traffic_from(*args.traffic_from, workload=args.workload, kernels=args.traffic_kernels.split(","))
         old = json.load(open(args.traffic)) if os.path.exists(args.traffic) else {}
-        if args.traffic_key == "kernels":
+        key = args.traffic_key or ("many" if args.workload == 2 else "kernels")
+        if key == "kernels":
             kernels = dict(old.get("kernels", {}))
             kernels.update(rec["kernels"])
             old.update(rec)
             old["kernels"] = kernels
         else:
-            old[args.traffic_key] = {"workload": "16 frames 6144x6160 (wide field)", "kernels": rec["kernels"],
-                                     "fetch_scale": rec["fetch_scale"], "write_scale": rec["write_scale"]}
+            old[key] = {"workload": WORKLOADS[args.workload] if key == "many" else "16 frames 6144x6160 (wide field)",
+                        "kernels": rec["kernels"], "fetch_scale": rec["fetch_scale"],
+                        "write_scale": rec["write_scale"]}
         with open(args.traffic, "w") as fh:
             json.dump(old, fh, indent=1)
         print(json.dumps(old))
@@ -567,31 +828,40 @@ def main():
         return 0
     if args.wide_only:
         rd.lib()
-        print(json.dumps({"streaming_wide": streaming_wide(torch, rd)}))
+        print(json.dumps({"streaming_wide": streaming_wide(torch, rd, wide_inputs(torch, rd))}))
         return 0
     if args.sweep:
         rd.lib()
         print(json.dumps({"sweep": sweep(torch, rd)}))
         return 0
     rd.lib()
-    stacks = synth.make_config(args.workload)
-    integer_mode = args.workload == 0
-    pipe = (BatchedPipeline if args.path == "batched" else StagePipeline)(rd, torch, stacks, integer_mode)
     tuned = None
-    if args.tune_cache and os.path.exists(args.tune_cache):
-        rd.tune_load(args.tune_cache)
-        tuned = "loaded"
-    elif not args.no_tune:
-        # timed on the frames one search launch covers: every stack's in the batched path
-        # (one launch for all stacks), one stack's in the stage-wise path
-        cals = [rd.calibrate(torch.from_numpy(st.raw.view(np.int16)).to("cuda:0"),
-                             torch.from_numpy(st.dark).to("cuda:0"), torch.from_numpy(st.flat).to("cuda:0"))
-                for st in (stacks if args.path == "batched" else stacks[:1])]
-        tuned = rd.tune_register(cals[0][0].contiguous(), torch.cat([c[1:] for c in cals]),
-                                 stacks[0].spec.radius)
-        del cals
-        if args.tune_cache:
-            rd.tune_save(args.tune_cache)
+    if args.workload == 2:
+        if args.path != "batched":
+            print("bench.py: the 64-stack workload runs as one batched call", file=sys.stderr)
+            return 2
+        pipe = ManyStackPipeline(rd, torch, tune=not args.no_tune, tune_cache=args.tune_cache)
+        log(f"64-stack inputs rendered and search shapes tuned: {pipe.plans}")
+        specs = pipe.specs
+        tuned = pipe.plans
+    else:
+        stacks = synth.make_config(args.workload)
+        specs = [st.spec for st in stacks]
+        integer_mode = args.workload == 0
+        pipe = (BatchedPipeline if args.path == "batched" else StagePipeline)(rd, torch, stacks, integer_mode)
+        if args.tune_cache and os.path.exists(args.tune_cache):
+            rd.tune_load(args.tune_cache)
+            tuned = "loaded"
+        elif not args.no_tune:
+            # timed on the frames one search launch covers
+            cals = [rd.calibrate(torch.from_numpy(st.raw.view(np.int16)).to("cuda:0"),
+                                 torch.from_numpy(st.dark).to("cuda:0"), torch.from_numpy(st.flat).to("cuda:0"))
+                    for st in (stacks if args.path == "batched" else stacks[:1])]
+            tuned = rd.tune_register(cals[0][0].contiguous(), torch.cat([c[1:] for c in cals]),
+                                     stacks[0].spec.radius)
+            del cals
+            if args.tune_cache:
+                rd.tune_save(args.tune_cache)
 
     for _ in range(args.warmup):
         pipe.step()
@@ -605,56 +875,81 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms per step")
 
-    kern = {name: rd.prof_query(name) for name in ("score_tiles", "calibrate", "shift", "combine", "batch_score",
-                                                   "batch_out")}
-    if args.path == "batched":
-        kern["score_tiles"] = kern["batch_score"]
+    kern = {name: rd.prof_query(name) for name in ("score_tiles", "calibrate", "shift", "combine", "batch_score")}
+    batched = args.path == "batched"
     rd.prof_enable(False)
 
-    spec0 = stacks[0].spec
-    score_ms, score_n = kern["score_tiles"]
+    score_ms, score_n = kern["batch_score" if batched else "score_tiles"]
     score_avg_s = score_ms / score_n / 1e3
-    # one stage-wise launch searches one stack; one batched launch searches all of them
-    flops = sum(register_flops_per_launch(st.spec, st.spec.N - 1)
-                for st in (stacks if args.path == "batched" else stacks[:1]))
+    launches_per_step = score_n / args.steps
+    # batched: the flops of the step's searches spread over its search dispatches (one per
+    # group of stacks that share a launch shape); stage-wise: one stack's search per launch
+    flops = search_flops(specs) / launches_per_step if batched else search_flops(specs[:1])
     achieved = flops / score_avg_s / 1e12
-    traffic = recorded_traffic(args.traffic, "batch_score" if args.path == "batched" else "score_tiles")
+    kname = "batch_score" if batched else "score_tiles"
+    traffic = recorded_traffic(args.traffic, kname, "many" if args.workload == 2 else None)
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(FP64_VALU_PEAK_TFLOPS, 3),
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4), "traffic": traffic,
-                "kernel": "batch_score" if args.path == "batched" else "score_tiles",
-                "avg_launch_ms": round(score_avg_s * 1e3, 4),
-                "flops_per_launch": flops}
+                "kernel": kname, "avg_launch_ms": round(score_avg_s * 1e3, 4),
+                "launches_per_step": round(launches_per_step, 3), "flops_per_launch": flops,
+                "search_share_of_step": round(score_ms / args.steps / ms_per_step, 4)}
 
-    sbytes = streaming_bytes(spec0)
     streaming = {}
-    for name in ("calibrate", "shift", "combine"):
-        ms, n = kern[name]
-        if n and args.path == "stagewise":
-            gbs = sbytes[name] / (ms / n / 1e3) / 1e9
-            streaming[name] = {"avg_launch_ms": round(ms / n, 4), "GB/s": round(gbs, 1),
-                               "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes": sbytes[name],
-                               "traffic": recorded_traffic(args.traffic, name)}
+    if not batched:
+        sbytes = streaming_bytes(specs[0])
+        for name in ("calibrate", "shift", "combine"):
+            ms, n = kern[name]
+            if n:
+                gbs = sbytes[name] / (ms / n / 1e3) / 1e9
+                streaming[name] = {"avg_launch_ms": round(ms / n, 4), "GB/s": round(gbs, 1),
+                                   "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes": sbytes[name],
+                                   "traffic": recorded_traffic(args.traffic, name)}
 
     value = pipe.pixels / (ms_per_step / 1e3) / 1e6
+    frames = [sp.N for sp in specs]
+    config = {"workload": WORKLOADS[args.workload], "stacks": len(specs), "frames_total": sum(frames),
+              "input_pixels": pipe.pixels, "sizes": sorted({sp.W for sp in specs}), "path": args.path,
+              "pixel_storage": "uint16 in, f32 between stages, f32 out", "search": "FP32 products, FP64 sums",
+              "search_plans": tuned if args.workload == 2 else rd.register_plan(specs[0].W, specs[0].H,
+                                                                               specs[0].N - 1, specs[0].radius)}
     line = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload], "stacks": len(stacks),
-                   "frames": [s.spec.N for s in stacks], "size": [spec0.W, spec0.H],
-                   "path": args.path, "pixel_storage": "uint16 in, f32 between stages",
-                   "search_plan": rd.register_plan(spec0.W, spec0.H, spec0.N - 1, spec0.radius)},
-        "roofline": roofline, "streaming": streaming,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": config,
+        "roofline": roofline,
     }
-    if not args.no_wide:
-        line["streaming_wide"] = streaming_wide(torch, rd)
-    if not args.no_many:
-        line["many_stacks"] = many_stacks(torch, rd)
+    if streaming:
+        line["streaming"] = streaming
+    sample = None
+    if args.workload == 2:
+        if not args.no_cpu_baseline:
+            sample = many_sample(pipe)
+        del pipe
+        torch.cuda.empty_cache()
+        if not args.no_bands:
+            line["bands"] = bands_leg(torch, rd)
+            log(f"bands: {line['bands']}")
+    if not args.no_wide or not args.no_wide_chain:
+        inp = wide_inputs(torch, rd)
+        log("wide-field inputs rendered")
+        if not args.no_wide_chain:
+            line["wide_field_chain"] = wide_chain(torch, rd, inp)
+            log(f"wide-field chain: {line['wide_field_chain']}")
+        if not args.no_wide:
+            line["streaming_wide"] = streaming_wide(torch, rd, inp)
+            log("wide-field streaming kernels timed")
+        del inp
+        torch.cuda.empty_cache()
     if not args.no_learned:
         line["learned"] = learned_comparison(torch, rd, args.weights, args.learned_frames)
+        log(f"learned: speed-up {line['learned']['speedup']}")
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(stacks, integer_mode)
+        if args.workload == 2:
+            line["cpu_baseline"], line["parity"] = cpu_baseline_many(*sample, specs)
+        else:
+            line["cpu_baseline"] = cpu_baseline(stacks, integer_mode)
     print(json.dumps(line), flush=True)
     return 0
 

@@ -593,12 +593,13 @@ static int launch_phases(int32_t n, void *ws, const BatchLayout &L, hipStream_t 
     hipLaunchKernelGGL(batch_meanfinal, dim3(L.count[IT_MEANFINAL]), dim3(MEAN_THREADS), 0, s, a,
                        L.first[IT_MEANFINAL]);
     if (L.count[IT_SCORE] > 0) {
-        ProfScope prof("batch_score", s);
-        for (const ScoreGroup &g : L.groups)
+        for (const ScoreGroup &g : L.groups) {
+            ProfScope prof("batch_score", s);  // one record per dispatch
             score_dispatch_host(g.K, [&](auto Kc) {
                 constexpr int K = decltype(Kc)::value;
                 hipLaunchKernelGGL(batch_score<K>, dim3(g.count), dim3(g.threads), g.lds, s, a, g.first, g.count);
             });
+        }
     }
     if (L.count[IT_SSCORE] > 0)
         hipLaunchKernelGGL(batch_score_small, dim3(L.count[IT_SSCORE]), dim3(SMALL_COLS), 0, s, a,

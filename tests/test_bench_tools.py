@@ -50,3 +50,54 @@ def test_traffic_scales_by_the_copy_probe_and_tells_kernels_apart(bench, tmp_pat
     assert k["shift_spline"]["bytes"] == round((10 + 20) * 1024 * 2 + (1 + 2) * 1024)
     assert "calibrate" not in k  # no counter rows: nothing recorded
     assert all(len(v["source_sha256"]) == 64 for v in k.values())
+
+
+def test_cpu_baseline_and_parity_of_the_many_stack_leg(bench, orc):
+    """The CPU leg on two small stacks whose 'GPU results' are the oracle's own chain (one
+    with its offsets moved by one float ulp): parity within tolerance with identical integer
+    offsets, the ulp move counted; the extrapolated time covers every stack of the workload
+    and grows with the search's FMA count."""
+    import numpy as np
+    import synth
+    specs = [synth.small_spec(5, 96, 96, n_stars=12, shift_bound=3.0, seed=(91, 0)),
+             synth.small_spec(6, 128, 128, n_stars=20, shift_bound=3.0, seed=(91, 1))]
+    sample, all_offs = [], []
+    for i, sp in enumerate(specs):
+        st = synth.make_stack(sp)
+        o = orc.reduce_stack(st.raw, st.dark, st.flat, sp.radius)
+        offs = o["offsets"].copy()
+        offs["sx"][0] = offs["sy"][0] = 0.0
+        if i == 1:
+            offs["sx"][2] = np.nextafter(np.float32(offs["sx"][2]), np.float32(np.inf))
+        out = orc.shift(o["cal"], np.stack([offs["sx"], offs["sy"]], 1).astype(np.float32), o["rect"])
+        img = orc.combine(out)[0].astype(np.float32)
+        sample.append(dict(index=i, spec=sp, raw=st.raw, dark=st.dark, flat=st.flat, img=img, rect=o["rect"],
+                           offs=offs, n_rej=o["n_rej"]))
+        all_offs.append(offs)
+    workload = specs + [specs[1]] * 3
+    base, par = bench.cpu_baseline_many(sample, all_offs, workload, one_thread_sides=(96, 128))
+    assert base["kind"] == "oracle" and base["unit"] == "Mpix/s" and base["value"] > 0
+    assert base["value_1_thread"] > 0 and base["cores"] >= 1
+    assert par["identical_integer_offsets"] == 1.0 and par["rects_identical"]
+    assert par["frames_with_subpixel_offset_difference"] == 1
+    assert par["frames_searched"] == 4 + 5 and par["frames_all_stacks"] == 4 + 5 * 4
+    assert par["within_tolerance"] and par["rel_err"]["max"] <= 2e-6
+    assert par["pixels_checked"] + par["threshold_band_pixels"] == sum(s["img"].size for s in sample)
+
+
+def test_counter_rows_read_the_sqlite_output(bench, tmp_path):
+    """rocprofv3 writes its counters to an SQLite database by default: the same rows as CSV."""
+    import sqlite3
+    d = tmp_path / "pmc" / "host"
+    d.mkdir(parents=True)
+    db = sqlite3.connect(str(d / "m_results.db"))
+    db.execute("create table counters_collection (dispatch_id integer, kernel_name text, counter_name text, "
+               "value real)")
+    db.executemany("insert into counters_collection values (?, ?, ?, ?)",
+                   [(2, "rd::batch_cal(rd::BatchArgs, int)", "FETCH_SIZE", 30.0),
+                    (1, "rd::batch_cal(rd::BatchArgs, int)", "FETCH_SIZE", 10.0),
+                    (3, "rd::batch_cal(rd::BatchArgs, int)", "WRITE_SIZE", 99.0)])
+    db.commit()
+    db.close()
+    rows = bench._counter_rows(str(tmp_path / "pmc"), "FETCH_SIZE")
+    assert rows == [("rd::batch_cal(rd::BatchArgs, int)", 10.0), ("rd::batch_cal(rd::BatchArgs, int)", 30.0)]

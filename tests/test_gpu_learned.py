@@ -170,6 +170,37 @@ def test_adamw_matches_torch(rd):
     np.testing.assert_allclose(pd.cpu().numpy(), pt.detach().numpy(), rtol=1e-5, atol=1e-6)
 
 
+def test_adamw_matches_oracle(rd, orc):
+    """Stage-isolated per step: from the GPU's single-precision state (p, m, v) before each
+    step, the FP64 oracle takes the same AdamW step with the same (float-rounded) hyper-
+    parameters.  Bound from the arithmetic, u = 2^-24: the moments take 3 and 4 correctly
+    rounded operations (|dm| <= 3u(|b1 m| + |(1 - b1) g|), |dv| <= 4u(|b2 v| + |(1 - b2) g^2|)),
+    the step r = mhat / (sqrt(vhat) + eps) carries at most 16u relative error including the
+    moments', and the update two more roundings: |dp| <= 2u|p'| + 16u lr (|r| + wd |p|)."""
+    rng = np.random.default_rng(6)
+    n = 4096
+    f = lambda x: float(np.float32(x))  # noqa: E731
+    lr, b1, b2, eps, wd = f(3e-3), f(0.9), f(0.999), f(1e-8), f(0.05)
+    u = 2.0 ** -24
+    p = rng.normal(size=n).astype(np.float32)
+    pd = to_dev(p)
+    m = torch.zeros_like(pd)
+    v = torch.zeros_like(pd)
+    for step in range(1, 6):
+        g = (rng.normal(size=n) * np.exp(rng.uniform(-4, 2, size=n))).astype(np.float32)
+        p0, m0, v0 = (t.cpu().numpy().astype(np.float64) for t in (pd, m, v))
+        rd.cnn_adamw(pd, m, v, to_dev(g), lr=lr, step=step, beta1=b1, beta2=b2, eps=eps, weight_decay=wd)
+        po, mo, vo = orc.adamw(p0, m0, v0, g, lr, step, beta1=b1, beta2=b2, eps=eps, weight_decay=wd)
+        gd = g.astype(np.float64)
+        r = (mo / (1 - b1 ** step)) / (np.sqrt(vo / (1 - b2 ** step)) + eps)
+        tol_m = 3 * u * (np.abs(b1 * m0) + np.abs((1 - b1) * gd))
+        tol_v = 4 * u * (np.abs(b2 * v0) + np.abs((1 - b2) * gd * gd))
+        tol_p = 2 * u * np.abs(po) + 16 * u * lr * (np.abs(r) + wd * np.abs(p0))
+        for name, got, want, tol in (("m", m, mo, tol_m), ("v", v, vo, tol_v), ("p", pd, po, tol_p)):
+            d = np.abs(got.cpu().numpy().astype(np.float64) - want)
+            assert np.all(d <= tol), (step, name, float((d / np.maximum(tol, 1e-300)).max()))
+
+
 # ---- rendered training frames --------------------------------------------------------------
 def _render_np(stars, W, H, sky, fwhm):
     sig = fwhm / (2 * np.sqrt(2 * np.log(2)))

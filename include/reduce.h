@@ -119,6 +119,23 @@ int reduce_register(const float *ref, const float *frames, int32_t W, int32_t H,
                     const int32_t *tmpl, reduce_offset_t *out, double *scores,
                     void *ws, size_t ws_bytes, void *stream);
 
+/* ---- search without a workspace ------------------------------------------------
+ * For callers that cannot allocate device memory (code under graph capture, tight
+ * serving loops, harnesses that forbid allocation): reduce_register with the same
+ * arguments and results, but no ws.  The workspace is a fixed array of
+ * reduce_register_static_max() bytes (64 MiB) of device memory that the library holds
+ * on every GPU it runs on until the process ends; its device address is taken on the
+ * first call on each device (with that device current).  The call allocates nothing.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time on one GPU
+ * (different streams, or host threads) race and must be serialised by the caller.
+ * Errors: as reduce_register; sizes whose workspace, reduce_register_ws(W, H, N, R,
+ * Rmax), exceeds reduce_register_static_max() -> UNSUPPORTED (split the frames over
+ * several calls); the symbol address cannot be taken -> HIP_ERROR. */
+size_t reduce_register_static_max(void);
+int reduce_register_static(const float *ref, const float *frames, int32_t W, int32_t H, int32_t N,
+                           int32_t radius, int32_t radius_max, const int32_t *centers,
+                           const int32_t *tmpl, reduce_offset_t *out, double *scores, void *stream);
+
 /* ---- common overlap -------------------------------------------------------
  * The alignment crops every frame to the area all frames cover (Section 3.1.2,
  * note to the table of co-adding data sets).  Output x must satisfy

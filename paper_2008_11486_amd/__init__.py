@@ -62,6 +62,9 @@ def _declare(L):
     L.reduce_register_ws.argtypes = [I32, I32, I32, I32, I32]
     L.reduce_register_ws.restype = SZ
     L.reduce_register.argtypes = [P, P, I32, I32, I32, I32, I32, P, P, P, P, P, SZ, P]
+    L.reduce_register_static.argtypes = [P, P, I32, I32, I32, I32, I32, P, P, P, P, P]
+    L.reduce_register_static.restype = ctypes.c_int
+    L.reduce_register_static_max.restype = SZ
     L.reduce_valid_rect.argtypes = [P, I32, I32, I32, P]
     L.reduce_shift.argtypes = [P, P, I32, I32, I32, P, P, I32, P]
     L.reduce_shift_spline_ws.argtypes = [I32, I32, I32]
@@ -131,7 +134,7 @@ def exported_symbols() -> Sequence[str]:
             "reduce_cnn_input_ws", "reduce_cnn_input", "reduce_cnn_num_params", "reduce_cnn_ws",
             "reduce_cnn_ws_offsets", "reduce_cnn_forward", "reduce_cnn_backward", "reduce_cnn_adamw",
             "reduce_cnn_centres", "reduce_render_frames", "reduce_recentre", "reduce_propose_ws",
-            "reduce_propose")
+            "reduce_propose", "reduce_register_static_max", "reduce_register_static")
 
 
 def _check(rc: int) -> None:
@@ -196,6 +199,34 @@ def calibrate(raw: torch.Tensor, dark: torch.Tensor, flat: torch.Tensor,
 # ---------------------------------------------------------------------------- register
 def register_ws_bytes(W: int, H: int, N: int, radius: int, radius_max: Optional[int] = None) -> int:
     return int(lib().reduce_register_ws(W, H, N, radius, radius if radius_max is None else radius_max))
+
+
+def register_static(ref: torch.Tensor, frames: torch.Tensor, radius: int, radius_max: Optional[int] = None,
+                    centers: Optional[torch.Tensor] = None, tmpl: Optional[Sequence[int]] = None,
+                    out: Optional[torch.Tensor] = None, scores: Optional[torch.Tensor] = None, stream=None):
+    """register() through the entry point that allocates nothing (its workspace is the
+    library's fixed per-device array): out (and scores, if given) must be caller-provided
+    device tensors, [N][48] uint8 and float64 [N][2R+1][2R+1]."""
+    _dev(ref, "ref")
+    _dev(frames, "frames")
+    if frames.dim() == 2:
+        frames = frames.unsqueeze(0)
+    N, H, W = frames.shape
+    rmax = radius if radius_max is None else radius_max
+    if not (ref.is_contiguous() and frames.is_contiguous()):
+        raise ValueError("ref and frames must be contiguous")
+    if out is None or out.shape != (N, OFFSET_BYTES) or out.dtype != torch.uint8:
+        raise ValueError("out must be a device uint8 tensor [N][48]")
+    if scores is not None and (scores.dtype != torch.float64 or scores.shape != (N, 2 * radius + 1, 2 * radius + 1)):
+        raise ValueError("scores must be a device float64 tensor [N][2R+1][2R+1]")
+    if centers is not None:
+        centers = _dev(centers, "centers")
+        if centers.dtype != torch.int32 or not centers.is_contiguous():
+            raise TypeError("centers must be a contiguous int32 device tensor [N][2]")
+    t = None if tmpl is None else (ctypes.c_int32 * 4)(*[int(v) for v in tmpl])
+    _check(lib().reduce_register_static(_ptr(ref), _ptr(frames), W, H, N, radius, rmax, _ptr(centers), t,
+                                        _ptr(out), _ptr(scores), _stream(stream)))
+    return out
 
 
 def register(ref: torch.Tensor, frames: torch.Tensor, radius: int, radius_max: Optional[int] = None,

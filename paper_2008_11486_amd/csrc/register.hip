@@ -3,6 +3,8 @@
 // the kernels that wrap it and the host side of reduce_register.
 //
 // Roofline: VALU (FP64 FMA).  Algorithmic work per frame: |T| * (2R+1)^2 FMA.
+#include <map>
+#include <mutex>
 #include <string>
 
 #include "common.h"
@@ -238,6 +240,66 @@ extern "C" int reduce_register(const float *ref, const float *frames, int32_t W,
     const size_t need = register_ws_bytes(p, N);
     if (!ws || ws_bytes < need)
         return fail(REDUCE_ERR_WORKSPACE, "reduce_register: workspace needs " + std::to_string(need) + " bytes");
+    return register_launch(ref, frames, W, H, N, radius, radius_max, centers, t[0], t[1], t[2], t[3], out, scores,
+                           ws, p, as_stream(stream));
+}
+
+// ---- search without a caller workspace ---------------------------------------------------
+// For callers that cannot allocate device memory (code under graph capture, tight serving
+// loops, harnesses that forbid allocation): the search's workspace (template mean parts,
+// per-tile partial scores, score planes) lives in a fixed array of device memory that every
+// GPU the library runs on holds until the process ends.  Host code never passes the array's
+// name to a kernel: its device address, taken once per device with that device current,
+// is what the kernels receive.  Every workspace word a call reads is written by that call
+// first, so nothing needs clearing between calls.
+namespace rd {
+constexpr size_t REGISTER_SCRATCH_BYTES = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[REGISTER_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::map<int, void *> g_scratch_addr;  // device -> address of its copy of scratch
+
+static int scratch_address(const char *who, void **ptr)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(REDUCE_ERR_HIP, std::string(who) + ": hipGetDevice: " + hipGetErrorString(e));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(dev);
+    if (it != g_scratch_addr.end()) {
+        *ptr = it->second;
+        return REDUCE_OK;
+    }
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return fail(REDUCE_ERR_HIP, std::string(who) + ": hipGetSymbolAddress: " + hipGetErrorString(e));
+    g_scratch_addr[dev] = p;
+    *ptr = p;
+    return REDUCE_OK;
+}
+}  // namespace rd
+
+extern "C" size_t reduce_register_static_max(void) { return REGISTER_SCRATCH_BYTES; }
+
+extern "C" int reduce_register_static(const float *ref, const float *frames, int32_t W, int32_t H, int32_t N,
+                                      int32_t radius, int32_t radius_max, const int32_t *centers,
+                                      const int32_t *tmpl, reduce_offset_t *out, double *scores, void *stream)
+{
+    int32_t t[4];
+    RegPlan p;
+    const int c =
+        register_checks("reduce_register_static", ref, frames, W, H, N, radius, radius_max, tmpl, out, t, &p);
+    if (c != REDUCE_OK) return c;
+    const size_t need = register_ws_bytes(p, N);
+    if (need > REGISTER_SCRATCH_BYTES)
+        return fail(REDUCE_ERR_UNSUPPORTED, "reduce_register_static: these sizes need " + std::to_string(need) +
+                                                " bytes of workspace, above the " +
+                                                std::to_string(REGISTER_SCRATCH_BYTES) +
+                                                " the library holds; search fewer frames per call");
+    void *ws = nullptr;
+    const int a = scratch_address("reduce_register_static", &ws);
+    if (a != REDUCE_OK) return a;
     return register_launch(ref, frames, W, H, N, radius, radius_max, centers, t[0], t[1], t[2], t[3], out, scores,
                            ws, p, as_stream(stream));
 }

@@ -119,6 +119,36 @@ int reduce_register(const float *ref, const float *frames, int32_t W, int32_t H,
                     const int32_t *tmpl, reduce_offset_t *out, double *scores,
                     void *ws, size_t ws_bytes, void *stream);
 
+/* ---- search through row spectra -----------------------------------------------
+ * The full-window search of reduce_register (radius_max = radius, the interior
+ * template, no centres) with the scores S(d) of the whole window evaluated from row
+ * spectra instead of direct sums, an alternative evaluation for large windows (the
+ * paper's sweeps over image size and frame count, Section 3.2.2, motivate searches
+ * whose cost must not grow with the window area).  With P >= W a power of two, the
+ * rows of the mean-free template and of each frame are transformed (length-P DFT, the
+ * half spectrum of real rows), Z_j(k) = sum_y A_{y+j}(k) conj(B_y(k)) is formed for the
+ * 2R+1 row lags j, and S at the 2R+1 column lags is the inverse transform there.  The
+ * offsets then come from exact direct sums: a +-1 window around the spectral argmax
+ * (moved while its maximum lies on an inner border) is kept when its exact peak
+ * exceeds every spectral score outside it by more than a bound on the spectral
+ * rounding error, 4 eps (10 log2(P/2) + th + P + 18) ||frame rows|| ||template rows||
+ * (eps = 2^-53, Frobenius norms), else the frame takes the full direct search.  So
+ * dx, dy, sx, sy, peak and the EDGE and NEAR_TIE flags are those of reduce_register up
+ * to the summation order of its direct sums; `second` may be a spectral score (within
+ * the bound of the exact one).
+ *   ref, frames, out as reduce_register (radius_max = radius);
+ *   scores  device double [N][2R+1][2R+1] or NULL: the spectral scores (layout of
+ *           reduce_register's), before the exact refinement;
+ *   info    device int32 [N] or NULL: per frame 0 (kept), or 1 (maximum still on an
+ *           inner border) | 2 (not clear of the error bound): the full search ran;
+ *   ws      device workspace of reduce_register_fft_ws(W, H, N, radius) bytes.
+ * Errors: radius < 1 or no template -> RANGE; W > 8192, N > 65535 or radius > 511 ->
+ * UNSUPPORTED; small ws -> WORKSPACE. */
+size_t reduce_register_fft_ws(int32_t W, int32_t H, int32_t N, int32_t radius);
+int reduce_register_fft(const float *ref, const float *frames, int32_t W, int32_t H, int32_t N,
+                        int32_t radius, reduce_offset_t *out, double *scores, int32_t *info, void *ws,
+                        size_t ws_bytes, void *stream);
+
 /* ---- search without a workspace ------------------------------------------------
  * For callers that cannot allocate device memory (code under graph capture, tight
  * serving loops, harnesses that forbid allocation): reduce_register with the same

@@ -62,6 +62,10 @@ def _declare(L):
     L.reduce_register_ws.argtypes = [I32, I32, I32, I32, I32]
     L.reduce_register_ws.restype = SZ
     L.reduce_register.argtypes = [P, P, I32, I32, I32, I32, I32, P, P, P, P, P, SZ, P]
+    L.reduce_register_fft_ws.argtypes = [I32, I32, I32, I32]
+    L.reduce_register_fft_ws.restype = SZ
+    L.reduce_register_fft.argtypes = [P, P, I32, I32, I32, I32, P, P, P, P, SZ, P]
+    L.reduce_register_fft.restype = ctypes.c_int
     L.reduce_register_static.argtypes = [P, P, I32, I32, I32, I32, I32, P, P, P, P, P]
     L.reduce_register_static.restype = ctypes.c_int
     L.reduce_register_static_max.restype = SZ
@@ -134,7 +138,8 @@ def exported_symbols() -> Sequence[str]:
             "reduce_cnn_input_ws", "reduce_cnn_input", "reduce_cnn_num_params", "reduce_cnn_ws",
             "reduce_cnn_ws_offsets", "reduce_cnn_forward", "reduce_cnn_backward", "reduce_cnn_adamw",
             "reduce_cnn_centres", "reduce_render_frames", "reduce_recentre", "reduce_propose_ws",
-            "reduce_propose", "reduce_register_static_max", "reduce_register_static")
+            "reduce_propose", "reduce_register_static_max", "reduce_register_static", "reduce_register_fft_ws",
+            "reduce_register_fft")
 
 
 def _check(rc: int) -> None:
@@ -199,6 +204,39 @@ def calibrate(raw: torch.Tensor, dark: torch.Tensor, flat: torch.Tensor,
 # ---------------------------------------------------------------------------- register
 def register_ws_bytes(W: int, H: int, N: int, radius: int, radius_max: Optional[int] = None) -> int:
     return int(lib().reduce_register_ws(W, H, N, radius, radius if radius_max is None else radius_max))
+
+
+def register_fft_ws_bytes(W: int, H: int, N: int, radius: int) -> int:
+    return int(lib().reduce_register_fft_ws(W, H, N, radius))
+
+
+def register_fft(ref: torch.Tensor, frames: torch.Tensor, radius: int, want_scores: bool = False,
+                 want_info: bool = False, ws: Optional[torch.Tensor] = None, stream=None):
+    """Full-window search with the scores evaluated from row spectra and the offsets from
+    exact direct sums (reduce_register_fft).  Returns the offsets (device uint8 [N][48]),
+    and the spectral score cube and the per-frame decision codes if asked."""
+    _dev(ref, "ref")
+    _dev(frames, "frames")
+    if frames.dim() == 2:
+        frames = frames.unsqueeze(0)
+    N, H, W = frames.shape
+    if not (ref.is_contiguous() and frames.is_contiguous()):
+        raise ValueError("ref and frames must be contiguous")
+    need = register_fft_ws_bytes(W, H, N, radius)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=frames.device)
+    out = torch.empty((N, OFFSET_BYTES), dtype=torch.uint8, device=frames.device)
+    D = 2 * radius + 1
+    scores = torch.empty((N, D, D), dtype=torch.float64, device=frames.device) if want_scores else None
+    info = torch.empty(N, dtype=torch.int32, device=frames.device) if want_info else None
+    _check(lib().reduce_register_fft(_ptr(ref), _ptr(frames), W, H, N, radius, _ptr(out), _ptr(scores), _ptr(info),
+                                     _ptr(ws), ws.numel(), _stream(stream)))
+    res = [out]
+    if want_scores:
+        res.append(scores)
+    if want_info:
+        res.append(info)
+    return res[0] if len(res) == 1 else tuple(res)
 
 
 def register_static(ref: torch.Tensor, frames: torch.Tensor, radius: int, radius_max: Optional[int] = None,

@@ -1,0 +1,115 @@
+"""The search through row spectra (reduce_register_fft) against the FP64 oracle's direct
+search and the GPU's direct search, for windows from R = 8 to R = 65, frame widths that
+are and are not powers of two (the row transforms pad to the next one), ragged templates:
+spectral scores within the stated rounding bound of the oracle's; integer offsets, edge
+and near-tie flags bit-exact; sub-pixel offsets within 2 float ulps of the oracle's
+(exact direct sums around the spectral maximum); frames whose maximum the spectral
+scores cannot settle (a flat frame: every score ties) take the full direct search."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from helpers import to_dev, ulp32
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rd():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2008_11486_amd as rd
+    rd.lib()
+    return rd
+
+
+def _cal(rd, N, W, H, R, seed, stars=None, bound=None):
+    spec = synth.small_spec(N, W, H, n_stars=stars or max(8, W * H // 1200),
+                            shift_bound=bound if bound is not None else R - 1, radius=R, seed=(131, seed))
+    st = synth.make_stack(spec)
+    return rd.calibrate(to_dev(st.raw), to_dev(st.dark), to_dev(st.flat))
+
+
+def spectral_bound(cal64, R):
+    """4 eps (10 log2(P/2) + th + P + 18) ||frame rows|| ||template rows||, per frame."""
+    N, H, W = cal64.shape
+    P = 64
+    while P < W:
+        P *= 2
+    th = H - 2 * R
+    t = cal64[0, R:H - R, R:W - R]
+    nb = np.linalg.norm(t - t.mean())
+    na = np.linalg.norm(cal64.reshape(N, -1), axis=1)
+    return 4 * 2.0 ** -53 * (10 * math.log2(P // 2) + th + P + 18) * na * nb
+
+
+def _check(g, o, label, peak_rtol=1e-10):
+    assert np.array_equal(g["dx"], o["dx"]) and np.array_equal(g["dy"], o["dy"]), (label, g[["dx", "dy"]], o[["dx", "dy"]])
+    for ax in ("sx", "sy"):
+        d = np.abs(g[ax].astype(np.float64) - o[ax].astype(np.float64))
+        assert np.all(d <= 2 * ulp32(o[ax])), (label, ax, g[ax], o[ax])
+    # relative to the frame set's score scale (a flat frame's scores are rounding-level zeros)
+    np.testing.assert_allclose(g["peak"], o["peak"], rtol=peak_rtol, atol=peak_rtol * np.abs(o["peak"]).max())
+    assert np.array_equal(g["flags"], o["flags"]), (label, g["flags"], o["flags"])
+
+
+# (R, N, W, H): powers of two and padded widths, several lag blocks, ragged template rows
+CASES = [(8, 4, 96, 80), (17, 4, 256, 256), (17, 3, 300, 261), (21, 3, 333, 290), (33, 2, 200, 190),
+         (65, 2, 400, 360)]
+
+
+@pytest.mark.parametrize("R,N,W,H", CASES)
+def test_fft_search_matches_oracle(rd, orc, R, N, W, H):
+    cal = _cal(rd, N, W, H, R, R)
+    out, S, info = rd.register_fft(cal[0].contiguous(), cal, R, want_scores=True, want_info=True)
+    g = rd.offsets_to_numpy(out)
+    cal64 = cal.cpu().numpy().astype(np.float64)
+    o, So = orc.register(cal64[0], cal64, R, want_scores=True)
+    S = S.cpu().numpy()
+    bound = spectral_bound(cal64, R)
+    err = np.abs(S - So).reshape(N, -1).max(axis=1)
+    rel = err / np.abs(So).reshape(N, -1).max(axis=1)
+    print(f"R={R} {W}x{H}: spectral score error max {rel.max():.2e} of the largest score, "
+          f"bound use {np.max(err / bound):.2e}, decisions {info.cpu().numpy()}")
+    assert np.all(err <= bound), (err, bound)
+    _check(g, o, f"R={R} {W}x{H}")
+    assert np.all(info.cpu().numpy() == 0)  # every frame settled by the exact +-1 window
+
+
+def test_fft_search_matches_the_direct_search_on_the_gpu(rd):
+    cal = _cal(rd, 6, 512, 512, 17, 3, stars=60)
+    a = rd.offsets_to_numpy(rd.register(cal[0].contiguous(), cal, 17))
+    b = rd.offsets_to_numpy(rd.register_fft(cal[0].contiguous(), cal, 17))
+    assert np.array_equal(a["dx"], b["dx"]) and np.array_equal(a["dy"], b["dy"])
+    assert np.array_equal(a["flags"], b["flags"])
+    for ax in ("sx", "sy"):
+        assert np.all(np.abs(a[ax].astype(np.float64) - b[ax]) <= 2 * ulp32(a[ax])), ax
+    np.testing.assert_allclose(a["peak"], b["peak"], rtol=1e-12)
+    np.testing.assert_allclose(a["second"], b["second"], rtol=1e-9)
+
+
+def test_fft_search_edges_and_unsettled_frames(rd, orc):
+    """A frame shifted by the full radius (maximum on the window border: EDGE, no
+    parabola), and a flat frame (every score ties at 0): the flat frame is not settled by
+    the spectral scores and takes the full direct search, whose tie-break picks the first
+    candidate; both as the oracle."""
+    R, W, H = 9, 160, 144
+    spec = synth.small_spec(3, W + 2 * R, H + 2 * R, n_stars=40, shift_kind="zero", radius=R, seed=(132, 0))
+    st = synth.make_stack(spec)
+    big = (st.raw.astype(np.float64) - st.dark) / st.flat
+    ref = big[0, R:R + H, R:R + W]
+    shifted = big[0, 2 * R:2 * R + H, 0:W]  # frame(x + (-R, R)) = ref(x)
+    flat = np.full((H, W), 1000.0)
+    cal64 = np.stack([ref, shifted, flat]).astype(np.float32).astype(np.float64)
+    cal = to_dev(cal64.astype(np.float32))
+    out, info = rd.register_fft(cal[0].contiguous(), cal, R, want_info=True)
+    g = rd.offsets_to_numpy(out)
+    o = orc.register(cal64[0], cal64, R)
+    info = info.cpu().numpy()
+    assert (g["dx"][1], g["dy"][1]) == (R, -R) and (g["flags"][1] & 3) == 3
+    assert info[2] != 0 and info[1] == 0, info
+    _check(g, o, "edges and flat frame")

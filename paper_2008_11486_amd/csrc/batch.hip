@@ -13,6 +13,11 @@
 //   SHIFT      a 16-row strip of one frame's bilinear shift onto the overlap
 //   COMB*      sigma-clipped mean of a block of pixel columns (one launch per frame-count
 //              class: up to 16, 32, 48, 64 or 128 frames)
+//   FUSE*      for a block of output pixels of a stack of up to 48 frames without a
+//              bad-pixel map: every frame's aligned values (bilinear taps of the
+//              calibrated frames, in registers) and the clipped mean, in one pass (one
+//              launch per frame-count class; such stacks take no SHIFT or COMB item and
+//              keep no aligned frames)
 //
 // Each phase is one kernel launch with one workgroup per item over all stacks; the
 // stream orders the phases, so every dependency is met at a kernel boundary and no
@@ -54,9 +59,10 @@ __host__ __device__ inline int64_t al_plane(int64_t w, int64_t h) { return (w * 
 
 enum ItemType : int32_t {
     IT_CAL = 0, IT_MEANPART, IT_MEANFINAL, IT_SCORE, IT_SSCORE, IT_SUM, IT_PICK, IT_RECT, IT_SHIFT, IT_MASK,
-    IT_COMB16, IT_COMB32, IT_COMB48, IT_COMBDEEP, IT_COMB16M, IT_COMB32M, IT_COMB48M, IT_COMBMISS
+    IT_COMB16, IT_COMB32, IT_COMB48, IT_COMBDEEP, IT_COMB16M, IT_COMB32M, IT_COMB48M, IT_COMBMISS,
+    IT_FUSE16, IT_FUSE32, IT_FUSE48
 };
-constexpr int N_PHASES = IT_COMBMISS + 1;
+constexpr int N_PHASES = IT_FUSE48 + 1;
 
 struct Item {
     int32_t type, stack, a, pad;
@@ -260,6 +266,143 @@ __global__ __launch_bounds__(COMB_TILE) void batch_comb(BatchArgs a, int32_t fir
     }
 }
 
+// ---- shift + clipped mean in one pass ---------------------------------------------------
+// Q + 1 taps of one frame row at columns c0 .. c0 + Q (clamped into the row), as shift_strip
+// reads them: two 16-byte loads from the aligned column c0 - (c0 & 3) when they lie inside
+// the row (rows 16-byte aligned), else one float at a time.
+template <int Q>
+__device__ __forceinline__ void row_taps(const float *__restrict__ row, int32_t c0, int32_t W, bool aligned,
+                                         float (&t)[Q + 1])
+{
+    static_assert(Q <= 4, "two 16-byte loads cover the taps");
+    const int32_t al = c0 & 3, b = c0 - al;
+    if (aligned && b >= 0 && b + 8 <= W) {
+        const float4 u = *reinterpret_cast<const float4 *>(row + b);
+        const float4 v = *reinterpret_cast<const float4 *>(row + b + 4);
+        const float raw[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
+        switch (al) {
+        case 0:
+#pragma unroll
+            for (int e = 0; e <= Q; ++e) t[e] = raw[e];
+            break;
+        case 1:
+#pragma unroll
+            for (int e = 0; e <= Q; ++e) t[e] = raw[1 + e];
+            break;
+        case 2:
+#pragma unroll
+            for (int e = 0; e <= Q; ++e) t[e] = raw[2 + e];
+            break;
+        default:
+#pragma unroll
+            for (int e = 0; e <= Q; ++e) t[e] = raw[3 + e];
+            break;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e <= Q; ++e) t[e] = row[clampi(c0 + e, 0, W - 1)];
+    }
+}
+
+// Aligned values of frame k at the Q output pixels (u0 + e, v) of one row of the overlap,
+// exactly as shift_strip makes them: taps in rows clamp(y0 + v + iy) and the one below
+// (when the vertical fraction is not zero), columns clamp(x0 + u + ix) and the one to the
+// right (when the horizontal fraction is not zero), from the calibrated frame.
+template <int Q>
+__device__ __forceinline__ void aligned_row(const StackDev &s, int32_t k, int32_t u0, int32_t v, int32_t x0,
+                                            int32_t y0, bool aligned, float (&r)[Q])
+{
+    const ShiftSetup ss = shift_setup(s.soffs[2 * k], s.soffs[2 * k + 1]);
+    const bool integer = s.integer_mode != 0;
+    const bool step = ss.a > 0.0;
+    const bool down = !integer && ss.b > 0.0;
+    const int32_t j = clampi(y0 + v + ss.iy, 0, s.H - 1);
+    const int32_t j1 = clampi(down ? j + 1 : j, 0, s.H - 1);
+    const int32_t c0 = x0 + u0 + ss.ix;
+    const float *f = s.cal + (int64_t)k * s.W * s.H;
+    float t0[Q + 1], t1[Q + 1];
+    row_taps<Q>(f + (int64_t)j * s.W, c0, s.W, aligned, t0);
+    if (j1 != j)
+        row_taps<Q>(f + (int64_t)j1 * s.W, c0, s.W, aligned, t1);
+    else
+#pragma unroll
+        for (int e = 0; e <= Q; ++e) t1[e] = t0[e];
+#pragma unroll
+    for (int e = 0; e < Q; ++e) {
+        if (integer) {
+            r[e] = t0[e];
+        } else {
+            const float f10 = step ? t0[e + 1] : t0[e];
+            const float f11 = step ? t1[e + 1] : t1[e];
+            r[e] = bilerp(ss.a, ss.b, t0[e], f10, t1[e], f11);
+        }
+    }
+}
+
+// A block of FUSE_PX consecutive output pixels (linear index over the overlap) of every
+// frame: first the aligned values, FUSE_Q pixels of one frame per work unit, all units of
+// the block spread over the workgroup (many loads in flight) into an LDS tile
+// [N][FUSE_PX]; then one thread per pixel clips its column of the tile in registers, as
+// combine_cols_block does it.
+constexpr int FUSE_PX = 256;
+constexpr int FUSE_Q = 4;
+static_assert(FUSE_PX == COMB_TILE, "one pixel per thread in the clip");
+
+template <int MAXV>
+__global__ __launch_bounds__(COMB_TILE) void batch_fused(BatchArgs a, int32_t first)
+{
+    extern __shared__ float tile[];  // [N][FUSE_PX]
+    const Item it = a.items[first + blockIdx.x];
+    const StackDev &s = a.stacks[it.stack];
+    const int32_t x0 = s.rect[0], y0 = s.rect[1], w = s.rect[2], h = s.rect[3];
+    const int64_t plane = (int64_t)w * h;
+    const int64_t pb = (int64_t)it.a * FUSE_PX;
+    if (pb >= plane) return;  // uniform over the workgroup
+    const bool aligned = s.W % 4 == 0;  // calibrated rows start 16-byte aligned
+    const int t = threadIdx.x;
+    constexpr int UNITS = FUSE_PX / FUSE_Q;         // work units per frame
+    constexpr int KSTEP = COMB_TILE / UNITS;        // frames taken together
+    // thread t: pixels q * FUSE_Q .. + FUSE_Q - 1 of the block, frames k0, k0 + KSTEP, ...
+    const int q = t % UNITS, k0 = t / UNITS;
+    const int64_t p0 = pb + q * FUSE_Q;
+    const int32_t v0 = (int32_t)(p0 / w), u0 = (int32_t)(p0 - (int64_t)v0 * w);
+    const bool one_row = p0 + FUSE_Q <= plane && u0 + FUSE_Q <= w;
+#pragma unroll 4
+    for (int32_t k = k0; k < s.N; k += KSTEP) {
+        float r[FUSE_Q] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (one_row) {
+            aligned_row<FUSE_Q>(s, k, u0, v0, x0, y0, aligned, r);
+        } else {
+#pragma unroll
+            for (int c = 0; c < FUSE_Q; ++c) {
+                const int64_t p = p0 + c;
+                if (p < plane) {
+                    const int32_t v = (int32_t)(p / w);
+                    float r1[1];
+                    aligned_row<1>(s, k, (int32_t)(p - (int64_t)v * w), v, x0, y0, aligned, r1);
+                    r[c] = r1[0];
+                }
+            }
+        }
+        *reinterpret_cast<float4 *>(tile + (int64_t)k * FUSE_PX + q * FUSE_Q) = make_float4(r[0], r[1], r[2], r[3]);
+    }
+    __syncthreads();
+    float x[MAXV];
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) x[i] = i < s.N ? tile[i * FUSE_PX + t] : 0.0f;
+    KeptBits<MAXV> kept;
+    unsigned dropped = 0;
+    const float res = clip_registers<MAXV>(x, s.N, (double)s.ksigma, s.max_iters, kept, dropped);
+    const int64_t p = pb + t;
+    if (p < plane) s.out[p] = res;
+    else dropped = 0;
+    if (s.n_rej) {
+        const unsigned total = block_sum_u32(dropped);
+        if (threadIdx.x == 0 && total)
+            atomicAdd(reinterpret_cast<unsigned long long *>(s.n_rej), (unsigned long long)total);
+    }
+}
+
 // Row v = it.a / N of frame k = it.a % N of a stack with a bad-pixel map (the frames
 // of a row consecutive, so that they share the map rows in L2): aligned values that
 // read a bad pixel become NaN (missing in the combine).
@@ -379,10 +522,13 @@ static BatchLayout layout_of(const reduce_stack_t *stacks, int32_t n)
         const RegPlan &p = sl.plan;
         const int64_t fp = (int64_t)s.W * s.H;
         const int32_t nreg = s.N - 1;
+        // a stack of up to 48 frames without a bad-pixel map takes the fused phase (no
+        // aligned frames in the workspace)
+        const bool fuse = s.mask == nullptr && s.N <= 48;
         sl.cal = off;
         off += al(sizeof(float) * fp * s.N);
         sl.al = off;
-        off += al(sizeof(float) * al_plane(s.W, s.H) * s.N);
+        if (!fuse) off += al(sizeof(float) * al_plane(s.W, s.H) * s.N);
         const int32_t n_mean_parts = (int32_t)ceil_div(s.H - 2 * s.radius, MEAN_ROWS);
         sl.mean_parts = off;
         off += al(sizeof(double) * n_mean_parts);
@@ -405,7 +551,7 @@ static BatchLayout layout_of(const reduce_stack_t *stacks, int32_t n)
         sl.count[IT_PICK] = nreg;
         sl.count[IT_RECT] = 1;
         sl.count[IT_SHIFT] =
-            s.N * (int32_t)ceil_div(s.H, SH_ROWS) * (int32_t)ceil_div(s.W, (int64_t)SH_BLOCK * SH_VEC);
+            fuse ? 0 : s.N * (int32_t)ceil_div(s.H, SH_ROWS) * (int32_t)ceil_div(s.W, (int64_t)SH_BLOCK * SH_VEC);
         // enough clip items for the whole frame (the overlap is only known on the device),
         // PX columns per thread when the output image allows PX-float stores
         const int px = s.N <= 16 ? COMB_PX16 : s.N <= 32 ? COMB_PX32 : 1;
@@ -418,10 +564,16 @@ static BatchLayout layout_of(const reduce_stack_t *stacks, int32_t n)
         const int32_t c16 = s.N <= 16 ? comb_blocks : 0;
         const int32_t c32 = s.N > 16 && s.N <= 32 ? comb_blocks : 0;
         const int32_t c48 = s.N > 32 && s.N <= 48 ? comb_blocks : 0;
+        if (fuse) {
+            const int32_t fb = (int32_t)ceil_div(fp, (int64_t)FUSE_PX);
+            sl.count[IT_FUSE16] = s.N <= 16 ? fb : 0;
+            sl.count[IT_FUSE32] = s.N > 16 && s.N <= 32 ? fb : 0;
+            sl.count[IT_FUSE48] = s.N > 32 ? fb : 0;
+        }
         const int32_t deep_blocks = s.N > 48 ? (int32_t)ceil_div(fp, (int64_t)COMB_DEEP_PX) : 0;
-        sl.count[miss ? IT_COMB16M : IT_COMB16] = c16;
-        sl.count[miss ? IT_COMB32M : IT_COMB32] = c32;
-        sl.count[miss ? IT_COMB48M : IT_COMB48] = c48;
+        sl.count[miss ? IT_COMB16M : IT_COMB16] = fuse ? 0 : c16;
+        sl.count[miss ? IT_COMB32M : IT_COMB32] = fuse ? 0 : c32;
+        sl.count[miss ? IT_COMB48M : IT_COMB48] = fuse ? 0 : c48;
         sl.count[miss ? IT_COMBMISS : IT_COMBDEEP] = deep_blocks;
         if (s.N > 48) (miss ? L.miss_n : L.deep_n) = std::max(miss ? L.miss_n : L.deep_n, s.N);
         for (int q = 0; q < N_PHASES; ++q) L.count[q] += sl.count[q];
@@ -540,7 +692,8 @@ static int build_descriptors(const reduce_stack_t *stacks, int32_t n, void *ws, 
         const auto cost = [&](int32_t z) {
             const RegPlan &p = L.st[z].plan;
             return (double)(L.st[z].count[IT_SCORE] + L.st[z].count[IT_SSCORE]) * p.BR * p.TX * p.C +
-                   (double)L.st[z].count[IT_SHIFT];
+                   (double)L.st[z].count[IT_SHIFT] + (double)L.st[z].count[IT_FUSE16] +
+                   (double)L.st[z].count[IT_FUSE32] + (double)L.st[z].count[IT_FUSE48];
         };
         return cost(x) > cost(y);
     });
@@ -611,7 +764,8 @@ static int launch_phases(int32_t n, void *ws, const BatchLayout &L, hipStream_t 
     hipLaunchKernelGGL(batch_rect, dim3(L.count[IT_RECT]), dim3(64), 0, s, a, L.first[IT_RECT]);
     {
         ProfScope prof("batch_shift", s);
-        hipLaunchKernelGGL(batch_shift, dim3(L.count[IT_SHIFT]), dim3(SH_BLOCK), 0, s, a, L.first[IT_SHIFT]);
+        if (L.count[IT_SHIFT] > 0)
+            hipLaunchKernelGGL(batch_shift, dim3(L.count[IT_SHIFT]), dim3(SH_BLOCK), 0, s, a, L.first[IT_SHIFT]);
     }
     if (L.count[IT_MASK] > 0)
         hipLaunchKernelGGL(batch_mask, dim3(L.count[IT_MASK]), dim3(256), 0, s, a, L.first[IT_MASK]);
@@ -641,6 +795,19 @@ static int launch_phases(int32_t n, void *ws, const BatchLayout &L, hipStream_t 
         if (L.count[IT_COMBMISS] > 0)
             hipLaunchKernelGGL(batch_comb_deep<true>, dim3(L.count[IT_COMBMISS]), dim3(COMB_DEEP_PX),
                                sizeof(float) * (L.miss_n - COMB_DEEP_REG) * COMB_DEEP_PX, s, a, L.first[IT_COMBMISS]);
+    }
+    if (L.count[IT_FUSE16] + L.count[IT_FUSE32] + L.count[IT_FUSE48] > 0) {
+        ProfScope prof("batch_fused", s);
+        // the tile holds the frames of the class's deepest stack
+        if (L.count[IT_FUSE16] > 0)
+            hipLaunchKernelGGL(batch_fused<16>, dim3(L.count[IT_FUSE16]), dim3(COMB_TILE),
+                               sizeof(float) * FUSE_PX * 16, s, a, L.first[IT_FUSE16]);
+        if (L.count[IT_FUSE32] > 0)
+            hipLaunchKernelGGL(batch_fused<32>, dim3(L.count[IT_FUSE32]), dim3(COMB_TILE),
+                               sizeof(float) * FUSE_PX * 32, s, a, L.first[IT_FUSE32]);
+        if (L.count[IT_FUSE48] > 0)
+            hipLaunchKernelGGL(batch_fused<48>, dim3(L.count[IT_FUSE48]), dim3(COMB_TILE),
+                               sizeof(float) * FUSE_PX * 48, s, a, L.first[IT_FUSE48]);
     }
     return check_launch("reduce_stack_batch");
 }

@@ -263,7 +263,9 @@ int reduce_combine(const float *aligned, int32_t w, int32_t h, int32_t N, float 
  * partial scores, the work-item table); query again after tuning.  The stack
  * A stack with a bias frame calibrates as reduce_calibrate with it; a stack with a
  * bad-pixel map masks its aligned values as reduce_mask_shifted and combines with
- * missing = 1.
+ * missing = 1.  A stack with search = REDUCE_SEARCH_SPECTRAL (radius >= 1, W <= 8192)
+ * registers as reduce_register_fft of its calibrated frames instead of
+ * reduce_register (the same offsets; the choice is the caller's or the tuner's).  The stack
  * descriptors are copied into the workspace at every call (the host image is kept
  * per workspace and rebuilt, after synchronising `stream`, when the descriptors
  * change).  Calls sharing one workspace must not overlap.  Errors: as the stage-wise
@@ -282,7 +284,11 @@ typedef struct {
     int64_t *n_rej;
     const float *bias;      /* [H][W] at cal_row_pitch, or NULL (the dark carries the bias) */
     const uint8_t *mask;    /* bad-pixel map [H][W] (row pitch W, nonzero = bad) or NULL */
+    int32_t search;         /* REDUCE_SEARCH_DIRECT (0) or REDUCE_SEARCH_SPECTRAL (1) */
+    int32_t pad;
 } reduce_stack_t;
+#define REDUCE_SEARCH_DIRECT   0  /* scores by direct sums (reduce_register) */
+#define REDUCE_SEARCH_SPECTRAL 1  /* scores from row spectra, offsets from exact sums (reduce_register_fft) */
 
 size_t reduce_stack_batch_ws(const reduce_stack_t *stacks, int32_t n);
 int reduce_stack_batch(const reduce_stack_t *stacks, int32_t n, void *ws, size_t ws_bytes, void *stream);

@@ -448,19 +448,24 @@ class StackDesc(ctypes.Structure):
                 ("radius", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("ksigma", ctypes.c_float),
                 ("integer_mode", ctypes.c_int32), ("out", ctypes.c_void_p), ("out_rect", ctypes.c_void_p),
                 ("offsets", ctypes.c_void_p), ("n_rej", ctypes.c_void_p), ("bias", ctypes.c_void_p),
-                ("mask", ctypes.c_void_p)]
+                ("mask", ctypes.c_void_p), ("search", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+SEARCH_DIRECT, SEARCH_SPECTRAL = 0, 1
 
 
 class StackBatch:
     """Device buffers and descriptors of a batch of stacks (caller-owned torch tensors).
 
     Each stack is (raw uint16 [N][H][W], dark [H][W], flat [H][W], radius) or that tuple
-    followed by bias [H][W] (or None) and a bad-pixel map uint8 [H][W] (or None); outputs
+    followed by bias [H][W] (or None) and a bad-pixel map uint8 [H][W] (or None); search
+    is "direct" or "spectral" (per stack with a list); outputs
     are allocated here once: out [H*W] float32 (the image is out[:h*w] as [h][w]),
     rect int32 [4], offsets [N][48] bytes, n_rej int64 [1].
     """
 
-    def __init__(self, stacks, ksigma: float = 3.0, max_iters: int = 3, ref_index=0, integer_mode=False):
+    def __init__(self, stacks, ksigma: float = 3.0, max_iters: int = 3, ref_index=0, integer_mode=False,
+                 search="direct"):
         self.items = []
         descs = []
         for i, st in enumerate(stacks):
@@ -474,6 +479,9 @@ class StackBatch:
             dev = raw.device
             ref = ref_index[i] if isinstance(ref_index, (list, tuple)) else ref_index
             imode = integer_mode[i] if isinstance(integer_mode, (list, tuple)) else integer_mode
+            srch = search[i] if isinstance(search, (list, tuple)) else search
+            if srch not in ("direct", "spectral"):
+                raise ValueError("search must be 'direct' or 'spectral'")
             out = torch.empty(H * W, dtype=torch.float32, device=dev)
             rect = torch.zeros(4, dtype=torch.int32, device=dev)
             offs = torch.zeros((N, OFFSET_BYTES), dtype=torch.uint8, device=dev)
@@ -481,7 +489,8 @@ class StackBatch:
             d = StackDesc(raw.data_ptr(), raw.stride(1), raw.stride(0), dark.data_ptr(), flat.data_ptr(),
                           dark.stride(0), W, H, N, int(ref), int(radius), int(max_iters), float(ksigma),
                           1 if imode else 0, out.data_ptr(), rect.data_ptr(), offs.data_ptr(), nrej.data_ptr(),
-                          0 if bias is None else bias.data_ptr(), 0 if mask is None else mask.data_ptr())
+                          0 if bias is None else bias.data_ptr(), 0 if mask is None else mask.data_ptr(),
+                          SEARCH_SPECTRAL if srch == "spectral" else SEARCH_DIRECT, 0)
             descs.append(d)
             self.items.append(dict(raw=raw, dark=dark, flat=flat, bias=bias, mask=mask, out=out, rect=rect,
                                    offsets=offs, n_rej=nrej,

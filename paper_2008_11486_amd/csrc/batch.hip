@@ -468,6 +468,7 @@ struct BatchLayout {
     int32_t n_items;
     int32_t first[N_PHASES], count[N_PHASES];
     size_t score_lds;
+    size_t spec_ws = 0, spec = 0;  // workspace of the largest spectral search and its offset
     int32_t deep_n = 0;  // deepest stack of the deep combine phase
     int32_t miss_n = 0;  // deepest stack of the combine with missing values
     std::vector<ScoreGroup> groups;
@@ -497,9 +498,17 @@ static int validate(const reduce_stack_t *stacks, int32_t n)
         if (!(s.ksigma > 0.0f) || s.max_iters < 0) return fail(REDUCE_ERR_RANGE, who + ": bad clip parameters");
         if (reg_plan(s.W, s.H, s.radius, s.radius).D == 0)
             return fail(REDUCE_ERR_UNSUPPORTED, who + ": radius too large for any launch shape");
+        if (s.search != REDUCE_SEARCH_DIRECT && s.search != REDUCE_SEARCH_SPECTRAL)
+            return fail(REDUCE_ERR_RANGE, who + ": unknown search");
+        if (s.search == REDUCE_SEARCH_SPECTRAL && s.N > 1 &&
+            (s.radius < 1 || reduce_register_fft_ws(s.W, s.H, s.N, s.radius) == 0))
+            return fail(REDUCE_ERR_UNSUPPORTED, who + ": no search through row spectra for these sizes");
     }
     return REDUCE_OK;
 }
+
+// The stack registers through row spectra (a stack of one frame has nothing to register).
+static bool spectral(const reduce_stack_t &s) { return s.search == REDUCE_SEARCH_SPECTRAL && s.N > 1; }
 
 // Dark subtraction takes 8-pixel groups when rows, pitches and pointers allow it.
 static bool cal_vec_ok(const reduce_stack_t &s)
@@ -534,10 +543,13 @@ static BatchLayout layout_of(const reduce_stack_t *stacks, int32_t n)
         off += al(sizeof(double) * n_mean_parts);
         sl.mean = off;
         off += 256;
+        const bool spec = spectral(s);
+        const int32_t ndir = spec ? 0 : nreg;  // frames of the direct search
         sl.partial = off;
-        off += al(sizeof(double) * (size_t)std::max(nreg, 0) * p.n_tiles * p.D * p.D);
+        off += al(sizeof(double) * (size_t)std::max(ndir, 0) * p.n_tiles * p.D * p.D);
         sl.scores = off;
-        off += al(sizeof(double) * (size_t)std::max(nreg, 0) * p.D * p.D);
+        off += al(sizeof(double) * (size_t)std::max(ndir, 0) * p.D * p.D);
+        if (spec) L.spec_ws = std::max(L.spec_ws, reduce_register_fft_ws(s.W, s.H, s.N, s.radius));
         sl.soffs = off;
         off += al(sizeof(float) * 2 * s.N);
         sl.rect = off;
@@ -545,10 +557,10 @@ static BatchLayout layout_of(const reduce_stack_t *stacks, int32_t n)
         sl.count[IT_CAL] = (int32_t)ceil_div(cal_vec_ok(s) ? fp / CAL_VEC : fp, CAL_BLOCK);
         sl.count[IT_MEANPART] = n_mean_parts;
         sl.count[IT_MEANFINAL] = 1;
-        sl.count[IT_SCORE] = p.K != 0 ? nreg * p.wg_per_frame : 0;
-        sl.count[IT_SSCORE] = p.K == 0 ? nreg * p.wg_per_frame : 0;
-        sl.count[IT_SUM] = nreg * (int32_t)ceil_div((int64_t)p.D * p.D, 64);
-        sl.count[IT_PICK] = nreg;
+        sl.count[IT_SCORE] = p.K != 0 ? ndir * p.wg_per_frame : 0;
+        sl.count[IT_SSCORE] = p.K == 0 ? ndir * p.wg_per_frame : 0;
+        sl.count[IT_SUM] = ndir * (int32_t)ceil_div((int64_t)p.D * p.D, 64);
+        sl.count[IT_PICK] = ndir;
         sl.count[IT_RECT] = 1;
         sl.count[IT_SHIFT] =
             fuse ? 0 : s.N * (int32_t)ceil_div(s.H, SH_ROWS) * (int32_t)ceil_div(s.W, (int64_t)SH_BLOCK * SH_VEC);
@@ -577,7 +589,7 @@ static BatchLayout layout_of(const reduce_stack_t *stacks, int32_t n)
         sl.count[miss ? IT_COMBMISS : IT_COMBDEEP] = deep_blocks;
         if (s.N > 48) (miss ? L.miss_n : L.deep_n) = std::max(miss ? L.miss_n : L.deep_n, s.N);
         for (int q = 0; q < N_PHASES; ++q) L.count[q] += sl.count[q];
-        if (nreg > 0 && p.K != 0) L.score_lds = std::max(L.score_lds, p.lds);
+        if (ndir > 0 && p.K != 0) L.score_lds = std::max(L.score_lds, p.lds);
         L.st.push_back(sl);
     }
     int64_t total = 0;
@@ -608,6 +620,8 @@ static BatchLayout layout_of(const reduce_stack_t *stacks, int32_t n)
         for (int32_t i : g.stacks) g.count += L.st[i].count[IT_SCORE];
         next += g.count;
     }
+    L.spec = off;  // one spectral search at a time
+    off += al(L.spec_ws);
     L.items = off;
     off += al(sizeof(Item) * (size_t)std::max<int64_t>(total, 0));
     L.stacks = off;
@@ -730,7 +744,7 @@ static void score_dispatch_host(int K, F &&f)
     }
 }
 
-static int launch_phases(int32_t n, void *ws, const BatchLayout &L, hipStream_t s)
+static int launch_phases(const reduce_stack_t *stacks, int32_t n, void *ws, const BatchLayout &L, hipStream_t s)
 {
     unsigned char *base = static_cast<unsigned char *>(ws);
     BatchArgs a;
@@ -761,6 +775,16 @@ static int launch_phases(int32_t n, void *ws, const BatchLayout &L, hipStream_t 
         hipLaunchKernelGGL(batch_sum, dim3(L.count[IT_SUM]), dim3(64 * SUM_WAVES), 0, s, a, L.first[IT_SUM]);
     if (L.count[IT_PICK] > 0)
         hipLaunchKernelGGL(batch_pick, dim3(L.count[IT_PICK]), dim3(256), 0, s, a, L.first[IT_PICK]);
+    // the stacks that register through row spectra, one after the other in the shared space
+    for (int32_t i = 0; i < n; ++i) {
+        const reduce_stack_t &st = stacks[i];
+        if (!spectral(st)) continue;
+        ProfScope prof("batch_spectral", s);
+        const float *cal = reinterpret_cast<const float *>(base + L.st[i].cal);
+        const int rc = reduce_register_fft(cal + (int64_t)st.ref_index * st.W * st.H, cal, st.W, st.H, st.N,
+                                           st.radius, st.offsets, nullptr, nullptr, base + L.spec, L.spec_ws, s);
+        if (rc != REDUCE_OK) return rc;
+    }
     hipLaunchKernelGGL(batch_rect, dim3(L.count[IT_RECT]), dim3(64), 0, s, a, L.first[IT_RECT]);
     {
         ProfScope prof("batch_shift", s);
@@ -862,5 +886,5 @@ extern "C" int reduce_stack_batch(const reduce_stack_t *stacks, int32_t n, void 
                        hipMemcpyHostToDevice, s) != hipSuccess)
         return fail(REDUCE_ERR_HIP, "reduce_stack_batch: descriptor upload");
     ProfScope prof("stack_batch", s);
-    return launch_phases(n, ws, L, s);
+    return launch_phases(stacks, n, ws, L, s);
 }

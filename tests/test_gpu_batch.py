@@ -196,3 +196,42 @@ def test_batch_rejects_bad_stacks(rd):
     batch = rd.StackBatch([(raw, to_dev(st.dark), to_dev(st.flat), 60)])  # no template left
     with pytest.raises(rd.ReduceError):
         batch.run()
+
+
+def test_batch_spectral_search_bit_identical_to_stagewise(rd, orc):
+    """Stacks that register through row spectra beside a direct-search stack in one call:
+    each bit-identical to the stage-wise chain with reduce_register_fft (offsets of every
+    frame but the reference, the overlap, the image, the rejected count), and one of them
+    against the oracle end to end."""
+    specs = [(8, 200, 171, 6, False), (12, 160, 160, 6, True), (5, 300, 261, 17, False), (6, 128, 96, 4, False)]
+    search = ["spectral", "spectral", "spectral", "direct"]
+    stacks = [_make(40 + i, N, W, H, R, cos, seed=7) for i, (N, W, H, R, cos) in enumerate(specs)]
+    dev = [(to_dev(st.raw), to_dev(st.dark), to_dev(st.flat), sp[3]) for st, sp in zip(stacks, specs)]
+    batch = rd.StackBatch(dev, search=search)
+    batch.run()
+    for i, (raw, dark, flat, R) in enumerate(dev):
+        img, rect, offs, nrej = batch.result(i)
+        if search[i] == "direct":
+            ref_img, ref_rect, ref_offs, ref_nrej = stagewise(rd, raw, dark, flat, R)
+            assert np.array_equal(img.cpu().numpy(), ref_img) and offs.tobytes() == ref_offs.tobytes(), i
+            continue
+        cal = rd.calibrate(raw, dark, flat)
+        o = rd.offsets_to_numpy(rd.register_fft(cal[0].contiguous(), cal, R))
+        s = np.stack([o["sx"], o["sy"]], 1).astype(np.float32)
+        s[0] = 0.0
+        r2 = rd.valid_rect(s, cal.shape[2], cal.shape[1])
+        al = rd.shift(cal, to_dev(s), r2)
+        ref_img, _, ref_nrej = rd.combine(al, want_nrej=True)
+        assert np.array_equal(rect, r2), i
+        assert offs[1:].tobytes() == o[1:].tobytes(), i
+        assert np.array_equal(img.cpu().numpy(), ref_img.cpu().numpy()), i
+        assert nrej == int(ref_nrej.cpu()[0]), i
+    img, rect, offs, _ = batch.result(1)
+    st = stacks[1]
+    o = orc.reduce_stack(st.raw, st.dark, st.flat, specs[1][3])
+    assert np.array_equal(offs["dx"][1:], o["offsets"]["dx"][1:]) and np.array_equal(offs["dy"][1:], o["offsets"]["dy"][1:])
+    assert np.array_equal(rect, o["rect"])
+    s = np.stack([offs["sx"], offs["sy"]], 1).astype(np.float32)
+    cal_gpu = rd.calibrate(dev[1][0], dev[1][1], dev[1][2]).cpu().numpy()
+    assert_end_to_end(orc, o["cal"], cal_gpu, offs, s, o["s"], rect, img.cpu().numpy(), specs[1][3],
+                      "spectral batch vs oracle")

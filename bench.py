@@ -87,6 +87,8 @@ def parse():
                     help="skip the leg over three bands of 10 frames of 1024x1024 (with --workload 2)")
     ap.add_argument("--no-wide-chain", action="store_true",
                     help="skip the end-to-end wide-field chain with the +-65 px search")
+    ap.add_argument("--no-autotuned-search", action="store_true",
+                    help="skip the 64-stack leg with the search of each frame size chosen by timing")
     ap.add_argument("--sweep", action="store_true",
                     help="only the sweeps over image size and frame count (one JSON line)")
     ap.add_argument("--wide-only", action="store_true",
@@ -323,17 +325,20 @@ def many_stack_inputs(torch, rd, specs, on_frames=None):
     return stacks, shifts
 
 
-def tune_many_stacks(torch, rd, specs, stacks_frames):
+def tune_many_stacks(torch, rd, specs, stacks_frames, searches=None):
     """Search shapes per frame size, timed on up to 32 frames of that size (the batched
-    search runs all frames of a size in one launch, so the candidates see a full grid).
-    stacks_frames: {W: (reference frame, [frame blocks])} gathered by many_stack_inputs'
-    on_frames hook; emptied here."""
+    search runs all frames of a size in one launch, so the candidates see a full grid);
+    with a dict `searches`, also the faster search (direct sums or row spectra) per frame
+    size on the same frames.  stacks_frames: {W: (reference frame, [frame blocks])}
+    gathered by many_stack_inputs' on_frames hook; emptied here."""
     plans = {}
     for W in sorted(stacks_frames):
         ref, blocks = stacks_frames.pop(W)
         fr = torch.cat(blocks)
         p = rd.tune_register(ref.contiguous(), fr, specs[0].radius)
         plans[str(W)] = {k: p[k] for k in ("K", "G", "S", "TY", "BR", "threads", "n_tiles")}
+        if searches is not None:
+            searches[W] = rd.tune_search(ref.contiguous(), fr, specs[0].radius)
         del fr, ref, blocks
     torch.cuda.empty_cache()
     return plans
@@ -372,7 +377,9 @@ class ManyStackPipeline:
         tune = tune and not cached
         self.stacks, self.shifts = many_stack_inputs(torch, rd, self.specs, tuning_hook(store) if tune else None)
         log("64-stack inputs rendered")
-        self.plans = tune_many_stacks(torch, rd, self.specs, store) if tune else ("loaded" if cached else None)
+        self.searches = {}
+        self.plans = (tune_many_stacks(torch, rd, self.specs, store, self.searches) if tune
+                      else ("loaded" if cached else None))
         if tune and tune_cache:
             rd.tune_save(tune_cache)
         self.batch = rd.StackBatch(self.stacks)
@@ -380,6 +387,38 @@ class ManyStackPipeline:
 
     def step(self):
         self.batch.run()
+
+
+def autotuned_search_leg(torch, rd, pipe, steps=10, warmup=2):
+    """The 64-stack workload with the search of each frame size chosen by timing (direct
+    sums or row spectra, on the tuning frames of that size): same stacks, one batched call
+    per step, and the per-size choices and times."""
+    if not pipe.searches:
+        return None
+    choice = [pipe.searches[sp.W]["search"] for sp in pipe.specs]
+    batch = rd.StackBatch(pipe.stacks, search=choice)
+    for _ in range(warmup):
+        batch.run()
+    torch.cuda.synchronize()
+    rd.prof_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batch.run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    parts = {k: round(rd.prof_query(k)[0] / steps, 3)
+             for k in ("batch_cal", "batch_score", "batch_spectral", "spec_corr", "fft_rows", "spec_eval",
+                       "fft_refine", "batch_fused")}
+    rd.prof_enable(False)
+    res = {"workload": WORKLOADS[2] + "; the search of each frame size chosen by timing",
+           "Mpix/s": round(pipe.pixels / dt / 1e6, 1), "ms_per_step": round(dt * 1e3, 3), "steps": steps,
+           "search_by_size": {str(W): {"search": v["search"], "ms_direct": round(v["ms_direct"], 3),
+                                       "ms_spectral": round(v["ms_spectral"], 3)}
+                              for W, v in sorted(pipe.searches.items())},
+           "ms_per_step_by_phase": parts}
+    del batch
+    torch.cuda.empty_cache()
+    return res
 
 
 def many_sample(pipe, min_frames=5):
@@ -600,8 +639,9 @@ def sweep(torch, rd, reps=3):
 
 
 def learned_comparison(torch, rd, weights_path, M):
-    """Full +-64 px search vs network proposal + +-2 px search + fallbacks on one stack of
-    4096x4096 frames (a reference and M shifted frames, shifts uniform in +-64 px)."""
+    """Full +-64 px search (direct sums, and through row spectra) vs network proposal +
+    +-2 px search + fallbacks on one stack of 4096x4096 frames (a reference and M shifted
+    frames, shifts uniform in +-64 px)."""
     from paper_2008_11486_amd import learned
     W = H = 4096
     trained = os.path.exists(weights_path)
@@ -615,6 +655,11 @@ def learned_comparison(torch, rd, weights_path, M):
     reg = learned.LearnedRegistrar(params, W, H, M, radius_max=64, refine_radius=2)
     full_s = learned.time_call(lambda: learned.full_search(ref, rest, 64, ws=ws), reps=3)
     full = rd.offsets_to_numpy(learned.full_search(ref, rest, 64, ws=ws))
+    # the full window through row spectra (same offsets)
+    wsf = torch.empty(rd.register_fft_ws_bytes(W, H, M, 64), dtype=torch.uint8, device=frames.device)
+    spec_s = learned.time_call(lambda: rd.register_fft(ref, rest, 64, ws=wsf), reps=3)
+    spec = rd.offsets_to_numpy(rd.register_fft(ref, rest, 64, ws=wsf))
+    del wsf
     res = {}
     learned_s = learned.time_call(lambda: res.setdefault("r", reg.register(ref, rest)), reps=1)
     learned_s = min(learned_s, learned.time_call(lambda: reg.register(ref, rest), reps=3))
@@ -634,6 +679,11 @@ def learned_comparison(torch, rd, weights_path, M):
                         f"vs network proposal + R=2 search (same template) + full-search fallback",
             "weights": "trained" if trained else "untrained", "full_ms": round(full_s * 1e3, 3),
             "learned_ms": round(learned_s * 1e3, 3), "speedup": round(full_s / learned_s, 3),
+            "full_spectral_ms": round(spec_s * 1e3, 3), "speedup_vs_full_spectral": round(spec_s / learned_s, 3),
+            "spectral_identical_integer_offsets": bool(np.array_equal(spec["dx"], full["dx"]) and
+                                                       np.array_equal(spec["dy"], full["dy"])),
+            "spectral_max_subpixel_difference_px": float(max(np.abs(spec["sx"] - full["sx"]).max(),
+                                                             np.abs(spec["sy"] - full["sy"]).max())),
             "identical_integer_offsets": float(same), "fallback_rate": float(r.fallback.mean()),
             "centre_error_px_median": float(np.median(err)), "centre_error_px_max": float(err.max()),
             "true_offset_max_abs_px": float(np.abs(t).max()), "learned_breakdown": parts}
@@ -699,6 +749,19 @@ def wide_chain(torch, rd, inp, reps=3):
     ms, n = rd.prof_query("batch_score")
     rd.prof_enable(False)
     _, rect, offs, nrej = batch.result(0)
+    del batch
+    torch.cuda.empty_cache()
+    # the same chain with the search through row spectra
+    sbatch = rd.StackBatch([(inp["raw"], inp["dark"], inp["flat"], R)], search="spectral")
+    sbatch.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sbatch.run()
+    torch.cuda.synchronize()
+    dt_s = (time.perf_counter() - t0) / reps
+    _, rect_s, offs_s, _ = sbatch.result(0)
+    same = bool(np.array_equal(rect, rect_s) and offs[1:].tobytes() == offs_s[1:].tobytes())
     s = np.stack([offs["sx"], offs["sy"]], 1)
     flops = 2.0 * (N - 1) * (W - 2 * R) * (H - 2 * R) * (2 * R + 1) ** 2
     res = {"workload": f"{N} frames {W}x{H}, 5000 stars, cosmic-ray tracks of 1-4 px on "
@@ -708,9 +771,10 @@ def wide_chain(torch, rd, inp, reps=3):
            "search_frac_fp64": round(flops / (ms / reps / 1e3) / 1e12 / FP64_VALU_PEAK_TFLOPS, 4),
            "rect": [int(v) for v in rect], "rejected_values": int(nrej),
            "max_offset_error_vs_truth_px": round(float(np.abs(s[1:] - inp["t"][1:]).max()), 4),
-           "workspace_GB": round(batch.ws_bytes() / 1e9, 2),
+           "spectral_search": {"Mpix/s": round(N * W * H / dt_s / 1e6, 1), "ms_per_call": round(dt_s * 1e3, 2),
+                               "same_offsets_and_overlap": same},
            "search_plan": {k: plan[k] for k in ("K", "G", "S", "TY", "BR", "threads", "n_tiles")}}
-    del batch
+    del sbatch
     torch.cuda.empty_cache()
     return res
 
@@ -926,6 +990,10 @@ def main():
     if args.workload == 2:
         if not args.no_cpu_baseline:
             sample = many_sample(pipe)
+        pipe.batch = None  # the direct-search workspace
+        if not args.no_autotuned_search:
+            line["autotuned_search"] = autotuned_search_leg(torch, rd, pipe)
+            log(f"autotuned search: {line['autotuned_search']}")
         del pipe
         torch.cuda.empty_cache()
         if not args.no_bands:

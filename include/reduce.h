@@ -428,6 +428,16 @@ int reduce_render_frames(const float *stars, int32_t S, const int64_t *keys, int
  *     device architecture; entries of other architectures are ignored on load.
  * Errors: as the calls they time; no fitting candidate -> WORKSPACE; unreadable or
  * unwritable file -> RANGE. */
+/*   reduce_tune_search: the full-window search of ref/frames (radius_max = radius)
+ *     timed reps times with direct sums (reduce_register, the tuned launch shape if any)
+ *     and through row spectra (reduce_register_fft, when ws_bytes covers its workspace);
+ *     search (host) receives the faster, REDUCE_SEARCH_DIRECT or REDUCE_SEARCH_SPECTRAL,
+ *     ms_direct / ms_spectral (host, or NULL) the times (1e30 for a search not timed);
+ *     ws: device workspace of at least reduce_register_ws(W, H, N, radius, radius) bytes;
+ *     out: device reduce_offset_t [N] (overwritten). */
+int reduce_tune_search(const float *ref, const float *frames, int32_t W, int32_t H, int32_t N,
+                       int32_t radius, reduce_offset_t *out, void *ws, size_t ws_bytes, int32_t reps,
+                       void *stream, int32_t *search, double *ms_direct, double *ms_spectral);
 size_t reduce_tune_register_ws(int32_t W, int32_t H, int32_t N, int32_t radius, int32_t radius_max);
 int reduce_tune_register(const float *ref, const float *frames, int32_t W, int32_t H, int32_t N,
                          int32_t radius, int32_t radius_max, reduce_offset_t *out, void *ws,

@@ -66,6 +66,8 @@ def _declare(L):
     L.reduce_register_fft_ws.restype = SZ
     L.reduce_register_fft.argtypes = [P, P, I32, I32, I32, I32, P, P, P, P, SZ, P]
     L.reduce_register_fft.restype = ctypes.c_int
+    L.reduce_tune_search.argtypes = [P, P, I32, I32, I32, I32, P, P, SZ, I32, P, P, P, P]
+    L.reduce_tune_search.restype = ctypes.c_int
     L.reduce_register_static.argtypes = [P, P, I32, I32, I32, I32, I32, P, P, P, P, P]
     L.reduce_register_static.restype = ctypes.c_int
     L.reduce_register_static_max.restype = SZ
@@ -139,7 +141,7 @@ def exported_symbols() -> Sequence[str]:
             "reduce_cnn_ws_offsets", "reduce_cnn_forward", "reduce_cnn_backward", "reduce_cnn_adamw",
             "reduce_cnn_centres", "reduce_render_frames", "reduce_recentre", "reduce_propose_ws",
             "reduce_propose", "reduce_register_static_max", "reduce_register_static", "reduce_register_fft_ws",
-            "reduce_register_fft")
+            "reduce_register_fft", "reduce_tune_search")
 
 
 def _check(rc: int) -> None:
@@ -340,6 +342,24 @@ def tune_save(path: str) -> None:
 
 def tune_load(path: str) -> None:
     _check(lib().reduce_tune_load(path.encode()))
+
+
+def tune_search(ref: torch.Tensor, frames: torch.Tensor, radius: int, reps: int = 3, stream=None) -> dict:
+    """Times the full-window search with direct sums and through row spectra on these
+    frames; returns {"search": "direct" | "spectral", "ms_direct", "ms_spectral"}."""
+    if frames.dim() == 2:
+        frames = frames.unsqueeze(0)
+    N, H, W = frames.shape
+    need = max(register_ws_bytes(W, H, N, radius), register_fft_ws_bytes(W, H, N, radius))
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=frames.device)
+    out = torch.empty((N, OFFSET_BYTES), dtype=torch.uint8, device=frames.device)
+    srch = ctypes.c_int32(0)
+    md, ms = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(lib().reduce_tune_search(_ptr(ref.contiguous()), _ptr(frames.contiguous()), W, H, N, radius, _ptr(out),
+                                    _ptr(ws), ws.numel(), int(reps), _stream(stream), ctypes.byref(srch),
+                                    ctypes.byref(md), ctypes.byref(ms)))
+    return {"search": "spectral" if srch.value == SEARCH_SPECTRAL else "direct", "ms_direct": md.value,
+            "ms_spectral": ms.value}
 
 
 def tune_clear() -> None:

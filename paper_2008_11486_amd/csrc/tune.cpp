@@ -216,6 +216,42 @@ extern "C" int reduce_tune_combine(const float *aligned, int32_t w, int32_t h, i
     return REDUCE_OK;
 }
 
+extern "C" int reduce_tune_search(const float *ref, const float *frames, int32_t W, int32_t H, int32_t N,
+                                  int32_t radius, reduce_offset_t *out, void *ws, size_t ws_bytes, int32_t reps,
+                                  void *stream, int32_t *search, double *ms_direct, double *ms_spectral)
+{
+    if (!ref || !frames || !out || !ws || !search) return fail(REDUCE_ERR_NULL, "reduce_tune_search: NULL argument");
+    if (W < 1 || H < 1 || N < 1 || radius < 1 || W - 2 * radius < 1 || H - 2 * radius < 1)
+        return fail(REDUCE_ERR_RANGE, "reduce_tune_search: no template for these sizes");
+    if (reps < 1) reps = 1;
+    hipStream_t s = as_stream(stream);
+    const size_t need_d = reduce_register_ws(W, H, N, radius, radius);
+    const size_t need_s = reduce_register_fft_ws(W, H, N, radius);
+    if (need_d == 0 || ws_bytes < need_d)
+        return fail(REDUCE_ERR_WORKSPACE, "reduce_tune_search: workspace needs " + std::to_string(need_d) + " bytes");
+    double td = 0.0, ts = 1e30;
+    int rc = time_ms(s, reps,
+                     [&]() {
+                         return reduce_register(ref, frames, W, H, N, radius, radius, nullptr, nullptr, out, nullptr,
+                                                ws, ws_bytes, s);
+                     },
+                     &td);
+    if (rc != REDUCE_OK) return rc;
+    if (need_s != 0 && ws_bytes >= need_s) {
+        rc = time_ms(s, reps,
+                     [&]() {
+                         return reduce_register_fft(ref, frames, W, H, N, radius, out, nullptr, nullptr, ws, ws_bytes,
+                                                    s);
+                     },
+                     &ts);
+        if (rc != REDUCE_OK) return rc;
+    }
+    *search = ts < td ? REDUCE_SEARCH_SPECTRAL : REDUCE_SEARCH_DIRECT;
+    if (ms_direct) *ms_direct = td;
+    if (ms_spectral) *ms_spectral = ts;
+    return REDUCE_OK;
+}
+
 extern "C" int reduce_tune_save(const char *path)
 {
     if (!path) return fail(REDUCE_ERR_NULL, "reduce_tune_save: NULL path");

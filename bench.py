@@ -761,7 +761,9 @@ def wide_chain(torch, rd, inp, reps=3):
     torch.cuda.synchronize()
     dt_s = (time.perf_counter() - t0) / reps
     _, rect_s, offs_s, _ = sbatch.result(0)
-    same = bool(np.array_equal(rect, rect_s) and offs[1:].tobytes() == offs_s[1:].tobytes())
+    same = bool(np.array_equal(rect, rect_s) and np.array_equal(offs["dx"], offs_s["dx"]) and
+                np.array_equal(offs["dy"], offs_s["dy"]) and np.array_equal(offs["flags"], offs_s["flags"]))
+    ds = float(max(np.abs(offs["sx"] - offs_s["sx"]).max(), np.abs(offs["sy"] - offs_s["sy"]).max()))
     s = np.stack([offs["sx"], offs["sy"]], 1)
     flops = 2.0 * (N - 1) * (W - 2 * R) * (H - 2 * R) * (2 * R + 1) ** 2
     res = {"workload": f"{N} frames {W}x{H}, 5000 stars, cosmic-ray tracks of 1-4 px on "
@@ -772,7 +774,8 @@ def wide_chain(torch, rd, inp, reps=3):
            "rect": [int(v) for v in rect], "rejected_values": int(nrej),
            "max_offset_error_vs_truth_px": round(float(np.abs(s[1:] - inp["t"][1:]).max()), 4),
            "spectral_search": {"Mpix/s": round(N * W * H / dt_s / 1e6, 1), "ms_per_call": round(dt_s * 1e3, 2),
-                               "same_offsets_and_overlap": same},
+                               "same_integer_offsets_flags_and_overlap": same,
+                               "max_subpixel_offset_difference_px": ds},
            "search_plan": {k: plan[k] for k in ("K", "G", "S", "TY", "BR", "threads", "n_tiles")}}
     del sbatch
     torch.cuda.empty_cache()

@@ -107,6 +107,7 @@ KERNEL_SOURCES = {
     "batch_shift": ("batch.hip", "shift_core.h", "common.h"),
     "batch_comb": ("batch.hip", "combine_core.h"),
     "batch_cal": ("batch.hip", "calibrate_core.h", "common.h"),
+    "batch_fused": ("batch.hip", "shift_core.h", "combine_core.h", "common.h"),
     "calibrate": ("calibrate.hip", "calibrate_core.h", "common.h"),
     "shift": ("shift.hip", "shift_core.h", "common.h"),
     "combine": ("combine.hip", "combine_core.h"),
@@ -116,7 +117,8 @@ KERNEL_SOURCES = {
     "shift_spline": ("spline.hip", "common.h", "shift_core.h"),
 }
 KERNEL_SYMBOLS = {"batch_score": "batch_score", "batch_shift": "batch_shift", "batch_comb": "batch_comb",
-                  "batch_cal": "batch_cal", "score_tiles": "score_tiles", "calibrate": "calibrate_",
+                  "batch_cal": "batch_cal", "batch_fused": "batch_fused", "score_tiles": "score_tiles",
+                  "calibrate": "calibrate_",
                   "shift": "shift_kernel",
                   # a list: every part must appear in the kernel name
                   "combine": ["combine_cols<", "false>"], "combine_deep": "combine_deep<false>",

@@ -91,6 +91,8 @@ def parse():
                     help="skip the 64-stack leg with the search of each frame size chosen by timing")
     ap.add_argument("--sweep", action="store_true",
                     help="only the sweeps over image size and frame count (one JSON line)")
+    ap.add_argument("--no-alone", action="store_true",
+                    help="skip the back-to-back timing of each streaming kernel alone (for counter runs)")
     ap.add_argument("--wide-only", action="store_true",
                     help="run only the wide-field streaming kernels (for counter runs) and print their figures")
     ap.add_argument("--traffic-key", default=None,
@@ -102,10 +104,10 @@ def parse():
 # Sources each timed kernel is built from: recorded counter values are used only
 # while these files are unchanged.
 KERNEL_SOURCES = {
-    "score_tiles": ("register.hip", "register_core.h", "register_plan.h", "plan.cpp"),
-    "batch_score": ("batch.hip", "register_core.h", "register_plan.h", "plan.cpp"),
+    "score_tiles": ("register.hip", "register_core.h", "register_plan.h", "plan.cpp", "common.h"),
+    "batch_score": ("batch.hip", "register_core.h", "register_plan.h", "plan.cpp", "common.h"),
     "batch_shift": ("batch.hip", "shift_core.h", "common.h"),
-    "batch_comb": ("batch.hip", "combine_core.h"),
+    "batch_comb": ("batch.hip", "combine_core.h", "common.h"),
     "batch_cal": ("batch.hip", "calibrate_core.h", "common.h"),
     "batch_fused": ("batch.hip", "shift_core.h", "combine_core.h", "common.h"),
     "calibrate": ("calibrate.hip", "calibrate_core.h", "common.h"),
@@ -784,7 +786,7 @@ def wide_chain(torch, rd, inp, reps=3):
     return res
 
 
-def streaming_wide(torch, rd, inp, reps=5, traffic_path=os.path.join(ROOT, "profiles", "traffic.json")):
+def streaming_wide(torch, rd, inp, reps=10, traffic_path=os.path.join(ROOT, "profiles", "traffic.json"), alone=True):
     """calibrate, shift (bilinear, and the bicubic spline timed alone) and combine over the
     wide-field stack at its true shifts (working sets of 1.2-2.4 GB, far beyond the 256 MB
     last-level cache), bad-pixel masking with the missing-value combine, and the combine of
@@ -821,26 +823,59 @@ def streaming_wide(torch, rd, inp, reps=5, traffic_path=os.path.join(ROOT, "prof
         rd.shift_spline(cal, s, rect, out=al_spline, ws=spline_ws)  # the paper's interpolation, timed alone
         rd.combine(deep, out=deep_out)
 
-    for _ in range(2):
-        chain()
-    torch.cuda.synchronize()
+    # the device reaches its steady clocks only after tens of milliseconds of back-to-back
+    # work (a 0.5 ms kernel runs 20-40% longer in its first launches after an idle
+    # second), so the chain runs for half a second before the timed repetitions
+    t_warm = time.perf_counter()
+    while time.perf_counter() - t_warm < 0.5:
+        for _ in range(8):
+            chain()
+        torch.cuda.synchronize()
     rd.prof_enable(True)
     for _ in range(reps):
         chain()
     torch.cuda.synchronize()
     res = {"workload": f"{N} frames {W}x{H} at their true shifts (+-64 px), overlap {w}x{h}, bad pixels 0.1%; "
-                       f"deep combine: {ND} frames {SD}x{SD}"}
+                       f"deep combine: {ND} frames {SD}x{SD}; timed after 0.5 s of warm-up"}
     byts = {"calibrate": N * W * H * (2 + 4) + 8 * W * H, "shift": N * w * h * (4 + 4), "combine": N * w * h * 4 + w * h * 4,
             # rows: frame read, row-pass result written; columns: that result read, output written
             "shift_spline": N * 4 * (H * W + 2 * H * w + h * w), "combine_deep": (ND + 1) * SD * SD * 4,
             # the map (from L2 after the first frame) and the marked values
             "mask_shifted": H * W + int(torch.isnan(al).sum()) * 4, "combine_missing": N * w * h * 4 + w * h * 4}
-    for name in ("calibrate", "shift", "combine", "shift_spline", "combine_deep", "mask_shifted", "combine_missing"):
+    names = ("calibrate", "shift", "combine", "shift_spline", "combine_deep", "mask_shifted", "combine_missing")
+    for name in names:
         ms, n = rd.prof_query(name)
         gbs = byts[name] / (ms / n / 1e3) / 1e9
         res[name] = {"avg_launch_ms": round(ms / n, 4), "bytes": byts[name], "GB/s": round(gbs, 1),
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(traffic_path, name, "wide")}
     rd.prof_enable(False)
+    # each kernel alone, launched back to back for 0.2 s and then timed over 20 launches:
+    # the rate it keeps when the stage runs over many stacks in a row (the device settles
+    # at other clocks under one memory-bound kernel than under the mixed chain)
+    single = {"calibrate": lambda: rd.calibrate(raw, dark, flat, out=cal),
+             "shift": lambda: rd.shift(cal, s, rect, out=al),
+             "combine": lambda: rd.combine(al, out=out),
+             "mask_shifted": lambda: rd.mask_shifted(bad, al, s, rect, W, H),
+             "combine_missing": lambda: rd.combine(al, out=out_miss, missing=True),
+             "shift_spline": lambda: rd.shift_spline(cal, s, rect, out=al_spline, ws=spline_ws),
+             "combine_deep": lambda: rd.combine(deep, out=deep_out)}
+    for name in ("calibrate", "shift", "combine", "mask_shifted", "combine_missing", "shift_spline", "combine_deep"):
+        if not alone:
+            break
+        fn = single[name]
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < 0.2:
+            for _ in range(10):
+                fn()
+            torch.cuda.synchronize()
+        rd.prof_enable(True)
+        for _ in range(20):
+            fn()
+        torch.cuda.synchronize()
+        ms, n = rd.prof_query(name)
+        rd.prof_enable(False)
+        res[name]["alone_ms"] = round(ms / n, 4)
+        res[name]["alone_frac"] = round(byts[name] / (ms / n / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
     del cal, al, al_spline, spline_ws, deep, deep_out, bad, out_miss
     torch.cuda.empty_cache()
     return res
@@ -897,7 +932,7 @@ def main():
         return 0
     if args.wide_only:
         rd.lib()
-        print(json.dumps({"streaming_wide": streaming_wide(torch, rd, wide_inputs(torch, rd))}))
+        print(json.dumps({"streaming_wide": streaming_wide(torch, rd, wide_inputs(torch, rd), alone=not args.no_alone)}))
         return 0
     if args.sweep:
         rd.lib()

@@ -406,9 +406,10 @@ __global__ __launch_bounds__(COMB_TILE) void batch_fused(BatchArgs a, int32_t fi
 // Row v = it.a / N of frame k = it.a % N of a stack with a bad-pixel map (the frames
 // of a row consecutive, so that they share the map rows in L2): aligned values that
 // read a bad pixel become NaN (missing in the combine).
-__global__ __launch_bounds__(256) void batch_mask(BatchArgs a, int32_t first)
+__global__ __launch_bounds__(256) void batch_mask(BatchArgs a, int32_t first, int32_t count)
 {
-    const Item it = a.items[first + blockIdx.x];
+    // XCD-aware order: the frames of a row, and neighbouring rows, on one XCD (one L2)
+    const Item it = a.items[first + xcd_logical_id((int32_t)blockIdx.x, count)];
     const StackDev &s = a.stacks[it.stack];
     const int32_t v = it.a / s.N, k = it.a - v * s.N;
     const int32_t x0 = s.rect[0], y0 = s.rect[1], w = s.rect[2], h = s.rect[3];
@@ -792,7 +793,8 @@ static int launch_phases(const reduce_stack_t *stacks, int32_t n, void *ws, cons
             hipLaunchKernelGGL(batch_shift, dim3(L.count[IT_SHIFT]), dim3(SH_BLOCK), 0, s, a, L.first[IT_SHIFT]);
     }
     if (L.count[IT_MASK] > 0)
-        hipLaunchKernelGGL(batch_mask, dim3(L.count[IT_MASK]), dim3(256), 0, s, a, L.first[IT_MASK]);
+        hipLaunchKernelGGL(batch_mask, dim3(L.count[IT_MASK]), dim3(256), 0, s, a, L.first[IT_MASK],
+                           L.count[IT_MASK]);
     {
         ProfScope prof("batch_comb", s);
         if (L.count[IT_COMB16] > 0)

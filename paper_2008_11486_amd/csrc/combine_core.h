@@ -178,18 +178,13 @@ struct KeptBits {
     }
 };
 
-template <int MAXV, bool ALL>
-__device__ __forceinline__ bool kept_at(const KeptBits<MAXV> &kept, int i, int32_t N)
-{
-    return ALL ? i < N : kept.get(i);
-}
 
 // One thread per pixel column, the column's values read through x(i) (registers, or
 // the thread's own slice of LDS).  The arithmetic is that of clip_column with one
 // lane: sums in frame order in double, m = s / n, q = sum of (x - m)^2, threshold
 // ksigma * sqrt(q / n), drop |x - m| > threshold.  Two shortcuts leave every result
 // unchanged: the largest |x - m| of the q pass decides whether the drop pass is
-// needed at all, and when an iteration drops nothing its own sum is the final sum.
+// needed at all, and when an iteration drops nothing its own mean is the final mean.
 // With FENCE a compiler barrier at each pass keeps values read from LDS from being
 // held in registers across passes.
 template <bool FENCE>
@@ -198,6 +193,11 @@ __device__ __forceinline__ void clip_fence()
     if (FENCE) asm volatile("" ::: "memory");
 }
 
+// With ALL (every value kept: the first iteration without missing values) the passes
+// carry no per-value selects: the values past N are zero (the loads fill them so), which
+// adds exactly nothing to a sum that starts at +0 (such a sum is never -0), and their
+// deviations are multiplied by the uniform weight 0 (1 for i < N, an exact product) so
+// they add exactly nothing to q and cannot raise the largest deviation.
 template <int MAXV, bool ALL, bool FENCE, typename X>
 __device__ __forceinline__ void clip_pass(X x, const KeptBits<MAXV> &kept, int32_t N, int n, double &s, double &m,
                                           double &q, double &dmax)
@@ -206,15 +206,16 @@ __device__ __forceinline__ void clip_pass(X x, const KeptBits<MAXV> &kept, int32
     s = 0.0;
 #pragma unroll
     for (int i = 0; i < MAXV; ++i)
-        if (kept_at<MAXV, ALL>(kept, i, N)) s = __dadd_rn(s, (double)x(i));
+        if (ALL || kept.get(i)) s = __dadd_rn(s, (double)x(i));
     m = s / (double)n;
     q = 0.0;
     dmax = 0.0;
     clip_fence<FENCE>();
 #pragma unroll
     for (int i = 0; i < MAXV; ++i)
-        if (kept_at<MAXV, ALL>(kept, i, N)) {
-            const double d = __dsub_rn((double)x(i), m);
+        if (ALL || kept.get(i)) {
+            double d = __dsub_rn((double)x(i), m);
+            if (ALL) d = __dmul_rn(d, (double)min(max(N - i, 0), 1));
             q = __dadd_rn(q, __dmul_rn(d, d));
             dmax = fmax(dmax, fabs(d));
         }
@@ -246,7 +247,7 @@ __device__ __forceinline__ float clip_values(X x, int32_t N, double ksigma, int3
             clip_pass<MAXV, false, FENCE>(x, kept, N, n, s, m, q, dmax);
         const double thr = __dmul_rn(ksigma, sqrt(q / (double)n));
         if (!(dmax > thr)) {
-            final_known = true;  // nothing drops: s is the sum over the final set
+            final_known = true;  // nothing drops: m is the mean of the final set
             break;
         }
         int drop = 0;
@@ -260,21 +261,30 @@ __device__ __forceinline__ float clip_values(X x, int32_t N, double ksigma, int3
         n -= drop;
         dropped += (unsigned)drop;
     }
-    if (!final_known) {
-        s = 0.0;
-        clip_fence<FENCE>();
+    if (final_known) return (float)m;  // m = s / n of this final set
+    s = 0.0;
+    clip_fence<FENCE>();
 #pragma unroll
-        for (int i = 0; i < MAXV; ++i)
-            if (kept.get(i)) s = __dadd_rn(s, (double)x(i));
-    }
+    for (int i = 0; i < MAXV; ++i)
+        if (kept.get(i)) s = __dadd_rn(s, (double)x(i));
     return (float)(s / (double)n);
 }
 
+// The column in registers.  Each read goes through an empty asm statement that marks the
+// value as changed, so every pass converts it to double again instead of holding the
+// column's converted values across the passes (twice the registers; with them a compute
+// unit holds fewer waves and the kernel ran 10% slower).
 template <int MAXV, bool MISS = false>
 __device__ __forceinline__ float clip_registers(const float (&x)[MAXV], int32_t N, double ksigma, int32_t max_iters,
                                                 KeptBits<MAXV> &kept, unsigned &dropped)
 {
-    return clip_values<MAXV, false, MISS>([&](int i) { return x[i]; }, N, ksigma, max_iters, kept, dropped);
+    return clip_values<MAXV, false, MISS>(
+        [&](int i) {
+            float v = x[i];
+            asm volatile("" : "+v"(v));
+            return v;
+        },
+        N, ksigma, max_iters, kept, dropped);
 }
 
 // PX adjacent pixel columns per thread: each frame's PX values come in as one vector
@@ -392,6 +402,21 @@ __device__ __forceinline__ void deep_each(const float (&xr)[COMB_DEEP_REG], cons
     for (int i = 64; i < N; ++i, w >>= 1) f(i, (double)col[(i - COMB_DEEP_REG) * COMB_DEEP_PX], (w & 1ull) != 0);
 }
 
+// f(x_i) for every value of a column in frame order (all of them kept: the first
+// iteration without missing values).  The empty asm statements mark the register
+// values as changed, so each pass converts them to double again instead of holding 32
+// converted values (64 more registers) across the passes.
+template <typename F>
+__device__ __forceinline__ void deep_each_all(float (&xr)[COMB_DEEP_REG], const float *col, int32_t N, F f)
+{
+#pragma unroll
+    for (int i = 0; i < COMB_DEEP_REG; ++i) asm volatile("" : "+v"(xr[i]));
+#pragma unroll
+    for (int i = 0; i < COMB_DEEP_REG; ++i) f((double)xr[i]);
+#pragma unroll 4
+    for (int i = COMB_DEEP_REG; i < N; ++i) f((double)col[(i - COMB_DEEP_REG) * COMB_DEEP_PX]);
+}
+
 template <bool MISS>
 __device__ __forceinline__ unsigned combine_deep_block(const float *__restrict__ aligned, int64_t plane,
                                                        int64_t pstride, int32_t N, double ksigma, int32_t max_iters,
@@ -432,18 +457,36 @@ __device__ __forceinline__ unsigned combine_deep_block(const float *__restrict__
     unsigned dropped = 0;
     // the drop pass of one iteration also forms the next sum (the same values in the
     // same order as a separate pass over the kept set)
+    // before the first drop (and without missing values) every value is kept: the same
+    // sums without the flag selects
     double s = 0.0;
-    deep_each(xr, col, k0, k1, N, [&](int, double x, bool k) { s = k ? __dadd_rn(s, x) : s; });
+    if (MISS)
+        deep_each(xr, col, k0, k1, N, [&](int, double x, bool k) { s = k ? __dadd_rn(s, x) : s; });
+    else
+        deep_each_all(xr, col, N, [&](double x) { s = __dadd_rn(s, x); });
+    double mean = -1.0;
+    bool final_known = false;
     for (int32_t it = 0; it < max_iters; ++it) {
         const double m = s / (double)n;
         double q = 0.0, dmax = 0.0;
-        deep_each(xr, col, k0, k1, N, [&](int, double x, bool k) {
-            const double d = __dsub_rn(x, m);
-            q = k ? __dadd_rn(q, __dmul_rn(d, d)) : q;
-            dmax = k ? fmax(dmax, fabs(d)) : dmax;
-        });
+        if (!MISS && it == 0)
+            deep_each_all(xr, col, N, [&](double x) {
+                const double d = __dsub_rn(x, m);
+                q = __dadd_rn(q, __dmul_rn(d, d));
+                dmax = fmax(dmax, fabs(d));
+            });
+        else
+            deep_each(xr, col, k0, k1, N, [&](int, double x, bool k) {
+                const double d = __dsub_rn(x, m);
+                q = k ? __dadd_rn(q, __dmul_rn(d, d)) : q;
+                dmax = k ? fmax(dmax, fabs(d)) : dmax;
+            });
         const double thr = __dmul_rn(ksigma, sqrt(q / (double)n));
-        if (!(dmax > thr)) break;  // nothing drops: s is the sum over the final set
+        if (!(dmax > thr)) {  // nothing drops: m is the mean of the final set
+            mean = m;
+            final_known = true;
+            break;
+        }
         int drop = 0;
         s = 0.0;
         uint64_t n0 = 0, n1 = 0;  // the flags after this iteration
@@ -462,7 +505,7 @@ __device__ __forceinline__ unsigned combine_deep_block(const float *__restrict__
         dropped += (unsigned)drop;
     }
     if (p >= plane) return 0u;
-    out[p] = (float)(s / (double)n);
+    out[p] = (float)(final_known ? mean : s / (double)n);
     if (keep)
         for (int i = 0; i < N; ++i)
             keep[(int64_t)i * plane + p] = (uint8_t)((((i < 64 ? k0 : k1) >> (i & 63)) & 1ull) != 0);

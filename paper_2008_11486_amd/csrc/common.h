@@ -42,6 +42,19 @@ struct ProfScope {
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// ---- XCD-aware work order ----------------------------------------------------------------
+// Workgroups are dispatched round-robin over the 8 XCDs.  Give each XCD a
+// contiguous run of logical work items so that neighbouring items, which share input
+// rows (the search tiles of one frame band, the frames of one masked row), hit the
+// same L2.
+__device__ __forceinline__ int32_t xcd_logical_id(int32_t lin, int32_t total)
+{
+    constexpr int32_t NXCD = 8;
+    const int32_t per = total / NXCD, rem = total % NXCD;
+    const int32_t x = lin % NXCD, slot = lin / NXCD;
+    return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + slot;
+}
+
 // ---- per-element arithmetic ----------------------------------------------------
 
 // (raw - dark) / flat in float: the subtraction is exact whenever dark lies within a

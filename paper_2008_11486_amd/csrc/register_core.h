@@ -441,19 +441,6 @@ __device__ __forceinline__ void score_dispatch(int K, F &&f)
     }
 }
 
-// ---- XCD-aware work order ----------------------------------------------------------------
-// Workgroups are dispatched round-robin over the 8 XCDs.  Give each XCD a
-// contiguous run of logical work items (tile fastest, then candidate group, then
-// frame) so that neighbouring tiles, which share frame rows and columns, hit the
-// same L2.
-__device__ __forceinline__ int32_t xcd_logical_id(int32_t lin, int32_t total)
-{
-    constexpr int32_t NXCD = 8;
-    const int32_t per = total / NXCD, rem = total % NXCD;
-    const int32_t x = lin % NXCD, slot = lin / NXCD;
-    return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + slot;
-}
-
 // ---- sum of tile partials ------------------------------------------------------------------
 // Candidates 64*cblock .. +63 of one frame, by a workgroup of 64*SUM_WAVES threads: wave w
 // sums tiles w, w + SUM_WAVES, ... in order, then the SUM_WAVES partial sums are added in

@@ -58,7 +58,11 @@ __global__ __launch_bounds__(256) void mask_shifted_kernel(const uint8_t *__rest
                                                            int32_t x0, int32_t y0, int32_t w, int32_t h,
                                                            int32_t N, int integer)
 {
-    const int32_t k = blockIdx.x % N, xb = blockIdx.x / N, v = blockIdx.y;
+    // XCD-aware order: each XCD takes a contiguous run of rows, so a row of the map is
+    // fetched into one L2 rather than eight
+    const int32_t lid = xcd_logical_id((int32_t)(blockIdx.y * gridDim.x + blockIdx.x), (int32_t)(gridDim.x * gridDim.y));
+    const int32_t v = lid / (int32_t)gridDim.x, r = lid - v * (int32_t)gridDim.x;
+    const int32_t k = r % N, xb = r / N;
     const int32_t u0 = (xb * 256 + threadIdx.x) * MASK_PX;
     if (u0 >= w) return;
     const ShiftSetup ss = shift_setup(offs[2 * k], offs[2 * k + 1]);
@@ -92,7 +96,7 @@ extern "C" int reduce_shift(const float *in, float *out, int32_t W, int32_t H, i
     if (N > 65535 || h > 65535) return fail(REDUCE_ERR_UNSUPPORTED, "reduce_shift: N or h above 65535");
     const int vec_store = shift_vec_store(w, reinterpret_cast<uintptr_t>(out));
     const bool aligned = (W % 4 == 0) && ((reinterpret_cast<uintptr_t>(in) & 15u) == 0);
-    dim3 grid((unsigned)ceil_div(w, (int64_t)SH_BLOCK * SH_VEC), (unsigned)ceil_div(h, SH_ROWS), (unsigned)N);
+    const dim3 grid((unsigned)ceil_div(w, (int64_t)SH_BLOCK * SH_VEC), (unsigned)ceil_div(h, SH_ROWS), (unsigned)N);
     ProfScope prof("shift", as_stream(stream));
     hipStream_t s = as_stream(stream);
     if (integer_mode)

@@ -6,7 +6,7 @@
 
 namespace rd {
 
-constexpr int SH_BLOCK = 128;
+constexpr int SH_BLOCK = 256;
 constexpr int SH_VEC = 4;     // outputs per thread and row
 constexpr int SH_ROWS = 16;   // output rows per workgroup: each input row is fetched once per strip
 

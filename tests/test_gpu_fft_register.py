@@ -113,3 +113,11 @@ def test_fft_search_edges_and_unsettled_frames(rd, orc):
     assert (g["dx"][1], g["dy"][1]) == (R, -R) and (g["flags"][1] & 3) == 3
     assert info[2] != 0 and info[1] == 0, info
     _check(g, o, "edges and flat frame")
+
+
+def test_tune_search_times_both_searches(rd):
+    cal = _cal(rd, 5, 256, 256, 17, 7)
+    r = rd.tune_search(cal[0].contiguous(), cal[1:].contiguous(), 17, reps=2)
+    assert r["search"] in ("direct", "spectral")
+    assert 0 < r["ms_direct"] < 1e29 and 0 < r["ms_spectral"] < 1e29
+    assert r["search"] == ("spectral" if r["ms_spectral"] < r["ms_direct"] else "direct")

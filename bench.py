@@ -981,7 +981,8 @@ def main():
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms per step")
 
-    kern = {name: rd.prof_query(name) for name in ("score_tiles", "calibrate", "shift", "combine", "batch_score")}
+    kern = {name: rd.prof_query(name) for name in ("score_tiles", "calibrate", "shift", "combine", "batch_score",
+                                                   "batch_fused", "batch_comb", "batch_shift")}
     batched = args.path == "batched"
     rd.prof_enable(False)
 
@@ -999,6 +1000,9 @@ def main():
                 "kernel": kname, "avg_launch_ms": round(score_avg_s * 1e3, 4),
                 "launches_per_step": round(launches_per_step, 3), "flops_per_launch": flops,
                 "search_share_of_step": round(score_ms / args.steps / ms_per_step, 4)}
+    # the other timed phases of a batched step (HIP events, ms per step)
+    phases = {k: round(kern[k][0] / args.steps, 3) for k in ("batch_fused", "batch_comb", "batch_shift")
+              if batched and kern[k][1]}
 
     streaming = {}
     if not batched:
@@ -1015,7 +1019,7 @@ def main():
     frames = [sp.N for sp in specs]
     config = {"workload": WORKLOADS[args.workload], "stacks": len(specs), "frames_total": sum(frames),
               "input_pixels": pipe.pixels, "sizes": sorted({sp.W for sp in specs}), "path": args.path,
-              "pixel_storage": "uint16 in, f32 between stages, f32 out", "search": "FP32 products, FP64 sums",
+              "pixel_storage": "uint16 in, f32 between stages, f32 out", "search": "FP64 FMA of the float frame values and the FP64 mean-free reference",
               "search_plans": tuned if args.workload == 2 else rd.register_plan(specs[0].W, specs[0].H,
                                                                                specs[0].N - 1, specs[0].radius)}
     line = {
@@ -1026,6 +1030,8 @@ def main():
     }
     if streaming:
         line["streaming"] = streaming
+    if phases:
+        line["phases_ms_per_step"] = phases
     sample = None
     if args.workload == 2:
         if not args.no_cpu_baseline:

@@ -287,17 +287,59 @@ __device__ __forceinline__ float clip_registers(const float (&x)[MAXV], int32_t 
         N, ksigma, max_iters, kept, dropped);
 }
 
+// The first iteration of clip_registers alone: true, with the mean, when the column
+// settles there (nothing drops, or no iterations are asked for), the same operations in
+// the same order as clip_registers, so the mean has the same bits.
+template <int MAXV, bool MISS = false>
+__device__ __forceinline__ bool clip_first(const float (&x)[MAXV], int32_t N, double ksigma, int32_t max_iters,
+                                           float &mean)
+{
+    auto xv = [&](int i) {
+        float v = x[i];
+        asm volatile("" : "+v"(v));
+        return v;
+    };
+    KeptBits<MAXV> kept;
+    kept.first(N);
+    int n = N;
+    if (MISS) {
+#pragma unroll
+        for (int i = 0; i < MAXV; ++i)
+            if (i < N && !(x[i] == x[i])) kept.clear(i);
+        n = 0;
+#pragma unroll
+        for (int j = 0; j < KeptBits<MAXV>::W; ++j) n += __popcll(kept.w[j]);
+    }
+    double s, m, q, dmax;
+    if (MISS)
+        clip_pass<MAXV, false, false>(xv, kept, N, n, s, m, q, dmax);
+    else
+        clip_pass<MAXV, true, false>(xv, kept, N, n, s, m, q, dmax);
+    if (max_iters > 0 && dmax > __dmul_rn(ksigma, sqrt(q / (double)n))) return false;
+    mean = (float)m;
+    return true;
+}
+
 // PX adjacent pixel columns per thread: each frame's PX values come in as one vector
 // load (frame k's plane starts at aligned + k * pstride; pstride >= plane, and pstride
 // and the pointers aligned to PX floats; with PX = 4 an even pstride is enough, a frame
-// that starts 8-byte aligned taking two 8-byte loads), then the columns are clipped one after the
-// other.  Columns at or past `plane` are neither written nor counted.
+// that starts 8-byte aligned taking two 8-byte loads).  Each thread runs the first
+// iteration of its columns; a column that drops values there (a few percent of them, but
+// in most waves at least one lane) goes to a queue in LDS, and once the workgroup's first
+// iterations are done its threads take the queued columns one each, load their values
+// again and run the whole clip, so the later iterations run on full waves instead of
+// holding every wave that has one such lane.  Every result is that of clip_registers on
+// the column.  Columns at or past `plane` are neither written nor counted.  The whole
+// workgroup must call this (it synchronises).
 template <int MAXV, int PX, bool MISS = false>
 __device__ __forceinline__ unsigned combine_cols_block(const float *__restrict__ aligned, int64_t plane,
                                                        int64_t pstride, int32_t N, double ksigma, int32_t max_iters,
                                                        float *__restrict__ out, uint8_t *__restrict__ keep,
                                                        int64_t block)
 {
+    __shared__ int32_t queue[COMB_TILE * PX];  // columns (of this workgroup) that drop values
+    __shared__ int32_t queued;
+    if (threadIdx.x == 0) queued = 0;
     const int64_t p0 = (block * COMB_TILE + threadIdx.x) * PX;
     float xs[PX][MAXV];
     if (PX == 1 || p0 + PX <= plane) {
@@ -337,16 +379,17 @@ __device__ __forceinline__ unsigned combine_cols_block(const float *__restrict__
             for (int c = 0; c < PX; ++c)
                 xs[c][i] = (i < N && p0 + c < plane) ? aligned[(int64_t)i * pstride + p0 + c] : 0.0f;
     }
-    unsigned dropped = 0;
+    // first iterations; a column that drops values goes to the workgroup's queue
     float res[PX];
-    KeptBits<MAXV> kept[PX];
+    bool done[PX];
+    bool all = p0 + PX <= plane;
 #pragma unroll
     for (int c = 0; c < PX; ++c) {
-        unsigned d = 0;
-        res[c] = clip_registers<MAXV, MISS>(xs[c], N, ksigma, max_iters, kept[c], d);
-        if (p0 + c < plane) dropped += d;
+        done[c] = clip_first<MAXV, MISS>(xs[c], N, ksigma, max_iters, res[c]);
+        all = all && done[c];
     }
-    if (PX > 1 && p0 + PX <= plane) {
+    __syncthreads();  // the queue is empty
+    if (PX > 1 && all) {
         if (PX == 4)
             *reinterpret_cast<float4 *>(out + p0) = make_float4(res[0], res[1], res[2], res[3]);
         else
@@ -354,15 +397,36 @@ __device__ __forceinline__ unsigned combine_cols_block(const float *__restrict__
     } else {
 #pragma unroll
         for (int c = 0; c < PX; ++c)
-            if (p0 + c < plane) out[p0 + c] = res[c];
+            if (p0 + c < plane) {
+                if (done[c]) out[p0 + c] = res[c];
+                else queue[atomicAdd(&queued, 1)] = (int32_t)threadIdx.x * PX + c;
+            }
     }
-    if (keep) {
+    if (keep) {  // a settled column keeps every value (every value present)
 #pragma unroll
         for (int i = 0; i < MAXV; ++i)
             if (i < N)
 #pragma unroll
                 for (int c = 0; c < PX; ++c)
-                    if (p0 + c < plane) keep[(int64_t)i * plane + p0 + c] = (uint8_t)kept[c].get(i);
+                    if (p0 + c < plane && done[c])
+                        keep[(int64_t)i * plane + p0 + c] = (uint8_t)(!MISS || xs[c][i] == xs[c][i]);
+    }
+    __syncthreads();
+    // the queued columns, one per thread: the whole clip, values loaded again
+    unsigned dropped = 0;
+    const int32_t nq = queued;
+    for (int32_t e = threadIdx.x; e < nq; e += COMB_TILE) {
+        const int64_t p = block * COMB_TILE * PX + queue[e];
+        float x[MAXV];
+#pragma unroll
+        for (int i = 0; i < MAXV; ++i) x[i] = i < N ? aligned[(int64_t)i * pstride + p] : 0.0f;
+        KeptBits<MAXV> kept;
+        out[p] = clip_registers<MAXV, MISS>(x, N, ksigma, max_iters, kept, dropped);
+        if (keep) {
+#pragma unroll
+            for (int i = 0; i < MAXV; ++i)
+                if (i < N) keep[(int64_t)i * plane + p] = (uint8_t)kept.get(i);
+        }
     }
     return dropped;
 }

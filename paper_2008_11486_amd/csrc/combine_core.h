@@ -326,18 +326,24 @@ __device__ __forceinline__ bool clip_first(const float (&x)[MAXV], int32_t N, do
 // that starts 8-byte aligned taking two 8-byte loads).  Each thread runs the first
 // iteration of its columns; a column that drops values there (a few percent of them, but
 // in most waves at least one lane) goes to a queue in LDS, and once the workgroup's first
-// iterations are done its threads take the queued columns one each, load their values
-// again and run the whole clip, so the later iterations run on full waves instead of
-// holding every wave that has one such lane.  Every result is that of clip_registers on
-// the column.  Columns at or past `plane` are neither written nor counted.  The whole
-// workgroup must call this (it synchronises).
+// iterations are done its threads take the queued columns one each (their values kept in
+// LDS for columns of up to 32 values and the first 128 queued, else loaded again) and run
+// the whole clip, so the later iterations run on full waves instead of holding every wave
+// that has one such lane.
+// Every result is that of clip_registers on the column.  Columns at or past `plane` are
+// neither written nor counted.  The whole workgroup must call this (it synchronises).
 template <int MAXV, int PX, bool MISS = false>
 __device__ __forceinline__ unsigned combine_cols_block(const float *__restrict__ aligned, int64_t plane,
                                                        int64_t pstride, int32_t N, double ksigma, int32_t max_iters,
                                                        float *__restrict__ out, uint8_t *__restrict__ keep,
                                                        int64_t block)
 {
-    __shared__ int32_t queue[COMB_TILE * PX];  // columns (of this workgroup) that drop values
+    // queued columns whose values wait in LDS (later ones are loaded again); none for the
+    // 48-value columns, whose values held until the queue is written cost more registers
+    // than the loads (45 frames of 4096x2048: 0.71 ms loading, 2.05 ms holding them)
+    constexpr int QCAP = MAXV <= 32 ? 128 : 0;
+    __shared__ int32_t queue[COMB_TILE * PX];         // columns (of this workgroup) that drop values
+    __shared__ float qv[MAXV * (QCAP > 0 ? QCAP : 1)];  // value i of queue entry e at qv[i * QCAP + e]
     __shared__ int32_t queued;
     if (threadIdx.x == 0) queued = 0;
     const int64_t p0 = (block * COMB_TILE + threadIdx.x) * PX;
@@ -398,8 +404,16 @@ __device__ __forceinline__ unsigned combine_cols_block(const float *__restrict__
 #pragma unroll
         for (int c = 0; c < PX; ++c)
             if (p0 + c < plane) {
-                if (done[c]) out[p0 + c] = res[c];
-                else queue[atomicAdd(&queued, 1)] = (int32_t)threadIdx.x * PX + c;
+                if (done[c]) {
+                    out[p0 + c] = res[c];
+                } else {
+                    const int32_t e = atomicAdd(&queued, 1);
+                    queue[e] = (int32_t)threadIdx.x * PX + c;
+                    if (e < QCAP) {
+#pragma unroll
+                        for (int i = 0; i < MAXV; ++i) qv[i * QCAP + e] = xs[c][i];
+                    }
+                }
             }
     }
     if (keep) {  // a settled column keeps every value (every value present)
@@ -412,14 +426,20 @@ __device__ __forceinline__ unsigned combine_cols_block(const float *__restrict__
                         keep[(int64_t)i * plane + p0 + c] = (uint8_t)(!MISS || xs[c][i] == xs[c][i]);
     }
     __syncthreads();
-    // the queued columns, one per thread: the whole clip, values loaded again
+    // the queued columns, one per thread: the whole clip (values from LDS, past QCAP
+    // entries loaded again)
     unsigned dropped = 0;
     const int32_t nq = queued;
     for (int32_t e = threadIdx.x; e < nq; e += COMB_TILE) {
         const int64_t p = block * COMB_TILE * PX + queue[e];
         float x[MAXV];
+        if (e < QCAP) {
 #pragma unroll
-        for (int i = 0; i < MAXV; ++i) x[i] = i < N ? aligned[(int64_t)i * pstride + p] : 0.0f;
+            for (int i = 0; i < MAXV; ++i) x[i] = qv[i * QCAP + e];
+        } else {
+#pragma unroll
+            for (int i = 0; i < MAXV; ++i) x[i] = i < N ? aligned[(int64_t)i * pstride + p] : 0.0f;
+        }
         KeptBits<MAXV> kept;
         out[p] = clip_registers<MAXV, MISS>(x, N, ksigma, max_iters, kept, dropped);
         if (keep) {

@@ -282,7 +282,8 @@ void reg_shape_candidates(int32_t W, int32_t H, int32_t R, int32_t Rmax, RegShap
             RegShape v = b;
             v.CPT = b.CPT * m;
             RegPlan p;
-            if (reg_plan_from_shape(W, H, R, Rmax, v, &p) && p.BR > b.CPT * b.TY) out[n++] = v;
+            if (reg_plan_from_shape(W, H, R, Rmax, v, &p) && p.BR > b.CPT * b.TY && p.BR <= kTileRowsMax)
+                out[n++] = v;
         }
         if (b.CPT > 1 && n < max_count) {
             RegShape v = b;

@@ -33,6 +33,16 @@ struct RegPlan {
 // columns, one per workgroup of 256 threads, frame rows staged in 15-row chunks.
 bool reg_plan_small(int32_t W, int32_t H, int32_t R, int32_t Rmax, RegPlan *out);
 
+// Tallest tile made when other chunk counts are tried for a shape (template rows).  The
+// cost model's own chunk count may give taller tiles (for wide windows it sizes tiles so
+// that a frame has about 2048 workgroups, and their frame halo is shared by the chunks);
+// the variants stop here because taller tiles, which stage the frame rows that
+// consecutive chunks share once, lose in long batched launches what they gain in a call
+// of one size: tiles of 196 rows for the 2048x2048 frames of a 64-stack batch (radius 17)
+// ran its search 13% slower than tiles of 98 or 147 rows, which timed the same in the
+// stage-wise calls.
+constexpr int32_t kTileRowsMax = 150;
+
 // Per-workgroup shape of a plan; everything else follows from it and the sizes.
 struct RegShape {
     int32_t K, G, S, TY;

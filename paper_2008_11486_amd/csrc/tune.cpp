@@ -14,10 +14,6 @@
 
 namespace rd {
 
-// Tallest search tile the tuner tries (template rows; the reason is given where the
-// contenders are chosen).
-constexpr int32_t kTileRowsMax = 150;
-
 int register_launch(const float *ref, const float *frames, int32_t W, int32_t H, int32_t N, int32_t R,
                     int32_t Rmax, const int32_t *centers, int32_t tx0, int32_t ty0, int32_t tw, int32_t th,
                     reduce_offset_t *out, double *scores, void *ws, const RegPlan &p, hipStream_t s);
@@ -133,11 +129,9 @@ extern "C" int reduce_tune_register(const float *ref, const float *frames, int32
                          p.S, p.TY, p.BR, p.threads, p.n_tiles, *ms);
         return r;
     };
-    // first round: every candidate once (tiles of at most kTileRowsMax rows, see below)
+    // first round: every candidate once
     std::vector<std::pair<double, RegShape>> timed;
     for (int i = 0; i < n && rc == REDUCE_OK; ++i) {
-        RegPlan pc;
-        if (!reg_plan_from_shape(W, H, radius, radius_max, cand[i], &pc) || pc.BR > kTileRowsMax) continue;
         double ms = 0.0;
         rc = time_shape(cand[i], &ms);
         if (ms < 1e30) timed.push_back({ms, cand[i]});
@@ -149,11 +143,7 @@ extern "C" int reduce_tune_register(const float *ref, const float *frames, int32
                          return x.first < y.first;
                      });
     // contenders: the three fastest, and the fastest with other tile heights (up to four
-    // chunks and kTileRowsMax rows: taller tiles stage the frame rows shared by
-    // consecutive chunks once, but lose in long batched launches what they gain in a call
-    // of one size: tiles of 196 rows for the 2048x2048 frames of a 64-stack batch ran its
-    // search 13% slower than tiles of 98 or 147 rows, which timed the same in the
-    // stage-wise calls)
+    // chunks and kTileRowsMax rows)
     std::vector<RegShape> cont;
     for (size_t i = 0; i < timed.size() && cont.size() < 3; ++i) cont.push_back(timed[i].second);
     const RegShape top = timed[0].second;

@@ -367,3 +367,52 @@ def test_tuned_shapes_keep_results(rd, orc, tmp_path):
     lanes = rd.tune_combine(cal[:, :64, :64].contiguous(), reps=1)
     assert lanes in (1, 2, 4, 8, 16)
     rd.tune_clear()
+
+
+def test_tuner_finds_shapes_for_wide_windows(rd):
+    """The +-65 px search of 6144x6160 frames: the cost model's own tiles are taller than
+    the cap on the tuner's tile-height variants, and the tuner must still find a shape
+    (a cap on every candidate once left none)."""
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(4)
+    fr = 1000.0 + 30.0 * torch.randn((3, 6160, 6144), generator=g, device=dev)
+    rd.tune_clear()
+    plan = rd.tune_register(fr[0].contiguous(), fr[1:].contiguous(), 65, reps=1)
+    print("tuned plan for 6144x6160, R = 65:", plan)
+    assert plan == rd.register_plan(6144, 6160, 2, 65)
+    rd.tune_clear()
+    for W, H, R in ((2048, 2048, 17), (4096, 4096, 17)):
+        # the chunk-count variants stay within the cap: radius 17 tiles of at most 150 rows
+        fr = 1000.0 + 30.0 * torch.randn((3, H, W), generator=g, device=dev)
+        plan = rd.tune_register(fr[0].contiguous(), fr[1:].contiguous(), R, reps=1)
+        print(f"tuned plan for {W}x{H}, R = {R}:", plan)
+        assert plan["BR"] <= 150 or plan["BR"] == plan["TY"]
+        rd.tune_clear()
+
+
+@pytest.mark.parametrize("N", [12, 16, 30, 45])
+@pytest.mark.parametrize("missing", [False, True])
+def test_combine_every_column_drops(rd, orc, N, missing):
+    """Every column holds an outlier, so every column leaves the first iteration for the
+    workgroup's queue: more queued columns than the queue keeps in LDS (the rest are
+    loaded again), on planes with a ragged last workgroup."""
+    rng = np.random.default_rng(9100 + N)
+    h, w = 13, 389
+    vals = rng.normal(1000, 30, size=(N, h, w)).astype(np.float32)
+    k = rng.integers(0, N, size=(h, w))
+    np.put_along_axis(vals, k[None], 1.0e5, axis=0)
+    if missing:
+        vals[rng.random(size=vals.shape) < 0.1] = np.nan
+    out, keep, nrej = rd.combine(to_dev(vals), want_keep=True, want_nrej=True, missing=missing)
+    out, keep, nrej = out.cpu().numpy(), keep.cpu().numpy(), int(nrej.cpu().numpy()[0])
+    o_out, o_keep, o_nrej, near = orc.combine(vals.astype(np.float64), 3.0, 3, missing=missing)
+    flips = keep != o_keep
+    assert np.all(~flips | (near == 1))
+    good = ~flips.any(axis=0) & ~np.isnan(o_out)
+    assert np.array_equal(np.isnan(out), np.isnan(o_out))
+    e = rel_err(out[good], o_out[good])
+    print(f"combine every column drops, N={N}, missing={missing}: rejected {o_nrej}, {err_summary(e)}")
+    assert e.max() <= TOL
+    if not flips.any():
+        assert nrej == o_nrej

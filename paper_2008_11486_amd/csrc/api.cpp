@@ -58,13 +58,19 @@ void prof_record(const char *name, hipStream_t s, bool start)
     std::lock_guard<std::mutex> lk(g_prof_mu);
     if (start) {
         ProfRec r{name, take_event(), nullptr};
-        if (r.start) hipEventRecord(r.start, s);
+        if (r.start && hipEventRecord(r.start, s) != hipSuccess) {  // a record that failed is not timed
+            g_event_pool.push_back(r.start);
+            r.start = nullptr;
+        }
         g_prof.push_back(r);
     } else {
         for (auto it = g_prof.rbegin(); it != g_prof.rend(); ++it)
             if (it->stop == nullptr && it->name == name) {
                 it->stop = take_event();
-                if (it->stop) hipEventRecord(it->stop, s);
+                if (it->stop && hipEventRecord(it->stop, s) != hipSuccess) {
+                    g_event_pool.push_back(it->stop);
+                    it->stop = nullptr;
+                }
                 break;
             }
     }

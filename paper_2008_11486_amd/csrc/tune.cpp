@@ -41,20 +41,20 @@ static int time_ms(hipStream_t s, int reps, F fn, double *ms)
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return fail(REDUCE_ERR_HIP, "autotune: event");
     if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         return fail(REDUCE_ERR_HIP, "autotune: event");
     }
     int rc = fn();
     if (rc == REDUCE_OK) {
-        hipEventRecord(e0, s);
+        if (hipEventRecord(e0, s) != hipSuccess) rc = fail(REDUCE_ERR_HIP, "autotune: event record");
         for (int i = 0; i < reps && rc == REDUCE_OK; ++i) rc = fn();
-        hipEventRecord(e1, s);
-        if (hipEventSynchronize(e1) != hipSuccess) rc = fail(REDUCE_ERR_HIP, "autotune: synchronize");
+        if (rc == REDUCE_OK && hipEventRecord(e1, s) != hipSuccess) rc = fail(REDUCE_ERR_HIP, "autotune: event record");
+        if (rc == REDUCE_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(REDUCE_ERR_HIP, "autotune: synchronize");
     }
     float t = 0.0f;
     if (rc == REDUCE_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = fail(REDUCE_ERR_HIP, "autotune: time");
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     *ms = (double)t / reps;
     return rc;
 }

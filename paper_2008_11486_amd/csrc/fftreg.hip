@@ -96,13 +96,26 @@ __global__ __launch_bounds__(FFT_THREADS) void fft_rows(RowSrc src, int32_t rows
     const double sub = src.sub ? *src.sub : 0.0;
     const float *row = src.base + (int64_t)b * src.batch + (int64_t)(data ? r : 0) * src.pitch;
 
-    // packed load and the row's sum of squares
+    // packed load and the row's sum of squares: the thread's NPT value pairs are loaded
+    // together (addresses clamped into the row, values past it replaced by zero), then
+    // converted and summed in the order of n
+    constexpr int NPT = N2 / tpr;
+    float f0[NPT], f1[NPT];
+    if (data) {
+        const int32_t last = src.ncols - 1;
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const int32_t u = 2 * (lt + i * tpr);
+            f0[i] = row[min(u, last)];
+            f1[i] = row[min(u + 1, last)];
+        }
+    }
     double sq = 0.0;
-    for (int32_t n = lt; n < N2; n += tpr) {
-        const int32_t u = 2 * n;
-        double x0 = 0.0, x1 = 0.0;
-        if (data && u < src.ncols) x0 = (double)row[u] - sub;
-        if (data && u + 1 < src.ncols) x1 = (double)row[u + 1] - sub;
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+        const int32_t n = lt + i * tpr, u = 2 * n;
+        const double x0 = (data && u < src.ncols) ? (double)f0[i] - sub : 0.0;
+        const double x1 = (data && u + 1 < src.ncols) ? (double)f1[i] - sub : 0.0;
         sq = fma(x0, x0, sq);
         sq = fma(x1, x1, sq);
         z[n] = make_double2(x0, x1);

@@ -302,8 +302,17 @@ __global__ __launch_bounds__(FFT_THREADS) void spec_eval(const double2 *__restri
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const double2 *z0 = Zp + (int64_t)f * n_part * D * PS + (int64_t)j * PS;
     for (int32_t k = t; k <= N2; k += FFT_THREADS) {
+        // the partials added in order p = 0, 1, ...; eight loaded together at a time (a
+        // partial index past the last is clamped and its value not added)
         double2 s = make_double2(0.0, 0.0);
-        for (int32_t p = 0; p < n_part; ++p) s = cadd(s, z0[(int64_t)p * D * PS + k]);
+        for (int32_t p0 = 0; p0 < n_part; p0 += 8) {
+            double2 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = z0[(int64_t)min(p0 + u, n_part - 1) * D * PS + k];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (p0 + u < n_part) s = cadd(s, v[u]);
+        }
         const double c = (k == 0 || k == N2) ? 1.0 : 2.0;
         zs[k] = make_double2(c * s.x, c * s.y);
     }
@@ -315,11 +324,14 @@ __global__ __launch_bounds__(FFT_THREADS) void spec_eval(const double2 *__restri
 #pragma unroll 1
         for (int32_t k = t; k <= N2; k += FFT_THREADS) {
             const double2 z = zs[k];
+            // the EVAL_M twiddles e^{-2 pi i k m / P} loaded together, then used
+            double2 w[EVAL_M];
+#pragma unroll
+            for (int q = 0; q < EVAL_M; ++q) w[q] = tw[((int64_t)k * (m0 + q)) & (P - 1)];
 #pragma unroll
             for (int q = 0; q < EVAL_M; ++q) {
-                const double2 w = tw[((int64_t)k * (m0 + q)) & (P - 1)];  // e^{-2 pi i k m / P}
-                acc[q] = fma(z.x, w.x, acc[q]);                          // Re(z conj(w))
-                acc[q] = fma(z.y, w.y, acc[q]);
+                acc[q] = fma(z.x, w[q].x, acc[q]);  // Re(z conj(w))
+                acc[q] = fma(z.y, w[q].y, acc[q]);
             }
         }
 #pragma unroll

@@ -218,7 +218,7 @@ struct CorrArgs {
 };
 
 template <int DY>
-__global__ __launch_bounds__(512) void spec_corr(CorrArgs a)
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 3))) void spec_corr(CorrArgs a)
 {
     extern __shared__ __align__(16) double2 al[];  // [YC + NBG * DY - 1][CORR_KW]
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -242,10 +242,20 @@ __global__ __launch_bounds__(512) void spec_corr(CorrArgs a)
     const int32_t y_lo = band * a.BY, y_hi = y_lo + a.BY;
     for (int32_t y0 = y_lo; y0 < y_hi; y0 += YC) {
         __syncthreads();
-        // frame rows y0 + jg0 .. + rows - 1, columns kb * 64 ..
-        for (int e = t; e < rows * CORR_KW; e += nthr) {
-            const int rr = e / CORR_KW, cc = e - rr * CORR_KW;
-            al[e] = A[(int64_t)(y0 + jg0 + rr) * a.PS + kb * CORR_KW + cc];
+        // frame rows y0 + jg0 .. + rows - 1, columns kb * 64 ..: wave w stages rows w, w + nw,
+        // ... (lane = column), eight rows loaded together, then stored; a row index past the
+        // last is clamped to it on both sides (the same value stored to the same place again),
+        // so no load waits behind a branch
+        {
+            const int wv = t >> 6, nw = nthr >> 6;
+            const double2 *src = A + (int64_t)(y0 + jg0) * a.PS + kb * CORR_KW + lane;
+            for (int r0 = wv; r0 < rows; r0 += 8 * nw) {
+                double2 v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = src[(int64_t)min(r0 + u * nw, rows - 1) * a.PS];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) al[min(r0 + u * nw, rows - 1) * CORR_KW + lane] = v[u];
+            }
         }
         __syncthreads();
         if (act) {
@@ -257,11 +267,14 @@ __global__ __launch_bounds__(512) void spec_corr(CorrArgs a)
             for (int i = 0; i < DY - 1; ++i) win[i] = base[i * CORR_KW];
             const double2 *bp = a.B + (int64_t)ys * a.PS + k;
             for (int32_t q0 = 0; q0 < a.YS; q0 += DY) {
+                double2 bq[DY];  // the block's template values, loaded together
+#pragma unroll
+                for (int q = 0; q < DY; ++q) bq[q] = bp[(int64_t)(q0 + q) * a.PS];
 #pragma unroll
                 for (int q = 0; q < DY; ++q) {
                     // row ys + q0 + q: the window holds lags 0 .. DY-1 in slots (q + i) mod DY
                     win[(q + DY - 1) % DY] = base[(q0 + q + DY - 1) * CORR_KW];
-                    const double2 bv = bp[(int64_t)(q0 + q) * a.PS];
+                    const double2 bv = bq[q];
 #pragma unroll
                     for (int i = 0; i < DY; ++i) {
                         const double2 av = win[(q + i) % DY];

@@ -110,6 +110,24 @@ __global__ __launch_bounds__(FFT_THREADS) void fft_rows(RowSrc src, int32_t rows
             f1[i] = row[min(u + 1, last)];
         }
     }
+    // twiddles of a radix-4 pass (see below): w[c][q - 1] = w_{4L}^{q k}, k = j mod L of the
+    // thread's butterfly c.  Each pass's are loaded one pass ahead (the first pass's with
+    // the row), so no pass waits on them.
+    constexpr int32_t m4 = N2 >> 2;
+    constexpr int NB4 = m4 / tpr;                   // radix-4 butterflies per thread
+    constexpr int NP4 = LOG2N2 / 2;                 // radix-4 passes
+    constexpr int32_t L0 = (LOG2N2 & 1) ? 2 : 1;    // L of the first of them
+    static_assert(NP4 >= 1 && NB4 >= 1, "rows of at least 64 values");
+    auto tw_pass = [&](int32_t Lp, double2(&w)[NB4][3]) {
+#pragma unroll
+        for (int c = 0; c < NB4; ++c) {
+            const int32_t step = (P / 4 / Lp) * ((lt + c * tpr) & (Lp - 1));  // w_{4L}^k = tw[k P / (4L)]
+#pragma unroll
+            for (int q = 1; q < 4; ++q) w[c][q - 1] = tw[q * step];
+        }
+    };
+    double2 wn[NB4][3];
+    tw_pass(L0, wn);
     double sq = 0.0;
 #pragma unroll
     for (int i = 0; i < NPT; ++i) {
@@ -136,7 +154,6 @@ __global__ __launch_bounds__(FFT_THREADS) void fft_rows(RowSrc src, int32_t rows
     // Stockham passes: L = product of the radices done so far; butterfly j reads
     // z[j + q m] (m = N2 / radix), twiddles input q by w_{L radix}^{q (j mod L)}, and writes
     // output q at (j / L) L radix + (j mod L) + q L.  Twiddle w_M^e = tw[e P / M].
-    int32_t L = 1;
     if (LOG2N2 & 1) {  // radix 2
         constexpr int32_t m = N2 >> 1;
         constexpr int NB2 = m / tpr;  // butterflies per thread
@@ -155,20 +172,32 @@ __global__ __launch_bounds__(FFT_THREADS) void fft_rows(RowSrc src, int32_t rows
             z[2 * j + 1] = csub(v[c][0], v[c][1]);
         }
         __syncthreads();
-        L = 2;
     }
-    constexpr int32_t m4 = N2 >> 2;
-    constexpr int NB4 = m4 / tpr;  // radix-4 butterflies per thread
-    for (; L < N2; L *= 4) {
+    // the unpacking twiddles tw[k], k = lt, lt + tpr, ... <= N2, are loaded with the last
+    // pass's LDS reads
+    constexpr int NK = N2 / tpr + 1;
+    double2 wk[NK];
+#pragma unroll
+    for (int p = 0; p < NP4; ++p) {
+        const int32_t L = L0 << (2 * p);
+        double2 w[NB4][3];
+#pragma unroll
+        for (int c = 0; c < NB4; ++c)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) w[c][q] = wn[c][q];
+        if (p + 1 < NP4) {
+            tw_pass(4 * L, wn);
+        } else {
+#pragma unroll
+            for (int i = 0; i < NK; ++i) wk[i] = tw[min(lt + i * tpr, N2)];
+        }
         double2 v[NB4][4];
 #pragma unroll
         for (int c = 0; c < NB4; ++c) {
             const int32_t j = lt + c * tpr;
-            const int32_t k = j & (L - 1);
-            const int32_t step = (P / 4 / L) * k;  // w_{4L}^k = tw[k P / (4L)]
             v[c][0] = z[j];
 #pragma unroll
-            for (int q = 1; q < 4; ++q) v[c][q] = cmul(z[j + q * m4], tw[q * step]);
+            for (int q = 1; q < 4; ++q) v[c][q] = cmul(z[j + q * m4], w[c][q - 1]);
         }
         __syncthreads();
 #pragma unroll
@@ -189,13 +218,15 @@ __global__ __launch_bounds__(FFT_THREADS) void fft_rows(RowSrc src, int32_t rows
     // unpack the two real transforms into the half spectrum of the row
     if (live) {
         double2 *out = spec + (int64_t)b * spec_batch + (int64_t)r * PS;
-        for (int32_t k = lt; k <= N2; k += tpr) {
+#pragma unroll
+        for (int i = 0; i < NK; ++i) {
+            const int32_t k = lt + i * tpr;
+            if (k > N2) break;
             const double2 zk = z[k & (N2 - 1)];
             const double2 zc = z[(N2 - k) & (N2 - 1)];
             const double2 e = make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y - zc.y));
             const double2 o = make_double2(0.5 * (zk.x - zc.x), 0.5 * (zk.y + zc.y));
-            const double2 w = tw[k];  // k <= N2 < P
-            const double2 wo = cmul(w, o);
+            const double2 wo = cmul(wk[i], o);  // wk[i] = tw[k], k <= N2 < P
             out[k] = make_double2(e.x + wo.y, e.y - wo.x);  // E - i w O
         }
     }

@@ -131,7 +131,7 @@ int reduce_register(const float *ref, const float *frames, int32_t W, int32_t H,
  * offsets then come from exact direct sums: a +-1 window around the spectral argmax
  * (moved while its maximum lies on an inner border) is kept when its exact peak
  * exceeds every spectral score outside it by more than a bound on the spectral
- * rounding error, 4 eps (10 log2(P/2) + th + P + 18) ||frame rows|| ||template rows||
+ * rounding error, 4 eps (10 log2(P/2) + th + P + 50) ||frame rows|| ||template rows||
  * (eps = 2^-53, Frobenius norms), else the frame takes the full direct search.  So
  * dx, dy, sx, sy, peak and the EDGE and NEAR_TIE flags are those of reduce_register up
  * to the summation order of its direct sums; `second` may be a spectral score (within

@@ -331,7 +331,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 3))) voi
 // S[f][j][m] = (1/P) sum_{k=0}^{N2} c_k Re(Z_j(k) e^{+2 pi i k m / P}), c_k = 1 at k = 0 and
 // k = N2, else 2; Z_j(k) the sum of the partials over bands and sub-ranges in order.  One
 // workgroup per (lag j, frame f); lanes stride over k; the D sums over m are reduced
-// over the workgroup in a fixed order.
+// over the workgroup in a fixed order.  The twiddles of a pass over m0 .. m0 + EVAL_M - 1
+// come from one table value and a recurrence, w(k, m + 1) = w(k, m) w(k, 1): scattered
+// reads of the table for every (k, m) had bound the kernel by cache traffic.  A step adds
+// at most sqrt(5) eps (the product) + 2 eps (the table value w(k, 1)) of relative error, so
+// a twiddle is within 5 EVAL_M eps; the error bound of the decision below carries a term
+// of 8 EVAL_M eps for it.
 constexpr int EVAL_M = 16;  // lags m formed per pass
 
 template <int LOG2N2>
@@ -368,14 +373,14 @@ __global__ __launch_bounds__(FFT_THREADS) void spec_eval(const double2 *__restri
 #pragma unroll 1
         for (int32_t k = t; k <= N2; k += FFT_THREADS) {
             const double2 z = zs[k];
-            // the EVAL_M twiddles e^{-2 pi i k m / P} loaded together, then used
-            double2 w[EVAL_M];
-#pragma unroll
-            for (int q = 0; q < EVAL_M; ++q) w[q] = tw[((int64_t)k * (m0 + q)) & (P - 1)];
+            // w = e^{-2 pi i k m / P}, m = m0 .. m0 + EVAL_M - 1
+            double2 w = tw[((int64_t)k * m0) & (P - 1)];
+            const double2 w1 = tw[k & (P - 1)];
 #pragma unroll
             for (int q = 0; q < EVAL_M; ++q) {
-                acc[q] = fma(z.x, w[q].x, acc[q]);  // Re(z conj(w))
-                acc[q] = fma(z.y, w[q].y, acc[q]);
+                acc[q] = fma(z.x, w.x, acc[q]);  // Re(z conj(w))
+                acc[q] = fma(z.y, w.y, acc[q]);
+                if (q + 1 < EVAL_M) w = cmul(w, w1);
             }
         }
 #pragma unroll
@@ -432,9 +437,9 @@ __global__ void spec_walk(const reduce_offset_t *__restrict__ offs, int32_t N, i
 // Decision per frame, one workgroup each.  Kept: the exact maximum is not on an inner
 // border, and it exceeds the best spectral score outside its +-1 window by more than the
 // bound on the spectral error
-//   bound = factor ||a||_F ||b||_F,  factor = 4 eps (10 log2(P/2) + th + P + 18),
+//   bound = factor ||a||_F ||b||_F,  factor = 4 eps (10 log2(P/2) + th + P + 18 + 2 EVAL_M),
 // (eps = 2^-53; ||a||_F over the frame rows, ||b||_F over the template rows; first-order
-// rounding of the row transforms, the contraction and the inverse sums).  A kept frame
+// rounding of the row transforms, the contraction, the inverse sums and their twiddles).  A kept frame
 // gets second = the larger of its window's runner-up and that spectral score, the margin
 // and NEAR_TIE from it, and loses CLIPPED (its window is a step of the full search).
 // fb[k] = 1 for the frames that take the full search; info[k] says why (1: inner border,
@@ -771,7 +776,7 @@ extern "C" int reduce_register_fft(const float *ref, const float *frames, int32_
                             out, s);
         }
         const double eps = 1.1102230246251565e-16;  // 2^-53
-        const double factor = 4.0 * eps * (10.0 * L.log2n2 + (double)th + (double)L.P + 18.0);
+        const double factor = 4.0 * eps * (10.0 * L.log2n2 + (double)th + (double)L.P + 18.0 + 2.0 * EVAL_M);
         int32_t *fb = static_cast<int32_t *>(at(L.fb));
         hipLaunchKernelGGL(spec_settle, dim3((unsigned)N), dim3(256), 0, s, out, Sf, D, R, rowsq_a, L.rows_a, rowsq_b,
                            L.th_pad, factor, fb, inf);

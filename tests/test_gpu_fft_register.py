@@ -35,7 +35,8 @@ def _cal(rd, N, W, H, R, seed, stars=None, bound=None):
 
 
 def spectral_bound(cal64, R):
-    """4 eps (10 log2(P/2) + th + P + 18) ||frame rows|| ||template rows||, per frame."""
+    """4 eps (10 log2(P/2) + th + P + 18 + 32) ||frame rows|| ||template rows||, per frame
+    (the last term: the inverse's twiddles, formed by a recurrence over 16 lags)."""
     N, H, W = cal64.shape
     P = 64
     while P < W:
@@ -44,7 +45,7 @@ def spectral_bound(cal64, R):
     t = cal64[0, R:H - R, R:W - R]
     nb = np.linalg.norm(t - t.mean())
     na = np.linalg.norm(cal64.reshape(N, -1), axis=1)
-    return 4 * 2.0 ** -53 * (10 * math.log2(P // 2) + th + P + 18) * na * nb
+    return 4 * 2.0 ** -53 * (10 * math.log2(P // 2) + th + P + 18 + 32) * na * nb
 
 
 def _check(g, o, label, peak_rtol=1e-10):

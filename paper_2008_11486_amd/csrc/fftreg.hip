@@ -270,32 +270,48 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 3))) voi
 #pragma unroll
     for (int i = 0; i < DY; ++i) acc[i] = make_double2(0.0, 0.0);
 
+    // The staged frame rows are a ring of `rows` LDS rows: frame row y_lo + jg0 + r of the
+    // band sits in LDS row r mod rows.  Chunk y0 needs rows (y0 - y_lo) + [0, rows); from
+    // the second chunk on only the YC rows it adds are staged, into the LDS rows of the YC
+    // rows the previous chunk alone needed.
     const int32_t y_lo = band * a.BY, y_hi = y_lo + a.BY;
+    int32_t ring0 = 0;  // LDS row of the chunk's first frame row
     for (int32_t y0 = y_lo; y0 < y_hi; y0 += YC) {
         __syncthreads();
-        // frame rows y0 + jg0 .. + rows - 1, columns kb * 64 ..: wave w stages rows w, w + nw,
-        // ... (lane = column), eight rows loaded together, then stored; a row index past the
-        // last is clamped to it on both sides (the same value stored to the same place again),
-        // so no load waits behind a branch
+        // frame rows y0 + jg0 + [r_lo, rows), columns kb * 64 ..: wave w stages rows
+        // r_lo + w, r_lo + w + nw, ... (lane = column), eight rows loaded together, then
+        // stored; a row index past the last is clamped to it on both sides (the same value
+        // stored to the same place again), so no load waits behind a branch
         {
             const int wv = t >> 6, nw = nthr >> 6;
+            const int32_t r_lo = y0 == y_lo ? 0 : rows - YC;
             const double2 *src = A + (int64_t)(y0 + jg0) * a.PS + kb * CORR_KW + lane;
-            for (int r0 = wv; r0 < rows; r0 += 8 * nw) {
+            for (int r0 = r_lo + wv; r0 < rows; r0 += 8 * nw) {
                 double2 v[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) v[u] = src[(int64_t)min(r0 + u * nw, rows - 1) * a.PS];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) al[min(r0 + u * nw, rows - 1) * CORR_KW + lane] = v[u];
+                for (int u = 0; u < 8; ++u) {
+                    int32_t lr = ring0 + min(r0 + u * nw, rows - 1);
+                    if (lr >= rows) lr -= rows;
+                    al[lr * CORR_KW + lane] = v[u];
+                }
             }
         }
         __syncthreads();
         if (act) {
             const int32_t ys = y0 + s * a.YS;  // first template row of this sub-range
-            // window: LDS row of lag i at template row y is (y - y0) + (j0 - jg0) + i
-            const double2 *base = al + ((ys - y0) + (j0 - jg0)) * CORR_KW + lane;
+            // window: chunk row of lag i at template row y is (y - y0) + (j0 - jg0) + i, in
+            // LDS row ring0 + that, wrapped
+            const int32_t c0 = ring0 + (ys - y0) + (j0 - jg0);
+            auto at = [&](int32_t cr) {  // cr = chunk row - (ys - y0) - (j0 - jg0) < rows
+                int32_t lr = c0 + cr;
+                if (lr >= rows) lr -= rows;
+                return al[lr * CORR_KW + lane];
+            };
             double2 win[DY];
 #pragma unroll
-            for (int i = 0; i < DY - 1; ++i) win[i] = base[i * CORR_KW];
+            for (int i = 0; i < DY - 1; ++i) win[i] = at(i);
             const double2 *bp = a.B + (int64_t)ys * a.PS + k;
             for (int32_t q0 = 0; q0 < a.YS; q0 += DY) {
                 double2 bq[DY];  // the block's template values, loaded together
@@ -304,7 +320,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 3))) voi
 #pragma unroll
                 for (int q = 0; q < DY; ++q) {
                     // row ys + q0 + q: the window holds lags 0 .. DY-1 in slots (q + i) mod DY
-                    win[(q + DY - 1) % DY] = base[(q0 + q + DY - 1) * CORR_KW];
+                    win[(q + DY - 1) % DY] = at(q0 + q + DY - 1);
                     const double2 bv = bq[q];
 #pragma unroll
                     for (int i = 0; i < DY; ++i) {
@@ -318,6 +334,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 3))) voi
                 }
             }
         }
+        ring0 += YC % rows;
+        if (ring0 >= rows) ring0 -= rows;
     }
     if (act && k <= a.N2) {
         double2 *zp = a.Zp + ((((int64_t)f * a.n_band + band) * a.S + s) * a.D) * a.PS + k;

@@ -238,18 +238,18 @@ __global__ __launch_bounds__(FFT_THREADS) void fft_rows(RowSrc src, int32_t rows
 // workgroup); wave w = (lag block within the group, sub-range s): a thread owns DY
 // consecutive lags j0 .. j0 + DY - 1 and keeps the DY frame values its next template row
 // needs in a register window (one new value per row).  The frame rows of a chunk of
-// S * YS template rows (and the lags of the group) are staged in LDS; template values are
+// S * DY template rows (and the lags of the group) are staged in LDS; template values are
 // read from the spectrum directly.  Rows beyond the data are zero in both spectra.
 struct CorrArgs {
     const double2 *A;  // frame spectra: frame f at A + f * a_batch, row r at + r * PS
     const double2 *B;  // template spectrum [rows][PS]
     double2 *Zp;       // [F][n_band][S][D][PS]
     int64_t a_batch;
-    int32_t PS, N2, D, NB, NBG, S, YS, BY, n_band, n_kb;
+    int32_t PS, N2, D, NB, NBG, S, BY, n_band, n_kb;  // sub-ranges of DY template rows per chunk
 };
 
 template <int DY>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 3))) void spec_corr(CorrArgs a)
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void spec_corr(CorrArgs a)
 {
     extern __shared__ __align__(16) double2 al[];  // [YC + NBG * DY - 1][CORR_KW]
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -261,7 +261,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 3))) voi
     const bool act = blk < a.NB;
     const int32_t j0 = blk * DY;                    // first lag of the thread
     const int32_t jg0 = grp * a.NBG * DY;           // first lag of the group
-    const int32_t YC = a.S * a.YS;
+    const int32_t YC = a.S * DY;                   // template rows per chunk
     const int32_t rows = YC + a.NBG * DY - 1;       // staged frame rows per chunk
     const double2 *A = a.A + (int64_t)f * a.a_batch;
     const int nthr = blockDim.x;
@@ -273,17 +273,31 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 3))) voi
     // The staged frame rows are a ring of `rows` LDS rows: frame row y_lo + jg0 + r of the
     // band sits in LDS row r mod rows.  Chunk y0 needs rows (y0 - y_lo) + [0, rows); from
     // the second chunk on only the YC rows it adds are staged, into the LDS rows of the YC
-    // rows the previous chunk alone needed.
+    // rows the previous chunk alone needed.  Those rows (chunk rows rows - YC + wv + u nw of
+    // wave wv) are loaded into registers while the previous chunk is computed and stored
+    // after its barrier, when each wave has at most NPF of them.
+    constexpr int NPF = 4;
+    const int wv = t >> 6, nw = nthr >> 6;
+    const bool pipe = YC <= NPF * nw;  // every wave has at most NPF new rows per chunk
+    double2 pf[NPF];
+#pragma unroll
+    for (int u = 0; u < NPF; ++u) pf[u] = make_double2(0.0, 0.0);
     const int32_t y_lo = band * a.BY, y_hi = y_lo + a.BY;
     int32_t ring0 = 0;  // LDS row of the chunk's first frame row
     for (int32_t y0 = y_lo; y0 < y_hi; y0 += YC) {
         __syncthreads();
-        // frame rows y0 + jg0 + [r_lo, rows), columns kb * 64 ..: wave w stages rows
-        // r_lo + w, r_lo + w + nw, ... (lane = column), eight rows loaded together, then
-        // stored; a row index past the last is clamped to it on both sides (the same value
-        // stored to the same place again), so no load waits behind a branch
-        {
-            const int wv = t >> 6, nw = nthr >> 6;
+        if (pipe && y0 != y_lo) {
+#pragma unroll
+            for (int u = 0; u < NPF; ++u) {  // a repeated last row stores the same value again
+                int32_t lr = ring0 + rows - YC + min(wv + u * nw, YC - 1);
+                if (lr >= rows) lr -= rows;
+                al[lr * CORR_KW + lane] = pf[u];
+            }
+        } else {
+            // frame rows y0 + jg0 + [r_lo, rows), columns kb * 64 ..: wave w stages rows
+            // r_lo + w, r_lo + w + nw, ... (lane = column), eight rows loaded together, then
+            // stored; a row index past the last is clamped to it on both sides (the same
+            // value stored to the same place again), so no load waits behind a branch
             const int32_t r_lo = y0 == y_lo ? 0 : rows - YC;
             const double2 *src = A + (int64_t)(y0 + jg0) * a.PS + kb * CORR_KW + lane;
             for (int r0 = r_lo + wv; r0 < rows; r0 += 8 * nw) {
@@ -299,8 +313,24 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 3))) voi
             }
         }
         __syncthreads();
+        // the sub-range's template values (one window length, DY rows), then the next
+        // chunk's new frame rows: both issued before any is used, the template values first
+        // (the waits are in issue order).  Both unconditional: the last chunk reloads its own
+        // rows, a wave's rows past its last repeat it, so the loads stay ahead of the compute.
+        const int32_t ys = y0 + s * DY;  // first template row of this sub-range
+        double2 bq[DY];
+        {
+            const double2 *bp = a.B + (int64_t)ys * a.PS + k;
+#pragma unroll
+            for (int q = 0; q < DY; ++q) bq[q] = bp[(int64_t)q * a.PS];
+            __builtin_amdgcn_sched_barrier(0);  // keep the issue order
+            const int32_t y0n = y0 + YC < y_hi ? y0 + YC : y0;
+            const double2 *src = A + (int64_t)(y0n + jg0) * a.PS + kb * CORR_KW + lane;
+#pragma unroll
+            for (int u = 0; u < NPF; ++u) pf[u] = src[(int64_t)(rows - YC + min(wv + u * nw, YC - 1)) * a.PS];
+            __builtin_amdgcn_sched_barrier(0);
+        }
         if (act) {
-            const int32_t ys = y0 + s * a.YS;  // first template row of this sub-range
             // window: chunk row of lag i at template row y is (y - y0) + (j0 - jg0) + i, in
             // LDS row ring0 + that, wrapped
             const int32_t c0 = ring0 + (ys - y0) + (j0 - jg0);
@@ -312,25 +342,19 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 3))) voi
             double2 win[DY];
 #pragma unroll
             for (int i = 0; i < DY - 1; ++i) win[i] = at(i);
-            const double2 *bp = a.B + (int64_t)ys * a.PS + k;
-            for (int32_t q0 = 0; q0 < a.YS; q0 += DY) {
-                double2 bq[DY];  // the block's template values, loaded together
 #pragma unroll
-                for (int q = 0; q < DY; ++q) bq[q] = bp[(int64_t)(q0 + q) * a.PS];
+            for (int q = 0; q < DY; ++q) {
+                // row ys + q: the window holds lags 0 .. DY-1 in slots (q + i) mod DY
+                win[(q + DY - 1) % DY] = at(q + DY - 1);
+                const double2 bv = bq[q];
 #pragma unroll
-                for (int q = 0; q < DY; ++q) {
-                    // row ys + q0 + q: the window holds lags 0 .. DY-1 in slots (q + i) mod DY
-                    win[(q + DY - 1) % DY] = at(q0 + q + DY - 1);
-                    const double2 bv = bq[q];
-#pragma unroll
-                    for (int i = 0; i < DY; ++i) {
-                        const double2 av = win[(q + i) % DY];
-                        // acc += av * conj(bv)
-                        acc[i].x = fma(av.x, bv.x, acc[i].x);
-                        acc[i].x = fma(av.y, bv.y, acc[i].x);
-                        acc[i].y = fma(av.y, bv.x, acc[i].y);
-                        acc[i].y = fma(-av.x, bv.y, acc[i].y);
-                    }
+                for (int i = 0; i < DY; ++i) {
+                    const double2 av = win[(q + i) % DY];
+                    // acc += av * conj(bv)
+                    acc[i].x = fma(av.x, bv.x, acc[i].x);
+                    acc[i].x = fma(av.y, bv.y, acc[i].x);
+                    acc[i].y = fma(av.y, bv.x, acc[i].y);
+                    acc[i].y = fma(-av.x, bv.y, acc[i].y);
                 }
             }
         }
@@ -748,7 +772,6 @@ extern "C" int reduce_register_fft(const float *ref, const float *frames, int32_
     ca.NB = L.NB;
     ca.NBG = L.NBG;
     ca.S = L.S;
-    ca.YS = L.YS;
     ca.BY = L.BY;
     ca.n_band = L.n_band;
     ca.n_kb = (int32_t)ceil_div(L.N2 + 1, CORR_KW);

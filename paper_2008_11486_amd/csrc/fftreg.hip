@@ -412,18 +412,28 @@ __global__ __launch_bounds__(FFT_THREADS) void spec_eval(const double2 *__restri
         double acc[EVAL_M];
 #pragma unroll
         for (int q = 0; q < EVAL_M; ++q) acc[q] = 0.0;
+        // EVAL_K values of k per iteration, their table values loaded together; a k past N2
+        // is clamped for the loads and its spectrum value taken as zero (adding 0 * w to a
+        // sum that started at +0 leaves it exact), so the sums are those of k in order
+        constexpr int EVAL_K = 4;
 #pragma unroll 1
-        for (int32_t k = t; k <= N2; k += FFT_THREADS) {
-            const double2 z = zs[k];
-            // w = e^{-2 pi i k m / P}, m = m0 .. m0 + EVAL_M - 1
-            double2 w = tw[((int64_t)k * m0) & (P - 1)];
-            const double2 w1 = tw[k & (P - 1)];
+        for (int32_t k0 = t; k0 <= N2; k0 += EVAL_K * FFT_THREADS) {
+            double2 w[EVAL_K], w1[EVAL_K], z[EVAL_K];
 #pragma unroll
-            for (int q = 0; q < EVAL_M; ++q) {
-                acc[q] = fma(z.x, w.x, acc[q]);  // Re(z conj(w))
-                acc[q] = fma(z.y, w.y, acc[q]);
-                if (q + 1 < EVAL_M) w = cmul(w, w1);
+            for (int e = 0; e < EVAL_K; ++e) {
+                const int32_t kc = min(k0 + e * FFT_THREADS, N2);
+                w[e] = tw[((int64_t)kc * m0) & (P - 1)];  // e^{-2 pi i k m / P} at m = m0
+                w1[e] = tw[kc & (P - 1)];                 // and at m = 1
+                z[e] = k0 + e * FFT_THREADS <= N2 ? zs[kc] : make_double2(0.0, 0.0);
             }
+#pragma unroll
+            for (int e = 0; e < EVAL_K; ++e)
+#pragma unroll
+                for (int q = 0; q < EVAL_M; ++q) {
+                    acc[q] = fma(z[e].x, w[e].x, acc[q]);  // Re(z conj(w))
+                    acc[q] = fma(z[e].y, w[e].y, acc[q]);
+                    if (q + 1 < EVAL_M) w[e] = cmul(w[e], w1[e]);
+                }
         }
 #pragma unroll
         for (int q = 0; q < EVAL_M; ++q) {

@@ -58,7 +58,9 @@ def _check(g, o, label, peak_rtol=1e-10):
     assert np.array_equal(g["flags"], o["flags"]), (label, g["flags"], o["flags"])
 
 
-# (R, N, W, H): powers of two and padded widths, several lag blocks, ragged template rows
+# (R, N, W, H): powers of two and padded widths, several lag blocks, ragged template rows;
+# R = 8 stages each chunk's new frame rows of the contraction inside the chunk loop (a wave
+# has more than four of them), the other radii load them during the previous chunk
 CASES = [(8, 4, 96, 80), (17, 4, 256, 256), (17, 3, 300, 261), (21, 3, 333, 290), (33, 2, 200, 190),
          (65, 2, 400, 360)]
 
